@@ -1,0 +1,449 @@
+// Serial CPU oracle for the content digest and the mapping-trace analysis of
+// "Dynamic Detection of Inefficient Data Mapping Patterns in Heterogeneous
+// OpenMP Applications" (PPoPP '26).
+//
+// TEST INFRASTRUCTURE ONLY. Nothing in the product library calls, links or
+// loads this file; only the test suite, the smoke check and the CPU-baseline
+// leg of the benchmark do. It shares no code, header or table with the GPU
+// path: the event layout is re-declared here from the documented format.
+//
+// Everything here is plain, serial and written for checking by eye:
+//   * xxh64      : XXH64 from the public xxHash specification (the paper's
+//                  hash study, Appendix B, evaluates XXH64 among its 19 hashes).
+//   * d64        : the chunked, tree-combined digest ODP-D64 v1 built on XXH64
+//                  (leaves of 4096 bytes, fan-in 64, per-level seeds). The
+//                  paper hashes each transfer whole (Sec. 5.1 and App. B); the
+//                  tree form is this project's parallel definition.
+//   * analyze    : the detection rules of Sec. 5 (Defs. 1-4 of Sec. 4 with the
+//                  keys of Algorithms 1-4), computed by single chronological
+//                  passes over per-key state.
+//   * alg1..alg4 : the paper's Algorithms 1-4 taken step by step with ordered
+//                  maps and queues, kept to cross-check the rules above.
+// Parity status of each part is listed in the header of oracle/__init__.py.
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <set>
+#include <tuple>
+#include <unordered_map>
+#include <unordered_set>
+#include <utility>
+#include <vector>
+
+namespace {
+
+// ----------------------------------------------------------------------------
+// XXH64, public xxHash specification (five 64-bit primes, 32-byte stripes over
+// four accumulators, then the remaining 8/4/1-byte pieces, then avalanche).
+// ----------------------------------------------------------------------------
+const uint64_t PRIME1 = 0x9E3779B185EBCA87ULL;
+const uint64_t PRIME2 = 0xC2B2AE3D27D4EB4FULL;
+const uint64_t PRIME3 = 0x165667B19E3779F9ULL;
+const uint64_t PRIME4 = 0x85EBCA77C2B2AE63ULL;
+const uint64_t PRIME5 = 0x27D4EB2F165667C5ULL;
+
+uint64_t rotl(uint64_t x, int r) { return (x << r) | (x >> (64 - r)); }
+
+uint64_t read_le64(const uint8_t* p) {
+  uint64_t v = 0;
+  for (int i = 0; i < 8; ++i) v |= (uint64_t)p[i] << (8 * i);
+  return v;
+}
+uint32_t read_le32(const uint8_t* p) {
+  uint32_t v = 0;
+  for (int i = 0; i < 4; ++i) v |= (uint32_t)p[i] << (8 * i);
+  return v;
+}
+
+uint64_t xxh_round(uint64_t acc, uint64_t input) {
+  acc += input * PRIME2;
+  acc = rotl(acc, 31);
+  acc *= PRIME1;
+  return acc;
+}
+uint64_t xxh_merge(uint64_t h, uint64_t acc) {
+  h ^= xxh_round(0, acc);
+  h = h * PRIME1 + PRIME4;
+  return h;
+}
+
+uint64_t xxh64(const uint8_t* p, uint64_t len, uint64_t seed) {
+  const uint8_t* end = p + len;
+  uint64_t h;
+  if (len >= 32) {
+    uint64_t v1 = seed + PRIME1 + PRIME2;
+    uint64_t v2 = seed + PRIME2;
+    uint64_t v3 = seed;
+    uint64_t v4 = seed - PRIME1;
+    const uint8_t* limit = end - 32;
+    do {
+      v1 = xxh_round(v1, read_le64(p));
+      v2 = xxh_round(v2, read_le64(p + 8));
+      v3 = xxh_round(v3, read_le64(p + 16));
+      v4 = xxh_round(v4, read_le64(p + 24));
+      p += 32;
+    } while (p <= limit);
+    h = rotl(v1, 1) + rotl(v2, 7) + rotl(v3, 12) + rotl(v4, 18);
+    h = xxh_merge(h, v1);
+    h = xxh_merge(h, v2);
+    h = xxh_merge(h, v3);
+    h = xxh_merge(h, v4);
+  } else {
+    h = seed + PRIME5;
+  }
+  h += len;
+  while (p + 8 <= end) {
+    h ^= xxh_round(0, read_le64(p));
+    h = rotl(h, 27) * PRIME1 + PRIME4;
+    p += 8;
+  }
+  if (p + 4 <= end) {
+    h ^= (uint64_t)read_le32(p) * PRIME1;
+    h = rotl(h, 23) * PRIME2 + PRIME3;
+    p += 4;
+  }
+  while (p < end) {
+    h ^= (uint64_t)(*p) * PRIME5;
+    h = rotl(h, 11) * PRIME1;
+    p += 1;
+  }
+  h ^= h >> 33;
+  h *= PRIME2;
+  h ^= h >> 29;
+  h *= PRIME3;
+  h ^= h >> 32;
+  return h;
+}
+
+// ----------------------------------------------------------------------------
+// ODP-D64 v1: leaves of L = 4096 bytes hashed with seed 0; then, level by
+// level, groups of up to F = 64 child digests serialised little-endian and
+// hashed with seed = level number, until one digest remains. Inputs of at most
+// one leaf are hashed directly (the empty input included).
+// ----------------------------------------------------------------------------
+const uint64_t LEAF = 4096;
+const uint64_t FANIN = 64;
+
+uint64_t d64(const uint8_t* p, uint64_t n) {
+  if (n <= LEAF) return xxh64(p, n, 0);
+  std::vector<uint64_t> level;
+  for (uint64_t off = 0; off < n; off += LEAF) level.push_back(xxh64(p + off, std::min(LEAF, n - off), 0));
+  uint64_t seed = 0;
+  while (level.size() > 1) {
+    seed += 1;
+    std::vector<uint64_t> parent;
+    for (size_t first = 0; first < level.size(); first += FANIN) {
+      size_t last = std::min(level.size(), (size_t)(first + FANIN));
+      std::vector<uint8_t> bytes;
+      for (size_t c = first; c < last; ++c)
+        for (int b = 0; b < 8; ++b) bytes.push_back((uint8_t)(level[c] >> (8 * b)));
+      parent.push_back(xxh64(bytes.data(), bytes.size(), seed));
+    }
+    level.swap(parent);
+  }
+  return level[0];
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------------------
+// Event log record and report, re-declared from the documented 64-byte layout.
+// ----------------------------------------------------------------------------
+extern "C" {
+
+struct orc_event {
+  uint64_t digest;    // transfers: digest of the bytes moved
+  uint64_t src_addr;  // transfers: source address; ALLOC/DELETE: host address
+  uint64_t dst_addr;  // transfers: destination address; ALLOC/DELETE: device address
+  uint64_t bytes;
+  uint64_t t_start, t_end;
+  uint64_t codeptr;
+  int16_t src_dev, dst_dev;  // -1 = host; ALLOC/DELETE/KERNEL use dst_dev
+  uint8_t op, rsv0;
+  uint16_t rsv1;
+};
+static_assert(sizeof(orc_event) == 64, "event record is 64 bytes");
+
+struct orc_report {
+  uint64_t n_events, n_invalid, n_transfers, n_kernels;
+  uint64_t n_alloc_pairs, n_unpaired_alloc, n_unpaired_delete;
+  uint64_t dd_events, dd_groups, dd_members, dd_bytes, dd_time_ns;
+  uint64_t rt_pairs, rt_rx_events, rt_bytes, rt_time_ns;
+  uint64_t ra_events, ra_groups, ra_members, ra_bytes, ra_time_ns;
+  uint64_t ua_events, ua_bytes, ua_time_ns;
+  int32_t status;
+  uint32_t first_bad_event;
+};
+
+enum { OP_ALLOC = 1, OP_H2D = 2, OP_D2H = 3, OP_D2D = 4, OP_DELETE = 5, OP_KERNEL = 6 };
+enum { F_DD = 1, F_RT_TX = 2, F_RT_RX = 4, F_RA = 8, F_UA = 16, F_PAIRED = 32, F_INVALID = 128 };
+const int MAX_DEVICE = 9;  // device numbers -1 (host) .. 9 are accepted
+
+uint64_t orc_xxh64(const uint8_t* p, uint64_t n, uint64_t seed) { return xxh64(p, n, seed); }
+uint64_t orc_d64(const uint8_t* p, uint64_t n) { return d64(p, n); }
+void orc_d64_many(const uint8_t* const* ptrs, const uint64_t* sizes, uint64_t n, uint64_t* out) {
+  for (uint64_t i = 0; i < n; ++i) out[i] = d64(ptrs[i], sizes[i]);
+}
+
+static bool is_transfer(uint8_t op) { return op == OP_H2D || op == OP_D2H || op == OP_D2D; }
+static bool dev_ok(int d) { return d >= -1 && d <= MAX_DEVICE; }
+static uint64_t dur(const orc_event& e) { return e.t_end - e.t_start; }
+
+// Validity: known op code, t_end >= t_start, t_start not below the previous
+// record's (the log is chronological), and the device numbers the record uses
+// within range. Invalid records take part in no rule.
+static bool event_valid(const orc_event* ev, uint64_t i) {
+  const orc_event& e = ev[i];
+  if (e.op < OP_ALLOC || e.op > OP_KERNEL) return false;
+  if (e.t_end < e.t_start) return false;
+  if (i > 0 && e.t_start < ev[i - 1].t_start) return false;
+  if (!dev_ok(e.dst_dev)) return false;
+  if (is_transfer(e.op) && !dev_ok(e.src_dev)) return false;
+  return true;
+}
+
+// The detection rules, one chronological pass per rule. flags[i] receives the
+// F_* bits of record i; *rep receives the counts and sums.
+int orc_analyze(const orc_event* ev, uint64_t n, uint8_t* flags, orc_report* rep) {
+  std::memset(rep, 0, sizeof(*rep));
+  rep->n_events = n;
+  rep->first_bad_event = 0xFFFFFFFFu;
+  std::vector<char> valid(n);
+  for (uint64_t i = 0; i < n; ++i) {
+    valid[i] = event_valid(ev, i);
+    flags[i] = valid[i] ? 0 : F_INVALID;
+    if (!valid[i]) {
+      rep->n_invalid++;
+      if (rep->status == 0) { rep->status = 1; rep->first_bad_event = (uint32_t)i; }
+    }
+  }
+  std::vector<uint64_t> transfers, allocdel, kernels;
+  for (uint64_t i = 0; i < n; ++i) {
+    if (!valid[i]) continue;
+    if (is_transfer(ev[i].op)) transfers.push_back(i);
+    else if (ev[i].op == OP_ALLOC || ev[i].op == OP_DELETE) allocdel.push_back(i);
+    else kernels.push_back(i);
+  }
+  rep->n_transfers = transfers.size();
+  rep->n_kernels = kernels.size();
+
+  // Duplicate transfer (Def. 1, key <hash, receiving device> of Alg. 1): a
+  // transfer is a duplicate when the same receiver already got the same digest.
+  {
+    std::map<std::pair<uint64_t, int>, uint64_t> count;
+    for (uint64_t i : transfers) {
+      auto key = std::make_pair(ev[i].digest, (int)ev[i].dst_dev);
+      if (count[key] > 0) {
+        flags[i] |= F_DD;
+        rep->dd_events++;
+        rep->dd_bytes += ev[i].bytes;
+        rep->dd_time_ns += dur(ev[i]);
+      }
+      count[key]++;
+    }
+    for (auto& kv : count)
+      if (kv.second >= 2) { rep->dd_groups++; rep->dd_members += kv.second; }
+  }
+
+  // Round trip (Def. 2). Self-transfers (src == dst) take no part.
+  //   RT_TX: a strictly later transfer carries the same digest in the reverse
+  //          direction (A sent to B; later A gets the same data back from B).
+  //   RT_RX: the latest earlier transfer with the same digest between the same
+  //          two endpoints went the other way (this record is a return leg).
+  {
+    std::set<std::tuple<uint64_t, int, int>> later;
+    for (size_t k = transfers.size(); k-- > 0;) {
+      const orc_event& e = ev[transfers[k]];
+      if (e.src_dev == e.dst_dev) continue;
+      if (later.count(std::make_tuple(e.digest, (int)e.dst_dev, (int)e.src_dev))) {
+        flags[transfers[k]] |= F_RT_TX;
+        rep->rt_pairs++;
+      }
+      later.insert(std::make_tuple(e.digest, (int)e.src_dev, (int)e.dst_dev));
+    }
+    std::map<std::tuple<uint64_t, int, int>, std::pair<int, int>> last_dir;
+    for (uint64_t i : transfers) {
+      const orc_event& e = ev[i];
+      if (e.src_dev == e.dst_dev) continue;
+      int lo = std::min((int)e.src_dev, (int)e.dst_dev), hi = std::max((int)e.src_dev, (int)e.dst_dev);
+      auto key = std::make_tuple(e.digest, lo, hi);
+      auto it = last_dir.find(key);
+      if (it != last_dir.end() && it->second == std::make_pair((int)e.dst_dev, (int)e.src_dev)) {
+        flags[i] |= F_RT_RX;
+        rep->rt_rx_events++;
+        rep->rt_bytes += e.bytes;
+        rep->rt_time_ns += dur(e);
+      }
+      last_dir[key] = std::make_pair((int)e.src_dev, (int)e.dst_dev);
+    }
+  }
+
+  // Allocation/deletion pairing (the helper the paper calls in Algs. 3 and 4):
+  // records grouped by (device, device address) in log order; a DELETE pairs
+  // with the record just before it in its group when that record is an ALLOC.
+  std::vector<std::pair<uint64_t, uint64_t>> pairs;  // (alloc, delete), in delete order
+  {
+    std::map<std::pair<int, uint64_t>, uint64_t> prev;
+    for (uint64_t i : allocdel) {
+      auto key = std::make_pair((int)ev[i].dst_dev, ev[i].dst_addr);
+      auto it = prev.find(key);
+      if (ev[i].op == OP_DELETE && it != prev.end() && ev[it->second].op == OP_ALLOC) {
+        pairs.emplace_back(it->second, i);
+        flags[it->second] |= F_PAIRED;
+        flags[i] |= F_PAIRED;
+      }
+      prev[key] = i;
+    }
+    std::sort(pairs.begin(), pairs.end());  // alloc order
+    rep->n_alloc_pairs = pairs.size();
+    for (uint64_t i : allocdel) {
+      if (flags[i] & F_PAIRED) continue;
+      if (ev[i].op == OP_ALLOC) rep->n_unpaired_alloc++; else rep->n_unpaired_delete++;
+    }
+  }
+
+  // Repeated allocation (Def. 3, key <host address, device, bytes> of Alg. 3):
+  // every paired allocation after the first of its key.
+  {
+    std::map<std::tuple<uint64_t, int, uint64_t>, uint64_t> count;
+    for (auto& pr : pairs) {
+      const orc_event& a = ev[pr.first];
+      auto key = std::make_tuple(a.src_addr, (int)a.dst_dev, a.bytes);
+      if (count[key] > 0) {
+        flags[pr.first] |= F_RA;
+        rep->ra_events++;
+        rep->ra_bytes += a.bytes;
+        rep->ra_time_ns += dur(a) + dur(ev[pr.second]);
+      }
+      count[key]++;
+    }
+    for (auto& kv : count)
+      if (kv.second >= 2) { rep->ra_groups++; rep->ra_members += kv.second; }
+  }
+
+  // Unused allocation (Def. 4, allocation half; Alg. 4): the closed interval
+  // [alloc.t_start, delete.t_end] meets no kernel's [t_start, t_end] on the same
+  // device. The number of kernels meeting it is
+  //   #{kernels with t_start <= delete.t_end} - #{kernels with t_end < alloc.t_start},
+  // because every kernel ending before the allocation also starts before the
+  // deletion ends.
+  {
+    std::map<int, std::vector<uint64_t>> starts, ends;
+    for (uint64_t k : kernels) {
+      starts[ev[k].dst_dev].push_back(ev[k].t_start);
+      ends[ev[k].dst_dev].push_back(ev[k].t_end);
+    }
+    for (auto& kv : starts) std::sort(kv.second.begin(), kv.second.end());
+    for (auto& kv : ends) std::sort(kv.second.begin(), kv.second.end());
+    for (auto& pr : pairs) {
+      const orc_event& a = ev[pr.first];
+      const orc_event& d = ev[pr.second];
+      uint64_t meets = 0;
+      auto s = starts.find(a.dst_dev);
+      if (s != starts.end()) {
+        const std::vector<uint64_t>& st = s->second;
+        const std::vector<uint64_t>& en = ends[a.dst_dev];
+        uint64_t started = std::upper_bound(st.begin(), st.end(), d.t_end) - st.begin();
+        uint64_t ended = std::lower_bound(en.begin(), en.end(), a.t_start) - en.begin();
+        meets = started - ended;
+      }
+      if (meets == 0) {
+        flags[pr.first] |= F_UA;
+        rep->ua_events++;
+        rep->ua_bytes += a.bytes;
+        rep->ua_time_ns += dur(a) + dur(d);
+      }
+    }
+  }
+  return 0;
+}
+
+// ----------------------------------------------------------------------------
+// The paper's Algorithms 1-4, step by step, for cross-checking. Each takes the
+// indices of the records it is given (already restricted to the kind of record
+// the algorithm expects) and returns what the algorithm returns, flattened.
+// ----------------------------------------------------------------------------
+
+// Algorithm 1: map <hash, destination device> -> events; groups of size >= 2.
+// Output: group_of[i] = group number (0-based, in order of first member) for
+// members of returned groups, else -1. Returns the number of groups.
+int64_t orc_alg1(const orc_event* ev, const uint64_t* idx, uint64_t m, int64_t* group_of) {
+  std::map<std::pair<uint64_t, int>, std::vector<uint64_t>> received;
+  for (uint64_t k = 0; k < m; ++k)
+    received[std::make_pair(ev[idx[k]].digest, (int)ev[idx[k]].dst_dev)].push_back(k);
+  std::vector<std::vector<uint64_t>> dup;
+  for (auto& kv : received)
+    if (kv.second.size() >= 2) dup.push_back(kv.second);
+  std::sort(dup.begin(), dup.end(), [](const std::vector<uint64_t>& x, const std::vector<uint64_t>& y) { return x[0] < y[0]; });
+  for (uint64_t k = 0; k < m; ++k) group_of[k] = -1;
+  for (size_t g = 0; g < dup.size(); ++g)
+    for (uint64_t k : dup[g]) group_of[k] = (int64_t)g;
+  return (int64_t)dup.size();
+}
+
+// Algorithm 2: queues of received events per <hash, destination>; for each
+// transfer, peek the queue of its source; record <tx, rx>; dequeue the queue
+// of its destination. Output: tx_pos[p], rx_pos[p] (positions in idx), in the
+// order the algorithm records them. Returns the number of pairs.
+int64_t orc_alg2(const orc_event* ev, const uint64_t* idx, uint64_t m, int64_t* tx_pos, int64_t* rx_pos) {
+  std::map<std::pair<uint64_t, int>, std::deque<uint64_t>> received;
+  for (uint64_t k = 0; k < m; ++k)
+    received[std::make_pair(ev[idx[k]].digest, (int)ev[idx[k]].dst_dev)].push_back(k);
+  int64_t np = 0;
+  for (uint64_t k = 0; k < m; ++k) {
+    const orc_event& tx = ev[idx[k]];
+    auto rx_it = received.find(std::make_pair(tx.digest, (int)tx.src_dev));
+    if (rx_it == received.end() || rx_it->second.empty()) continue;
+    tx_pos[np] = (int64_t)k;
+    rx_pos[np] = (int64_t)rx_it->second.front();
+    np++;
+    received[std::make_pair(tx.digest, (int)tx.dst_dev)].pop_front();
+  }
+  return np;
+}
+
+// Algorithm 3 over given <alloc, delete> pairs (positions in the event array):
+// map <host address, device, bytes> -> pairs; keep groups of size >= 2.
+// Output: rank[p] = position of pair p inside its kept group (0 = first), or
+// -1 when its group was removed. Returns the number of kept groups.
+int64_t orc_alg3(const orc_event* ev, const uint64_t* alloc_idx, const uint64_t* delete_idx, uint64_t m, int64_t* rank) {
+  (void)delete_idx;
+  std::map<std::tuple<uint64_t, int, uint64_t>, std::vector<uint64_t>> repeated;
+  for (uint64_t p = 0; p < m; ++p) {
+    const orc_event& a = ev[alloc_idx[p]];
+    repeated[std::make_tuple(a.src_addr, (int)a.dst_dev, a.bytes)].push_back(p);
+  }
+  for (auto it = repeated.begin(); it != repeated.end();) {
+    if (it->second.size() < 2) it = repeated.erase(it); else ++it;
+  }
+  for (uint64_t p = 0; p < m; ++p) rank[p] = -1;
+  for (auto& kv : repeated)
+    for (size_t r = 0; r < kv.second.size(); ++r) rank[kv.second[r]] = (int64_t)r;
+  return (int64_t)repeated.size();
+}
+
+// Algorithm 4: per device, a pointer over that device's kernels (in log
+// order) skips kernels that end before the allocation starts; the pair is
+// unused when no kernel is left or the next one starts after the deletion ends.
+// Pairs must be in allocation order. Output: unused[p] in {0, 1}.
+void orc_alg4(const orc_event* ev, const uint64_t* kernel_idx, uint64_t nk,
+              const uint64_t* alloc_idx, const uint64_t* delete_idx, uint64_t m, uint8_t* unused) {
+  std::map<int, std::vector<uint64_t>> dev_kernels;
+  for (uint64_t k = 0; k < nk; ++k) dev_kernels[ev[kernel_idx[k]].dst_dev].push_back(kernel_idx[k]);
+  std::map<int, std::vector<uint64_t>> dev_pairs;
+  for (uint64_t p = 0; p < m; ++p) dev_pairs[ev[alloc_idx[p]].dst_dev].push_back(p);
+  for (auto& dp : dev_pairs) {
+    const std::vector<uint64_t>& tgt = dev_kernels[dp.first];
+    size_t t = 0;
+    for (uint64_t p : dp.second) {
+      const orc_event& a = ev[alloc_idx[p]];
+      const orc_event& d = ev[delete_idx[p]];
+      while (t < tgt.size() && ev[tgt[t]].t_end < a.t_start) t++;
+      unused[p] = (t == tgt.size() || ev[tgt[t]].t_start > d.t_end) ? 1 : 0;
+    }
+  }
+}
+
+}  // extern "C"
