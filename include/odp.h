@@ -1,0 +1,232 @@
+/*
+ * odp.h -- C ABI of the MI355X (gfx950) content-digest and mapping-trace
+ * analysis library: the data-parallel hot path of "Dynamic Detection of
+ * Inefficient Data Mapping Patterns in Heterogeneous OpenMP Applications"
+ * (PPoPP '26).
+ *
+ * The paper's detector (Sec. 5) takes a chronological log of OpenMP target
+ * events, each carrying start/end time, a hash of the data it moved, source and
+ * destination device numbers, a code pointer, a byte count and an operation
+ * type, and finds four inefficient mapping patterns (Sec. 4, Defs. 1-4):
+ * duplicate transfers, round-trip transfers, repeated device allocations and
+ * unused device allocations. This library computes the two data-parallel
+ * parts of that method on one GPU:
+ *
+ *   odp_digest_buffers   the content digest of every transferred or mapped
+ *                        buffer (the paper hashes each transfer, Sec. 5.1 and
+ *                        App. B; here the digest is ODP-D64 v1, defined below)
+ *   odp_analyze_trace    one pass over the event log that flags the four
+ *                        patterns from those digests and addresses
+ *
+ * Conventions for every entry point
+ *   - All pointers marked DEVICE must be device-accessible: hipMalloc memory,
+ *     or pinned host memory mapped into the device address space. HOST marks
+ *     ordinary host memory read during the call.
+ *   - The caller owns every array. The library keeps only its own workspace
+ *     (grow-only, per device and stream), released by odp_release().
+ *   - Calls only enqueue work on `stream` (a hipStream_t; NULL means the
+ *     default stream) and return; results are valid once the stream reaches
+ *     that point. odp_digest_buffers_plain is the exception noted there.
+ *   - Return value: ODP_OK (0) or a negative ODP_E* code. Nothing throws
+ *     across the ABI. odp_last_error_string() describes the last failure of
+ *     the calling thread.
+ *   - Calls on different streams may run concurrently; calls on one stream are
+ *     ordered by the stream.
+ */
+#ifndef ODP_H
+#define ODP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void* odp_stream_t; /* a hipStream_t */
+
+enum {
+  ODP_OK = 0,
+  ODP_EINVAL = -1,  /* null array with n > 0, null buffer with size > 0, bad tuning */
+  ODP_ERANGE = -2,  /* n above the supported maximum (2^32 - 1 events or buffers) */
+  ODP_ENOMEM = -3,  /* workspace could not be allocated */
+  ODP_EHIP = -4,    /* HIP launch or runtime failure (see odp_last_error_string) */
+  ODP_ECAPACITY = -5 /* digest tree workspace too small for the call (see odp_reserve) */
+};
+
+/* ---------------------------------------------------------------------------
+ * ODP-D64 v1, the content digest (this library's definition).
+ *
+ * The paper hashes every transferred buffer whole with a 64-bit
+ * non-cryptographic hash and assumes no collisions (Sec. 5.1; App. B studies 19
+ * such hashes, XXH64 among them). A whole-buffer serial hash cannot use a GPU,
+ * so the digest is defined as a tree of XXH64 calls (XXH64 as in the public
+ * xxHash specification, input read little-endian):
+ *
+ *   n <= 4096 bytes:  D64(b) = XXH64(b, seed 0)            (also for n = 0)
+ *   n  > 4096 bytes:  leaves  = XXH64 of each 4096-byte piece (last one
+ *                               shorter), seed 0
+ *                     level s = groups of up to 64 consecutive digests of
+ *                               level s-1, serialised as little-endian u64,
+ *                               each group hashed with XXH64(seed = s),
+ *                               s = 1, 2, ... until one digest remains.
+ *
+ * Only the bytes matter: the same bytes at any address or alignment give the
+ * same digest, and no tuning choice changes it. Duplicate and round-trip
+ * detection need digest equality only, so under the paper's collision-free
+ * assumption the flags do not depend on which 64-bit hash is used.
+ * ------------------------------------------------------------------------ */
+
+/* Batched digest: one persistent launch over all buffers.
+ *   ptrs   DEVICE, n entries: start address of buffer i (device memory; any
+ *          alignment; buffers may overlap or alias; they are only read).
+ *   sizes  DEVICE, n entries: byte length of buffer i (0 allowed).
+ *   out    DEVICE, n entries: receives D64(buffer i). Must not overlap the
+ *          inputs.
+ * Work plan, leaf hashing, level-1 combine and upper levels all run on the
+ * device; the host reads no size. The sum over buffers of ceil(size/262144)
+ * must fit the tree workspace (odp_reserve; by default sized for four times
+ * the device's memory in distinct buffers). When it does not, every out[i] of
+ * the call is set to 0 and odp_device_status() reports ODP_ECAPACITY once the
+ * stream has completed. n = 0 returns ODP_OK and enqueues nothing.
+ * Capture-safe (no allocation, no memset node) once odp_reserve covered n. */
+int odp_digest_buffers(const void* const* ptrs, const uint64_t* sizes, size_t n, uint64_t* out,
+                       odp_stream_t stream);
+
+/* Per-buffer digest: the plain form, one kernel launch per buffer.
+ *   host_ptrs   HOST, n entries: device start address of buffer i.
+ *   host_sizes  HOST, n entries: byte length of buffer i.
+ *   out         DEVICE, n entries: receives D64(buffer i).
+ * Same result as odp_digest_buffers. May allocate (grow) workspace before the
+ * first launch; not capture-safe when it has to grow. */
+int odp_digest_buffers_plain(const void* const* host_ptrs, const uint64_t* host_sizes, size_t n,
+                             uint64_t* out, odp_stream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Event log record (64 bytes, 8-byte aligned). The paper's tool logs 72 bytes
+ * per data operation and 24 per target launch (Sec. 7.3) with the fields its
+ * detector needs (Sec. 5); this record carries the same fields, and a target
+ * launch is a record with op = ODP_KERNEL.
+ * ------------------------------------------------------------------------ */
+enum {
+  ODP_ALLOC = 1,  /* device allocation: host address in src_addr, device address in dst_addr */
+  ODP_H2D = 2,    /* host -> device transfer */
+  ODP_D2H = 3,    /* device -> host transfer */
+  ODP_D2D = 4,    /* device -> device transfer */
+  ODP_DELETE = 5, /* device deallocation: addresses as for ALLOC */
+  ODP_KERNEL = 6  /* target kernel execution on device dst_dev */
+};
+
+typedef struct odp_event {
+  uint64_t digest;   /* transfers: D64 of the bytes moved; ignored otherwise */
+  uint64_t src_addr; /* transfers: source address; ALLOC/DELETE: host address */
+  uint64_t dst_addr; /* transfers: destination address; ALLOC/DELETE: device address */
+  uint64_t bytes;    /* bytes moved or allocated */
+  uint64_t t_start;  /* ns; must not decrease along the array (the log is chronological) */
+  uint64_t t_end;    /* ns; must be >= t_start */
+  uint64_t codeptr;  /* opaque return address (kept, not used by the rules) */
+  int16_t src_dev;   /* transfers: sending device, -1 = host */
+  int16_t dst_dev;   /* transfers: receiving device; ALLOC/DELETE/KERNEL: the device */
+  uint8_t op;        /* ODP_ALLOC .. ODP_KERNEL */
+  uint8_t rsv0;
+  uint16_t rsv1;
+} odp_event;
+
+#define ODP_MAX_DEVICE 9 /* device numbers -1 (host) .. 9 are accepted */
+
+/* Per-event flag bits written to out_flags. */
+enum {
+  ODP_F_DD = 1,      /* duplicate transfer: the receiver already got this digest (Def. 1, Alg. 1) */
+  ODP_F_RT_TX = 2,   /* round trip, outbound: a later transfer carries this digest back (Def. 2, Alg. 2) */
+  ODP_F_RT_RX = 4,   /* round trip, return leg: the latest earlier transfer of this digest
+                        between the same two endpoints went the other way */
+  ODP_F_RA = 8,      /* repeated allocation: an earlier paired ALLOC had the same
+                        (host address, device, bytes) (Def. 3, Alg. 3) */
+  ODP_F_UA = 16,     /* unused allocation: no kernel on the device meets the closed interval
+                        [ALLOC.t_start, DELETE.t_end] (Def. 4, Alg. 4) */
+  ODP_F_PAIRED = 32, /* ALLOC/DELETE matched into a pair (see below) */
+  ODP_F_INVALID = 128 /* record rejected: unknown op, t_end < t_start, t_start below the
+                         previous record's, or a device number outside -1..ODP_MAX_DEVICE */
+};
+
+/* Counts and sums over one log. Filled on the device; valid after the stream
+ * completes. *_bytes and *_time_ns sum `bytes` and (t_end - t_start) over the
+ * flagged records (round trips: over return legs; RA/UA: the ALLOC plus its
+ * DELETE's duration), the inputs of the paper's savings estimate (Sec. 7.5). */
+typedef struct odp_report {
+  uint64_t n_events, n_invalid, n_transfers, n_kernels;
+  uint64_t n_alloc_pairs, n_unpaired_alloc, n_unpaired_delete;
+  uint64_t dd_events, dd_groups, dd_members, dd_bytes, dd_time_ns;
+  uint64_t rt_pairs, rt_rx_events, rt_bytes, rt_time_ns;
+  uint64_t ra_events, ra_groups, ra_members, ra_bytes, ra_time_ns;
+  uint64_t ua_events, ua_bytes, ua_time_ns;
+  int32_t status;           /* 0, or 1 when some record was rejected */
+  uint32_t first_bad_event; /* index of the first rejected record, 0xFFFFFFFF if none */
+} odp_report;
+
+/* Mapping-trace analysis (Sec. 5, Algs. 1-4) over a chronological log.
+ *   events      DEVICE, n records in log order (array order is time order; the
+ *               index breaks ties).
+ *   out_flags   DEVICE, n bytes: ODP_F_* bits of each record.
+ *   out_report  DEVICE, one odp_report.
+ * Rules (transfers are valid records with op H2D/D2H/D2D, in log order):
+ *   DD     some earlier transfer has the same digest and the same dst_dev.
+ *   RT_TX  src_dev != dst_dev, and some later transfer has the same digest with
+ *          (src_dev, dst_dev) swapped. rt_pairs counts these.
+ *   RT_RX  src_dev != dst_dev, and the latest earlier transfer with the same
+ *          digest between the same two endpoints went the other way.
+ *   Pairing (the allocation/deletion pairing the paper's Algs. 3-4 use but do
+ *          not define): ALLOC/DELETE records grouped by (dst_dev, dst_addr) in
+ *          log order; a DELETE pairs with the record just before it in its
+ *          group when that record is an ALLOC.
+ *   RA     a paired ALLOC with an earlier paired ALLOC of the same
+ *          (src_addr, dst_dev, bytes).
+ *   UA     a paired ALLOC on device d whose [t_start, DELETE.t_end] meets no
+ *          KERNEL record's [t_start, t_end] on d (closed intervals).
+ * Data-dependent problems do not fail the call: rejected records get
+ * ODP_F_INVALID, take part in no rule, and set report.status.
+ * n = 0 writes an empty report. n > 2^32 - 1 returns ODP_ERANGE.
+ * Capture-safe once odp_reserve covered n. */
+int odp_analyze_trace(const odp_event* events, size_t n, uint8_t* out_flags, odp_report* out_report,
+                      odp_stream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Helpers (workspace, tuning, status). Not part of the method.
+ * ------------------------------------------------------------------------ */
+
+/* Library version as 10000*major + 100*minor + patch. */
+int odp_version(void);
+
+/* Text of the calling thread's last error ("" if none). Owned by the library. */
+const char* odp_last_error_string(void);
+
+/* Pre-size the workspace of the current device for `stream`: up to max_buffers
+ * buffers totalling max_total_bytes for odp_digest_buffers, and up to
+ * max_events records for odp_analyze_trace. Synchronous; allocates. Call it
+ * before capturing calls into a hipGraph. */
+int odp_reserve(size_t max_buffers, uint64_t max_total_bytes, size_t max_events, odp_stream_t stream);
+
+/* Frees every workspace the library holds (all devices and streams). Waits for
+ * the device first. */
+int odp_release(void);
+
+/* Sticky device-side status of the current device: ODP_OK or ODP_ECAPACITY
+ * when a batched digest call found its tree workspace too small. Reading it
+ * synchronises the device and clears it. */
+int odp_device_status(void);
+
+/* Launch parameters of the batched digest. They change speed, never results. */
+typedef struct odp_tuning {
+  uint32_t blocks_per_cu;   /* persistent workgroups per compute unit, 1..8 */
+  uint32_t use_graph;       /* 1: replay the work plan + digest launch as a hipGraph */
+  uint32_t reserved[6];
+} odp_tuning;
+
+int odp_get_tuning(odp_tuning* out);
+int odp_set_tuning(const odp_tuning* in);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ODP_H */

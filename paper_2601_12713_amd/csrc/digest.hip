@@ -1,0 +1,632 @@
+// ODP-D64 v1 content digest on gfx950.
+//
+// The paper hashes every transferred buffer with one serial 64-bit hash on the
+// host (Sec. 5.1, App. B). Here every 4096-byte leaf is hashed by four lanes of
+// a wavefront (one per XXH64 accumulator), leaves are staged through LDS from
+// coalesced 128-bit nontemporal loads, 64 leaf digests are combined inside the
+// workgroup, and the upper tree levels are finished by whichever workgroup
+// completes the last child of a node (an atomic ticket per node).
+//
+// Work unit ("item"): either one level-1 node (64 leaves, 256 KiB) of a buffer
+// larger than one leaf, or a group of 64 buffers of at most one leaf each.
+// A workgroup (4 wavefronts) handles one item; each wavefront owns 16 rows
+// (leaves or small buffers) and stages, hashes and finishes them on its own,
+// so the only workgroup barriers are around the level-1 combine.
+#include "internal.h"
+#include "xxh64_dev.h"
+
+namespace odp {
+namespace {
+
+constexpr int kWaves = 4;
+constexpr int kThreads = 64 * kWaves;
+constexpr int kRows = 64;                  // rows per item
+constexpr int kRowsPerWave = kRows / kWaves;
+constexpr int kSlab = 256;                 // bytes of each row staged per step
+constexpr int kPad = 16;                   // LDS row padding (bank spread)
+constexpr int kStride = kSlab + kPad;
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+struct RowDesc {
+  const uint8_t* base;
+  uint32_t len;
+  uint32_t present;
+};
+
+struct Smem {
+  uint8_t slab[kWaves][kRowsPerWave * kStride];
+  RowDesc rows[kRows];
+  uint64_t leafdig[kRows];
+  uint32_t outidx[kRows];
+  uint32_t item;
+};
+
+__device__ __forceinline__ void wave_fence() { __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront"); }
+
+__host__ __device__ __forceinline__ uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+
+// Tree slots below the root and ticket slots (levels >= 2) of a buffer with
+// n1 level-1 nodes.
+__host__ __device__ inline void tree_need(uint64_t n1, uint64_t& tree_slots, uint64_t& tk_slots) {
+  tree_slots = 0;
+  tk_slots = 0;
+  uint64_t nj = n1;
+  while (nj > 1) {
+    tree_slots += nj;
+    nj = (nj + kFanIn - 1) / kFanIn;
+    tk_slots += nj;
+  }
+}
+
+// Hashes the 16 rows of the calling wavefront (`rows` in LDS). Returns the
+// XXH64 (seed 0) of row r in lane 4r; other lanes return 0.
+__device__ uint64_t hash_wave_rows(const RowDesc* rows, uint8_t* slab) {
+  const int lane = threadIdx.x & 63;
+  constexpr int NL = kSlab / 64;    // 128-bit loads per lane per step
+  constexpr int LPR = kSlab / 16;   // lanes covering one row in a load
+  constexpr int RPI = 64 / LPR;     // rows covered by one wavefront load
+  const int col = (lane % LPR) * 16;
+
+  const RowDesc mine = rows[lane & 15];
+  uint32_t mlen = mine.present ? mine.len : 0u;
+  const bool aligned = !mine.present || ((reinterpret_cast<uintptr_t>(mine.base) & 15) == 0);
+#pragma unroll
+  for (int o = 8; o >= 1; o >>= 1) mlen = max(mlen, (uint32_t)__shfl_xor((int)mlen, o, 64));
+  const bool all_aligned = __all(aligned);
+
+  const int hr = lane >> 2, a = lane & 3;
+  const RowDesc hrow = rows[hr];
+  const uint32_t hlen = hrow.present ? hrow.len : 0u;
+  const uint32_t nstripes = hlen >> 5;
+  uint64_t acc = xx_acc_init(0, a);
+
+  if (all_aligned) {
+    const uint8_t* lb[NL];
+    uint32_t ll[NL], ls[NL];
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+      const int r = k * RPI + lane / LPR;
+      const RowDesc d = rows[r];
+      lb[k] = d.base + col;
+      ll[k] = d.present ? d.len : 0u;
+      ls[k] = r * kStride + col;
+    }
+    u32x4 R[NL];
+#pragma unroll
+    for (int k = 0; k < NL; ++k)
+      if ((uint32_t)col < ll[k]) R[k] = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(lb[k]));
+    const uint8_t* hp = slab + hr * kStride + a * 8;
+    const uint32_t nslab = (mlen + kSlab - 1) / kSlab;
+    for (uint32_t s = 0; s < nslab; ++s) {
+      const uint32_t o = s * kSlab + col;
+#pragma unroll
+      for (int k = 0; k < NL; ++k)
+        if (o < ll[k]) *reinterpret_cast<u32x4*>(slab + ls[k]) = R[k];
+      if (s + 1 < nslab) {
+        const uint32_t o2 = o + kSlab;
+#pragma unroll
+        for (int k = 0; k < NL; ++k)
+          if (o2 < ll[k]) R[k] = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(lb[k] + (s + 1) * kSlab));
+      }
+      wave_fence();
+      const uint32_t q0 = s * (kSlab / 32);
+#pragma unroll
+      for (int q = 0; q < kSlab / 32; ++q)
+        if (q0 + q < nstripes) acc = xx_round(acc, *reinterpret_cast<const uint64_t*>(hp + q * 32));
+      wave_fence();
+    }
+  } else {
+    for (uint32_t s = 0; s < nstripes; ++s) acc = xx_round(acc, load64_any(hrow.base + s * 32 + a * 8));
+  }
+  uint64_t v1, v2, v3, v4;
+  xx_gather4(acc, v1, v2, v3, v4);
+  uint64_t h = 0;
+  if (a == 0 && hrow.present) {
+    h = nstripes ? xx_converge(v1, v2, v3, v4) : kP5;
+    h += hlen;
+    h = xx_tail_bytes(h, hrow.base + nstripes * 32, hlen - nstripes * 32);
+    h = xx_avalanche(h);
+  }
+  return h;
+}
+
+// Called by one whole wavefront after it computed the digest `h` (lane 0) of
+// node m of a level holding nj nodes. Stores it, and while this wavefront
+// completes the last missing child of the parent, climbs: hashes the parent
+// (seed = its level) and repeats; the root goes to *out.
+//   tree: the buffer's node slots, level by level (level 1 first)
+//   tk:   the buffer's tickets, level 2 first; reset to 0 by their last user
+__device__ void tree_up(uint64_t h, uint64_t m, uint64_t nj, uint64_t* out, uint64_t* tree, uint32_t* tk) {
+  const int lane = threadIdx.x & 63;
+  uint64_t loff = 0, tkoff = 0, level = 1;
+  h = __shfl(h, 0, 64);
+  for (;;) {
+    if (nj == 1) {
+      if (lane == 0) *out = h;
+      return;
+    }
+    if (lane == 0) tree[loff + m] = h;
+    __threadfence();
+    const uint64_t p = m / kFanIn;
+    const uint32_t nchild = (uint32_t)min<uint64_t>(kFanIn, nj - p * kFanIn);
+    const uint64_t nnext = ceil_div(nj, kFanIn);
+    uint32_t old = 0;
+    if (lane == 0) old = atomicAdd(&tk[tkoff + p], 1u);
+    old = __shfl(old, 0, 64);
+    if (old != nchild - 1) return;
+    __threadfence();
+    if (lane == 0) tk[tkoff + p] = 0;
+    h = xx_words4(tree + loff + p * kFanIn, nchild, level + 1);
+    h = __shfl(h, 0, 64);
+    ++level;
+    m = p;
+    loff += nj;
+    tkoff += nnext;
+    nj = nnext;
+  }
+}
+
+// One level-1 node of a buffer larger than one leaf.
+__device__ void run_node(Smem& sm, const uint8_t* buf, uint64_t size, uint64_t node, uint64_t* out,
+                         uint64_t* tree, uint32_t* tk) {
+  const int t = threadIdx.x;
+  const uint64_t nleaves = ceil_div(size, kLeaf);
+  const uint64_t n1 = ceil_div(nleaves, kFanIn);
+  const uint64_t first = node * kFanIn;
+  const uint32_t nl = (uint32_t)min<uint64_t>(kFanIn, nleaves - first);
+  if (t < kRows) {
+    RowDesc d;
+    const uint64_t off = (first + t) * kLeaf;
+    d.present = (uint32_t)t < nl;
+    d.base = buf + (d.present ? off : 0);
+    d.len = d.present ? (uint32_t)min<uint64_t>(kLeaf, size - off) : 0u;
+    sm.rows[t] = d;
+  }
+  __syncthreads();
+  const int w = t >> 6, r = (t & 63) >> 2;
+  const uint64_t h = hash_wave_rows(sm.rows + w * kRowsPerWave, sm.slab[w]);
+  if ((t & 3) == 0 && sm.rows[w * kRowsPerWave + r].present) sm.leafdig[w * kRowsPerWave + r] = h;
+  __syncthreads();
+  if (w == 0) {
+    const uint64_t d = xx_words4(sm.leafdig, nl, 1);
+    tree_up(d, node, n1, out, tree, tk);
+  }
+  __syncthreads();
+}
+
+// Up to 64 buffers of at most one leaf each (digest = XXH64 seed 0).
+__device__ void run_small(Smem& sm, uint64_t group, uint64_t n_small, const uint32_t* small_list,
+                          const void* const* ptrs, const uint64_t* sizes, uint64_t* out) {
+  const int t = threadIdx.x;
+  if (t < kRows) {
+    const uint64_t k = group * kRows + t;
+    RowDesc d;
+    d.present = k < n_small;
+    uint32_t idx = d.present ? small_list[k] : 0u;
+    d.base = d.present ? static_cast<const uint8_t*>(ptrs[idx]) : nullptr;
+    d.len = d.present ? (uint32_t)sizes[idx] : 0u;
+    sm.rows[t] = d;
+    sm.outidx[t] = idx;
+  }
+  __syncthreads();
+  const int w = t >> 6, r = (t & 63) >> 2;
+  const uint64_t h = hash_wave_rows(sm.rows + w * kRowsPerWave, sm.slab[w]);
+  if ((t & 3) == 0 && sm.rows[w * kRowsPerWave + r].present) out[sm.outidx[w * kRowsPerWave + r]] = h;
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Plain form: one launch per buffer, one workgroup per level-1 node.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void digest_one_kernel(const uint8_t* p, uint64_t size, uint64_t* out,
+                                                             uint64_t* tree, uint32_t* tk) {
+  __shared__ Smem sm;
+  if (size <= kLeaf) {
+    const int t = threadIdx.x;
+    if (t < kRows) {
+      RowDesc d;
+      d.present = t == 0;
+      d.base = p;
+      d.len = t == 0 ? (uint32_t)size : 0u;
+      sm.rows[t] = d;
+    }
+    __syncthreads();
+    if (t < 64) {
+      const uint64_t h = hash_wave_rows(sm.rows, sm.slab[0]);
+      if (t == 0) *out = h;
+    }
+    return;
+  }
+  run_node(sm, p, size, blockIdx.x, out, tree, tk);
+}
+
+// ---------------------------------------------------------------------------
+// Batched form: device-side work plan, then one persistent launch.
+// ---------------------------------------------------------------------------
+struct PlanArgs {
+  const uint64_t* sizes;
+  uint64_t n;
+  uint64_t* node_off;   // [n] first node item of buffer i
+  uint64_t* tree_off;   // [n]
+  uint64_t* tk_off;     // [n]
+  uint32_t* small_list; // [n]
+  uint64_t* blk;        // [4 * nblk] per-tile sums, then exclusive prefixes
+  uint64_t nblk;
+  DigestCtl* ctl;
+  uint64_t cap_items, cap_tree, cap_tk;
+};
+
+constexpr int kPlanThreads = 256;
+constexpr int kPlanPer = 8;  // buffers per thread
+constexpr int kPlanTile = kPlanThreads * kPlanPer;
+
+__device__ __forceinline__ void buffer_counts(uint64_t size, uint64_t c[4]) {
+  if (size <= kLeaf) {
+    c[0] = 0;
+    c[1] = 1;
+    c[2] = 0;
+    c[3] = 0;
+  } else {
+    c[0] = ceil_div(ceil_div(size, kLeaf), kFanIn);
+    c[1] = 0;
+    tree_need(c[0], c[2], c[3]);
+  }
+}
+
+// Exclusive scan of 4 u64 quantities over the threads of a block; returns the
+// block totals in tot[].
+__device__ void block_scan4(uint64_t v[4], uint64_t tot[4]) {
+  __shared__ uint64_t sh[kPlanThreads / 64][4];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    uint64_t x = v[q];
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      uint64_t y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) sh[w][q] = x;
+    v[q] = x - v[q];  // exclusive within the wavefront
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    uint64_t before = 0, all = 0;
+    for (int j = 0; j < kPlanThreads / 64; ++j) {
+      if (j < w) before += sh[j][q];
+      all += sh[j][q];
+    }
+    v[q] += before;
+    tot[q] = all;
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kPlanThreads) void plan_count_kernel(PlanArgs A) {
+  const uint64_t base = (uint64_t)blockIdx.x * kPlanTile + threadIdx.x * kPlanPer;
+  uint64_t s[4] = {0, 0, 0, 0};
+  for (int j = 0; j < kPlanPer; ++j) {
+    const uint64_t i = base + j;
+    if (i < A.n) {
+      uint64_t c[4];
+      buffer_counts(A.sizes[i], c);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) s[q] += c[q];
+    }
+  }
+  uint64_t tot[4];
+  block_scan4(s, tot);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) A.blk[4 * blockIdx.x + q] = tot[q];
+  }
+}
+
+__global__ __launch_bounds__(kPlanThreads) void plan_scan_kernel(PlanArgs A) {
+  __shared__ uint64_t carry[4];
+  if (threadIdx.x < 4) carry[threadIdx.x] = 0;
+  __syncthreads();
+  for (uint64_t b0 = 0; b0 < A.nblk; b0 += kPlanThreads) {
+    const uint64_t b = b0 + threadIdx.x;
+    uint64_t v[4] = {0, 0, 0, 0};
+    if (b < A.nblk) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) v[q] = A.blk[4 * b + q];
+    }
+    uint64_t tot[4];
+    block_scan4(v, tot);
+    if (b < A.nblk) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) A.blk[4 * b + q] = v[q] + carry[q];
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) carry[threadIdx.x] += tot[threadIdx.x];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    DigestCtl* c = A.ctl;
+    c->n_node_items = carry[0];
+    c->n_small = carry[1];
+    c->n_items = carry[0] + ceil_div(carry[1], kRows);
+    c->tree_total = carry[2];
+    c->tk_total = carry[3];
+    c->head = 0;
+    c->overflow = (carry[0] > A.cap_items || carry[2] > A.cap_tree || carry[3] > A.cap_tk ||
+                   c->n_items >= 0xFFFFFFFFull) ? 1u : 0u;
+  }
+}
+
+__global__ __launch_bounds__(kPlanThreads) void plan_write_kernel(PlanArgs A) {
+  const uint64_t base = (uint64_t)blockIdx.x * kPlanTile + threadIdx.x * kPlanPer;
+  uint64_t c[kPlanPer][4];
+  uint64_t s[4] = {0, 0, 0, 0};
+  for (int j = 0; j < kPlanPer; ++j) {
+    const uint64_t i = base + j;
+    if (i < A.n) buffer_counts(A.sizes[i], c[j]);
+    else c[j][0] = c[j][1] = c[j][2] = c[j][3] = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) s[q] += c[j][q];
+  }
+  uint64_t tot[4];
+  block_scan4(s, tot);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) s[q] += A.blk[4 * blockIdx.x + q];
+  for (int j = 0; j < kPlanPer; ++j) {
+    const uint64_t i = base + j;
+    if (i < A.n) {
+      A.node_off[i] = s[0];
+      A.tree_off[i] = s[2];
+      A.tk_off[i] = s[3];
+      if (c[j][1]) A.small_list[s[1]] = (uint32_t)i;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) s[q] += c[j][q];
+  }
+}
+
+// item_buf[k] = buffer owning node item k (largest i with node_off[i] <= k).
+__global__ __launch_bounds__(kPlanThreads) void plan_items_kernel(PlanArgs A, uint32_t* item_buf) {
+  const DigestCtl* c = A.ctl;
+  if (c->overflow) return;
+  const uint64_t total = c->n_node_items;
+  for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total; k += (uint64_t)gridDim.x * blockDim.x) {
+    uint64_t lo = 0, hi = A.n;  // invariant: node_off[lo] <= k < node_off[hi] (node_off[n] = total)
+    while (hi - lo > 1) {
+      const uint64_t mid = (lo + hi) / 2;
+      if (A.node_off[mid] <= k) lo = mid; else hi = mid;
+    }
+    item_buf[k] = (uint32_t)lo;
+  }
+}
+
+struct BatchArgs {
+  const void* const* ptrs;
+  const uint64_t* sizes;
+  uint64_t n;
+  uint64_t* out;
+  const uint64_t* node_off;
+  const uint64_t* tree_off;
+  const uint64_t* tk_off;
+  const uint32_t* small_list;
+  const uint32_t* item_buf;
+  uint64_t* tree;
+  uint32_t* tickets;
+  DigestCtl* ctl;
+  uint32_t* status;  // host-mapped sticky status word
+};
+
+__global__ __launch_bounds__(kThreads) void digest_batched_kernel(BatchArgs A) {
+  __shared__ Smem sm;
+  const DigestCtl* c = A.ctl;
+  if (c->overflow) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < A.n; i += (uint64_t)gridDim.x * blockDim.x)
+      A.out[i] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && A.status) *reinterpret_cast<volatile uint32_t*>(A.status) = (uint32_t)(-ODP_ECAPACITY);
+    return;
+  }
+  const uint64_t n_node = c->n_node_items, n_items = c->n_items, n_small = c->n_small;
+  for (;;) {
+    if (threadIdx.x == 0) sm.item = atomicAdd(&A.ctl->head, 1u);
+    __syncthreads();
+    const uint64_t item = sm.item;
+    if (item >= n_items) break;
+    if (item < n_node) {
+      const uint32_t b = A.item_buf[item];
+      const uint64_t size = A.sizes[b];
+      run_node(sm, static_cast<const uint8_t*>(A.ptrs[b]), size, item - A.node_off[b], A.out + b,
+               A.tree + A.tree_off[b], A.tickets + A.tk_off[b]);
+    } else {
+      run_small(sm, item - n_node, n_small, A.small_list, A.ptrs, A.sizes, A.out);
+    }
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Host side.
+// ---------------------------------------------------------------------------
+int digest_reserve(Workspace* ws, size_t max_buffers, uint64_t max_total_bytes) {
+  // A captured graph holds workspace addresses: drop it before anything moves.
+  if (ws->graph) {
+    ODP_HIP(hipDeviceSynchronize());
+    ODP_HIP(hipGraphExecDestroy(ws->graph));
+    ws->graph = nullptr;
+  }
+  size_t nb = max_buffers < 1024 ? 1024 : max_buffers;
+  if (nb > ws->cap_buffers) {
+    const size_t nblk = (nb + kPlanTile - 1) / kPlanTile;
+    int e;
+    if ((e = ws->node_off.ensure((nb + 1) * 8)) || (e = ws->tree_off.ensure(nb * 8)) ||
+        (e = ws->tk_off.ensure(nb * 8)) || (e = ws->small_list.ensure(nb * 4)) ||
+        (e = ws->blk.ensure(nblk * 4 * 8)))
+      return e;
+    ws->cap_buffers = nb;
+  }
+  if (!ws->ctl.ptr) {
+    int e = ws->ctl.ensure(sizeof(DigestCtl));
+    if (e) return e;
+    ODP_HIP(hipMemset(ws->ctl.ptr, 0, sizeof(DigestCtl)));
+  }
+  uint64_t items = max_total_bytes / kNodeBytes + nb;
+  if (items > ws->cap_items) {
+    const uint64_t tree = items + items / 32 + 4 * (uint64_t)nb;
+    const uint64_t tk = items / 32 + 4 * (uint64_t)nb;
+    int e;
+    if ((e = ws->item_buf.ensure(items * 4)) || (e = ws->tree.ensure(tree * 8)) || (e = ws->tickets.ensure(tk * 4)))
+      return e;
+    ODP_HIP(hipMemset(ws->tickets.ptr, 0, tk * 4));
+    ws->cap_items = items;
+    ws->cap_tree = tree;
+    ws->cap_tk = tk;
+  }
+  return ODP_OK;
+}
+
+static int enqueue_batched(Workspace* ws, const void* const* ptrs, const uint64_t* sizes, size_t n, uint64_t* out,
+                           hipStream_t stream) {
+  PlanArgs P;
+  P.sizes = sizes;
+  P.n = n;
+  P.node_off = static_cast<uint64_t*>(ws->node_off.ptr);
+  P.tree_off = static_cast<uint64_t*>(ws->tree_off.ptr);
+  P.tk_off = static_cast<uint64_t*>(ws->tk_off.ptr);
+  P.small_list = static_cast<uint32_t*>(ws->small_list.ptr);
+  P.blk = static_cast<uint64_t*>(ws->blk.ptr);
+  P.nblk = (n + kPlanTile - 1) / kPlanTile;
+  P.ctl = static_cast<DigestCtl*>(ws->ctl.ptr);
+  P.cap_items = ws->cap_items;
+  P.cap_tree = ws->cap_tree;
+  P.cap_tk = ws->cap_tk;
+  hipLaunchKernelGGL(plan_count_kernel, dim3((unsigned)P.nblk), dim3(kPlanThreads), 0, stream, P);
+  hipLaunchKernelGGL(plan_scan_kernel, dim3(1), dim3(kPlanThreads), 0, stream, P);
+  hipLaunchKernelGGL(plan_write_kernel, dim3((unsigned)P.nblk), dim3(kPlanThreads), 0, stream, P);
+  const int cus = cu_count(ws->device);
+  hipLaunchKernelGGL(plan_items_kernel, dim3(cus * 4), dim3(kPlanThreads), 0, stream, P,
+                     static_cast<uint32_t*>(ws->item_buf.ptr));
+  BatchArgs B;
+  B.ptrs = ptrs;
+  B.sizes = sizes;
+  B.n = n;
+  B.out = out;
+  B.node_off = P.node_off;
+  B.tree_off = P.tree_off;
+  B.tk_off = P.tk_off;
+  B.small_list = P.small_list;
+  B.item_buf = static_cast<const uint32_t*>(ws->item_buf.ptr);
+  B.tree = static_cast<uint64_t*>(ws->tree.ptr);
+  B.tickets = static_cast<uint32_t*>(ws->tickets.ptr);
+  B.ctl = P.ctl;
+  B.status = device_status_word(ws->device);
+  const uint32_t bpc = tuning().blocks_per_cu;
+  hipLaunchKernelGGL(digest_batched_kernel, dim3(cus * bpc), dim3(kThreads), 0, stream, B);
+  return check_hip(hipGetLastError(), "digest launch");
+}
+
+}  // namespace odp
+
+using namespace odp;
+
+extern "C" int odp_digest_buffers(const void* const* ptrs, const uint64_t* sizes, size_t n, uint64_t* out,
+                                  odp_stream_t stream_) {
+  hipStream_t stream = static_cast<hipStream_t>(stream_);
+  if (n == 0) return ODP_OK;
+  if (!ptrs || !sizes || !out) return set_error(ODP_EINVAL, "odp_digest_buffers: null array with n = %zu", n);
+  if (n > 0xFFFFFFFFull) return set_error(ODP_ERANGE, "odp_digest_buffers: n = %zu above 2^32 - 1", n);
+  int err = 0;
+  Workspace* ws = workspace_for(stream, &err);
+  if (!ws) return err;
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  ODP_HIP(hipStreamIsCapturing(stream, &cap));
+  const bool capturing = cap != hipStreamCaptureStatusNone;
+  if (n > ws->cap_buffers || !ws->cap_items) {
+    if (capturing)
+      return set_error(ODP_ENOMEM, "odp_digest_buffers: workspace for %zu buffers not reserved before capture", n);
+    hipDeviceProp_t prop;
+    ODP_HIP(hipGetDeviceProperties(&prop, ws->device));
+    int e = digest_reserve(ws, n, (uint64_t)prop.totalGlobalMem * 4);
+    if (e) return e;
+  }
+  const Tuning& tn = tuning();
+  if (!tn.use_graph || capturing) return enqueue_batched(ws, ptrs, sizes, n, out, stream);
+  const uint32_t grid = cu_count(ws->device) * tn.blocks_per_cu;
+  if (!(ws->graph && ws->g_ptrs == ptrs && ws->g_sizes == sizes && ws->g_out == out && ws->g_n == n &&
+        ws->g_grid == grid)) {
+    if (ws->graph) {
+      ODP_HIP(hipGraphExecDestroy(ws->graph));
+      ws->graph = nullptr;
+    }
+    hipStream_t cs;
+    ODP_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    hipError_t he = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    int e = ODP_OK;
+    if (he == hipSuccess) {
+      e = enqueue_batched(ws, ptrs, sizes, n, out, cs);
+      he = hipStreamEndCapture(cs, &g);
+    }
+    (void)hipStreamDestroy(cs);
+    if (he != hipSuccess) return check_hip(he, "graph capture");
+    if (e) {
+      if (g) (void)hipGraphDestroy(g);
+      return e;
+    }
+    he = hipGraphInstantiate(&ws->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (he != hipSuccess) {
+      ws->graph = nullptr;
+      return check_hip(he, "graph instantiate");
+    }
+    ws->g_ptrs = ptrs;
+    ws->g_sizes = sizes;
+    ws->g_out = out;
+    ws->g_n = n;
+    ws->g_grid = grid;
+  }
+  ODP_HIP(hipGraphLaunch(ws->graph, stream));
+  return ODP_OK;
+}
+
+extern "C" int odp_digest_buffers_plain(const void* const* host_ptrs, const uint64_t* host_sizes, size_t n,
+                                        uint64_t* out, odp_stream_t stream_) {
+  hipStream_t stream = static_cast<hipStream_t>(stream_);
+  if (n == 0) return ODP_OK;
+  if (!host_ptrs || !host_sizes || !out)
+    return set_error(ODP_EINVAL, "odp_digest_buffers_plain: null array with n = %zu", n);
+  if (n > 0xFFFFFFFFull) return set_error(ODP_ERANGE, "odp_digest_buffers_plain: n = %zu above 2^32 - 1", n);
+  uint64_t need_tree = 0, need_tk = 0;
+  for (size_t i = 0; i < n; ++i) {
+    if (!host_ptrs[i] && host_sizes[i] > 0)
+      return set_error(ODP_EINVAL, "odp_digest_buffers_plain: buffer %zu is null with size %llu", i,
+                       (unsigned long long)host_sizes[i]);
+    if (host_sizes[i] > kLeaf) {
+      uint64_t tr, tk;
+      tree_need(ceil_div(ceil_div(host_sizes[i], kLeaf), kFanIn), tr, tk);
+      need_tree = std::max(need_tree, tr);
+      need_tk = std::max(need_tk, tk);
+    }
+  }
+  int err = 0;
+  Workspace* ws = workspace_for(stream, &err);
+  if (!ws) return err;
+  if (need_tree > ws->p_cap_tree || need_tk > ws->p_cap_tk || !ws->p_tickets.ptr) {
+    ODP_HIP(hipStreamSynchronize(stream));
+    const uint64_t tr = std::max<uint64_t>(need_tree, 1024), tk = std::max<uint64_t>(need_tk, 256);
+    int e;
+    if ((e = ws->p_tree.ensure(tr * 8)) || (e = ws->p_tickets.ensure(tk * 4))) return e;
+    ODP_HIP(hipMemset(ws->p_tickets.ptr, 0, tk * 4));
+    ws->p_cap_tree = tr;
+    ws->p_cap_tk = tk;
+  }
+  uint64_t* tree = static_cast<uint64_t*>(ws->p_tree.ptr);
+  uint32_t* tk = static_cast<uint32_t*>(ws->p_tickets.ptr);
+  for (size_t i = 0; i < n; ++i) {
+    const uint64_t s = host_sizes[i];
+    const unsigned grid = s <= kLeaf ? 1u : (unsigned)ceil_div(ceil_div(s, kLeaf), kFanIn);
+    hipLaunchKernelGGL(digest_one_kernel, dim3(grid), dim3(kThreads), 0, stream,
+                       static_cast<const uint8_t*>(host_ptrs[i]), s, out + i, tree, tk);
+  }
+  return check_hip(hipGetLastError(), "digest_one launch");
+}

@@ -1,0 +1,84 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <mutex>
+#include <string>
+
+#include "../../include/odp.h"
+
+namespace odp {
+
+// Digest geometry of ODP-D64 v1.
+constexpr uint32_t kLeaf = 4096;              // leaf bytes
+constexpr uint32_t kFanIn = 64;               // children per tree node
+constexpr uint64_t kNodeBytes = uint64_t(kLeaf) * kFanIn;  // bytes under one level-1 node
+
+// Error plumbing (thread-local message, codes from odp.h).
+int set_error(int code, const char* fmt, ...);
+int check_hip(hipError_t e, const char* what);
+#define ODP_HIP(call)                                   \
+  do {                                                  \
+    hipError_t odp_e_ = (call);                         \
+    if (odp_e_ != hipSuccess) return ::odp::check_hip(odp_e_, #call); \
+  } while (0)
+
+// Grow-only device buffer.
+struct DevBuf {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+  int ensure(size_t need);  // may synchronise the device before freeing the old block
+  void release();
+};
+
+// Control block of one batched digest call (device memory).
+struct DigestCtl {
+  uint64_t n_node_items;  // level-1 node work items
+  uint64_t n_small;       // buffers of at most one leaf
+  uint64_t n_items;       // node items + small groups
+  uint64_t tree_total;    // tree scratch slots needed
+  uint64_t tk_total;      // ticket slots needed
+  uint32_t head;          // work-queue head
+  uint32_t overflow;      // 1 when the plan did not fit the workspace
+};
+
+struct Workspace {
+  int device = -1;
+  hipStream_t stream = nullptr;
+  // batched digest
+  DevBuf node_off, tree_off, tk_off, small_list, blk, ctl, item_buf, tree, tickets;
+  size_t cap_buffers = 0;
+  uint64_t cap_items = 0, cap_tree = 0, cap_tk = 0;
+  // plain digest (one buffer at a time)
+  DevBuf p_tree, p_tickets;
+  uint64_t p_cap_tree = 0, p_cap_tk = 0;
+  // analysis
+  DevBuf a_bufs[24];
+  size_t a_cap_events = 0;
+  // graph cache of the batched digest
+  hipGraphExec_t graph = nullptr;
+  const void* g_ptrs = nullptr;
+  const void* g_sizes = nullptr;
+  void* g_out = nullptr;
+  size_t g_n = 0;
+  uint32_t g_grid = 0;
+};
+
+Workspace* workspace_for(hipStream_t stream, int* err);
+uint32_t* device_status_word(int device);  // device-visible sticky status (host-mapped)
+int current_device(int* dev);
+int cu_count(int device);
+
+struct Tuning {
+  uint32_t blocks_per_cu = 8;
+  uint32_t use_graph = 1;
+};
+Tuning& tuning();
+
+int digest_reserve(Workspace* ws, size_t max_buffers, uint64_t max_total_bytes);
+int analyze_reserve(Workspace* ws, size_t max_events);
+void analyze_release(Workspace* ws);
+
+}  // namespace odp

@@ -1,0 +1,148 @@
+"""GPU parity of the digest path (batched and per-buffer forms) against the
+CPU oracle, bit-exact, through the C ABI."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2601_12713_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def dev_bytes(arr):
+    return torch.from_numpy(np.ascontiguousarray(arr)).to("cuda")
+
+
+def both_forms(odp, tensors):
+    b = odp.digest_tensors(tensors)
+    p = odp.digest_tensors(tensors, plain=True)
+    return b, p
+
+
+SIZES = [0, 1, 7, 8, 31, 32, 33, 63, 64, 100, 255, 256, 257, 4095, 4096, 4097, 4100, 8191, 8192, 8193,
+         65536, 262143, 262144, 262145, 300000, 64 * 262144, 64 * 262144 + 1, 4097 * 4096 + 3]
+
+
+def test_sizes_every_class(odp):
+    rng = np.random.default_rng(11)
+    host = [rng.integers(0, 256, size=s, dtype=np.uint8) for s in SIZES]
+    want = [oracle.d64(h) for h in host]
+    t = [dev_bytes(h) for h in host]
+    b, p = both_forms(odp, t)
+    assert b.tolist() == want
+    assert p.tolist() == want
+
+
+def test_unaligned_starts(odp):
+    rng = np.random.default_rng(12)
+    base = dev_bytes(rng.integers(0, 256, size=600_000, dtype=np.uint8))
+    host = base.cpu().numpy()
+    views, want = [], []
+    for off in list(range(16)) + [24, 40, 4096 + 3]:
+        for size in [0, 5, 40, 4096, 5000, 300_000]:
+            views.append(base[off:off + size])
+            want.append(oracle.d64(host[off:off + size]))
+    b, p = both_forms(odp, views)
+    assert b.tolist() == want
+    assert p.tolist() == want
+
+
+def test_same_bytes_same_digest_any_alignment(odp):
+    rng = np.random.default_rng(13)
+    src = rng.integers(0, 256, size=270_000, dtype=np.uint8)
+    arena = torch.zeros(16 * 300_000, dtype=torch.uint8, device="cuda")
+    views = []
+    for k in range(16):
+        o = k * 300_000 + k
+        arena[o:o + src.size] = dev_bytes(src)
+        views.append(arena[o:o + src.size])
+    b, p = both_forms(odp, views)
+    assert len(set(b.tolist())) == 1 and b[0] == oracle.d64(src) and (p == b).all()
+
+
+def test_four_level_tree(odp):
+    # 2^30 + 4097 bytes: 262146 leaves -> 4097 level-1 -> 65 -> 2 -> root at level 4
+    n = (1 << 30) + 4097
+    g = torch.Generator(device="cuda")
+    g.manual_seed(14)
+    t = torch.randint(0, 256, (n,), dtype=torch.uint8, device="cuda", generator=g)
+    want = oracle.d64(t.cpu().numpy())
+    b, p = both_forms(odp, [t])
+    assert int(b[0]) == want and int(p[0]) == want
+
+
+def test_mixed_batch_random_sizes(odp):
+    rng = np.random.default_rng(15)
+    sizes = np.floor(np.exp(rng.uniform(0, np.log(3 << 20), size=3000))).astype(np.int64)
+    sizes[rng.random(sizes.size) < 0.05] = 0
+    host = [rng.integers(0, 256, size=int(s), dtype=np.uint8) for s in sizes]
+    want = oracle.d64_many(host)
+    t = [dev_bytes(h) for h in host]
+    b, p = both_forms(odp, t)
+    assert (b == want).all()
+    assert (p == want).all()
+
+
+def test_repeated_calls_graph_and_direct(odp):
+    """Tickets reset themselves: repeated calls (graph replay and direct
+    launches, several launch widths) give the same digests."""
+    rng = np.random.default_rng(16)
+    host = [rng.integers(0, 256, size=int(s), dtype=np.uint8) for s in [5_000_000, 17_000_000, 3000, 262144 * 65]]
+    want = oracle.d64_many(host).tolist()
+    t = [dev_bytes(h) for h in host]
+    saved = odp.get_tuning()
+    try:
+        for use_graph in (1, 0, 1):
+            for bpc in (1, 3, 8):
+                odp.set_tuning(blocks_per_cu=bpc, use_graph=use_graph)
+                for _ in range(3):
+                    assert odp.digest_tensors(t).tolist() == want
+    finally:
+        odp.set_tuning(**saved)
+    assert odp.device_status() == 0
+
+
+def test_non_default_stream(odp):
+    rng = np.random.default_rng(17)
+    host = [rng.integers(0, 256, size=int(s), dtype=np.uint8) for s in [100, 70_000, 2_000_000]]
+    want = oracle.d64_many(host).tolist()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        t = [dev_bytes(h) for h in host]
+        got = odp.digest_tensors(t, stream=s)
+        gotp = odp.digest_tensors(t, stream=s, plain=True)
+    assert got.tolist() == want and gotp.tolist() == want
+
+
+def test_invalid_arguments(odp):
+    out = torch.zeros(4, dtype=torch.int64, device="cuda")
+    with pytest.raises(odp.OdpError) as e:
+        odp.digest_buffers_plain([0], [16], out)
+    assert e.value.code == odp.ODP_EINVAL
+    # n = 0 is a no-op
+    odp.digest_buffers_plain([], [], out)
+
+
+def test_plain_small_workload_digests(odp):
+    ps = W.PlainSmall(seed=1)
+    want = [oracle.d64(s) for s in ps.snapshots]
+    t = [dev_bytes(s) for s in ps.snapshots]
+    b, p = both_forms(odp, t)
+    assert p.tolist() == want and b.tolist() == want
+
+
+def test_large_arrays_full_size(odp):
+    """16 fp64 arrays of 2^25 elements, each sent 4 times: sampled digests
+    against the oracle, and digest equality exactly where the bytes are equal."""
+    la = W.LargeArrays(seed=2, device="cuda")
+    la.materialize()
+    got = odp.digest_tensors(la.snapshots, plain=True)
+    gotb = odp.digest_tensors(la.snapshots)
+    assert (got == gotb).all()
+    for i in [0, 17, 40, 63]:
+        assert int(got[i]) == oracle.d64(la.snapshots[i].cpu().numpy().view(np.uint8)), i
+    for i in range(len(la.snapshots)):
+        prev = [j for j in range(i) if la.array_of[j] == la.array_of[i]]
+        if prev:
+            assert (got[i] == got[prev[-1]]) == la.identical[i], i
