@@ -22,7 +22,7 @@ constexpr int kWaves = 4;
 constexpr int kThreads = 64 * kWaves;
 constexpr int kRows = 64;                  // rows per item
 constexpr int kRowsPerWave = kRows / kWaves;
-constexpr int kSlab = 256;                 // bytes of each row staged per step
+constexpr int kSlab = 512;                 // bytes of each row staged per step
 constexpr int kPad = 16;                   // LDS row padding (bank spread)
 constexpr int kStride = kSlab + kPad;
 
@@ -59,76 +59,187 @@ __host__ __device__ inline void tree_need(uint64_t n1, uint64_t& tree_slots, uin
   }
 }
 
-// Hashes the 16 rows of the calling wavefront (`rows` in LDS). Returns the
-// XXH64 (seed 0) of row r in lane 4r; other lanes return 0.
-__device__ uint64_t hash_wave_rows(const RowDesc* rows, uint8_t* slab) {
-  const int lane = threadIdx.x & 63;
-  constexpr int NL = kSlab / 64;    // 128-bit loads per lane per step
-  constexpr int LPR = kSlab / 16;   // lanes covering one row in a load
-  constexpr int RPI = 64 / LPR;     // rows covered by one wavefront load
-  const int col = (lane % LPR) * 16;
+typedef __attribute__((address_space(1))) const u32x4 gu32x4;
 
-  const RowDesc mine = rows[lane & 15];
-  uint32_t mlen = mine.present ? mine.len : 0u;
-  const bool aligned = !mine.present || ((reinterpret_cast<uintptr_t>(mine.base) & 15) == 0);
-#pragma unroll
-  for (int o = 8; o >= 1; o >>= 1) mlen = max(mlen, (uint32_t)__shfl_xor((int)mlen, o, 64));
-  const bool all_aligned = __all(aligned);
+__device__ __forceinline__ u32x4 ld_global_nt(const uint8_t* p) {
+  return __builtin_nontemporal_load(reinterpret_cast<gu32x4*>(reinterpret_cast<uintptr_t>(p)));
+}
 
-  const int hr = lane >> 2, a = lane & 3;
-  const RowDesc hrow = rows[hr];
-  const uint32_t hlen = hrow.present ? hrow.len : 0u;
-  const uint32_t nstripes = hlen >> 5;
-  uint64_t acc = xx_acc_init(0, a);
-
-  if (all_aligned) {
-    const uint8_t* lb[NL];
-    uint32_t ll[NL], ls[NL];
-#pragma unroll
-    for (int k = 0; k < NL; ++k) {
-      const int r = k * RPI + lane / LPR;
-      const RowDesc d = rows[r];
-      lb[k] = d.base + col;
-      ll[k] = d.present ? d.len : 0u;
-      ls[k] = r * kStride + col;
-    }
-    u32x4 R[NL];
-#pragma unroll
-    for (int k = 0; k < NL; ++k)
-      if ((uint32_t)col < ll[k]) R[k] = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(lb[k]));
-    const uint8_t* hp = slab + hr * kStride + a * 8;
-    const uint32_t nslab = (mlen + kSlab - 1) / kSlab;
-    for (uint32_t s = 0; s < nslab; ++s) {
-      const uint32_t o = s * kSlab + col;
-#pragma unroll
-      for (int k = 0; k < NL; ++k)
-        if (o < ll[k]) *reinterpret_cast<u32x4*>(slab + ls[k]) = R[k];
-      if (s + 1 < nslab) {
-        const uint32_t o2 = o + kSlab;
-#pragma unroll
-        for (int k = 0; k < NL; ++k)
-          if (o2 < ll[k]) R[k] = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(lb[k] + (s + 1) * kSlab));
-      }
-      wave_fence();
-      const uint32_t q0 = s * (kSlab / 32);
-#pragma unroll
-      for (int q = 0; q < kSlab / 32; ++q)
-        if (q0 + q < nstripes) acc = xx_round(acc, *reinterpret_cast<const uint64_t*>(hp + q * 32));
-      wave_fence();
-    }
+template <typename T>
+__device__ __forceinline__ T uniform(T v) {
+  static_assert(sizeof(T) == 8 || sizeof(T) == 4, "");
+  if constexpr (sizeof(T) == 4) {
+    return (T)__builtin_amdgcn_readfirstlane((int)v);
   } else {
-    for (uint32_t s = 0; s < nstripes; ++s) acc = xx_round(acc, load64_any(hrow.base + s * 32 + a * 8));
+    uint64_t x = (uint64_t)v;
+    uint32_t lo = __builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+    uint32_t hi = __builtin_amdgcn_readfirstlane((int)(uint32_t)(x >> 32));
+    return (T)(((uint64_t)hi << 32) | lo);
   }
+}
+
+__device__ __forceinline__ const uint8_t* uniform_ptr(const uint8_t* p) {
+  return reinterpret_cast<const uint8_t*>(uniform(reinterpret_cast<uint64_t>(p)));
+}
+
+// Finishes the XXH64 of one row from its four lane accumulators; the result
+// is valid in lane 4r (accumulator 0) of row r.
+__device__ __forceinline__ uint64_t finish_row(uint64_t acc, const RowDesc& hrow) {
+  const int a = threadIdx.x & 3;
   uint64_t v1, v2, v3, v4;
   xx_gather4(acc, v1, v2, v3, v4);
   uint64_t h = 0;
   if (a == 0 && hrow.present) {
+    const uint32_t nstripes = hrow.len >> 5;
     h = nstripes ? xx_converge(v1, v2, v3, v4) : kP5;
-    h += hlen;
-    h = xx_tail_bytes(h, hrow.base + nstripes * 32, hlen - nstripes * 32);
+    h += hrow.len;
+    h = xx_tail_bytes(h, hrow.base + nstripes * 32, hrow.len - nstripes * 32);
     h = xx_avalanche(h);
   }
   return h;
+}
+
+// Fast path: 16 whole, 16-byte aligned leaves at leaf_base + r*4096 (leaf_base
+// wave-uniform). Each step stages 512 bytes of every leaf (8 KiB per wavefront,
+// eight fully coalesced 1 KiB loads of 128-bit per lane) through the
+// wavefront's LDS slab; lane 4r+a then folds accumulator a's words of leaf r.
+// Two steps are in flight while one is hashed. Returns the leaf digest in
+// lane 4r.
+__device__ __forceinline__ uint64_t hash_wave_full_leaves(const uint8_t* leaf_base, uint8_t* slab) {
+  const int lane = threadIdx.x & 63;
+  constexpr int NL = kSlab / 64;    // 128-bit loads per lane per step
+  constexpr int LPR = kSlab / 16;   // lanes covering one row in a load
+  constexpr int RPI = 64 / LPR;     // rows covered by one wavefront load
+  constexpr uint32_t NS = kLeaf / kSlab;
+  const uint32_t lrow = lane / LPR, col = (lane % LPR) * 16;
+  const uint32_t goff = lrow * kLeaf + col;           // per-lane byte offset of load k = 0
+  uint8_t* const wr = slab + lrow * kStride + col;    // per-lane LDS target of load k = 0
+  const int hr = lane >> 2, a = lane & 3;
+  const uint8_t* const rd = slab + hr * kStride + a * 8;
+  uint64_t acc = xx_acc_init(0, a);
+
+  u32x4 RA[NL], RB[NL];
+#pragma unroll
+  for (int k = 0; k < NL; ++k) RA[k] = ld_global_nt(leaf_base + k * RPI * kLeaf + goff);
+#pragma unroll
+  for (int k = 0; k < NL; ++k) RB[k] = ld_global_nt(leaf_base + k * RPI * kLeaf + goff + kSlab);
+#pragma unroll 1
+  for (uint32_t s = 0; s < NS; s += 2) {
+#pragma unroll
+    for (int k = 0; k < NL; ++k) *reinterpret_cast<u32x4*>(wr + k * RPI * kStride) = RA[k];
+    if (s + 2 < NS) {
+#pragma unroll
+      for (int k = 0; k < NL; ++k) RA[k] = ld_global_nt(leaf_base + k * RPI * kLeaf + goff + (s + 2) * kSlab);
+    }
+    wave_fence();
+#pragma unroll
+    for (int h2 = 0; h2 < kSlab / 128; ++h2) {
+      uint64_t w[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) w[q] = *reinterpret_cast<const uint64_t*>(rd + (h2 * 4 + q) * 32);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc = xx_round(acc, w[q]);
+    }
+    wave_fence();
+#pragma unroll
+    for (int k = 0; k < NL; ++k) *reinterpret_cast<u32x4*>(wr + k * RPI * kStride) = RB[k];
+    if (s + 3 < NS) {
+#pragma unroll
+      for (int k = 0; k < NL; ++k) RB[k] = ld_global_nt(leaf_base + k * RPI * kLeaf + goff + (s + 3) * kSlab);
+    }
+    wave_fence();
+#pragma unroll
+    for (int h2 = 0; h2 < kSlab / 128; ++h2) {
+      uint64_t w[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) w[q] = *reinterpret_cast<const uint64_t*>(rd + (h2 * 4 + q) * 32);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc = xx_round(acc, w[q]);
+    }
+    wave_fence();
+  }
+  RowDesc full;
+  full.base = leaf_base + hr * kLeaf;
+  full.len = kLeaf;
+  full.present = 1;
+  return finish_row(acc, full);
+}
+
+// General path: 16 rows of any length (<= 4096) and presence. 16-byte aligned
+// rows are staged through LDS with predicated loads, one step at a time;
+// otherwise every lane reads its words straight from memory at any alignment.
+// Returns the row digest in lane 4r.
+__device__ __forceinline__ uint64_t hash_wave_rows(const RowDesc* rows, uint8_t* slab) {
+  const int lane = threadIdx.x & 63;
+  constexpr int LPR = kSlab / 16;
+  constexpr int RPI = 64 / LPR;
+  const uint32_t lrow = lane / LPR, col = (lane % LPR) * 16;
+
+  const RowDesc mine = rows[lane & 15];
+  const bool aligned = !mine.present || ((reinterpret_cast<uintptr_t>(mine.base) & 15) == 0);
+  const bool all_aligned = __all(aligned);
+  uint32_t mlen = mine.present ? mine.len : 0u;
+#pragma unroll
+  for (int o = 8; o >= 1; o >>= 1) mlen = max(mlen, (uint32_t)__shfl_xor((int)mlen, o, 64));
+  mlen = uniform(mlen);
+
+  const int hr = lane >> 2, a = lane & 3;
+  const RowDesc hrow = rows[hr];
+  const uint32_t nstripes = hrow.present ? hrow.len >> 5 : 0u;
+  uint64_t acc = xx_acc_init(0, a);
+
+  if (all_aligned) {
+    const uint8_t* rd = slab + hr * kStride + a * 8;
+    const uint32_t nslab = (mlen + kSlab - 1) / kSlab;
+#pragma unroll 1
+    for (uint32_t s = 0; s < nslab; ++s) {
+      const uint32_t o = s * kSlab + col;
+#pragma unroll 1
+      for (int k = 0; k < kSlab / 64; ++k) {
+        const RowDesc d = rows[k * RPI + lrow];
+        if (d.present && o < d.len)
+          *reinterpret_cast<u32x4*>(slab + (k * RPI + lrow) * kStride + col) = ld_global_nt(d.base + o);
+      }
+      wave_fence();
+      const uint32_t q0 = s * (kSlab / 32);
+#pragma unroll 1
+      for (int q = 0; q < kSlab / 32; ++q)
+        if (q0 + q < nstripes) acc = xx_round(acc, *reinterpret_cast<const uint64_t*>(rd + q * 32));
+      wave_fence();
+    }
+  } else {
+#pragma unroll 1
+    for (uint32_t s = 0; s < nstripes; ++s) acc = xx_round(acc, load64_any(hrow.base + s * 32 + a * 8));
+  }
+  return finish_row(acc, hrow);
+}
+
+// Cross-workgroup hand-off of tree digests. Each XCD has its own L2, so a
+// digest stored by one workgroup must reach the device-coherent level before
+// the ticket that announces it, and the last arriver must read past its own
+// L2. Agent-scope relaxed atomic stores and loads do exactly that per access;
+// waiting for the stores to complete orders them before the ticket. This
+// avoids agent-scope fences, which write back and invalidate a whole L2.
+__device__ __forceinline__ void store_coherent(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t load_coherent(const uint64_t* p) {
+  return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void wait_stores_done() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// XXH64 of `nw` child digests written by other workgroups (see xx_words4).
+__device__ __forceinline__ uint64_t xx_words4_coherent(const uint64_t* w, uint32_t nw, uint64_t seed) {
+  const int a = threadIdx.x & 3;
+  const uint32_t nstripes = nw / 4;
+  uint64_t acc = xx_acc_init(seed, a);
+  for (uint32_t s = 0; s < nstripes; ++s) acc = xx_round(acc, load_coherent(w + s * 4 + a));
+  uint64_t v1, v2, v3, v4;
+  xx_gather4(acc, v1, v2, v3, v4);
+  uint64_t h = nstripes ? xx_converge(v1, v2, v3, v4) : seed + kP5;
+  h += uint64_t(nw) * 8;
+  for (uint32_t i = nstripes * 4; i < nw; ++i) h = xx_step8(h, load_coherent(w + i));
+  return xx_avalanche(h);
 }
 
 // Called by one whole wavefront after it computed the digest `h` (lane 0) of
@@ -137,7 +248,7 @@ __device__ uint64_t hash_wave_rows(const RowDesc* rows, uint8_t* slab) {
 // (seed = its level) and repeats; the root goes to *out.
 //   tree: the buffer's node slots, level by level (level 1 first)
 //   tk:   the buffer's tickets, level 2 first; reset to 0 by their last user
-__device__ void tree_up(uint64_t h, uint64_t m, uint64_t nj, uint64_t* out, uint64_t* tree, uint32_t* tk) {
+__device__ __forceinline__ void tree_up(uint64_t h, uint64_t m, uint64_t nj, uint64_t* out, uint64_t* tree, uint32_t* tk) {
   const int lane = threadIdx.x & 63;
   uint64_t loff = 0, tkoff = 0, level = 1;
   h = __shfl(h, 0, 64);
@@ -146,18 +257,17 @@ __device__ void tree_up(uint64_t h, uint64_t m, uint64_t nj, uint64_t* out, uint
       if (lane == 0) *out = h;
       return;
     }
-    if (lane == 0) tree[loff + m] = h;
-    __threadfence();
+    if (lane == 0) store_coherent(tree + loff + m, h);
+    wait_stores_done();
     const uint64_t p = m / kFanIn;
     const uint32_t nchild = (uint32_t)min<uint64_t>(kFanIn, nj - p * kFanIn);
     const uint64_t nnext = ceil_div(nj, kFanIn);
     uint32_t old = 0;
-    if (lane == 0) old = atomicAdd(&tk[tkoff + p], 1u);
+    if (lane == 0) old = __hip_atomic_fetch_add(tk + tkoff + p, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     old = __shfl(old, 0, 64);
     if (old != nchild - 1) return;
-    __threadfence();
-    if (lane == 0) tk[tkoff + p] = 0;
-    h = xx_words4(tree + loff + p * kFanIn, nchild, level + 1);
+    if (lane == 0) __hip_atomic_store(tk + tkoff + p, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    h = xx_words4_coherent(tree + loff + p * kFanIn, nchild, level + 1);
     h = __shfl(h, 0, 64);
     ++level;
     m = p;
@@ -167,26 +277,39 @@ __device__ void tree_up(uint64_t h, uint64_t m, uint64_t nj, uint64_t* out, uint
   }
 }
 
-// One level-1 node of a buffer larger than one leaf.
-__device__ void run_node(Smem& sm, const uint8_t* buf, uint64_t size, uint64_t node, uint64_t* out,
+// One level-1 node of a buffer larger than one leaf. `buf`, `size`, `node`
+// and the tree pointers are wave-uniform.
+__device__ __forceinline__ void run_node(Smem& sm, const uint8_t* buf, uint64_t size, uint64_t node, uint64_t* out,
                          uint64_t* tree, uint32_t* tk) {
   const int t = threadIdx.x;
+  const int w = t >> 6, r = (t & 63) >> 2;
   const uint64_t nleaves = ceil_div(size, kLeaf);
   const uint64_t n1 = ceil_div(nleaves, kFanIn);
   const uint64_t first = node * kFanIn;
   const uint32_t nl = (uint32_t)min<uint64_t>(kFanIn, nleaves - first);
-  if (t < kRows) {
-    RowDesc d;
-    const uint64_t off = (first + t) * kLeaf;
-    d.present = (uint32_t)t < nl;
-    d.base = buf + (d.present ? off : 0);
-    d.len = d.present ? (uint32_t)min<uint64_t>(kLeaf, size - off) : 0u;
-    sm.rows[t] = d;
+  // leaves [first + 16w, first + 16w + 16) belong to this wavefront
+  const uint64_t wfirst = first + (uint64_t)w * kRowsPerWave;
+  const bool wave_full = ((reinterpret_cast<uintptr_t>(buf) & 15) == 0) &&
+                         (wfirst + kRowsPerWave) * kLeaf <= size;
+  uint64_t h;
+  if (wave_full) {
+    h = hash_wave_full_leaves(buf + wfirst * kLeaf, sm.slab[w]);
+  } else {
+    RowDesc* rows = sm.rows + w * kRowsPerWave;
+    if ((t & 63) < kRowsPerWave) {
+      const uint32_t rr = t & 63;
+      RowDesc d;
+      const uint64_t leaf = wfirst + rr;
+      const uint64_t off = leaf * kLeaf;
+      d.present = leaf < first + nl;
+      d.base = buf + (d.present ? off : 0);
+      d.len = d.present ? (uint32_t)min<uint64_t>(kLeaf, size - off) : 0u;
+      rows[rr] = d;
+    }
+    wave_fence();
+    h = hash_wave_rows(rows, sm.slab[w]);
   }
-  __syncthreads();
-  const int w = t >> 6, r = (t & 63) >> 2;
-  const uint64_t h = hash_wave_rows(sm.rows + w * kRowsPerWave, sm.slab[w]);
-  if ((t & 3) == 0 && sm.rows[w * kRowsPerWave + r].present) sm.leafdig[w * kRowsPerWave + r] = h;
+  if ((t & 3) == 0 && (uint64_t)(w * kRowsPerWave + r) < nl) sm.leafdig[w * kRowsPerWave + r] = h;
   __syncthreads();
   if (w == 0) {
     const uint64_t d = xx_words4(sm.leafdig, nl, 1);
@@ -196,7 +319,7 @@ __device__ void run_node(Smem& sm, const uint8_t* buf, uint64_t size, uint64_t n
 }
 
 // Up to 64 buffers of at most one leaf each (digest = XXH64 seed 0).
-__device__ void run_small(Smem& sm, uint64_t group, uint64_t n_small, const uint32_t* small_list,
+__device__ __forceinline__ void run_small(Smem& sm, uint64_t group, uint64_t n_small, const uint32_t* small_list,
                           const void* const* ptrs, const uint64_t* sizes, uint64_t* out) {
   const int t = threadIdx.x;
   if (t < kRows) {
@@ -219,7 +342,7 @@ __device__ void run_small(Smem& sm, uint64_t group, uint64_t n_small, const uint
 // ---------------------------------------------------------------------------
 // Plain form: one launch per buffer, one workgroup per level-1 node.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kThreads) void digest_one_kernel(const uint8_t* p, uint64_t size, uint64_t* out,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void digest_one_kernel(const uint8_t* p, uint64_t size, uint64_t* out,
                                                              uint64_t* tree, uint32_t* tk) {
   __shared__ Smem sm;
   if (size <= kLeaf) {
@@ -417,7 +540,7 @@ struct BatchArgs {
   uint32_t* status;  // host-mapped sticky status word
 };
 
-__global__ __launch_bounds__(kThreads) void digest_batched_kernel(BatchArgs A) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void digest_batched_kernel(BatchArgs A) {
   __shared__ Smem sm;
   const DigestCtl* c = A.ctl;
   if (c->overflow) {
@@ -430,13 +553,13 @@ __global__ __launch_bounds__(kThreads) void digest_batched_kernel(BatchArgs A) {
   for (;;) {
     if (threadIdx.x == 0) sm.item = atomicAdd(&A.ctl->head, 1u);
     __syncthreads();
-    const uint64_t item = sm.item;
+    const uint64_t item = uniform(sm.item);
     if (item >= n_items) break;
     if (item < n_node) {
-      const uint32_t b = A.item_buf[item];
-      const uint64_t size = A.sizes[b];
-      run_node(sm, static_cast<const uint8_t*>(A.ptrs[b]), size, item - A.node_off[b], A.out + b,
-               A.tree + A.tree_off[b], A.tickets + A.tk_off[b]);
+      const uint32_t b = uniform(A.item_buf[item]);
+      const uint64_t size = uniform(A.sizes[b]);
+      run_node(sm, uniform_ptr(static_cast<const uint8_t*>(A.ptrs[b])), size, item - uniform(A.node_off[b]), A.out + b,
+               A.tree + uniform(A.tree_off[b]), A.tickets + uniform(A.tk_off[b]));
     } else {
       run_small(sm, item - n_node, n_small, A.small_list, A.ptrs, A.sizes, A.out);
     }

@@ -7,7 +7,7 @@
 #include <mutex>
 #include <string>
 
-#include "../../include/odp.h"
+#include "odp.h"
 
 namespace odp {
 
