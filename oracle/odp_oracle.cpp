@@ -187,6 +187,24 @@ void orc_d64_many(const uint8_t* const* ptrs, const uint64_t* sizes, uint64_t n,
   for (uint64_t i = 0; i < n; ++i) out[i] = d64(ptrs[i], sizes[i]);
 }
 
+// Hash of a small tuple of integers, for the per-key state of the rules.
+struct KeyHash {
+  size_t operator()(const std::pair<uint64_t, int>& k) const { return mix(k.first, (uint64_t)k.second, 0); }
+  size_t operator()(const std::pair<int, uint64_t>& k) const { return mix((uint64_t)k.first, k.second, 0); }
+  size_t operator()(const std::tuple<uint64_t, int, int>& k) const {
+    return mix(std::get<0>(k), (uint64_t)std::get<1>(k), (uint64_t)std::get<2>(k));
+  }
+  size_t operator()(const std::tuple<uint64_t, int, uint64_t>& k) const {
+    return mix(std::get<0>(k), (uint64_t)std::get<1>(k), std::get<2>(k));
+  }
+  static size_t mix(uint64_t a, uint64_t b, uint64_t c) {
+    uint64_t h = a * 0x9E3779B97F4A7C15ULL;
+    h ^= (b + 0x632BE59BD9B4E019ULL + (h << 6) + (h >> 2)) * 0xC2B2AE3D27D4EB4FULL;
+    h ^= (c + 0x27D4EB2F165667C5ULL + (h << 6) + (h >> 2)) * 0x9E3779B97F4A7C15ULL;
+    return (size_t)(h ^ (h >> 29));
+  }
+};
+
 static bool is_transfer(uint8_t op) { return op == OP_H2D || op == OP_D2H || op == OP_D2D; }
 static bool dev_ok(int d) { return d >= -1 && d <= MAX_DEVICE; }
 static uint64_t dur(const orc_event& e) { return e.t_end - e.t_start; }
@@ -232,7 +250,7 @@ int orc_analyze(const orc_event* ev, uint64_t n, uint8_t* flags, orc_report* rep
   // Duplicate transfer (Def. 1, key <hash, receiving device> of Alg. 1): a
   // transfer is a duplicate when the same receiver already got the same digest.
   {
-    std::map<std::pair<uint64_t, int>, uint64_t> count;
+    std::unordered_map<std::pair<uint64_t, int>, uint64_t, KeyHash> count;
     for (uint64_t i : transfers) {
       auto key = std::make_pair(ev[i].digest, (int)ev[i].dst_dev);
       if (count[key] > 0) {
@@ -253,7 +271,7 @@ int orc_analyze(const orc_event* ev, uint64_t n, uint8_t* flags, orc_report* rep
   //   RT_RX: the latest earlier transfer with the same digest between the same
   //          two endpoints went the other way (this record is a return leg).
   {
-    std::set<std::tuple<uint64_t, int, int>> later;
+    std::unordered_set<std::tuple<uint64_t, int, int>, KeyHash> later;
     for (size_t k = transfers.size(); k-- > 0;) {
       const orc_event& e = ev[transfers[k]];
       if (e.src_dev == e.dst_dev) continue;
@@ -263,7 +281,7 @@ int orc_analyze(const orc_event* ev, uint64_t n, uint8_t* flags, orc_report* rep
       }
       later.insert(std::make_tuple(e.digest, (int)e.src_dev, (int)e.dst_dev));
     }
-    std::map<std::tuple<uint64_t, int, int>, std::pair<int, int>> last_dir;
+    std::unordered_map<std::tuple<uint64_t, int, int>, std::pair<int, int>, KeyHash> last_dir;
     for (uint64_t i : transfers) {
       const orc_event& e = ev[i];
       if (e.src_dev == e.dst_dev) continue;
@@ -285,7 +303,7 @@ int orc_analyze(const orc_event* ev, uint64_t n, uint8_t* flags, orc_report* rep
   // with the record just before it in its group when that record is an ALLOC.
   std::vector<std::pair<uint64_t, uint64_t>> pairs;  // (alloc, delete), in delete order
   {
-    std::map<std::pair<int, uint64_t>, uint64_t> prev;
+    std::unordered_map<std::pair<int, uint64_t>, uint64_t, KeyHash> prev;
     for (uint64_t i : allocdel) {
       auto key = std::make_pair((int)ev[i].dst_dev, ev[i].dst_addr);
       auto it = prev.find(key);
@@ -307,7 +325,7 @@ int orc_analyze(const orc_event* ev, uint64_t n, uint8_t* flags, orc_report* rep
   // Repeated allocation (Def. 3, key <host address, device, bytes> of Alg. 3):
   // every paired allocation after the first of its key.
   {
-    std::map<std::tuple<uint64_t, int, uint64_t>, uint64_t> count;
+    std::unordered_map<std::tuple<uint64_t, int, uint64_t>, uint64_t, KeyHash> count;
     for (auto& pr : pairs) {
       const orc_event& a = ev[pr.first];
       auto key = std::make_tuple(a.src_addr, (int)a.dst_dev, a.bytes);
