@@ -1,9 +1,1377 @@
-// Mapping-trace analysis (placeholder until the kernels land).
+// Mapping-trace analysis on gfx950 (the paper's Sec. 5, Algorithms 1-4).
+//
+// The paper groups records with host-side maps: <hash, destination> for
+// duplicates (Alg. 1), queues per <hash, destination> for round trips
+// (Alg. 2), <host address, device, bytes> for repeated allocations (Alg. 3)
+// and a two-pointer sweep per device for unused allocations (Alg. 4). Here the
+// grouping is a stable LSD radix sort and the per-group logic is a pass over
+// the sorted order:
+//
+//   classify   one read of the 64-byte records: validity, per-record flags,
+//              the digest sort keys, and a 1-byte class / endpoint code
+//   subsets    ordered compaction of ALLOC/DELETE and KERNEL records
+//   sort #1    (all in the same launches) records by digest; ALLOC/DELETE by
+//              (device, device address); KERNELs by (device, start) and by
+//              (device, end)
+//   DD/RT      forward and backward segmented scans over each digest group
+//   pairing    a DELETE pairs with its predecessor in its (device, address)
+//              group when that is an ALLOC; paired ALLOCs compacted in order
+//   sort #2    pairs by (bytes, device, host address)
+//   RA/UA      RA = not first of its key group; UA by two binary searches in
+//              the device's sorted kernel starts and ends
+//
+// Sort keys are 64-bit words; a job lists its words least significant first,
+// and digit passes whose byte is the same in every key are skipped on the
+// device, so the launches are fixed while the work follows the data.
+#include <cstring>
+
 #include "internal.h"
+
 namespace odp {
-int analyze_reserve(Workspace*, size_t) { return ODP_OK; }
-void analyze_release(Workspace*) {}
+namespace {
+
+constexpr int kT = 256;                 // threads per block
+constexpr int kItems = 16;              // elements per thread in a tile
+constexpr int kTile = kT * kItems;      // elements per tile
+constexpr int kMaxWords = 3;
+constexpr int kMaxPasses = 24;
+constexpr int kEp = 11;                 // endpoints: host (0) and devices 0..9 (1..10)
+constexpr uint8_t kNotTransfer = 0xFF;
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+
+enum : uint8_t { C_INVALID = 0, C_TRANSFER = 1, C_ALLOCDEL = 2, C_KERNEL = 3 };
+
+__host__ __device__ inline uint32_t ceil_div32(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
+
+// ---------------------------------------------------------------------------
+// Device-side control block of one call.
+// ---------------------------------------------------------------------------
+struct WordMask {
+  unsigned long long vor, vand;  // OR and AND over the word's values
+};
+
+struct AnaCtl {
+  uint32_t n;           // records
+  uint32_t n_ad;        // ALLOC/DELETE records
+  uint32_t n_k;         // KERNEL records
+  uint32_t n_pairs;     // paired allocations
+  uint32_t first_bad;
+  uint32_t pad;
+  WordMask m_digest, m_ad_dev, m_ad_addr, m_k_start, m_k_end, m_k_dev, m_p_bytes, m_p_dev, m_p_haddr;
+  uint32_t dev_lo[kEp], dev_hi[kEp];  // per-device ranges in the sorted kernel order
+};
+
+// One radix sort job: either "keyed" (64-bit keys move with the values) or
+// "gathered" (only values move; a digit is read from words[w][value]).
+struct SortJob {
+  const uint32_t* n_ptr;
+  unsigned long long* keys[2];
+  uint32_t* vals[2];
+  const uint64_t* words[kMaxWords];
+  const WordMask* masks[kMaxWords];
+  uint32_t word_bytes[kMaxWords];  // bytes of each word that may vary
+  uint32_t nwords;
+  uint32_t ntiles_max;             // row length of `hist` (tiles of the capacity)
+  uint32_t* hist;                  // [256][ntiles_max]
+  uint32_t* totals;                // [kMaxPasses][256]
+  uint32_t npasses;                // device-computed
+  uint8_t pw[kMaxPasses], ps[kMaxPasses];
+};
+
+struct JobSet {
+  SortJob* jobs;
+  uint32_t njobs;
+  uint32_t stride;   // blocks per job in this launch (tiles of the call)
+};
+
+// ---------------------------------------------------------------------------
+// Small helpers.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  const int lane = threadIdx.x & 63;
+  return lane ? (~0ull >> (64 - lane)) : 0ull;
+}
+
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sums v over the block and adds it to *dst once (dst may be null).
+__device__ void block_add(uint64_t* dst64, unsigned long long v) {
+  unsigned long long* dst = reinterpret_cast<unsigned long long*>(dst64);
+  __shared__ unsigned long long sh[kT / 64];
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long s = 0;
+    for (int w = 0; w < kT / 64; ++w) s += sh[w];
+    if (s && dst) atomicAdd(dst, s);
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ void mask_update(WordMask* m, unsigned long long vor, unsigned long long vand) {
+  // vor/vand are block-reduced by the caller when it can; here per thread.
+  atomicOr(&m->vor, vor);
+  atomicAnd(&m->vand, vand);
+}
+
+__device__ void block_mask(WordMask* m, unsigned long long vor, unsigned long long vand, bool any) {
+  __shared__ unsigned long long so[kT / 64], sa[kT / 64];
+  __shared__ int sany[kT / 64];
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    vor |= __shfl_xor(vor, o, 64);
+    vand &= __shfl_xor(vand, o, 64);
+  }
+  const int anyw = __any(any);
+  if ((threadIdx.x & 63) == 0) {
+    so[threadIdx.x >> 6] = vor;
+    sa[threadIdx.x >> 6] = vand;
+    sany[threadIdx.x >> 6] = anyw;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long o = 0, a = ~0ull;
+    int an = 0;
+    for (int w = 0; w < kT / 64; ++w) {
+      o |= so[w];
+      a &= sa[w];
+      an |= sany[w];
+    }
+    if (an) mask_update(m, o, a);
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// 0. Reset of the report and the call's counters.
+// ---------------------------------------------------------------------------
+__global__ void init_kernel(AnaCtl* ctl, odp_report* rep, uint32_t* totals, uint32_t ntotals, uint32_t n) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  for (uint32_t i = t; i < ntotals; i += gridDim.x * blockDim.x) totals[i] = 0;
+  if (t == 0) {
+    unsigned long long* r = reinterpret_cast<unsigned long long*>(rep);
+    for (int i = 0; i < 24; ++i) r[i] = 0;
+    rep->n_events = n;
+    rep->status = 0;
+    rep->first_bad_event = kNone;
+    ctl->n = n;
+    ctl->n_ad = ctl->n_k = ctl->n_pairs = 0;
+    ctl->first_bad = kNone;
+    WordMask* m = &ctl->m_digest;
+    for (int i = 0; i < 9; ++i) {
+      m[i].vor = 0;
+      m[i].vand = ~0ull;
+    }
+    for (int d = 0; d < kEp; ++d) {
+      ctl->dev_lo[d] = 0;
+      ctl->dev_hi[d] = 0;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 1. Classification: one read of every record.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool dev_ok(int d) { return d >= -1 && d <= ODP_MAX_DEVICE; }
+
+__global__ __launch_bounds__(kT) void classify_kernel(const odp_event* __restrict__ ev, uint32_t n, uint8_t* __restrict__ flags,
+                                                      uint8_t* __restrict__ cls, uint8_t* __restrict__ aux,
+                                                      unsigned long long* __restrict__ keys, uint32_t* __restrict__ vals,
+                                                      AnaCtl* ctl, odp_report* rep) {
+  unsigned long long n_inv = 0, n_tx = 0, n_k = 0, kor = 0, kand = ~0ull;
+  uint32_t bad = kNone;
+  for (uint32_t i = blockIdx.x * kT + threadIdx.x; i < n; i += gridDim.x * kT) {
+    const odp_event e = ev[i];
+    const uint64_t prev_start = i ? ev[i - 1].t_start : 0;
+    const bool is_tx = e.op == ODP_H2D || e.op == ODP_D2H || e.op == ODP_D2D;
+    bool valid = e.op >= ODP_ALLOC && e.op <= ODP_KERNEL && e.t_end >= e.t_start && (i == 0 || e.t_start >= prev_start) &&
+                 dev_ok(e.dst_dev) && (!is_tx || dev_ok(e.src_dev));
+    uint8_t c = C_INVALID, a = kNotTransfer;
+    unsigned long long key = ~0ull;
+    if (valid) {
+      if (is_tx) {
+        c = C_TRANSFER;
+        a = (uint8_t)(((e.src_dev + 1) << 4) | (e.dst_dev + 1));
+        key = e.digest;
+        ++n_tx;
+      } else if (e.op == ODP_KERNEL) {
+        c = C_KERNEL;
+        ++n_k;
+      } else {
+        c = C_ALLOCDEL;
+      }
+    } else {
+      ++n_inv;
+      bad = min(bad, i);
+    }
+    flags[i] = valid ? 0 : ODP_F_INVALID;
+    cls[i] = c;
+    aux[i] = a;
+    keys[i] = key;
+    vals[i] = i;
+    kor |= key;
+    kand &= key;
+  }
+  block_add(&rep->n_invalid, n_inv);
+  block_add(&rep->n_transfers, n_tx);
+  block_add(&rep->n_kernels, n_k);
+  block_mask(&ctl->m_digest, kor, kand, true);
+  // first rejected record
+  for (int o = 32; o >= 1; o >>= 1) bad = min(bad, (uint32_t)__shfl_xor((int)bad, o, 64));
+  if ((threadIdx.x & 63) == 0 && bad != kNone) atomicMin(&ctl->first_bad, bad);
+}
+
+// ---------------------------------------------------------------------------
+// 2. Ordered compaction of the ALLOC/DELETE and KERNEL subsets.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kT) void subset_count_kernel(const uint8_t* __restrict__ cls, uint32_t n,
+                                                          uint32_t* __restrict__ tile_cnt) {
+  const uint32_t t = blockIdx.x;
+  const uint32_t b = t * kTile;
+  uint32_t cad = 0, ck = 0;
+  for (uint32_t j = threadIdx.x; j < (uint32_t)kTile; j += kT) {
+    const uint32_t i = b + j;
+    if (i < n) {
+      cad += cls[i] == C_ALLOCDEL;
+      ck += cls[i] == C_KERNEL;
+    }
+  }
+  __shared__ uint32_t s0[kT / 64], s1[kT / 64];
+  for (int o = 32; o >= 1; o >>= 1) {
+    cad += __shfl_xor(cad, o, 64);
+    ck += __shfl_xor(ck, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    s0[threadIdx.x >> 6] = cad;
+    s1[threadIdx.x >> 6] = ck;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t a = 0, k = 0;
+    for (int w = 0; w < kT / 64; ++w) {
+      a += s0[w];
+      k += s1[w];
+    }
+    tile_cnt[2 * t] = a;
+    tile_cnt[2 * t + 1] = k;
+  }
+}
+
+// Exclusive scan of pairs of u32 counters over `ntiles` tiles (one block).
+__global__ __launch_bounds__(1024) void scan_pairs_kernel(uint32_t* tile_cnt, uint32_t ntiles, uint32_t* tot0,
+                                                          uint32_t* tot1) {
+  __shared__ uint32_t sh0[1024], sh1[1024];
+  __shared__ uint32_t c0, c1;
+  if (threadIdx.x == 0) c0 = c1 = 0;
+  __syncthreads();
+  for (uint32_t base = 0; base < ntiles; base += 1024) {
+    const uint32_t t = base + threadIdx.x;
+    const uint32_t a = t < ntiles ? tile_cnt[2 * t] : 0, b = t < ntiles ? tile_cnt[2 * t + 1] : 0;
+    sh0[threadIdx.x] = a;
+    sh1[threadIdx.x] = b;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+      uint32_t x = threadIdx.x >= (uint32_t)o ? sh0[threadIdx.x - o] : 0;
+      uint32_t y = threadIdx.x >= (uint32_t)o ? sh1[threadIdx.x - o] : 0;
+      __syncthreads();
+      sh0[threadIdx.x] += x;
+      sh1[threadIdx.x] += y;
+      __syncthreads();
+    }
+    if (t < ntiles) {
+      tile_cnt[2 * t] = c0 + sh0[threadIdx.x] - a;
+      tile_cnt[2 * t + 1] = c1 + sh1[threadIdx.x] - b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 1023) {
+      c0 += sh0[1023];
+      c1 += sh1[1023];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (tot0) *tot0 = c0;
+    if (tot1) *tot1 = c1;
+  }
+}
+
+struct SubsetOut {
+  uint32_t* ad_idx;
+  uint8_t* ad_op;
+  uint64_t* ad_w_dev;
+  uint64_t* ad_w_addr;
+  uint32_t* ad_vals;
+  uint32_t* ad_alloc_partner;
+  uint32_t* k_idx;
+  uint64_t* k_w_start;
+  uint64_t* k_w_end;
+  uint64_t* k_w_dev;
+  uint32_t* k_vals_s;
+  uint32_t* k_vals_e;
+};
+
+__global__ __launch_bounds__(kT) void subset_scatter_kernel(const odp_event* __restrict__ ev, const uint8_t* __restrict__ cls,
+                                                            uint32_t n, const uint32_t* __restrict__ tile_cnt, SubsetOut S,
+                                                            AnaCtl* ctl) {
+  const uint32_t t = blockIdx.x;
+  const uint32_t b = t * kTile;
+  __shared__ uint32_t wc0[kT / 64], wc1[kT / 64];
+  __shared__ uint32_t run0, run1;
+  if (threadIdx.x == 0) {
+    run0 = tile_cnt[2 * t];
+    run1 = tile_cnt[2 * t + 1];
+  }
+  unsigned long long o_dev = 0, a_dev = ~0ull, o_addr = 0, a_addr = ~0ull, o_ks = 0, a_ks = ~0ull, o_ke = 0,
+                     a_ke = ~0ull, o_kd = 0, a_kd = ~0ull;
+  bool any_ad = false, any_k = false;
+  __syncthreads();
+  const int w = threadIdx.x >> 6;
+  for (uint32_t r = 0; r < (uint32_t)kItems; ++r) {
+    const uint32_t i = b + r * kT + threadIdx.x;
+    const uint8_t c = i < n ? cls[i] : C_INVALID;
+    const uint64_t bad = __ballot(c == C_ALLOCDEL), bk = __ballot(c == C_KERNEL);
+    if ((threadIdx.x & 63) == 0) {
+      wc0[w] = __popcll(bad);
+      wc1[w] = __popcll(bk);
+    }
+    __syncthreads();
+    uint32_t p0 = run0, p1 = run1;
+    for (int x = 0; x < w; ++x) {
+      p0 += wc0[x];
+      p1 += wc1[x];
+    }
+    p0 += __popcll(bad & lanemask_lt());
+    p1 += __popcll(bk & lanemask_lt());
+    if (c == C_ALLOCDEL) {
+      const odp_event& e = ev[i];
+      const uint64_t dv = (uint64_t)(e.dst_dev + 1), ad = e.dst_addr;
+      S.ad_idx[p0] = i;
+      S.ad_op[p0] = e.op;
+      S.ad_w_dev[p0] = dv;
+      S.ad_w_addr[p0] = ad;
+      S.ad_vals[p0] = p0;
+      S.ad_alloc_partner[p0] = kNone;
+      o_dev |= dv;
+      a_dev &= dv;
+      o_addr |= ad;
+      a_addr &= ad;
+      any_ad = true;
+    } else if (c == C_KERNEL) {
+      const odp_event& e = ev[i];
+      const uint64_t dv = (uint64_t)(e.dst_dev + 1);
+      S.k_idx[p1] = i;
+      S.k_w_start[p1] = e.t_start;
+      S.k_w_end[p1] = e.t_end;
+      S.k_w_dev[p1] = dv;
+      S.k_vals_s[p1] = p1;
+      S.k_vals_e[p1] = p1;
+      o_ks |= e.t_start;
+      a_ks &= e.t_start;
+      o_ke |= e.t_end;
+      a_ke &= e.t_end;
+      o_kd |= dv;
+      a_kd &= dv;
+      any_k = true;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int x = 0; x < kT / 64; ++x) {
+        run0 += wc0[x];
+        run1 += wc1[x];
+      }
+    }
+    __syncthreads();
+  }
+  block_mask(&ctl->m_ad_dev, o_dev, a_dev, any_ad);
+  block_mask(&ctl->m_ad_addr, o_addr, a_addr, any_ad);
+  block_mask(&ctl->m_k_start, o_ks, a_ks, any_k);
+  block_mask(&ctl->m_k_end, o_ke, a_ke, any_k);
+  block_mask(&ctl->m_k_dev, o_kd, a_kd, any_k);
+}
+
+// ---------------------------------------------------------------------------
+// 3. LSD radix sort, 8-bit digits, several independent jobs per launch.
+// ---------------------------------------------------------------------------
+__global__ void sort_plan_kernel(JobSet J) {
+  const uint32_t j = threadIdx.x;
+  if (j >= J.njobs) return;
+  SortJob& s = J.jobs[j];
+  uint32_t np = 0;
+  for (uint32_t w = 0; w < s.nwords; ++w) {
+    // bits that are 1 in some key and 0 in another (0 when there are no keys)
+    const unsigned long long var = s.masks[w]->vor & ~s.masks[w]->vand;
+    for (uint32_t b = 0; b < s.word_bytes[w]; ++b)
+      if ((var >> (8 * b)) & 0xFF) {
+        s.pw[np] = (uint8_t)w;
+        s.ps[np] = (uint8_t)(8 * b);
+        ++np;
+      }
+  }
+  s.npasses = np;
+}
+
+// Locates this block's job and tile; returns false when the block has no work
+// in pass p.
+__device__ __forceinline__ bool job_tile(const JobSet& J, uint32_t p, const SortJob*& s, uint32_t& tile, uint32_t& n) {
+  const uint32_t j = blockIdx.x / J.stride;
+  if (j >= J.njobs) return false;
+  const SortJob& c = J.jobs[j];
+  s = &c;
+  tile = blockIdx.x % J.stride;
+  n = *c.n_ptr;
+  return p < c.npasses && (uint64_t)tile * kTile < n && tile < c.ntiles_max;
+}
+
+__device__ __forceinline__ uint32_t digit_of(const SortJob& s, uint32_t p, uint32_t src, uint32_t j) {
+  const uint32_t shift = s.ps[p];
+  if (s.keys[0]) return (uint32_t)(s.keys[src][j] >> shift) & 0xFF;
+  const uint32_t v = s.vals[src][j];
+  return (uint32_t)(s.words[s.pw[p]][v] >> shift) & 0xFF;
+}
+
+__global__ __launch_bounds__(kT) void sort_hist_kernel(JobSet J, uint32_t p) {
+  const SortJob* s;
+  uint32_t tile, n;
+  if (!job_tile(J, p, s, tile, n)) return;
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const uint32_t src = p & 1;
+  const uint32_t b = tile * kTile;
+  for (uint32_t r = 0; r < (uint32_t)kItems; ++r) {
+    const uint32_t j = b + r * kT + threadIdx.x;
+    if (j < n) atomicAdd(&h[digit_of(*s, p, src, j)], 1u);
+  }
+  __syncthreads();
+  const uint32_t c = h[threadIdx.x];
+  s->hist[threadIdx.x * s->ntiles_max + tile] = c;
+  if (c) atomicAdd(&s->totals[p * 256 + threadIdx.x], c);
+}
+
+// One block per (job, digit): exclusive scan of the digit's row over tiles,
+// offset by the counts of all smaller digits.
+__global__ __launch_bounds__(kT) void sort_scan_kernel(JobSet J, uint32_t p) {
+  const uint32_t j = blockIdx.x / 256, d = blockIdx.x % 256;
+  if (j >= J.njobs) return;
+  const SortJob& s = J.jobs[j];
+  if (p >= s.npasses) return;
+  const uint32_t n = *s.n_ptr;
+  const uint32_t nt = ceil_div32(n, kTile);
+  __shared__ uint32_t base;
+  __shared__ uint32_t sh[kT];
+  if (threadIdx.x == 0) {
+    uint32_t b = 0;
+    for (uint32_t x = 0; x < d; ++x) b += s.totals[p * 256 + x];
+    base = b;
+  }
+  __syncthreads();
+  uint32_t* row = s.hist + (size_t)d * s.ntiles_max;
+  uint32_t carry = base;
+  for (uint32_t t0 = 0; t0 < nt; t0 += kT) {
+    const uint32_t t = t0 + threadIdx.x;
+    const uint32_t v = t < nt ? row[t] : 0;
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 1; o < kT; o <<= 1) {
+      const uint32_t x = threadIdx.x >= (uint32_t)o ? sh[threadIdx.x - o] : 0;
+      __syncthreads();
+      sh[threadIdx.x] += x;
+      __syncthreads();
+    }
+    if (t < nt) row[t] = carry + sh[threadIdx.x] - v;
+    const uint32_t total = sh[kT - 1];
+    __syncthreads();
+    carry += total;
+  }
+}
+
+// Stable scatter: each wavefront ranks its 1,024 consecutive elements (16
+// rounds of 64) by digit with ballots; wavefronts are then offset by the
+// counts of earlier wavefronts, tiles by the scanned histogram.
+__global__ __launch_bounds__(kT) void sort_scatter_kernel(JobSet J, uint32_t p) {
+  const SortJob* s;
+  uint32_t tile, n;
+  if (!job_tile(J, p, s, tile, n)) return;
+  __shared__ uint32_t wcnt[kT / 64][256];
+  __shared__ uint32_t base[kT / 64][256];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int x = 0; x < 256; x += 64) wcnt[w][x + lane] = 0;
+  __syncthreads();
+  const uint32_t src = p & 1, dst = src ^ 1;
+  const uint32_t wb = tile * kTile + w * (kTile / (kT / 64));
+  uint32_t dg[kItems], rk[kItems], vl[kItems];
+  unsigned long long ky[kItems];
+  const bool keyed = s->keys[0] != nullptr;
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    const uint32_t j = wb + r * 64 + lane;
+    const bool in = j < n;
+    uint32_t d = 0;
+    if (in) {
+      vl[r] = s->vals[src][j];
+      if (keyed) {
+        ky[r] = s->keys[src][j];
+        d = (uint32_t)(ky[r] >> s->ps[p]) & 0xFF;
+      } else {
+        d = (uint32_t)(s->words[s->pw[p]][vl[r]] >> s->ps[p]) & 0xFF;
+      }
+    }
+    // peers: lanes of this round holding the same digit
+    uint64_t peers = __ballot(in);
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+      const uint64_t bb = __ballot((d >> bit) & 1);
+      peers &= ((d >> bit) & 1) ? bb : ~bb;
+    }
+    const uint32_t before = in ? wcnt[w][d] : 0;
+    const uint32_t cnt = __popcll(peers);
+    const bool leader = in && (peers >> lane) == 1ull;  // highest lane among peers
+    dg[r] = d;
+    rk[r] = before + (uint32_t)__popcll(peers & lanemask_lt());
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    if (leader) wcnt[w][d] = before + cnt;
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  }
+  __syncthreads();
+  {
+    const uint32_t d = threadIdx.x;
+    uint32_t acc = s->hist[(size_t)d * s->ntiles_max + tile];
+    for (int x = 0; x < kT / 64; ++x) {
+      base[x][d] = acc;
+      acc += wcnt[x][d];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    const uint32_t j = wb + r * 64 + lane;
+    if (j < n) {
+      const uint32_t pos = base[w][dg[r]] + rk[r];
+      s->vals[dst][pos] = vl[r];
+      if (keyed) s->keys[dst][pos] = ky[r];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 4. Duplicate and round-trip transfers: segmented scans per digest group.
+// ---------------------------------------------------------------------------
+struct U128 {
+  uint64_t lo, hi;
+};
+__device__ __forceinline__ U128 u128_bit(uint32_t b) {
+  U128 r;
+  r.lo = b < 64 ? (1ull << b) : 0ull;
+  r.hi = b >= 64 ? (1ull << (b - 64)) : 0ull;
+  return r;
+}
+__device__ __forceinline__ bool u128_has(const U128& a, uint32_t b) {
+  return b < 64 ? ((a.lo >> b) & 1) : ((a.hi >> (b - 64)) & 1);
+}
+
+// Forward state over earlier transfers of a group: receivers seen, and for
+// every unordered endpoint pair whether it occurred and the direction of its
+// latest transfer (bit set: from the lower to the higher endpoint).
+struct Fwd {
+  uint32_t dst;
+  U128 pres, dir;
+};
+// Backward state over later transfers of a group: ordered pairs seen, receivers seen.
+struct Bwd {
+  U128 pairs;
+  uint32_t dst;
+};
+
+__device__ __forceinline__ Fwd fwd_id() { return Fwd{0, {0, 0}, {0, 0}}; }
+__device__ __forceinline__ Bwd bwd_id() { return Bwd{{0, 0}, 0}; }
+
+__device__ __forceinline__ Fwd fwd_lift(uint8_t a) {
+  Fwd f = fwd_id();
+  if (a == kNotTransfer) return f;
+  const uint32_t s = a >> 4, d = a & 15;
+  f.dst = 1u << d;
+  if (s != d) {
+    const uint32_t lo = min(s, d), hi = max(s, d);
+    const U128 b = u128_bit(lo * kEp + hi);
+    f.pres = b;
+    if (s == lo) f.dir = b;
+  }
+  return f;
+}
+__device__ __forceinline__ Bwd bwd_lift(uint8_t a) {
+  Bwd g = bwd_id();
+  if (a == kNotTransfer) return g;
+  const uint32_t s = a >> 4, d = a & 15;
+  g.dst = 1u << d;
+  if (s != d) g.pairs = u128_bit(s * kEp + d);
+  return g;
+}
+// a earlier, b later
+__device__ __forceinline__ Fwd fwd_op(const Fwd& a, const Fwd& b) {
+  Fwd r;
+  r.dst = a.dst | b.dst;
+  r.pres.lo = a.pres.lo | b.pres.lo;
+  r.pres.hi = a.pres.hi | b.pres.hi;
+  r.dir.lo = (a.dir.lo & ~b.pres.lo) | b.dir.lo;
+  r.dir.hi = (a.dir.hi & ~b.pres.hi) | b.dir.hi;
+  return r;
+}
+__device__ __forceinline__ Bwd bwd_op(const Bwd& a, const Bwd& b) {
+  return Bwd{{a.pairs.lo | b.pairs.lo, a.pairs.hi | b.pairs.hi}, a.dst | b.dst};
+}
+
+struct FwdSeg {
+  uint32_t f;  // a group starts inside
+  Fwd v;       // combination since the last start
+};
+struct BwdSeg {
+  uint32_t f;  // a group ends inside
+  Bwd v;       // combination up to the first end
+};
+// x before y
+__device__ __forceinline__ FwdSeg fseg_op(const FwdSeg& x, const FwdSeg& y) {
+  return FwdSeg{x.f | y.f, y.f ? y.v : fwd_op(x.v, y.v)};
+}
+// x before y, combining towards x (y is later)
+__device__ __forceinline__ BwdSeg bseg_op(const BwdSeg& x, const BwdSeg& y) {
+  return BwdSeg{x.f | y.f, x.f ? x.v : bwd_op(x.v, y.v)};
+}
+
+struct DDArgs {
+  const odp_event* ev;
+  uint32_t n;
+  const uint8_t* aux;
+  const SortJob* job;  // the digest job (keys/vals in buffer npasses & 1)
+  FwdSeg* tf;          // per tile
+  BwdSeg* tb;
+  FwdSeg* cf;          // carries per tile
+  BwdSeg* cb;
+  uint8_t* flags;
+  odp_report* rep;
+};
+
+// Element j of the sorted order: group start / end flags.
+__device__ __forceinline__ bool is_head(const unsigned long long* k, uint32_t j) { return j == 0 || k[j] != k[j - 1]; }
+__device__ __forceinline__ bool is_tail(const unsigned long long* k, uint32_t j, uint32_t n) {
+  return j + 1 == n || k[j] != k[j + 1];
+}
+
+// Block-wide exclusive scans of the threads' FwdSeg (forward) and BwdSeg
+// (backward, i.e. over later threads).
+__device__ void block_scan_fwd(FwdSeg& x) {
+  __shared__ FwdSeg sh[kT];
+  sh[threadIdx.x] = x;
+  __syncthreads();
+  for (int o = 1; o < kT; o <<= 1) {
+    FwdSeg y = x;
+    if (threadIdx.x >= (uint32_t)o) y = fseg_op(sh[threadIdx.x - o], x);
+    __syncthreads();
+    sh[threadIdx.x] = y;
+    x = y;
+    __syncthreads();
+  }
+  x = threadIdx.x ? sh[threadIdx.x - 1] : FwdSeg{0, fwd_id()};
+  __syncthreads();
+}
+__device__ void block_scan_bwd(BwdSeg& x) {
+  __shared__ BwdSeg sh[kT];
+  sh[threadIdx.x] = x;
+  __syncthreads();
+  for (int o = 1; o < kT; o <<= 1) {
+    BwdSeg y = x;
+    if (threadIdx.x + o < (uint32_t)kT) y = bseg_op(x, sh[threadIdx.x + o]);
+    __syncthreads();
+    sh[threadIdx.x] = y;
+    x = y;
+    __syncthreads();
+  }
+  x = threadIdx.x + 1 < (uint32_t)kT ? sh[threadIdx.x + 1] : BwdSeg{0, bwd_id()};
+  __syncthreads();
+}
+
+// Each thread owns kItems consecutive elements of the tile.
+__device__ void thread_aggs(const unsigned long long* k, const uint32_t* v, const uint8_t* aux, uint32_t n, uint32_t j0,
+                            FwdSeg& fa, BwdSeg& ba) {
+  fa = FwdSeg{0, fwd_id()};
+  for (int r = 0; r < kItems; ++r) {
+    const uint32_t j = j0 + r;
+    if (j >= n) break;
+    const Fwd x = fwd_lift(aux[v[j]]);
+    if (is_head(k, j)) fa = FwdSeg{1, x};
+    else fa.v = fwd_op(fa.v, x);
+  }
+  ba = BwdSeg{0, bwd_id()};
+  for (int r = kItems - 1; r >= 0; --r) {
+    const uint32_t j = j0 + r;
+    if (j >= n) continue;
+    const Bwd x = bwd_lift(aux[v[j]]);
+    if (is_tail(k, j, n)) ba = BwdSeg{1, x};
+    else ba.v = bwd_op(x, ba.v);
+  }
+}
+
+__global__ __launch_bounds__(kT) void ddrt_tile_kernel(DDArgs A) {
+  const SortJob& s = *A.job;
+  const uint32_t buf = s.npasses & 1;
+  const unsigned long long* k = s.keys[buf];
+  const uint32_t* v = s.vals[buf];
+  const uint32_t j0 = blockIdx.x * kTile + threadIdx.x * kItems;
+  FwdSeg fa;
+  BwdSeg ba;
+  thread_aggs(k, v, A.aux, A.n, j0, fa, ba);
+  // tile aggregates: forward = combination of all threads; backward likewise
+  __shared__ FwdSeg shf[kT];
+  __shared__ BwdSeg shb[kT];
+  shf[threadIdx.x] = fa;
+  shb[threadIdx.x] = ba;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    FwdSeg f = shf[0];
+    for (int t = 1; t < kT; ++t) f = fseg_op(f, shf[t]);
+    A.tf[blockIdx.x] = f;
+  } else if (threadIdx.x == 64) {
+    BwdSeg b = shb[kT - 1];
+    for (int t = kT - 2; t >= 0; --t) b = bseg_op(shb[t], b);
+    A.tb[blockIdx.x] = b;
+  }
+}
+
+// Carries between tiles (one block): forward carry of tile t combines tiles
+// < t; backward carry combines tiles > t.
+__global__ __launch_bounds__(kT) void ddrt_carry_kernel(DDArgs A, uint32_t ntiles) {
+  __shared__ FwdSeg cf;
+  __shared__ BwdSeg cb;
+  // Each thread handles a contiguous run of tiles.
+  const uint32_t per = ceil_div32(ntiles, kT);
+  const uint32_t t0 = threadIdx.x * per;
+  FwdSeg f{0, fwd_id()};
+  for (uint32_t t = t0; t < min(ntiles, t0 + per); ++t) f = fseg_op(f, A.tf[t]);
+  BwdSeg b{0, bwd_id()};
+  for (uint32_t t = min(ntiles, t0 + per); t > t0; --t) b = bseg_op(A.tb[t - 1], b);
+  block_scan_fwd(f);
+  block_scan_bwd(b);
+  // f: combination of tiles before t0; b: combination of tiles after the run
+  FwdSeg run = f;
+  for (uint32_t t = t0; t < min(ntiles, t0 + per); ++t) {
+    A.cf[t] = run;
+    run = fseg_op(run, A.tf[t]);
+  }
+  BwdSeg runb = b;
+  for (uint32_t t = min(ntiles, t0 + per); t > t0; --t) {
+    A.cb[t - 1] = runb;
+    runb = bseg_op(A.tb[t - 1], runb);
+  }
+  (void)cf;
+  (void)cb;
+}
+
+__global__ __launch_bounds__(kT) void ddrt_final_kernel(DDArgs A) {
+  const SortJob& s = *A.job;
+  const uint32_t buf = s.npasses & 1;
+  const unsigned long long* k = s.keys[buf];
+  const uint32_t* v = s.vals[buf];
+  const uint32_t j0 = blockIdx.x * kTile + threadIdx.x * kItems;
+  FwdSeg fa;
+  BwdSeg ba;
+  thread_aggs(k, v, A.aux, A.n, j0, fa, ba);
+  block_scan_fwd(fa);
+  block_scan_bwd(ba);
+  // carry-in from other tiles
+  const FwdSeg tcf = A.cf[blockIdx.x];
+  const BwdSeg tcb = A.cb[blockIdx.x];
+  Fwd fin = fa.f ? fa.v : fwd_op(tcf.v, fa.v);       // state before this thread's first element
+  Bwd bin = ba.f ? ba.v : bwd_op(ba.v, tcb.v);       // state after this thread's last element
+  uint32_t res[kItems];
+  unsigned long long c_dd = 0, c_grp = 0, c_tx = 0, c_rx = 0, b_dd = 0, t_dd = 0, b_rx = 0, t_rx = 0;
+  Fwd st = fin;
+  for (int r = 0; r < kItems; ++r) {
+    const uint32_t j = j0 + r;
+    res[r] = 0;
+    if (j >= A.n) break;
+    if (is_head(k, j)) st = fwd_id();
+    const uint8_t a = A.aux[v[j]];
+    if (a != kNotTransfer) {
+      const uint32_t sr = a >> 4, d = a & 15;
+      if ((st.dst >> d) & 1) res[r] |= ODP_F_DD;
+      if (sr != d) {
+        const uint32_t lo = min(sr, d), hi = max(sr, d), bit = lo * kEp + hi;
+        if (u128_has(st.pres, bit) && (u128_has(st.dir, bit) != (sr == lo))) res[r] |= ODP_F_RT_RX;
+      }
+    }
+    st = fwd_op(st, fwd_lift(a));
+  }
+  Bwd bt = bin;
+  for (int r = kItems - 1; r >= 0; --r) {
+    const uint32_t j = j0 + r;
+    if (j >= A.n) continue;
+    if (is_tail(k, j, A.n)) bt = bwd_id();
+    const uint32_t idx = v[j];
+    const uint8_t a = A.aux[idx];
+    if (a != kNotTransfer) {
+      const uint32_t sr = a >> 4, d = a & 15;
+      if (sr != d && u128_has(bt.pairs, d * kEp + sr)) res[r] |= ODP_F_RT_TX;
+      const bool leader = !(res[r] & ODP_F_DD) && ((bt.dst >> d) & 1);
+      c_grp += leader;
+      c_dd += (res[r] & ODP_F_DD) != 0;
+      c_tx += (res[r] & ODP_F_RT_TX) != 0;
+      c_rx += (res[r] & ODP_F_RT_RX) != 0;
+      if (res[r] & (ODP_F_DD | ODP_F_RT_RX)) {
+        const odp_event& e = A.ev[idx];
+        const uint64_t du = e.t_end - e.t_start;
+        if (res[r] & ODP_F_DD) {
+          b_dd += e.bytes;
+          t_dd += du;
+        }
+        if (res[r] & ODP_F_RT_RX) {
+          b_rx += e.bytes;
+          t_rx += du;
+        }
+      }
+      A.flags[idx] = (uint8_t)res[r];
+    }
+    bt = bwd_op(bwd_lift(a), bt);
+  }
+  block_add(&A.rep->dd_events, c_dd);
+  block_add(&A.rep->dd_groups, c_grp);
+  block_add(&A.rep->dd_bytes, b_dd);
+  block_add(&A.rep->dd_time_ns, t_dd);
+  block_add(&A.rep->rt_pairs, c_tx);
+  block_add(&A.rep->rt_rx_events, c_rx);
+  block_add(&A.rep->rt_bytes, b_rx);
+  block_add(&A.rep->rt_time_ns, t_rx);
+}
+
+// ---------------------------------------------------------------------------
+// 5. Allocation/deletion pairing and the paired-allocation list.
+// ---------------------------------------------------------------------------
+struct PairArgs {
+  const odp_event* ev;
+  const SortJob* ad_job;
+  const uint32_t* n_ad;
+  const uint32_t* ad_idx;
+  const uint8_t* ad_op;
+  const uint64_t* ad_w_dev;
+  const uint64_t* ad_w_addr;
+  uint32_t* ad_alloc_partner;
+  uint32_t* tile_cnt;
+  // pair list
+  uint32_t* pr_alloc;  // AD positions
+  uint32_t* pr_del;
+  uint64_t* pr_w_bytes;
+  uint64_t* pr_w_dev;
+  uint64_t* pr_w_haddr;
+  uint32_t* pr_vals;
+  uint8_t* flags;
+  AnaCtl* ctl;
+  odp_report* rep;
+};
+
+__global__ __launch_bounds__(kT) void pair_kernel(PairArgs P) {
+  const uint32_t n = *P.n_ad;
+  const SortJob& s = *P.ad_job;
+  const uint32_t* v = s.vals[s.npasses & 1];
+  for (uint32_t j = blockIdx.x * kT + threadIdx.x; j < n; j += gridDim.x * kT) {
+    if (j == 0) continue;
+    const uint32_t p = v[j], q = v[j - 1];
+    if (P.ad_op[p] == ODP_DELETE && P.ad_op[q] == ODP_ALLOC && P.ad_w_dev[p] == P.ad_w_dev[q] &&
+        P.ad_w_addr[p] == P.ad_w_addr[q])
+      P.ad_alloc_partner[q] = p;
+  }
+}
+
+__global__ __launch_bounds__(kT) void pair_count_kernel(PairArgs P) {
+  const uint32_t n = *P.n_ad;
+  const uint32_t b = blockIdx.x * kTile;
+  if (b >= n) {
+    if (threadIdx.x == 0) P.tile_cnt[2 * blockIdx.x] = P.tile_cnt[2 * blockIdx.x + 1] = 0;
+    return;
+  }
+  uint32_t c = 0;
+  for (uint32_t x = threadIdx.x; x < (uint32_t)kTile; x += kT) {
+    const uint32_t p = b + x;
+    if (p < n) c += P.ad_alloc_partner[p] != kNone;
+  }
+  for (int o = 32; o >= 1; o >>= 1) c += __shfl_xor(c, o, 64);
+  __shared__ uint32_t sh[kT / 64];
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t t = 0;
+    for (int w = 0; w < kT / 64; ++w) t += sh[w];
+    P.tile_cnt[2 * blockIdx.x] = t;
+    P.tile_cnt[2 * blockIdx.x + 1] = 0;
+  }
+}
+
+__global__ __launch_bounds__(kT) void pair_scatter_kernel(PairArgs P) {
+  const uint32_t n = *P.n_ad;
+  const uint32_t b = blockIdx.x * kTile;
+  if (b >= n) return;
+  __shared__ uint32_t wc[kT / 64];
+  __shared__ uint32_t run;
+  if (threadIdx.x == 0) run = P.tile_cnt[2 * blockIdx.x];
+  __syncthreads();
+  const int w = threadIdx.x >> 6;
+  unsigned long long o_b = 0, a_b = ~0ull, o_d = 0, a_d = ~0ull, o_h = 0, a_h = ~0ull;
+  unsigned long long unp_a = 0, unp_d = 0;
+  bool any = false;
+  for (uint32_t r = 0; r < (uint32_t)kItems; ++r) {
+    const uint32_t p = b + r * kT + threadIdx.x;
+    const bool in = p < n;
+    const uint32_t partner = in ? P.ad_alloc_partner[p] : kNone;
+    const bool paired_alloc = partner != kNone;
+    const uint64_t m = __ballot(paired_alloc);
+    if ((threadIdx.x & 63) == 0) wc[w] = __popcll(m);
+    __syncthreads();
+    uint32_t k = run;
+    for (int x = 0; x < w; ++x) k += wc[x];
+    k += __popcll(m & lanemask_lt());
+    if (paired_alloc) {
+      const odp_event& e = P.ev[P.ad_idx[p]];
+      const uint64_t dv = P.ad_w_dev[p];
+      P.pr_alloc[k] = p;
+      P.pr_del[k] = partner;
+      P.pr_w_bytes[k] = e.bytes;
+      P.pr_w_dev[k] = dv;
+      P.pr_w_haddr[k] = e.src_addr;
+      P.pr_vals[k] = k;
+      P.flags[P.ad_idx[partner]] = ODP_F_PAIRED;  // the DELETE of the pair
+      o_b |= e.bytes;
+      a_b &= e.bytes;
+      o_d |= dv;
+      a_d &= dv;
+      o_h |= e.src_addr;
+      a_h &= e.src_addr;
+      any = true;
+    } else if (in && P.ad_op[p] == ODP_ALLOC) {
+      ++unp_a;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+      for (int x = 0; x < kT / 64; ++x) run += wc[x];
+    __syncthreads();
+  }
+  (void)unp_d;
+  block_add(&P.rep->n_unpaired_alloc, unp_a);
+  block_mask(&P.ctl->m_p_bytes, o_b, a_b, any);
+  block_mask(&P.ctl->m_p_dev, o_d, a_d, any);
+  block_mask(&P.ctl->m_p_haddr, o_h, a_h, any);
+}
+
+// ---------------------------------------------------------------------------
+// 6. Kernel lists per device (sorted by device, then start / end).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kT) void kernel_ranges_kernel(const SortJob* ks, const uint64_t* k_w_dev, const uint32_t* n_k,
+                                                           AnaCtl* ctl) {
+  const uint32_t n = *n_k;
+  const uint32_t* v = ks->vals[ks->npasses & 1];
+  for (uint32_t j = blockIdx.x * kT + threadIdx.x; j < n; j += gridDim.x * kT) {
+    const uint32_t d = (uint32_t)k_w_dev[v[j]];
+    if (j == 0 || (uint32_t)k_w_dev[v[j - 1]] != d) ctl->dev_lo[d] = j;
+    if (j + 1 == n || (uint32_t)k_w_dev[v[j + 1]] != d) ctl->dev_hi[d] = j + 1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 7. Repeated and unused allocations, flags of paired allocations.
+// ---------------------------------------------------------------------------
+struct RaArgs {
+  const odp_event* ev;
+  const SortJob* pr_job;
+  const SortJob* ks_job;  // kernels by (device, start)
+  const SortJob* ke_job;  // kernels by (device, end)
+  const uint32_t* n_pairs;
+  const uint32_t* pr_alloc;
+  const uint32_t* pr_del;
+  const uint32_t* ad_idx;
+  const uint64_t* pr_w_bytes;
+  const uint64_t* pr_w_dev;
+  const uint64_t* pr_w_haddr;
+  const uint64_t* k_w_start;
+  const uint64_t* k_w_end;
+  const AnaCtl* ctl;
+  uint8_t* flags;
+  odp_report* rep;
+};
+
+__device__ __forceinline__ bool same_pair_key(const RaArgs& R, uint32_t a, uint32_t b) {
+  return R.pr_w_haddr[a] == R.pr_w_haddr[b] && R.pr_w_dev[a] == R.pr_w_dev[b] && R.pr_w_bytes[a] == R.pr_w_bytes[b];
+}
+
+// Number of entries of the sorted list (values into `w`) within [lo, hi) whose word is <= x (le) or < x.
+__device__ __forceinline__ uint32_t count_upto(const uint32_t* v, const uint64_t* w, uint32_t lo, uint32_t hi, uint64_t x,
+                                               bool le) {
+  uint32_t a = lo, b = hi;
+  while (a < b) {
+    const uint32_t m = (a + b) / 2;
+    const uint64_t y = w[v[m]];
+    if (le ? (y <= x) : (y < x)) a = m + 1; else b = m;
+  }
+  return a - lo;
+}
+
+__global__ __launch_bounds__(kT) void ra_ua_kernel(RaArgs R) {
+  const uint32_t n = *R.n_pairs;
+  const SortJob& s = *R.pr_job;
+  const uint32_t* v = s.vals[s.npasses & 1];
+  const uint32_t* vs = R.ks_job->vals[R.ks_job->npasses & 1];
+  const uint32_t* ve = R.ke_job->vals[R.ke_job->npasses & 1];
+  unsigned long long c_ra = 0, c_grp = 0, b_ra = 0, t_ra = 0, c_ua = 0, b_ua = 0, t_ua = 0;
+  for (uint32_t j = blockIdx.x * kT + threadIdx.x; j < n; j += gridDim.x * kT) {
+    const uint32_t k = v[j];
+    const bool head = j == 0 || !same_pair_key(R, k, v[j - 1]);
+    const bool group2 = head && j + 1 < n && same_pair_key(R, k, v[j + 1]);
+    const uint32_t ai = R.ad_idx[R.pr_alloc[k]], di = R.ad_idx[R.pr_del[k]];
+    const odp_event& a = R.ev[ai];
+    const odp_event& d = R.ev[di];
+    const uint64_t dur = (a.t_end - a.t_start) + (d.t_end - d.t_start);
+    uint8_t f = ODP_F_PAIRED;
+    if (!head) {
+      f |= ODP_F_RA;
+      ++c_ra;
+      b_ra += a.bytes;
+      t_ra += dur;
+    }
+    c_grp += group2;
+    const uint32_t dev = (uint32_t)R.pr_w_dev[k];
+    const uint32_t lo = R.ctl->dev_lo[dev], hi = R.ctl->dev_hi[dev];
+    const uint32_t started = count_upto(vs, R.k_w_start, lo, hi, d.t_end, true);
+    const uint32_t ended = count_upto(ve, R.k_w_end, lo, hi, a.t_start, false);
+    if (started == ended) {
+      f |= ODP_F_UA;
+      ++c_ua;
+      b_ua += a.bytes;
+      t_ua += dur;
+    }
+    R.flags[ai] = f;
+  }
+  block_add(&R.rep->ra_events, c_ra);
+  block_add(&R.rep->ra_groups, c_grp);
+  block_add(&R.rep->ra_bytes, b_ra);
+  block_add(&R.rep->ra_time_ns, t_ra);
+  block_add(&R.rep->ua_events, c_ua);
+  block_add(&R.rep->ua_bytes, b_ua);
+  block_add(&R.rep->ua_time_ns, t_ua);
+}
+
+__global__ void finalize_kernel(AnaCtl* ctl, odp_report* rep) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  rep->n_alloc_pairs = ctl->n_pairs;
+  rep->n_unpaired_delete = (ctl->n_ad - rep->n_unpaired_alloc - 2ull * ctl->n_pairs);
+  rep->dd_members = rep->dd_events + rep->dd_groups;
+  rep->ra_members = rep->ra_events + rep->ra_groups;
+  rep->first_bad_event = ctl->first_bad;
+  rep->status = ctl->first_bad != kNone ? 1 : 0;
+}
+
+// ---------------------------------------------------------------------------
+// Workspace layout.
+// ---------------------------------------------------------------------------
+enum Buf {
+  B_CTL, B_JOBS, B_CLS, B_AUX, B_BKEY0, B_BKEY1, B_BVAL0, B_BVAL1, B_TILECNT, B_AD, B_K, B_PR, B_HIST,
+  B_TOTALS, B_SEG
+};
+
+constexpr int kJobBig = 0, kJobAd = 1, kJobKs = 2, kJobKe = 3, kJobPr = 4, kNumJobs = 5;
+
+template <typename T>
+T* carve(char*& p, size_t count) {
+  uintptr_t a = (reinterpret_cast<uintptr_t>(p) + 7) & ~uintptr_t(7);
+  T* r = reinterpret_cast<T*>(a);
+  p = reinterpret_cast<char*>(a + count * sizeof(T));
+  return r;
+}
+
+// Every device array of the analysis, carved from the workspace buffers.
+struct Views {
+  size_t cap;
+  uint32_t ntc;  // tiles of the capacity
+  AnaCtl* ctl;
+  SortJob* jobs;
+  uint8_t* cls;
+  uint8_t* aux;
+  unsigned long long* bk[2];
+  uint32_t* bv[2];
+  uint32_t* tile_cnt;
+  SubsetOut S;
+  uint32_t* ad_vals1;
+  uint32_t* k_vals_s1;
+  uint32_t* k_vals_e1;
+  uint32_t *pr_alloc, *pr_del, *pr_vals, *pr_vals1;
+  uint64_t *pr_w_bytes, *pr_w_dev, *pr_w_haddr;
+  uint32_t* hist;
+  uint32_t* totals;
+  FwdSeg *tf, *cf;
+  BwdSeg *tb, *cb;
+};
+
+Views views(Workspace* ws) {
+  Views v;
+  DevBuf* b = ws->a_bufs;
+  v.cap = ws->a_cap_events;
+  v.ntc = ceil_div32(v.cap, kTile);
+  v.ctl = static_cast<AnaCtl*>(b[B_CTL].ptr);
+  v.jobs = static_cast<SortJob*>(b[B_JOBS].ptr);
+  v.cls = static_cast<uint8_t*>(b[B_CLS].ptr);
+  v.aux = static_cast<uint8_t*>(b[B_AUX].ptr);
+  v.bk[0] = static_cast<unsigned long long*>(b[B_BKEY0].ptr);
+  v.bk[1] = static_cast<unsigned long long*>(b[B_BKEY1].ptr);
+  v.bv[0] = static_cast<uint32_t*>(b[B_BVAL0].ptr);
+  v.bv[1] = static_cast<uint32_t*>(b[B_BVAL1].ptr);
+  v.tile_cnt = static_cast<uint32_t*>(b[B_TILECNT].ptr);
+  const size_t cap = v.cap;
+  char* pa = static_cast<char*>(b[B_AD].ptr);
+  v.S.ad_idx = carve<uint32_t>(pa, cap);
+  v.S.ad_w_dev = carve<uint64_t>(pa, cap);
+  v.S.ad_w_addr = carve<uint64_t>(pa, cap);
+  v.S.ad_vals = carve<uint32_t>(pa, cap);
+  v.ad_vals1 = carve<uint32_t>(pa, cap);
+  v.S.ad_alloc_partner = carve<uint32_t>(pa, cap);
+  v.S.ad_op = carve<uint8_t>(pa, cap);
+  char* pk = static_cast<char*>(b[B_K].ptr);
+  v.S.k_idx = carve<uint32_t>(pk, cap);
+  v.S.k_w_start = carve<uint64_t>(pk, cap);
+  v.S.k_w_end = carve<uint64_t>(pk, cap);
+  v.S.k_w_dev = carve<uint64_t>(pk, cap);
+  v.S.k_vals_s = carve<uint32_t>(pk, cap);
+  v.k_vals_s1 = carve<uint32_t>(pk, cap);
+  v.S.k_vals_e = carve<uint32_t>(pk, cap);
+  v.k_vals_e1 = carve<uint32_t>(pk, cap);
+  char* pp = static_cast<char*>(b[B_PR].ptr);
+  v.pr_alloc = carve<uint32_t>(pp, cap);
+  v.pr_del = carve<uint32_t>(pp, cap);
+  v.pr_w_bytes = carve<uint64_t>(pp, cap);
+  v.pr_w_dev = carve<uint64_t>(pp, cap);
+  v.pr_w_haddr = carve<uint64_t>(pp, cap);
+  v.pr_vals = carve<uint32_t>(pp, cap);
+  v.pr_vals1 = carve<uint32_t>(pp, cap);
+  v.hist = static_cast<uint32_t*>(b[B_HIST].ptr);
+  v.totals = static_cast<uint32_t*>(b[B_TOTALS].ptr);
+  char* ps = static_cast<char*>(b[B_SEG].ptr);
+  v.tf = carve<FwdSeg>(ps, v.ntc);
+  v.tb = carve<BwdSeg>(ps, v.ntc);
+  v.cf = carve<FwdSeg>(ps, v.ntc);
+  v.cb = carve<BwdSeg>(ps, v.ntc);
+  return v;
+}
+
+// Sort job table for a workspace capacity (device-resident; the pass lists
+// inside are refilled on the device by every call).
+void build_jobs(const Views& v, SortJob* hj) {
+  std::memset(static_cast<void*>(hj), 0, sizeof(SortJob) * kNumJobs);
+  AnaCtl* ctl = v.ctl;
+  // all records by digest (keyed; non-transfers carry an all-ones key and contribute nothing)
+  hj[kJobBig].n_ptr = &ctl->n;
+  hj[kJobBig].keys[0] = v.bk[0];
+  hj[kJobBig].keys[1] = v.bk[1];
+  hj[kJobBig].vals[0] = v.bv[0];
+  hj[kJobBig].vals[1] = v.bv[1];
+  hj[kJobBig].masks[0] = &ctl->m_digest;
+  hj[kJobBig].word_bytes[0] = 8;
+  hj[kJobBig].nwords = 1;
+  // ALLOC/DELETE by (device, device address); words least significant first
+  hj[kJobAd].n_ptr = &ctl->n_ad;
+  hj[kJobAd].vals[0] = v.S.ad_vals;
+  hj[kJobAd].vals[1] = v.ad_vals1;
+  hj[kJobAd].words[0] = v.S.ad_w_addr;
+  hj[kJobAd].masks[0] = &ctl->m_ad_addr;
+  hj[kJobAd].word_bytes[0] = 8;
+  hj[kJobAd].words[1] = v.S.ad_w_dev;
+  hj[kJobAd].masks[1] = &ctl->m_ad_dev;
+  hj[kJobAd].word_bytes[1] = 1;
+  hj[kJobAd].nwords = 2;
+  // kernels by (device, start) and by (device, end)
+  hj[kJobKs].n_ptr = &ctl->n_k;
+  hj[kJobKs].vals[0] = v.S.k_vals_s;
+  hj[kJobKs].vals[1] = v.k_vals_s1;
+  hj[kJobKs].words[0] = v.S.k_w_start;
+  hj[kJobKs].masks[0] = &ctl->m_k_start;
+  hj[kJobKs].word_bytes[0] = 8;
+  hj[kJobKs].words[1] = v.S.k_w_dev;
+  hj[kJobKs].masks[1] = &ctl->m_k_dev;
+  hj[kJobKs].word_bytes[1] = 1;
+  hj[kJobKs].nwords = 2;
+  hj[kJobKe] = hj[kJobKs];
+  hj[kJobKe].vals[0] = v.S.k_vals_e;
+  hj[kJobKe].vals[1] = v.k_vals_e1;
+  hj[kJobKe].words[0] = v.S.k_w_end;
+  hj[kJobKe].masks[0] = &ctl->m_k_end;
+  // paired allocations by (host address, device, bytes)
+  hj[kJobPr].n_ptr = &ctl->n_pairs;
+  hj[kJobPr].vals[0] = v.pr_vals;
+  hj[kJobPr].vals[1] = v.pr_vals1;
+  hj[kJobPr].words[0] = v.pr_w_bytes;
+  hj[kJobPr].masks[0] = &ctl->m_p_bytes;
+  hj[kJobPr].word_bytes[0] = 8;
+  hj[kJobPr].words[1] = v.pr_w_dev;
+  hj[kJobPr].masks[1] = &ctl->m_p_dev;
+  hj[kJobPr].word_bytes[1] = 1;
+  hj[kJobPr].words[2] = v.pr_w_haddr;
+  hj[kJobPr].masks[2] = &ctl->m_p_haddr;
+  hj[kJobPr].word_bytes[2] = 8;
+  hj[kJobPr].nwords = 3;
+  for (int j = 0; j < kNumJobs; ++j) {
+    hj[j].ntiles_max = v.ntc;
+    hj[j].hist = v.hist + (size_t)j * 256 * v.ntc;
+    hj[j].totals = v.totals + (size_t)j * kMaxPasses * 256;
+  }
+}
+
+}  // namespace
+
+int analyze_reserve(Workspace* ws, size_t max_events) {
+  size_t cap = max_events < 4096 ? 4096 : max_events;
+  if (cap <= ws->a_cap_events) return ODP_OK;
+  const uint32_t nt = ceil_div32(cap, kTile);
+  DevBuf* b = ws->a_bufs;
+  int e;
+  if ((e = b[B_CTL].ensure(sizeof(AnaCtl))) || (e = b[B_JOBS].ensure(sizeof(SortJob) * kNumJobs)) ||
+      (e = b[B_CLS].ensure(cap)) || (e = b[B_AUX].ensure(cap)) || (e = b[B_BKEY0].ensure(cap * 8)) ||
+      (e = b[B_BKEY1].ensure(cap * 8)) || (e = b[B_BVAL0].ensure(cap * 4)) || (e = b[B_BVAL1].ensure(cap * 4)) ||
+      (e = b[B_TILECNT].ensure((size_t)nt * 8)) ||
+      (e = b[B_AD].ensure(cap * (4 + 8 + 8 + 4 + 4 + 4 + 1) + 64)) ||
+      (e = b[B_K].ensure(cap * (4 + 8 + 8 + 8 + 4 * 4) + 64)) ||
+      (e = b[B_PR].ensure(cap * (4 + 4 + 8 + 8 + 8 + 4 + 4) + 64)) ||
+      (e = b[B_HIST].ensure((size_t)kNumJobs * 256 * nt * 4)) ||
+      (e = b[B_TOTALS].ensure((size_t)kNumJobs * kMaxPasses * 256 * 4)) ||
+      (e = b[B_SEG].ensure((size_t)nt * (2 * sizeof(FwdSeg) + 2 * sizeof(BwdSeg)) + 64)))
+    return e;
+  ws->a_cap_events = cap;
+  SortJob hj[kNumJobs];
+  build_jobs(views(ws), hj);
+  ODP_HIP(hipMemcpy(b[B_JOBS].ptr, hj, sizeof(hj), hipMemcpyHostToDevice));
+  return ODP_OK;
+}
+
+void analyze_release(Workspace* ws) {
+  for (DevBuf& b : ws->a_bufs) b.release();
+  ws->a_cap_events = 0;
+}
+
 }  // namespace odp
-extern "C" int odp_analyze_trace(const odp_event*, size_t, uint8_t*, odp_report*, odp_stream_t) {
-  return odp::set_error(ODP_EINVAL, "odp_analyze_trace: not built yet");
+
+using namespace odp;
+
+extern "C" int odp_analyze_trace(const odp_event* events, size_t n, uint8_t* out_flags, odp_report* out_report,
+                                 odp_stream_t stream_) {
+  hipStream_t stream = static_cast<hipStream_t>(stream_);
+  if (n > 0xFFFFFFFFull) return set_error(ODP_ERANGE, "odp_analyze_trace: n = %zu above 2^32 - 1", n);
+  if (!out_report) return set_error(ODP_EINVAL, "odp_analyze_trace: null report");
+  if (n > 0 && (!events || !out_flags)) return set_error(ODP_EINVAL, "odp_analyze_trace: null array with n = %zu", n);
+  int err = 0;
+  Workspace* ws = workspace_for(stream, &err);
+  if (!ws) return err;
+  hipStreamCaptureStatus capst = hipStreamCaptureStatusNone;
+  ODP_HIP(hipStreamIsCapturing(stream, &capst));
+  if (n > ws->a_cap_events || !ws->a_cap_events) {
+    if (capst != hipStreamCaptureStatusNone)
+      return set_error(ODP_ENOMEM, "odp_analyze_trace: workspace for %zu records not reserved before capture", n);
+    int e = analyze_reserve(ws, n);
+    if (e) return e;
+  }
+  const Views v = views(ws);
+  const uint32_t nn = (uint32_t)n;
+  const uint32_t nt = n ? ceil_div32(n, kTile) : 1;  // tiles of this call
+  const int cus = cu_count(ws->device);
+  const uint32_t grid_map = std::min<uint32_t>(nt * 4, (uint32_t)cus * 8);
+  AnaCtl* ctl = v.ctl;
+
+  hipLaunchKernelGGL(init_kernel, dim3(64), dim3(kT), 0, stream, ctl, out_report, v.totals,
+                     (uint32_t)(kNumJobs * kMaxPasses * 256), nn);
+  if (n == 0) {
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(64), 0, stream, ctl, out_report);
+    return check_hip(hipGetLastError(), "odp_analyze_trace launch");
+  }
+  hipLaunchKernelGGL(classify_kernel, dim3(grid_map), dim3(kT), 0, stream, events, nn, out_flags, v.cls, v.aux,
+                     v.bk[0], v.bv[0], ctl, out_report);
+  hipLaunchKernelGGL(subset_count_kernel, dim3(nt), dim3(kT), 0, stream, v.cls, nn, v.tile_cnt);
+  hipLaunchKernelGGL(scan_pairs_kernel, dim3(1), dim3(1024), 0, stream, v.tile_cnt, nt, &ctl->n_ad, &ctl->n_k);
+  hipLaunchKernelGGL(subset_scatter_kernel, dim3(nt), dim3(kT), 0, stream, events, v.cls, nn, v.tile_cnt, v.S, ctl);
+
+  // Sort round 1: digests, ALLOC/DELETE, kernel starts, kernel ends.
+  const JobSet J1{v.jobs, 4, nt};
+  hipLaunchKernelGGL(sort_plan_kernel, dim3(1), dim3(64), 0, stream, J1);
+  for (uint32_t p = 0; p < 9; ++p) {
+    hipLaunchKernelGGL(sort_hist_kernel, dim3(J1.njobs * nt), dim3(kT), 0, stream, J1, p);
+    hipLaunchKernelGGL(sort_scan_kernel, dim3(256 * J1.njobs), dim3(kT), 0, stream, J1, p);
+    hipLaunchKernelGGL(sort_scatter_kernel, dim3(J1.njobs * nt), dim3(kT), 0, stream, J1, p);
+  }
+
+  // Duplicates and round trips.
+  DDArgs D;
+  D.ev = events;
+  D.n = nn;
+  D.aux = v.aux;
+  D.job = v.jobs + kJobBig;
+  D.tf = v.tf;
+  D.tb = v.tb;
+  D.cf = v.cf;
+  D.cb = v.cb;
+  D.flags = out_flags;
+  D.rep = out_report;
+  hipLaunchKernelGGL(ddrt_tile_kernel, dim3(nt), dim3(kT), 0, stream, D);
+  hipLaunchKernelGGL(ddrt_carry_kernel, dim3(1), dim3(kT), 0, stream, D, nt);
+  hipLaunchKernelGGL(ddrt_final_kernel, dim3(nt), dim3(kT), 0, stream, D);
+
+  // Pairing and the pair list.
+  PairArgs P;
+  P.ev = events;
+  P.ad_job = v.jobs + kJobAd;
+  P.n_ad = &ctl->n_ad;
+  P.ad_idx = v.S.ad_idx;
+  P.ad_op = v.S.ad_op;
+  P.ad_w_dev = v.S.ad_w_dev;
+  P.ad_w_addr = v.S.ad_w_addr;
+  P.ad_alloc_partner = v.S.ad_alloc_partner;
+  P.tile_cnt = v.tile_cnt;
+  P.pr_alloc = v.pr_alloc;
+  P.pr_del = v.pr_del;
+  P.pr_w_bytes = v.pr_w_bytes;
+  P.pr_w_dev = v.pr_w_dev;
+  P.pr_w_haddr = v.pr_w_haddr;
+  P.pr_vals = v.pr_vals;
+  P.flags = out_flags;
+  P.ctl = ctl;
+  P.rep = out_report;
+  hipLaunchKernelGGL(pair_kernel, dim3(grid_map), dim3(kT), 0, stream, P);
+  hipLaunchKernelGGL(pair_count_kernel, dim3(nt), dim3(kT), 0, stream, P);
+  hipLaunchKernelGGL(scan_pairs_kernel, dim3(1), dim3(1024), 0, stream, v.tile_cnt, nt, &ctl->n_pairs, nullptr);
+  hipLaunchKernelGGL(pair_scatter_kernel, dim3(nt), dim3(kT), 0, stream, P);
+  hipLaunchKernelGGL(kernel_ranges_kernel, dim3(grid_map), dim3(kT), 0, stream, v.jobs + kJobKs, v.S.k_w_dev,
+                     &ctl->n_k, ctl);
+
+  // Sort round 2: pairs by (host address, device, bytes).
+  const JobSet J2{v.jobs + kJobPr, 1, nt};
+  hipLaunchKernelGGL(sort_plan_kernel, dim3(1), dim3(64), 0, stream, J2);
+  for (uint32_t p = 0; p < 17; ++p) {
+    hipLaunchKernelGGL(sort_hist_kernel, dim3(nt), dim3(kT), 0, stream, J2, p);
+    hipLaunchKernelGGL(sort_scan_kernel, dim3(256), dim3(kT), 0, stream, J2, p);
+    hipLaunchKernelGGL(sort_scatter_kernel, dim3(nt), dim3(kT), 0, stream, J2, p);
+  }
+
+  RaArgs R;
+  R.ev = events;
+  R.pr_job = v.jobs + kJobPr;
+  R.ks_job = v.jobs + kJobKs;
+  R.ke_job = v.jobs + kJobKe;
+  R.n_pairs = &ctl->n_pairs;
+  R.pr_alloc = v.pr_alloc;
+  R.pr_del = v.pr_del;
+  R.ad_idx = v.S.ad_idx;
+  R.pr_w_bytes = v.pr_w_bytes;
+  R.pr_w_dev = v.pr_w_dev;
+  R.pr_w_haddr = v.pr_w_haddr;
+  R.k_w_start = v.S.k_w_start;
+  R.k_w_end = v.S.k_w_end;
+  R.ctl = ctl;
+  R.flags = out_flags;
+  R.rep = out_report;
+  hipLaunchKernelGGL(ra_ua_kernel, dim3(grid_map), dim3(kT), 0, stream, R);
+  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(64), 0, stream, ctl, out_report);
+  return check_hip(hipGetLastError(), "odp_analyze_trace launch");
 }

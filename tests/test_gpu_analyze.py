@@ -1,0 +1,162 @@
+"""GPU parity of the trace analysis against the CPU oracle: every flag and
+every report field bit-exact, through the C ABI."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2601_12713_amd import workloads as W
+
+from golden_traces import load as load_golden
+from gpu_helpers import analyze_gpu, compare
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def with_digests(ev, payloads, payload_of):
+    ev = ev.copy()
+    dg = [oracle.d64(p) for p in payloads]
+    for i in range(len(ev)):
+        if payload_of[i] >= 0:
+            ev["digest"][i] = dg[payload_of[i]]
+    return ev
+
+
+def check(odp, ev):
+    fr, rr = oracle.analyze(ev)
+    fg, rg = analyze_gpu(odp, ev)
+    compare(fg, rg, fr, rr)
+    return fg, rg
+
+
+def test_empty_log(odp):
+    fg, rg = analyze_gpu(odp, W.empty_events(0))
+    assert rg["n_events"] == 0 and rg["status"] == 0 and rg["first_bad_event"] == 0xFFFFFFFF
+
+
+@pytest.mark.parametrize("name", ["listing1_trace.txt", "listing2_trace.txt"])
+def test_paper_listings(odp, name):
+    ev, payloads, payload_of, expect = load_golden(name)
+    fg, rg = check(odp, with_digests(ev, payloads, payload_of))
+    for k, v in expect.items():
+        assert rg[k] == v, k
+
+
+def test_tiny_random_traces(odp):
+    for seed in range(400):
+        n_dev = 1 + seed % 3
+        inv = 0.1 if seed % 4 == 0 else 0.0
+        ev, payloads, payload_of = W.tiny_trace(seed, n_events=1 + (seed * 7) % 90, n_devices=n_dev,
+                                                 invalid_rate=inv, overlap_kernels=seed % 5 == 0)
+        check(odp, with_digests(ev, payloads, payload_of))
+
+
+def test_traces_spanning_many_tiles(odp):
+    """Digest groups and ALLOC/DELETE groups that cross 4,096-record tiles."""
+    for seed, n in [(1, 5000), (2, 12289), (3, 40000)]:
+        ev, payloads, payload_of = W.tiny_trace(1000 + seed, n_events=n, n_devices=3, n_payloads=5, n_vars=3,
+                                                 invalid_rate=0.01)
+        check(odp, with_digests(ev, payloads, payload_of))
+
+
+def test_one_giant_group(odp):
+    """Every record carries the same digest: one group spanning every tile."""
+    m = 50_000
+    ev = W.empty_events(m)
+    rng = np.random.default_rng(5)
+    src = rng.integers(-1, 3, size=m)
+    dst = rng.integers(-1, 3, size=m)
+    ev["op"] = W.D2D
+    ev["src_dev"], ev["dst_dev"] = src, dst
+    ev["digest"] = 0x1234
+    ev["t_start"] = np.arange(m) * 10
+    ev["t_end"] = ev["t_start"] + 5
+    check(odp, ev)
+
+
+def test_all_endpoints_and_self_transfers(odp):
+    rng = np.random.default_rng(6)
+    m = 20_000
+    ev = W.empty_events(m)
+    ev["op"] = rng.choice([W.H2D, W.D2H, W.D2D], size=m)
+    ev["src_dev"] = rng.integers(-1, 10, size=m)
+    ev["dst_dev"] = rng.integers(-1, 10, size=m)
+    ev["digest"] = rng.integers(0, 40, size=m).astype(np.uint64)
+    ev["t_start"] = np.arange(m)
+    ev["t_end"] = ev["t_start"]
+    check(odp, ev)
+
+
+def test_sentinel_digest_and_ties(odp):
+    """A transfer whose digest is all ones sorts among the non-transfer records;
+    equal timestamps keep array order."""
+    ev = W.empty_events(8)
+    ev["op"] = [W.ALLOC, W.H2D, W.KERNEL, W.H2D, W.D2H, W.H2D, W.DELETE, W.H2D]
+    ev["src_dev"] = [-1, -1, -1, -1, 0, -1, -1, -1]
+    ev["dst_dev"] = [0, 0, 0, 0, -1, 0, 0, 0]
+    ev["digest"] = [0, 2**64 - 1, 0, 2**64 - 1, 2**64 - 1, 7, 0, 2**64 - 1]
+    ev["t_start"] = [0, 0, 0, 1, 1, 1, 2, 2]
+    ev["t_end"] = ev["t_start"] + 1
+    check(odp, ev)
+
+
+def test_invalid_records(odp):
+    for seed in range(30):
+        ev, payloads, payload_of = W.tiny_trace(5000 + seed, n_events=300, n_devices=2, invalid_rate=0.3)
+        fg, rg = check(odp, with_digests(ev, payloads, payload_of))
+        assert rg["status"] in (0, 1)
+
+
+def test_plain_small_end_to_end(odp):
+    """Digests of every snapshot on the GPU (per-buffer launches), then the
+    analysis on the GPU; the oracle digests and analyses the same bytes."""
+    ps = W.PlainSmall(seed=1)
+    snaps = [torch.from_numpy(s).to("cuda") for s in ps.snapshots]
+    gd = odp.digest_tensors(snaps, plain=True)
+    od = np.array([oracle.d64(s) for s in ps.snapshots], dtype=np.uint64)
+    assert (gd == od).all()
+    ev_g = ps.events.copy()
+    ev_o = ps.events.copy()
+    m = ps.snapshot_of >= 0
+    ev_g["digest"][m] = gd[ps.snapshot_of[m]]
+    ev_o["digest"][m] = od[ps.snapshot_of[m]]
+    fr, rr = oracle.analyze(ev_o)
+    fg, rg = analyze_gpu(odp, ev_g)
+    compare(fg, rg, fr, rr)
+    assert all(fg[i] & odp.F_DD for i in ps.planted_dd)
+    assert all(fg[i] & odp.F_RT_RX for i in ps.planted_rt_rx)
+
+
+def test_trace_at_scale_full_size(odp):
+    """10^7 map records over 10^5 Zipf(1.1) slots plus kernel records: every flag
+    against the oracle, and the planted counts exactly."""
+    tr = W.TraceAtScale(seed=4)
+    fg, rg = analyze_gpu(odp, tr.events)
+    for k, v in tr.planted.items():
+        assert rg[k] == v, k
+    fr, rr = oracle.analyze(tr.events)
+    compare(fg, rg, fr, rr)
+
+
+def test_repeated_calls_and_streams(odp):
+    ev, payloads, payload_of = W.tiny_trace(77, n_events=3000, n_devices=3, n_payloads=4)
+    ev = with_digests(ev, payloads, payload_of)
+    fr, rr = oracle.analyze(ev)
+    for _ in range(3):
+        fg, rg = analyze_gpu(odp, ev)
+        compare(fg, rg, fr, rr)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        fg, rg = analyze_gpu(odp, ev, stream=s)
+    compare(fg, rg, fr, rr)
+    # a smaller log after a larger one reuses the workspace
+    small = ev[:100].copy()
+    fr2, rr2 = oracle.analyze(small)
+    fg2, rg2 = analyze_gpu(odp, small)
+    compare(fg2, rg2, fr2, rr2)
+
+
+def test_null_report_rejected(odp):
+    import ctypes
+    rc = odp.load().odp_analyze_trace(None, 0, None, None, None)
+    assert rc == odp.ODP_EINVAL
