@@ -104,7 +104,7 @@ int odp_digest_buffers_plain(const void* const* host_ptrs, const uint64_t* host_
 
 /* ---------------------------------------------------------------------------
  * Event log record (64 bytes, 8-byte aligned). The paper's tool logs 72 bytes
- * per data operation and 24 per target launch (Sec. 7.3) with the fields its
+ * per data operation and 24 per target launch (Sec. 7.4) with the fields its
  * detector needs (Sec. 5); this record carries the same fields, and a target
  * launch is a record with op = ODP_KERNEL.
  * ------------------------------------------------------------------------ */
@@ -152,7 +152,7 @@ enum {
 /* Counts and sums over one log. Filled on the device; valid after the stream
  * completes. *_bytes and *_time_ns sum `bytes` and (t_end - t_start) over the
  * flagged records (round trips: over return legs; RA/UA: the ALLOC plus its
- * DELETE's duration), the inputs of the paper's savings estimate (Sec. 7.5). */
+ * DELETE's duration), the inputs of the paper's savings estimate (Sec. 7.6). */
 typedef struct odp_report {
   uint64_t n_events, n_invalid, n_transfers, n_kernels;
   uint64_t n_alloc_pairs, n_unpaired_alloc, n_unpaired_delete;

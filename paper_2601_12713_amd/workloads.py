@@ -10,7 +10,7 @@ where the workload specifies digests directly (the trace-at-scale log).
 Shapes follow the paper's applications as described in its evaluation
 (Sec. 7.2, App. C): large fp64 arrays re-sent every iteration (babelstream),
 tiny scalars and structs next to large arrays, and duplicate / round-trip /
-repeated / unused mixes of the magnitudes in the issue table (Sec. 7.4).
+repeated / unused mixes of the magnitudes in the issue table (Sec. 7.5).
 """
 import math
 
