@@ -56,7 +56,7 @@ struct AnaCtl {
   uint32_t n_k;         // KERNEL records
   uint32_t n_pairs;     // paired allocations
   uint32_t first_bad;
-  uint32_t pad;
+  uint32_t max_ep;      // largest endpoint code among valid transfers
   WordMask m_digest, m_ad_dev, m_ad_addr, m_k_start, m_k_end, m_k_dev, m_p_bytes, m_p_dev, m_p_haddr;
   uint32_t dev_lo[kEp], dev_hi[kEp];  // per-device ranges in the sorted kernel order
 };
@@ -162,6 +162,7 @@ __global__ void init_kernel(AnaCtl* ctl, odp_report* rep, uint32_t* totals, uint
     ctl->n = n;
     ctl->n_ad = ctl->n_k = ctl->n_pairs = 0;
     ctl->first_bad = kNone;
+    ctl->max_ep = 0;
     WordMask* m = &ctl->m_digest;
     for (int i = 0; i < 9; ++i) {
       m[i].vor = 0;
@@ -184,7 +185,7 @@ __global__ __launch_bounds__(kT) void classify_kernel(const odp_event* __restric
                                                       unsigned long long* __restrict__ keys, uint32_t* __restrict__ vals,
                                                       AnaCtl* ctl, odp_report* rep) {
   unsigned long long n_inv = 0, n_tx = 0, n_k = 0, kor = 0, kand = ~0ull;
-  uint32_t bad = kNone;
+  uint32_t bad = kNone, mep = 0;
   for (uint32_t i = blockIdx.x * kT + threadIdx.x; i < n; i += gridDim.x * kT) {
     const odp_event e = ev[i];
     const uint64_t prev_start = i ? ev[i - 1].t_start : 0;
@@ -197,6 +198,7 @@ __global__ __launch_bounds__(kT) void classify_kernel(const odp_event* __restric
       if (is_tx) {
         c = C_TRANSFER;
         a = (uint8_t)(((e.src_dev + 1) << 4) | (e.dst_dev + 1));
+        mep = max(mep, (uint32_t)max(e.src_dev + 1, e.dst_dev + 1));
         key = e.digest;
         ++n_tx;
       } else if (e.op == ODP_KERNEL) {
@@ -224,6 +226,8 @@ __global__ __launch_bounds__(kT) void classify_kernel(const odp_event* __restric
   // first rejected record
   for (int o = 32; o >= 1; o >>= 1) bad = min(bad, (uint32_t)__shfl_xor((int)bad, o, 64));
   if ((threadIdx.x & 63) == 0 && bad != kNone) atomicMin(&ctl->first_bad, bad);
+  for (int o = 32; o >= 1; o >>= 1) mep = max(mep, (uint32_t)__shfl_xor((int)mep, o, 64));
+  if ((threadIdx.x & 63) == 0 && mep) atomicMax(&ctl->max_ep, mep);
 }
 
 // ---------------------------------------------------------------------------
@@ -560,86 +564,202 @@ __global__ __launch_bounds__(kT) void sort_scatter_kernel(JobSet J, uint32_t p) 
 
 // ---------------------------------------------------------------------------
 // 4. Duplicate and round-trip transfers: segmented scans per digest group.
+//
+// Over the digest-sorted order (index order inside a group), the forward
+// state of a record is what the earlier transfers of its group hold: the
+// receivers seen and, per unordered endpoint pair, whether it occurred and the
+// direction of its latest transfer. The backward state is what the later
+// transfers hold: the ordered pairs and receivers seen.
+//   DD     my receiver is in the forward receivers
+//   RT_RX  my pair occurred earlier and its latest transfer went the other way
+//   RT_TX  the reverse of my ordered pair occurs later
+//   group  a record that is not DD but whose receiver occurs later starts a
+//          duplicate group (dd_groups)
+// Two state widths: one 32-bit word when only endpoint codes 0..3 occur (host
+// and devices 0..2), five words for all 11 endpoints.
 // ---------------------------------------------------------------------------
-struct U128 {
+template <int MODE>
+struct FS;  // forward state
+template <int MODE>
+struct BS;  // backward state
+
+// Small: endpoints 0..3. Forward: bits 0-3 receivers, 4-9 pair present,
+// 10-15 pair direction. Backward: bits 0-3 receivers, 4-15 ordered pairs.
+template <>
+struct FS<0> {
+  uint32_t w;
+};
+template <>
+struct BS<0> {
+  uint32_t w;
+};
+// General: endpoints 0..10.
+template <>
+struct FS<1> {
+  uint32_t dst;
+  uint64_t pres, dir;
+};
+template <>
+struct BS<1> {
+  uint32_t dst;
   uint64_t lo, hi;
 };
-__device__ __forceinline__ U128 u128_bit(uint32_t b) {
-  U128 r;
-  r.lo = b < 64 ? (1ull << b) : 0ull;
-  r.hi = b >= 64 ? (1ull << (b - 64)) : 0ull;
-  return r;
+
+// Unordered pair (lo < hi) of E endpoints -> 0 .. E(E-1)/2 - 1.
+__device__ __forceinline__ uint32_t upair(uint32_t lo, uint32_t hi, uint32_t E) {
+  return lo * (2 * E - lo - 1) / 2 + (hi - lo - 1);
 }
-__device__ __forceinline__ bool u128_has(const U128& a, uint32_t b) {
-  return b < 64 ? ((a.lo >> b) & 1) : ((a.hi >> (b - 64)) & 1);
+// Ordered pair (s != d) -> 0 .. E(E-1) - 1.
+__device__ __forceinline__ uint32_t opair(uint32_t s, uint32_t d, uint32_t E) {
+  return s * (E - 1) + (d < s ? d : d - 1);
 }
 
-// Forward state over earlier transfers of a group: receivers seen, and for
-// every unordered endpoint pair whether it occurred and the direction of its
-// latest transfer (bit set: from the lower to the higher endpoint).
-struct Fwd {
-  uint32_t dst;
-  U128 pres, dir;
-};
-// Backward state over later transfers of a group: ordered pairs seen, receivers seen.
-struct Bwd {
-  U128 pairs;
-  uint32_t dst;
-};
+template <int MODE>
+struct St;
 
-__device__ __forceinline__ Fwd fwd_id() { return Fwd{0, {0, 0}, {0, 0}}; }
-__device__ __forceinline__ Bwd bwd_id() { return Bwd{{0, 0}, 0}; }
-
-__device__ __forceinline__ Fwd fwd_lift(uint8_t a) {
-  Fwd f = fwd_id();
-  if (a == kNotTransfer) return f;
-  const uint32_t s = a >> 4, d = a & 15;
-  f.dst = 1u << d;
-  if (s != d) {
-    const uint32_t lo = min(s, d), hi = max(s, d);
-    const U128 b = u128_bit(lo * kEp + hi);
-    f.pres = b;
-    if (s == lo) f.dir = b;
+template <>
+struct St<0> {
+  static constexpr uint32_t E = 4;
+  __device__ static FS<0> fid() { return FS<0>{0}; }
+  __device__ static BS<0> bid() { return BS<0>{0}; }
+  __device__ static FS<0> flift(uint8_t a) {
+    if (a == kNotTransfer) return fid();
+    const uint32_t s = a >> 4, d = a & 15;
+    uint32_t w = 1u << d;
+    if (s != d) {
+      const uint32_t lo = min(s, d), hi = max(s, d), u = upair(lo, hi, E);
+      w |= 1u << (4 + u);
+      if (s == lo) w |= 1u << (10 + u);
+    }
+    return FS<0>{w};
   }
-  return f;
-}
-__device__ __forceinline__ Bwd bwd_lift(uint8_t a) {
-  Bwd g = bwd_id();
-  if (a == kNotTransfer) return g;
-  const uint32_t s = a >> 4, d = a & 15;
-  g.dst = 1u << d;
-  if (s != d) g.pairs = u128_bit(s * kEp + d);
-  return g;
-}
-// a earlier, b later
-__device__ __forceinline__ Fwd fwd_op(const Fwd& a, const Fwd& b) {
-  Fwd r;
-  r.dst = a.dst | b.dst;
-  r.pres.lo = a.pres.lo | b.pres.lo;
-  r.pres.hi = a.pres.hi | b.pres.hi;
-  r.dir.lo = (a.dir.lo & ~b.pres.lo) | b.dir.lo;
-  r.dir.hi = (a.dir.hi & ~b.pres.hi) | b.dir.hi;
-  return r;
-}
-__device__ __forceinline__ Bwd bwd_op(const Bwd& a, const Bwd& b) {
-  return Bwd{{a.pairs.lo | b.pairs.lo, a.pairs.hi | b.pairs.hi}, a.dst | b.dst};
-}
+  __device__ static BS<0> blift(uint8_t a) {
+    if (a == kNotTransfer) return bid();
+    const uint32_t s = a >> 4, d = a & 15;
+    uint32_t w = 1u << d;
+    if (s != d) w |= 1u << (4 + opair(s, d, E));
+    return BS<0>{w};
+  }
+  // a earlier, b later
+  __device__ static FS<0> fop(FS<0> a, FS<0> b) {
+    const uint32_t bp = (b.w >> 4) & 0x3F;
+    const uint32_t keep = ~(bp << 10);
+    return FS<0>{((a.w & keep) | b.w)};
+  }
+  __device__ static BS<0> bop(BS<0> a, BS<0> b) { return BS<0>{a.w | b.w}; }
+  __device__ static bool has_dst(FS<0> f, uint32_t d) { return (f.w >> d) & 1; }
+  __device__ static bool has_dst(BS<0> b, uint32_t d) { return (b.w >> d) & 1; }
+  __device__ static bool rx(FS<0> f, uint32_t s, uint32_t d) {
+    const uint32_t lo = min(s, d), hi = max(s, d), u = upair(lo, hi, E);
+    return ((f.w >> (4 + u)) & 1) && (((f.w >> (10 + u)) & 1) != (s == lo));
+  }
+  __device__ static bool tx(BS<0> b, uint32_t s, uint32_t d) { return (b.w >> (4 + opair(d, s, E))) & 1; }
+  __device__ static FS<0> shfl_up(FS<0> x, int o) { return FS<0>{(uint32_t)__shfl_up((int)x.w, o, 64)}; }
+  __device__ static BS<0> shfl_down(BS<0> x, int o) { return BS<0>{(uint32_t)__shfl_down((int)x.w, o, 64)}; }
+  __device__ static FS<0> shfl(FS<0> x, int l) { return FS<0>{(uint32_t)__shfl((int)x.w, l, 64)}; }
+  __device__ static BS<0> shfl(BS<0> x, int l) { return BS<0>{(uint32_t)__shfl((int)x.w, l, 64)}; }
+};
 
-struct FwdSeg {
-  uint32_t f;  // a group starts inside
-  Fwd v;       // combination since the last start
+template <>
+struct St<1> {
+  static constexpr uint32_t E = kEp;
+  __device__ static FS<1> fid() { return FS<1>{0, 0, 0}; }
+  __device__ static BS<1> bid() { return BS<1>{0, 0, 0}; }
+  __device__ static FS<1> flift(uint8_t a) {
+    if (a == kNotTransfer) return fid();
+    const uint32_t s = a >> 4, d = a & 15;
+    FS<1> f{1u << d, 0, 0};
+    if (s != d) {
+      const uint32_t lo = min(s, d), hi = max(s, d), u = upair(lo, hi, E);
+      f.pres = 1ull << u;
+      if (s == lo) f.dir = 1ull << u;
+    }
+    return f;
+  }
+  __device__ static BS<1> blift(uint8_t a) {
+    if (a == kNotTransfer) return bid();
+    const uint32_t s = a >> 4, d = a & 15;
+    BS<1> b{1u << d, 0, 0};
+    if (s != d) {
+      const uint32_t o = opair(s, d, E);
+      if (o < 64) b.lo = 1ull << o; else b.hi = 1ull << (o - 64);
+    }
+    return b;
+  }
+  __device__ static FS<1> fop(const FS<1>& a, const FS<1>& b) {
+    return FS<1>{a.dst | b.dst, a.pres | b.pres, (a.dir & ~b.pres) | b.dir};
+  }
+  __device__ static BS<1> bop(const BS<1>& a, const BS<1>& b) { return BS<1>{a.dst | b.dst, a.lo | b.lo, a.hi | b.hi}; }
+  __device__ static bool has_dst(const FS<1>& f, uint32_t d) { return (f.dst >> d) & 1; }
+  __device__ static bool has_dst(const BS<1>& b, uint32_t d) { return (b.dst >> d) & 1; }
+  __device__ static bool rx(const FS<1>& f, uint32_t s, uint32_t d) {
+    const uint32_t lo = min(s, d), hi = max(s, d), u = upair(lo, hi, E);
+    return ((f.pres >> u) & 1) && (((f.dir >> u) & 1) != (s == lo));
+  }
+  __device__ static bool tx(const BS<1>& b, uint32_t s, uint32_t d) {
+    const uint32_t o = opair(d, s, E);
+    return o < 64 ? ((b.lo >> o) & 1) : ((b.hi >> (o - 64)) & 1);
+  }
+  __device__ static FS<1> shfl_up(const FS<1>& x, int o) {
+    return FS<1>{(uint32_t)__shfl_up((int)x.dst, o, 64), __shfl_up(x.pres, o, 64), __shfl_up(x.dir, o, 64)};
+  }
+  __device__ static BS<1> shfl_down(const BS<1>& x, int o) {
+    return BS<1>{(uint32_t)__shfl_down((int)x.dst, o, 64), __shfl_down(x.lo, o, 64), __shfl_down(x.hi, o, 64)};
+  }
+  __device__ static FS<1> shfl(const FS<1>& x, int l) {
+    return FS<1>{(uint32_t)__shfl((int)x.dst, l, 64), __shfl(x.pres, l, 64), __shfl(x.dir, l, 64)};
+  }
+  __device__ static BS<1> shfl(const BS<1>& x, int l) {
+    return BS<1>{(uint32_t)__shfl((int)x.dst, l, 64), __shfl(x.lo, l, 64), __shfl(x.hi, l, 64)};
+  }
 };
-struct BwdSeg {
-  uint32_t f;  // a group ends inside
-  Bwd v;       // combination up to the first end
+
+// Carry records per wavefront (1,024 consecutive sorted elements).
+struct WaveAgg {
+  uint32_t ff, bf;   // a group starts (forward) / ends (backward) inside the wavefront
+  uint32_t fs[5];    // forward state since the last start
+  uint32_t bs[5];    // backward state up to the first end
 };
-// x before y
-__device__ __forceinline__ FwdSeg fseg_op(const FwdSeg& x, const FwdSeg& y) {
-  return FwdSeg{x.f | y.f, y.f ? y.v : fwd_op(x.v, y.v)};
+
+template <int MODE>
+__device__ __forceinline__ void put_f(uint32_t* w, const FS<MODE>& f);
+template <int MODE>
+__device__ __forceinline__ FS<MODE> get_f(const uint32_t* w);
+template <int MODE>
+__device__ __forceinline__ void put_b(uint32_t* w, const BS<MODE>& b);
+template <int MODE>
+__device__ __forceinline__ BS<MODE> get_b(const uint32_t* w);
+template <>
+__device__ __forceinline__ void put_f<0>(uint32_t* w, const FS<0>& f) { w[0] = f.w; }
+template <>
+__device__ __forceinline__ FS<0> get_f<0>(const uint32_t* w) { return FS<0>{w[0]}; }
+template <>
+__device__ __forceinline__ void put_b<0>(uint32_t* w, const BS<0>& b) { w[0] = b.w; }
+template <>
+__device__ __forceinline__ BS<0> get_b<0>(const uint32_t* w) { return BS<0>{w[0]}; }
+template <>
+__device__ __forceinline__ void put_f<1>(uint32_t* w, const FS<1>& f) {
+  w[0] = f.dst;
+  w[1] = (uint32_t)f.pres;
+  w[2] = (uint32_t)(f.pres >> 32);
+  w[3] = (uint32_t)f.dir;
+  w[4] = (uint32_t)(f.dir >> 32);
 }
-// x before y, combining towards x (y is later)
-__device__ __forceinline__ BwdSeg bseg_op(const BwdSeg& x, const BwdSeg& y) {
-  return BwdSeg{x.f | y.f, x.f ? x.v : bwd_op(x.v, y.v)};
+template <>
+__device__ __forceinline__ FS<1> get_f<1>(const uint32_t* w) {
+  return FS<1>{w[0], (uint64_t)w[1] | ((uint64_t)w[2] << 32), (uint64_t)w[3] | ((uint64_t)w[4] << 32)};
+}
+template <>
+__device__ __forceinline__ void put_b<1>(uint32_t* w, const BS<1>& b) {
+  w[0] = b.dst;
+  w[1] = (uint32_t)b.lo;
+  w[2] = (uint32_t)(b.lo >> 32);
+  w[3] = (uint32_t)b.hi;
+  w[4] = (uint32_t)(b.hi >> 32);
+}
+template <>
+__device__ __forceinline__ BS<1> get_b<1>(const uint32_t* w) {
+  return BS<1>{w[0], (uint64_t)w[1] | ((uint64_t)w[2] << 32), (uint64_t)w[3] | ((uint64_t)w[4] << 32)};
 }
 
 struct DDArgs {
@@ -647,194 +767,279 @@ struct DDArgs {
   uint32_t n;
   const uint8_t* aux;
   const SortJob* job;  // the digest job (keys/vals in buffer npasses & 1)
-  FwdSeg* tf;          // per tile
-  BwdSeg* tb;
-  FwdSeg* cf;          // carries per tile
-  BwdSeg* cb;
+  const AnaCtl* ctl;
+  WaveAgg* agg;        // per wavefront
+  WaveAgg* carry;      // per wavefront: forward carry-in / backward carry-in
   uint8_t* flags;
   odp_report* rep;
 };
 
-// Element j of the sorted order: group start / end flags.
-__device__ __forceinline__ bool is_head(const unsigned long long* k, uint32_t j) { return j == 0 || k[j] != k[j - 1]; }
-__device__ __forceinline__ bool is_tail(const unsigned long long* k, uint32_t j, uint32_t n) {
-  return j + 1 == n || k[j] != k[j + 1];
-}
+constexpr int kWaveElems = kTile / (kT / 64);  // 1,024
+constexpr int kRounds = kWaveElems / 64;       // 16
 
-// Block-wide exclusive scans of the threads' FwdSeg (forward) and BwdSeg
-// (backward, i.e. over later threads).
-__device__ void block_scan_fwd(FwdSeg& x) {
-  __shared__ FwdSeg sh[kT];
-  sh[threadIdx.x] = x;
-  __syncthreads();
-  for (int o = 1; o < kT; o <<= 1) {
-    FwdSeg y = x;
-    if (threadIdx.x >= (uint32_t)o) y = fseg_op(sh[threadIdx.x - o], x);
-    __syncthreads();
-    sh[threadIdx.x] = y;
-    x = y;
-    __syncthreads();
+// Inclusive segmented scans inside one round of 64 lanes.
+template <int MODE>
+__device__ __forceinline__ void wave_fscan(uint32_t& f, FS<MODE>& v) {
+  using S = St<MODE>;
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t fo = (uint32_t)__shfl_up((int)f, o, 64);
+    const FS<MODE> vo = S::shfl_up(v, o);
+    if (lane >= o) {
+      if (!f) v = S::fop(vo, v);
+      f |= fo;
+    }
   }
-  x = threadIdx.x ? sh[threadIdx.x - 1] : FwdSeg{0, fwd_id()};
-  __syncthreads();
 }
-__device__ void block_scan_bwd(BwdSeg& x) {
-  __shared__ BwdSeg sh[kT];
-  sh[threadIdx.x] = x;
-  __syncthreads();
-  for (int o = 1; o < kT; o <<= 1) {
-    BwdSeg y = x;
-    if (threadIdx.x + o < (uint32_t)kT) y = bseg_op(x, sh[threadIdx.x + o]);
-    __syncthreads();
-    sh[threadIdx.x] = y;
-    x = y;
-    __syncthreads();
-  }
-  x = threadIdx.x + 1 < (uint32_t)kT ? sh[threadIdx.x + 1] : BwdSeg{0, bwd_id()};
-  __syncthreads();
-}
-
-// Each thread owns kItems consecutive elements of the tile.
-__device__ void thread_aggs(const unsigned long long* k, const uint32_t* v, const uint8_t* aux, uint32_t n, uint32_t j0,
-                            FwdSeg& fa, BwdSeg& ba) {
-  fa = FwdSeg{0, fwd_id()};
-  for (int r = 0; r < kItems; ++r) {
-    const uint32_t j = j0 + r;
-    if (j >= n) break;
-    const Fwd x = fwd_lift(aux[v[j]]);
-    if (is_head(k, j)) fa = FwdSeg{1, x};
-    else fa.v = fwd_op(fa.v, x);
-  }
-  ba = BwdSeg{0, bwd_id()};
-  for (int r = kItems - 1; r >= 0; --r) {
-    const uint32_t j = j0 + r;
-    if (j >= n) continue;
-    const Bwd x = bwd_lift(aux[v[j]]);
-    if (is_tail(k, j, n)) ba = BwdSeg{1, x};
-    else ba.v = bwd_op(x, ba.v);
+template <int MODE>
+__device__ __forceinline__ void wave_bscan(uint32_t& f, BS<MODE>& v) {
+  using S = St<MODE>;
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t fo = (uint32_t)__shfl_down((int)f, o, 64);
+    const BS<MODE> vo = S::shfl_down(v, o);
+    if (lane + o < 64) {
+      if (!f) v = S::bop(v, vo);
+      f |= fo;
+    }
   }
 }
 
-__global__ __launch_bounds__(kT) void ddrt_tile_kernel(DDArgs A) {
+// Loads of one round: value, endpoint code, group start / end flags.
+__device__ __forceinline__ void load_round(const unsigned long long* k, const uint32_t* v, const uint8_t* aux,
+                                           uint32_t n, uint32_t j, uint32_t& val, uint8_t& a, bool& head,
+                                           bool& tail) {
+  const int lane = threadIdx.x & 63;
+  const bool in = j < n;
+  const unsigned long long key = in ? k[j] : 0ull;
+  unsigned long long prev = __shfl_up(key, 1, 64);
+  unsigned long long next = __shfl_down(key, 1, 64);
+  if (lane == 0 && in && j > 0) prev = k[j - 1];
+  if (lane == 63 && in && j + 1 < n) next = k[j + 1];
+  head = in && (j == 0 || prev != key);
+  tail = in && (j + 1 == n || next != key);
+  val = in ? v[j] : 0u;
+  a = in ? aux[val] : kNotTransfer;
+}
+
+template <int MODE>
+__device__ void ddrt_agg_body(const DDArgs& A) {
+  using S = St<MODE>;
   const SortJob& s = *A.job;
   const uint32_t buf = s.npasses & 1;
   const unsigned long long* k = s.keys[buf];
   const uint32_t* v = s.vals[buf];
-  const uint32_t j0 = blockIdx.x * kTile + threadIdx.x * kItems;
-  FwdSeg fa;
-  BwdSeg ba;
-  thread_aggs(k, v, A.aux, A.n, j0, fa, ba);
-  // tile aggregates: forward = combination of all threads; backward likewise
-  __shared__ FwdSeg shf[kT];
-  __shared__ BwdSeg shb[kT];
-  shf[threadIdx.x] = fa;
-  shb[threadIdx.x] = ba;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    FwdSeg f = shf[0];
-    for (int t = 1; t < kT; ++t) f = fseg_op(f, shf[t]);
-    A.tf[blockIdx.x] = f;
-  } else if (threadIdx.x == 64) {
-    BwdSeg b = shb[kT - 1];
-    for (int t = kT - 2; t >= 0; --t) b = bseg_op(shb[t], b);
-    A.tb[blockIdx.x] = b;
-  }
-}
-
-// Carries between tiles (one block): forward carry of tile t combines tiles
-// < t; backward carry combines tiles > t.
-__global__ __launch_bounds__(kT) void ddrt_carry_kernel(DDArgs A, uint32_t ntiles) {
-  __shared__ FwdSeg cf;
-  __shared__ BwdSeg cb;
-  // Each thread handles a contiguous run of tiles.
-  const uint32_t per = ceil_div32(ntiles, kT);
-  const uint32_t t0 = threadIdx.x * per;
-  FwdSeg f{0, fwd_id()};
-  for (uint32_t t = t0; t < min(ntiles, t0 + per); ++t) f = fseg_op(f, A.tf[t]);
-  BwdSeg b{0, bwd_id()};
-  for (uint32_t t = min(ntiles, t0 + per); t > t0; --t) b = bseg_op(A.tb[t - 1], b);
-  block_scan_fwd(f);
-  block_scan_bwd(b);
-  // f: combination of tiles before t0; b: combination of tiles after the run
-  FwdSeg run = f;
-  for (uint32_t t = t0; t < min(ntiles, t0 + per); ++t) {
-    A.cf[t] = run;
-    run = fseg_op(run, A.tf[t]);
-  }
-  BwdSeg runb = b;
-  for (uint32_t t = min(ntiles, t0 + per); t > t0; --t) {
-    A.cb[t - 1] = runb;
-    runb = bseg_op(A.tb[t - 1], runb);
-  }
-  (void)cf;
-  (void)cb;
-}
-
-__global__ __launch_bounds__(kT) void ddrt_final_kernel(DDArgs A) {
-  const SortJob& s = *A.job;
-  const uint32_t buf = s.npasses & 1;
-  const unsigned long long* k = s.keys[buf];
-  const uint32_t* v = s.vals[buf];
-  const uint32_t j0 = blockIdx.x * kTile + threadIdx.x * kItems;
-  FwdSeg fa;
-  BwdSeg ba;
-  thread_aggs(k, v, A.aux, A.n, j0, fa, ba);
-  block_scan_fwd(fa);
-  block_scan_bwd(ba);
-  // carry-in from other tiles
-  const FwdSeg tcf = A.cf[blockIdx.x];
-  const BwdSeg tcb = A.cb[blockIdx.x];
-  Fwd fin = fa.f ? fa.v : fwd_op(tcf.v, fa.v);       // state before this thread's first element
-  Bwd bin = ba.f ? ba.v : bwd_op(ba.v, tcb.v);       // state after this thread's last element
-  uint32_t res[kItems];
-  unsigned long long c_dd = 0, c_grp = 0, c_tx = 0, c_rx = 0, b_dd = 0, t_dd = 0, b_rx = 0, t_rx = 0;
-  Fwd st = fin;
-  for (int r = 0; r < kItems; ++r) {
-    const uint32_t j = j0 + r;
-    res[r] = 0;
-    if (j >= A.n) break;
-    if (is_head(k, j)) st = fwd_id();
-    const uint8_t a = A.aux[v[j]];
-    if (a != kNotTransfer) {
-      const uint32_t sr = a >> 4, d = a & 15;
-      if ((st.dst >> d) & 1) res[r] |= ODP_F_DD;
-      if (sr != d) {
-        const uint32_t lo = min(sr, d), hi = max(sr, d), bit = lo * kEp + hi;
-        if (u128_has(st.pres, bit) && (u128_has(st.dir, bit) != (sr == lo))) res[r] |= ODP_F_RT_RX;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint32_t wid = blockIdx.x * (kT / 64) + w;
+  const uint32_t wb = wid * kWaveElems;
+  uint32_t cf = 0, cb = 0;
+  FS<MODE> fv = S::fid();
+  BS<MODE> bv = S::bid();
+  bool first_tail_seen = false;
+  for (int r = 0; r < kRounds; ++r) {
+    const uint32_t j = wb + r * 64 + lane;
+    uint32_t val;
+    uint8_t a;
+    bool head, tail;
+    load_round(k, v, A.aux, A.n, j, val, a, head, tail);
+    uint32_t f = head;
+    FS<MODE> x = S::flift(a);
+    wave_fscan<MODE>(f, x);
+    const uint32_t f63 = (uint32_t)__shfl((int)f, 63, 64);
+    const FS<MODE> x63 = S::shfl(x, 63);
+    fv = f63 ? x63 : S::fop(fv, x63);
+    cf |= f63;
+    // backward aggregate: elements from the wave start up to its first group end
+    if (!first_tail_seen) {
+      uint32_t g = tail;
+      BS<MODE> y = S::blift(a);
+      wave_bscan<MODE>(g, y);
+      const uint32_t g0 = (uint32_t)__shfl((int)g, 0, 64);
+      const BS<MODE> y0 = S::shfl(y, 0);
+      bv = S::bop(bv, y0);
+      if (g0) {
+        cb = 1;
+        first_tail_seen = true;
       }
     }
-    st = fwd_op(st, fwd_lift(a));
   }
-  Bwd bt = bin;
-  for (int r = kItems - 1; r >= 0; --r) {
-    const uint32_t j = j0 + r;
-    if (j >= A.n) continue;
-    if (is_tail(k, j, A.n)) bt = bwd_id();
-    const uint32_t idx = v[j];
-    const uint8_t a = A.aux[idx];
+  if (lane == 0) {
+    WaveAgg& o = A.agg[wid];
+    o.ff = cf;
+    o.bf = cb;
+    put_f<MODE>(o.fs, fv);
+    put_b<MODE>(o.bs, bv);
+  }
+}
+
+__global__ __launch_bounds__(kT) void ddrt_agg_kernel(DDArgs A) {
+  if (A.ctl->max_ep < 4) ddrt_agg_body<0>(A); else ddrt_agg_body<1>(A);
+}
+
+// Carries between wavefronts (one block): forward carry-in of wavefront i
+// combines wavefronts < i; backward carry-in combines wavefronts > i.
+template <int MODE>
+__device__ void ddrt_carry_body(const DDArgs& A, uint32_t nw) {
+  using S = St<MODE>;
+  __shared__ uint32_t shf[kT];
+  __shared__ uint32_t shb[kT];
+  __shared__ uint32_t shfv[kT][5];
+  __shared__ uint32_t shbv[kT][5];
+  const uint32_t per = ceil_div32(nw, kT);
+  const uint32_t t0 = threadIdx.x * per, t1 = min(nw, t0 + per);
+  uint32_t ff = 0, bf = 0;
+  FS<MODE> fv = S::fid();
+  BS<MODE> bv = S::bid();
+  for (uint32_t t = t0; t < t1; ++t) {
+    const WaveAgg& g = A.agg[t];
+    fv = g.ff ? get_f<MODE>(g.fs) : S::fop(fv, get_f<MODE>(g.fs));
+    ff |= g.ff;
+  }
+  for (uint32_t t = t1; t > t0; --t) {
+    const WaveAgg& g = A.agg[t - 1];
+    if (g.bf) {
+      bv = get_b<MODE>(g.bs);
+      bf = 1;
+    } else {
+      bv = S::bop(get_b<MODE>(g.bs), bv);
+    }
+  }
+  shf[threadIdx.x] = ff;
+  shb[threadIdx.x] = bf;
+  put_f<MODE>(shfv[threadIdx.x], fv);
+  put_b<MODE>(shbv[threadIdx.x], bv);
+  __syncthreads();
+  // serial exclusive scans over the 256 run aggregates (thread 0 forward, thread 64 backward)
+  __shared__ uint32_t exf[kT], exb[kT];
+  __shared__ uint32_t exfv[kT][5], exbv[kT][5];
+  if (threadIdx.x == 0) {
+    uint32_t c = 0;
+    FS<MODE> cv = S::fid();
+    for (int t = 0; t < kT; ++t) {
+      exf[t] = c;
+      put_f<MODE>(exfv[t], cv);
+      const FS<MODE> x = get_f<MODE>(shfv[t]);
+      cv = shf[t] ? x : S::fop(cv, x);
+      c |= shf[t];
+    }
+  } else if (threadIdx.x == 64) {
+    uint32_t c = 0;
+    BS<MODE> cv = S::bid();
+    for (int t = kT - 1; t >= 0; --t) {
+      exb[t] = c;
+      put_b<MODE>(exbv[t], cv);
+      const BS<MODE> x = get_b<MODE>(shbv[t]);
+      cv = shb[t] ? x : S::bop(x, cv);
+      c |= shb[t];
+    }
+  }
+  __syncthreads();
+  FS<MODE> run = get_f<MODE>(exfv[threadIdx.x]);
+  for (uint32_t t = t0; t < t1; ++t) {
+    put_f<MODE>(A.carry[t].fs, run);
+    const WaveAgg& g = A.agg[t];
+    run = g.ff ? get_f<MODE>(g.fs) : S::fop(run, get_f<MODE>(g.fs));
+  }
+  BS<MODE> runb = get_b<MODE>(exbv[threadIdx.x]);
+  for (uint32_t t = t1; t > t0; --t) {
+    put_b<MODE>(A.carry[t - 1].bs, runb);
+    const WaveAgg& g = A.agg[t - 1];
+    runb = g.bf ? get_b<MODE>(g.bs) : S::bop(get_b<MODE>(g.bs), runb);
+  }
+  (void)exf;
+  (void)exb;
+}
+
+__global__ __launch_bounds__(kT) void ddrt_carry_kernel(DDArgs A, uint32_t nw) {
+  if (A.ctl->max_ep < 4) ddrt_carry_body<0>(A, nw); else ddrt_carry_body<1>(A, nw);
+}
+
+template <int MODE>
+__device__ void ddrt_final_body(const DDArgs& A) {
+  using S = St<MODE>;
+  const SortJob& s = *A.job;
+  const uint32_t buf = s.npasses & 1;
+  const unsigned long long* k = s.keys[buf];
+  const uint32_t* v = s.vals[buf];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint32_t wid = blockIdx.x * (kT / 64) + w;
+  const uint32_t wb = wid * kWaveElems;
+  // per round: value and endpoint code (LDS), start/end flags and forward results (bits)
+  __shared__ uint32_t s_val[kT / 64][kWaveElems];
+  __shared__ uint8_t s_code[kT / 64][kWaveElems];
+  uint32_t tails = 0, fres = 0;
+  FS<MODE> carry = get_f<MODE>(A.carry[wid].fs);
+#pragma unroll 1
+  for (int r = 0; r < kRounds; ++r) {
+    const uint32_t j = wb + r * 64 + lane;
+    uint32_t val;
+    uint8_t a;
+    bool head, tail;
+    load_round(k, v, A.aux, A.n, j, val, a, head, tail);
+    s_val[w][r * 64 + lane] = val;
+    s_code[w][r * 64 + lane] = a;
+    tails |= (uint32_t)tail << r;
+    uint32_t f = head;
+    FS<MODE> x = S::flift(a);
+    wave_fscan<MODE>(f, x);
+    // exclusive state of this lane
+    const uint32_t fp = (uint32_t)__shfl_up((int)f, 1, 64);
+    const FS<MODE> xp = S::shfl_up(x, 1);
+    FS<MODE> ex = lane == 0 ? carry : (fp ? xp : S::fop(carry, xp));
+    if (head) ex = S::fid();
     if (a != kNotTransfer) {
       const uint32_t sr = a >> 4, d = a & 15;
-      if (sr != d && u128_has(bt.pairs, d * kEp + sr)) res[r] |= ODP_F_RT_TX;
-      const bool leader = !(res[r] & ODP_F_DD) && ((bt.dst >> d) & 1);
-      c_grp += leader;
-      c_dd += (res[r] & ODP_F_DD) != 0;
-      c_tx += (res[r] & ODP_F_RT_TX) != 0;
-      c_rx += (res[r] & ODP_F_RT_RX) != 0;
-      if (res[r] & (ODP_F_DD | ODP_F_RT_RX)) {
+      if (S::has_dst(ex, d)) fres |= 1u << (2 * r);
+      if (sr != d && S::rx(ex, sr, d)) fres |= 2u << (2 * r);
+    }
+    const uint32_t f63 = (uint32_t)__shfl((int)f, 63, 64);
+    const FS<MODE> x63 = S::shfl(x, 63);
+    carry = f63 ? x63 : S::fop(carry, x63);
+  }
+  BS<MODE> bcarry = get_b<MODE>(A.carry[wid].bs);
+  unsigned long long c_dd = 0, c_grp = 0, c_tx = 0, c_rx = 0, b_dd = 0, t_dd = 0, b_rx = 0, t_rx = 0;
+#pragma unroll 1
+  for (int r = kRounds - 1; r >= 0; --r) {
+    const uint32_t j = wb + r * 64 + lane;
+    const uint8_t a = s_code[w][r * 64 + lane];
+    const bool tail = (tails >> r) & 1;
+    uint32_t g = tail;
+    BS<MODE> y = S::blift(a);
+    wave_bscan<MODE>(g, y);
+    const uint32_t gn = (uint32_t)__shfl_down((int)g, 1, 64);
+    const BS<MODE> yn = S::shfl_down(y, 1);
+    BS<MODE> ex = lane == 63 ? bcarry : (gn ? yn : S::bop(yn, bcarry));
+    if (tail) ex = S::bid();
+    if (j < A.n && a != kNotTransfer) {
+      const uint32_t sr = a >> 4, d = a & 15;
+      uint8_t res = 0;
+      if (fres & (1u << (2 * r))) res |= ODP_F_DD;
+      if (fres & (2u << (2 * r))) res |= ODP_F_RT_RX;
+      if (sr != d && S::tx(ex, sr, d)) res |= ODP_F_RT_TX;
+      c_grp += !(res & ODP_F_DD) && S::has_dst(ex, d);
+      c_dd += (res & ODP_F_DD) != 0;
+      c_tx += (res & ODP_F_RT_TX) != 0;
+      c_rx += (res & ODP_F_RT_RX) != 0;
+      const uint32_t idx = s_val[w][r * 64 + lane];
+      if (res & (ODP_F_DD | ODP_F_RT_RX)) {
         const odp_event& e = A.ev[idx];
         const uint64_t du = e.t_end - e.t_start;
-        if (res[r] & ODP_F_DD) {
+        if (res & ODP_F_DD) {
           b_dd += e.bytes;
           t_dd += du;
         }
-        if (res[r] & ODP_F_RT_RX) {
+        if (res & ODP_F_RT_RX) {
           b_rx += e.bytes;
           t_rx += du;
         }
       }
-      A.flags[idx] = (uint8_t)res[r];
+      A.flags[idx] = res;
     }
-    bt = bwd_op(bwd_lift(a), bt);
+    const uint32_t g0 = (uint32_t)__shfl((int)g, 0, 64);
+    const BS<MODE> y0 = S::shfl(y, 0);
+    bcarry = g0 ? y0 : S::bop(y0, bcarry);
   }
   block_add(&A.rep->dd_events, c_dd);
   block_add(&A.rep->dd_groups, c_grp);
@@ -844,6 +1049,10 @@ __global__ __launch_bounds__(kT) void ddrt_final_kernel(DDArgs A) {
   block_add(&A.rep->rt_rx_events, c_rx);
   block_add(&A.rep->rt_bytes, b_rx);
   block_add(&A.rep->rt_time_ns, t_rx);
+}
+
+__global__ __launch_bounds__(kT) void ddrt_final_kernel(DDArgs A) {
+  if (A.ctl->max_ep < 4) ddrt_final_body<0>(A); else ddrt_final_body<1>(A);
 }
 
 // ---------------------------------------------------------------------------
@@ -1106,8 +1315,8 @@ struct Views {
   uint64_t *pr_w_bytes, *pr_w_dev, *pr_w_haddr;
   uint32_t* hist;
   uint32_t* totals;
-  FwdSeg *tf, *cf;
-  BwdSeg *tb, *cb;
+  WaveAgg* agg;    // per wavefront of the digest job
+  WaveAgg* carry;
 };
 
 Views views(Workspace* ws) {
@@ -1153,10 +1362,8 @@ Views views(Workspace* ws) {
   v.hist = static_cast<uint32_t*>(b[B_HIST].ptr);
   v.totals = static_cast<uint32_t*>(b[B_TOTALS].ptr);
   char* ps = static_cast<char*>(b[B_SEG].ptr);
-  v.tf = carve<FwdSeg>(ps, v.ntc);
-  v.tb = carve<BwdSeg>(ps, v.ntc);
-  v.cf = carve<FwdSeg>(ps, v.ntc);
-  v.cb = carve<BwdSeg>(ps, v.ntc);
+  v.agg = carve<WaveAgg>(ps, (size_t)v.ntc * (kT / 64));
+  v.carry = carve<WaveAgg>(ps, (size_t)v.ntc * (kT / 64));
   return v;
 }
 
@@ -1239,7 +1446,7 @@ int analyze_reserve(Workspace* ws, size_t max_events) {
       (e = b[B_PR].ensure(cap * (4 + 4 + 8 + 8 + 8 + 4 + 4) + 64)) ||
       (e = b[B_HIST].ensure((size_t)kNumJobs * 256 * nt * 4)) ||
       (e = b[B_TOTALS].ensure((size_t)kNumJobs * kMaxPasses * 256 * 4)) ||
-      (e = b[B_SEG].ensure((size_t)nt * (2 * sizeof(FwdSeg) + 2 * sizeof(BwdSeg)) + 64)))
+      (e = b[B_SEG].ensure((size_t)nt * (kT / 64) * 2 * sizeof(WaveAgg) + 64)))
     return e;
   ws->a_cap_events = cap;
   SortJob hj[kNumJobs];
@@ -1308,14 +1515,13 @@ extern "C" int odp_analyze_trace(const odp_event* events, size_t n, uint8_t* out
   D.n = nn;
   D.aux = v.aux;
   D.job = v.jobs + kJobBig;
-  D.tf = v.tf;
-  D.tb = v.tb;
-  D.cf = v.cf;
-  D.cb = v.cb;
+  D.ctl = ctl;
+  D.agg = v.agg;
+  D.carry = v.carry;
   D.flags = out_flags;
   D.rep = out_report;
-  hipLaunchKernelGGL(ddrt_tile_kernel, dim3(nt), dim3(kT), 0, stream, D);
-  hipLaunchKernelGGL(ddrt_carry_kernel, dim3(1), dim3(kT), 0, stream, D, nt);
+  hipLaunchKernelGGL(ddrt_agg_kernel, dim3(nt), dim3(kT), 0, stream, D);
+  hipLaunchKernelGGL(ddrt_carry_kernel, dim3(1), dim3(kT), 0, stream, D, nt * (kT / 64));
   hipLaunchKernelGGL(ddrt_final_kernel, dim3(nt), dim3(kT), 0, stream, D);
 
   // Pairing and the pair list.
