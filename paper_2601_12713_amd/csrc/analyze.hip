@@ -33,6 +33,7 @@ namespace {
 constexpr int kT = 256;                 // threads per block
 constexpr int kItems = 16;              // elements per thread in a tile
 constexpr int kTile = kT * kItems;      // elements per tile
+constexpr int kWaveElems = kTile / (kT / 64);  // elements per wavefront of a tile
 constexpr int kMaxWords = 3;
 constexpr int kMaxPasses = 24;
 constexpr int kEp = 11;                 // endpoints: host (0) and devices 0..9 (1..10)
@@ -447,10 +448,24 @@ __global__ __launch_bounds__(kT) void sort_hist_kernel(JobSet J, uint32_t p) {
   __syncthreads();
   const uint32_t src = p & 1;
   const uint32_t b = tile * kTile;
-  for (uint32_t r = 0; r < (uint32_t)kItems; ++r) {
-    const uint32_t j = b + r * kT + threadIdx.x;
-    if (j < n) atomicAdd(&h[digit_of(*s, p, src, j)], 1u);
+  uint32_t d[kItems];
+  if (s->keys[0]) {
+    const uint32_t shift = s->ps[p];
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+      const uint32_t j = b + r * kT + threadIdx.x;
+      d[r] = j < n ? (uint32_t)(s->keys[src][j] >> shift) & 0xFF : 256u;
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+      const uint32_t j = b + r * kT + threadIdx.x;
+      d[r] = j < n ? digit_of(*s, p, src, j) : 256u;
+    }
   }
+#pragma unroll
+  for (int r = 0; r < kItems; ++r)
+    if (d[r] < 256u) atomicAdd(&h[d[r]], 1u);
   __syncthreads();
   const uint32_t c = h[threadIdx.x];
   s->hist[threadIdx.x * s->ntiles_max + tile] = c;
@@ -458,7 +473,8 @@ __global__ __launch_bounds__(kT) void sort_hist_kernel(JobSet J, uint32_t p) {
 }
 
 // One block per (job, digit): exclusive scan of the digit's row over tiles,
-// offset by the counts of all smaller digits.
+// offset by the counts of all smaller digits. Each thread sums a run of
+// consecutive tiles, the runs are scanned across the block, then written.
 __global__ __launch_bounds__(kT) void sort_scan_kernel(JobSet J, uint32_t p) {
   const uint32_t j = blockIdx.x / 256, d = blockIdx.x % 256;
   if (j >= J.njobs) return;
@@ -466,66 +482,78 @@ __global__ __launch_bounds__(kT) void sort_scan_kernel(JobSet J, uint32_t p) {
   if (p >= s.npasses) return;
   const uint32_t n = *s.n_ptr;
   const uint32_t nt = ceil_div32(n, kTile);
+  __shared__ uint32_t wsum[kT / 64];
   __shared__ uint32_t base;
-  __shared__ uint32_t sh[kT];
-  if (threadIdx.x == 0) {
-    uint32_t b = 0;
-    for (uint32_t x = 0; x < d; ++x) b += s.totals[p * 256 + x];
-    base = b;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  // digit base: counts of smaller digits
+  {
+    uint32_t x = threadIdx.x < d ? s.totals[p * 256 + threadIdx.x] : 0u;
+    for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
+    if (lane == 0) wsum[w] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) base = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    __syncthreads();
+  }
+  uint32_t* row = s.hist + (size_t)d * s.ntiles_max;
+  const uint32_t per = ceil_div32(nt, kT);
+  const uint32_t t0 = threadIdx.x * per, t1 = min(nt, t0 + per);
+  uint32_t run = 0;
+  for (uint32_t t = t0; t < t1; ++t) run += row[t];
+  // exclusive scan of the runs over the block
+  uint32_t x = run;
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
   }
   __syncthreads();
-  uint32_t* row = s.hist + (size_t)d * s.ntiles_max;
-  uint32_t carry = base;
-  for (uint32_t t0 = 0; t0 < nt; t0 += kT) {
-    const uint32_t t = t0 + threadIdx.x;
-    const uint32_t v = t < nt ? row[t] : 0;
-    sh[threadIdx.x] = v;
-    __syncthreads();
-    for (int o = 1; o < kT; o <<= 1) {
-      const uint32_t x = threadIdx.x >= (uint32_t)o ? sh[threadIdx.x - o] : 0;
-      __syncthreads();
-      sh[threadIdx.x] += x;
-      __syncthreads();
-    }
-    if (t < nt) row[t] = carry + sh[threadIdx.x] - v;
-    const uint32_t total = sh[kT - 1];
-    __syncthreads();
-    carry += total;
+  if (lane == 63) wsum[w] = x;
+  __syncthreads();
+  uint32_t before = base;
+  for (int q = 0; q < w; ++q) before += wsum[q];
+  before += x - run;
+  for (uint32_t t = t0; t < t1; ++t) {
+    const uint32_t c = row[t];
+    row[t] = before;
+    before += c;
   }
 }
 
-// Stable scatter: each wavefront ranks its 1,024 consecutive elements (16
-// rounds of 64) by digit with ballots; wavefronts are then offset by the
-// counts of earlier wavefronts, tiles by the scanned histogram.
+// Stable scatter. Each wavefront ranks its 1,024 consecutive elements (16
+// rounds of 64) by digit with ballots; the tile is then placed in digit
+// order in LDS and written out in that order, so the global writes form one
+// contiguous run per digit.
 __global__ __launch_bounds__(kT) void sort_scatter_kernel(JobSet J, uint32_t p) {
   const SortJob* s;
   uint32_t tile, n;
   if (!job_tile(J, p, s, tile, n)) return;
   __shared__ uint32_t wcnt[kT / 64][256];
-  __shared__ uint32_t base[kT / 64][256];
+  __shared__ uint32_t lbase[256];   // tile-local start of each digit
+  __shared__ uint32_t gbase[256];   // global start of each digit's run of this tile
+  __shared__ unsigned long long stage[kTile];
+  __shared__ uint8_t sdig[kTile];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   for (int x = 0; x < 256; x += 64) wcnt[w][x + lane] = 0;
   __syncthreads();
   const uint32_t src = p & 1, dst = src ^ 1;
-  const uint32_t wb = tile * kTile + w * (kTile / (kT / 64));
+  const uint32_t tb = tile * kTile;
+  const uint32_t wb = tb + w * kWaveElems;
+  const bool keyed = s->keys[0] != nullptr;
+  const uint32_t shift = s->ps[p];
   uint32_t dg[kItems], rk[kItems], vl[kItems];
   unsigned long long ky[kItems];
-  const bool keyed = s->keys[0] != nullptr;
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    const uint32_t j = wb + r * 64 + lane;
+    const bool in = j < n;
+    vl[r] = in ? s->vals[src][j] : 0u;
+    ky[r] = (in && keyed) ? s->keys[src][j] : 0ull;
+  }
 #pragma unroll
   for (int r = 0; r < kItems; ++r) {
     const uint32_t j = wb + r * 64 + lane;
     const bool in = j < n;
     uint32_t d = 0;
-    if (in) {
-      vl[r] = s->vals[src][j];
-      if (keyed) {
-        ky[r] = s->keys[src][j];
-        d = (uint32_t)(ky[r] >> s->ps[p]) & 0xFF;
-      } else {
-        d = (uint32_t)(s->words[s->pw[p]][vl[r]] >> s->ps[p]) & 0xFF;
-      }
-    }
-    // peers: lanes of this round holding the same digit
+    if (in) d = keyed ? (uint32_t)(ky[r] >> shift) & 0xFF : (uint32_t)(s->words[s->pw[p]][vl[r]] >> shift) & 0xFF;
     uint64_t peers = __ballot(in);
 #pragma unroll
     for (int bit = 0; bit < 8; ++bit) {
@@ -543,21 +571,56 @@ __global__ __launch_bounds__(kT) void sort_scatter_kernel(JobSet J, uint32_t p) 
   }
   __syncthreads();
   {
+    // per digit: counts of the wavefronts before, tile-local and global bases
     const uint32_t d = threadIdx.x;
-    uint32_t acc = s->hist[(size_t)d * s->ntiles_max + tile];
+    uint32_t c = 0;
     for (int x = 0; x < kT / 64; ++x) {
-      base[x][d] = acc;
-      acc += wcnt[x][d];
+      const uint32_t t = wcnt[x][d];
+      wcnt[x][d] = c;
+      c += t;
     }
+    // exclusive scan of the tile counts over digits
+    uint32_t xsc = c;
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(xsc, o, 64);
+      if (lane >= o) xsc += y;
+    }
+    __shared__ uint32_t ws[kT / 64];
+    if (lane == 63) ws[w] = xsc;
+    __syncthreads();
+    uint32_t pre = xsc - c;
+    for (int q = 0; q < w; ++q) pre += ws[q];
+    lbase[d] = pre;
+    gbase[d] = s->hist[(size_t)d * s->ntiles_max + tile];
   }
   __syncthreads();
+  const uint32_t cnt_tile = min(n - tb, (uint32_t)kTile);
+  // pass 1: values (and digits) into tile-local digit order
 #pragma unroll
   for (int r = 0; r < kItems; ++r) {
     const uint32_t j = wb + r * 64 + lane;
     if (j < n) {
-      const uint32_t pos = base[w][dg[r]] + rk[r];
-      s->vals[dst][pos] = vl[r];
-      if (keyed) s->keys[dst][pos] = ky[r];
+      const uint32_t lp = lbase[dg[r]] + wcnt[w][dg[r]] + rk[r];
+      reinterpret_cast<uint32_t*>(stage)[lp] = vl[r];
+      sdig[lp] = (uint8_t)dg[r];
+    }
+  }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < cnt_tile; i += kT) {
+    const uint32_t d = sdig[i];
+    s->vals[dst][gbase[d] + (i - lbase[d])] = reinterpret_cast<uint32_t*>(stage)[i];
+  }
+  if (keyed) {
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+      const uint32_t j = wb + r * 64 + lane;
+      if (j < n) stage[lbase[dg[r]] + wcnt[w][dg[r]] + rk[r]] = ky[r];
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < cnt_tile; i += kT) {
+      const uint32_t d = sdig[i];
+      s->keys[dst][gbase[d] + (i - lbase[d])] = stage[i];
     }
   }
 }
@@ -774,7 +837,6 @@ struct DDArgs {
   odp_report* rep;
 };
 
-constexpr int kWaveElems = kTile / (kT / 64);  // 1,024
 constexpr int kRounds = kWaveElems / 64;       // 16
 
 // Inclusive segmented scans inside one round of 64 lanes.
