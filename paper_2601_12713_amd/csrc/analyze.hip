@@ -34,6 +34,7 @@ constexpr int kT = 256;                 // threads per block
 constexpr int kItems = 16;              // elements per thread in a tile
 constexpr int kTile = kT * kItems;      // elements per tile
 constexpr int kWaveElems = kTile / (kT / 64);  // elements per wavefront of a tile
+constexpr int kRounds = kWaveElems / 64;       // rounds of 64 per wavefront
 constexpr int kMaxWords = 3;
 constexpr int kMaxPasses = 24;
 constexpr int kEp = 11;                 // endpoints: host (0) and devices 0..9 (1..10)
@@ -181,92 +182,82 @@ __global__ void init_kernel(AnaCtl* ctl, odp_report* rep, uint32_t* totals, uint
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ bool dev_ok(int d) { return d >= -1 && d <= ODP_MAX_DEVICE; }
 
+// One block per tile of kTile records; wavefront w takes the 1,024
+// consecutive records [tile*kTile + w*1024, ...) in 16 rounds of 64 and also
+// counts the ALLOC/DELETE and KERNEL records it sees (for the compaction).
 __global__ __launch_bounds__(kT) void classify_kernel(const odp_event* __restrict__ ev, uint32_t n, uint8_t* __restrict__ flags,
                                                       uint8_t* __restrict__ cls, uint8_t* __restrict__ aux,
                                                       unsigned long long* __restrict__ keys, uint32_t* __restrict__ vals,
-                                                      AnaCtl* ctl, odp_report* rep) {
+                                                      uint32_t* __restrict__ wave_cnt, AnaCtl* ctl, odp_report* rep) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint32_t wid = blockIdx.x * (kT / 64) + w;
+  const uint32_t wb = wid * kWaveElems;
   unsigned long long n_inv = 0, n_tx = 0, n_k = 0, kor = 0, kand = ~0ull;
-  uint32_t bad = kNone, mep = 0;
-  for (uint32_t i = blockIdx.x * kT + threadIdx.x; i < n; i += gridDim.x * kT) {
-    const odp_event e = ev[i];
-    const uint64_t prev_start = i ? ev[i - 1].t_start : 0;
-    const bool is_tx = e.op == ODP_H2D || e.op == ODP_D2H || e.op == ODP_D2D;
-    bool valid = e.op >= ODP_ALLOC && e.op <= ODP_KERNEL && e.t_end >= e.t_start && (i == 0 || e.t_start >= prev_start) &&
-                 dev_ok(e.dst_dev) && (!is_tx || dev_ok(e.src_dev));
-    uint8_t c = C_INVALID, a = kNotTransfer;
-    unsigned long long key = ~0ull;
-    if (valid) {
-      if (is_tx) {
-        c = C_TRANSFER;
-        a = (uint8_t)(((e.src_dev + 1) << 4) | (e.dst_dev + 1));
-        mep = max(mep, (uint32_t)max(e.src_dev + 1, e.dst_dev + 1));
-        key = e.digest;
-        ++n_tx;
-      } else if (e.op == ODP_KERNEL) {
-        c = C_KERNEL;
-        ++n_k;
+  uint32_t bad = kNone, mep = 0, c_ad = 0, c_k = 0;
+  for (int r = 0; r < kRounds; ++r) {
+    const uint32_t i = wb + r * 64 + lane;
+    const bool in = i < n;
+    odp_event e;
+    if (in) e = ev[i];
+    const uint64_t ts = in ? e.t_start : 0;
+    uint64_t prev_start = __shfl_up(ts, 1, 64);
+    if (lane == 0 && in && i > 0) prev_start = ev[i - 1].t_start;
+    if (in) {
+      const bool is_tx = e.op == ODP_H2D || e.op == ODP_D2H || e.op == ODP_D2D;
+      const bool valid = e.op >= ODP_ALLOC && e.op <= ODP_KERNEL && e.t_end >= e.t_start &&
+                         (i == 0 || e.t_start >= prev_start) && dev_ok(e.dst_dev) && (!is_tx || dev_ok(e.src_dev));
+      uint8_t c = C_INVALID, a = kNotTransfer;
+      unsigned long long key = ~0ull;
+      if (valid) {
+        if (is_tx) {
+          c = C_TRANSFER;
+          a = (uint8_t)(((e.src_dev + 1) << 4) | (e.dst_dev + 1));
+          mep = max(mep, (uint32_t)max(e.src_dev + 1, e.dst_dev + 1));
+          key = e.digest;
+          ++n_tx;
+        } else if (e.op == ODP_KERNEL) {
+          c = C_KERNEL;
+          ++n_k;
+          ++c_k;
+        } else {
+          c = C_ALLOCDEL;
+          ++c_ad;
+        }
       } else {
-        c = C_ALLOCDEL;
+        ++n_inv;
+        bad = min(bad, i);
       }
-    } else {
-      ++n_inv;
-      bad = min(bad, i);
+      flags[i] = valid ? 0 : ODP_F_INVALID;
+      cls[i] = c;
+      aux[i] = a;
+      keys[i] = key;
+      vals[i] = i;
+      kor |= key;
+      kand &= key;
     }
-    flags[i] = valid ? 0 : ODP_F_INVALID;
-    cls[i] = c;
-    aux[i] = a;
-    keys[i] = key;
-    vals[i] = i;
-    kor |= key;
-    kand &= key;
+  }
+  // per-wavefront subset counts
+  for (int o = 32; o >= 1; o >>= 1) {
+    c_ad += __shfl_xor(c_ad, o, 64);
+    c_k += __shfl_xor(c_k, o, 64);
+  }
+  if (lane == 0) {
+    wave_cnt[2 * wid] = c_ad;
+    wave_cnt[2 * wid + 1] = c_k;
   }
   block_add(&rep->n_invalid, n_inv);
   block_add(&rep->n_transfers, n_tx);
   block_add(&rep->n_kernels, n_k);
   block_mask(&ctl->m_digest, kor, kand, true);
-  // first rejected record
   for (int o = 32; o >= 1; o >>= 1) bad = min(bad, (uint32_t)__shfl_xor((int)bad, o, 64));
-  if ((threadIdx.x & 63) == 0 && bad != kNone) atomicMin(&ctl->first_bad, bad);
+  if (lane == 0 && bad != kNone) atomicMin(&ctl->first_bad, bad);
   for (int o = 32; o >= 1; o >>= 1) mep = max(mep, (uint32_t)__shfl_xor((int)mep, o, 64));
-  if ((threadIdx.x & 63) == 0 && mep) atomicMax(&ctl->max_ep, mep);
+  if (lane == 0 && mep) atomicMax(&ctl->max_ep, mep);
 }
 
 // ---------------------------------------------------------------------------
 // 2. Ordered compaction of the ALLOC/DELETE and KERNEL subsets.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kT) void subset_count_kernel(const uint8_t* __restrict__ cls, uint32_t n,
-                                                          uint32_t* __restrict__ tile_cnt) {
-  const uint32_t t = blockIdx.x;
-  const uint32_t b = t * kTile;
-  uint32_t cad = 0, ck = 0;
-  for (uint32_t j = threadIdx.x; j < (uint32_t)kTile; j += kT) {
-    const uint32_t i = b + j;
-    if (i < n) {
-      cad += cls[i] == C_ALLOCDEL;
-      ck += cls[i] == C_KERNEL;
-    }
-  }
-  __shared__ uint32_t s0[kT / 64], s1[kT / 64];
-  for (int o = 32; o >= 1; o >>= 1) {
-    cad += __shfl_xor(cad, o, 64);
-    ck += __shfl_xor(ck, o, 64);
-  }
-  if ((threadIdx.x & 63) == 0) {
-    s0[threadIdx.x >> 6] = cad;
-    s1[threadIdx.x >> 6] = ck;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t a = 0, k = 0;
-    for (int w = 0; w < kT / 64; ++w) {
-      a += s0[w];
-      k += s1[w];
-    }
-    tile_cnt[2 * t] = a;
-    tile_cnt[2 * t + 1] = k;
-  }
-}
-
 // Exclusive scan of pairs of u32 counters over `ntiles` tiles (one block).
 __global__ __launch_bounds__(1024) void scan_pairs_kernel(uint32_t* tile_cnt, uint32_t ntiles, uint32_t* tot0,
                                                           uint32_t* tot1) {
@@ -320,47 +311,32 @@ struct SubsetOut {
   uint32_t* k_vals_e;
 };
 
+// Wavefront w writes its records' subset entries at offsets from the scanned
+// per-wavefront counts, so no workgroup barrier is needed between rounds.
 __global__ __launch_bounds__(kT) void subset_scatter_kernel(const odp_event* __restrict__ ev, const uint8_t* __restrict__ cls,
-                                                            uint32_t n, const uint32_t* __restrict__ tile_cnt, SubsetOut S,
+                                                            uint32_t n, const uint32_t* __restrict__ wave_off, SubsetOut S,
                                                             AnaCtl* ctl) {
-  const uint32_t t = blockIdx.x;
-  const uint32_t b = t * kTile;
-  __shared__ uint32_t wc0[kT / 64], wc1[kT / 64];
-  __shared__ uint32_t run0, run1;
-  if (threadIdx.x == 0) {
-    run0 = tile_cnt[2 * t];
-    run1 = tile_cnt[2 * t + 1];
-  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint32_t wid = blockIdx.x * (kT / 64) + w;
+  const uint32_t wb = wid * kWaveElems;
+  uint32_t p0 = wave_off[2 * wid], p1 = wave_off[2 * wid + 1];
   unsigned long long o_dev = 0, a_dev = ~0ull, o_addr = 0, a_addr = ~0ull, o_ks = 0, a_ks = ~0ull, o_ke = 0,
                      a_ke = ~0ull, o_kd = 0, a_kd = ~0ull;
   bool any_ad = false, any_k = false;
-  __syncthreads();
-  const int w = threadIdx.x >> 6;
-  for (uint32_t r = 0; r < (uint32_t)kItems; ++r) {
-    const uint32_t i = b + r * kT + threadIdx.x;
+  for (int r = 0; r < kRounds; ++r) {
+    const uint32_t i = wb + r * 64 + lane;
     const uint8_t c = i < n ? cls[i] : C_INVALID;
     const uint64_t bad = __ballot(c == C_ALLOCDEL), bk = __ballot(c == C_KERNEL);
-    if ((threadIdx.x & 63) == 0) {
-      wc0[w] = __popcll(bad);
-      wc1[w] = __popcll(bk);
-    }
-    __syncthreads();
-    uint32_t p0 = run0, p1 = run1;
-    for (int x = 0; x < w; ++x) {
-      p0 += wc0[x];
-      p1 += wc1[x];
-    }
-    p0 += __popcll(bad & lanemask_lt());
-    p1 += __popcll(bk & lanemask_lt());
+    const uint32_t q0 = p0 + __popcll(bad & lanemask_lt()), q1 = p1 + __popcll(bk & lanemask_lt());
     if (c == C_ALLOCDEL) {
       const odp_event& e = ev[i];
       const uint64_t dv = (uint64_t)(e.dst_dev + 1), ad = e.dst_addr;
-      S.ad_idx[p0] = i;
-      S.ad_op[p0] = e.op;
-      S.ad_w_dev[p0] = dv;
-      S.ad_w_addr[p0] = ad;
-      S.ad_vals[p0] = p0;
-      S.ad_alloc_partner[p0] = kNone;
+      S.ad_idx[q0] = i;
+      S.ad_op[q0] = e.op;
+      S.ad_w_dev[q0] = dv;
+      S.ad_w_addr[q0] = ad;
+      S.ad_vals[q0] = q0;
+      S.ad_alloc_partner[q0] = kNone;
       o_dev |= dv;
       a_dev &= dv;
       o_addr |= ad;
@@ -369,12 +345,12 @@ __global__ __launch_bounds__(kT) void subset_scatter_kernel(const odp_event* __r
     } else if (c == C_KERNEL) {
       const odp_event& e = ev[i];
       const uint64_t dv = (uint64_t)(e.dst_dev + 1);
-      S.k_idx[p1] = i;
-      S.k_w_start[p1] = e.t_start;
-      S.k_w_end[p1] = e.t_end;
-      S.k_w_dev[p1] = dv;
-      S.k_vals_s[p1] = p1;
-      S.k_vals_e[p1] = p1;
+      S.k_idx[q1] = i;
+      S.k_w_start[q1] = e.t_start;
+      S.k_w_end[q1] = e.t_end;
+      S.k_w_dev[q1] = dv;
+      S.k_vals_s[q1] = q1;
+      S.k_vals_e[q1] = q1;
       o_ks |= e.t_start;
       a_ks &= e.t_start;
       o_ke |= e.t_end;
@@ -383,14 +359,8 @@ __global__ __launch_bounds__(kT) void subset_scatter_kernel(const odp_event* __r
       a_kd &= dv;
       any_k = true;
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      for (int x = 0; x < kT / 64; ++x) {
-        run0 += wc0[x];
-        run1 += wc1[x];
-      }
-    }
-    __syncthreads();
+    p0 += __popcll(bad);
+    p1 += __popcll(bk);
   }
   block_mask(&ctl->m_ad_dev, o_dev, a_dev, any_ad);
   block_mask(&ctl->m_ad_addr, o_addr, a_addr, any_ad);
@@ -467,14 +437,13 @@ __global__ __launch_bounds__(kT) void sort_hist_kernel(JobSet J, uint32_t p) {
   for (int r = 0; r < kItems; ++r)
     if (d[r] < 256u) atomicAdd(&h[d[r]], 1u);
   __syncthreads();
-  const uint32_t c = h[threadIdx.x];
-  s->hist[threadIdx.x * s->ntiles_max + tile] = c;
-  if (c) atomicAdd(&s->totals[p * 256 + threadIdx.x], c);
+  s->hist[threadIdx.x * s->ntiles_max + tile] = h[threadIdx.x];
 }
 
-// One block per (job, digit): exclusive scan of the digit's row over tiles,
-// offset by the counts of all smaller digits. Each thread sums a run of
-// consecutive tiles, the runs are scanned across the block, then written.
+// One block per (job, digit): exclusive scan of the digit's row over tiles;
+// the row total goes to totals[pass][digit] (the scatter adds the counts of
+// smaller digits). Each thread sums a run of consecutive tiles, the runs are
+// scanned across the block, then written back.
 __global__ __launch_bounds__(kT) void sort_scan_kernel(JobSet J, uint32_t p) {
   const uint32_t j = blockIdx.x / 256, d = blockIdx.x % 256;
   if (j >= J.njobs) return;
@@ -483,32 +452,20 @@ __global__ __launch_bounds__(kT) void sort_scan_kernel(JobSet J, uint32_t p) {
   const uint32_t n = *s.n_ptr;
   const uint32_t nt = ceil_div32(n, kTile);
   __shared__ uint32_t wsum[kT / 64];
-  __shared__ uint32_t base;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  // digit base: counts of smaller digits
-  {
-    uint32_t x = threadIdx.x < d ? s.totals[p * 256 + threadIdx.x] : 0u;
-    for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
-    if (lane == 0) wsum[w] = x;
-    __syncthreads();
-    if (threadIdx.x == 0) base = wsum[0] + wsum[1] + wsum[2] + wsum[3];
-    __syncthreads();
-  }
   uint32_t* row = s.hist + (size_t)d * s.ntiles_max;
   const uint32_t per = ceil_div32(nt, kT);
   const uint32_t t0 = threadIdx.x * per, t1 = min(nt, t0 + per);
   uint32_t run = 0;
   for (uint32_t t = t0; t < t1; ++t) run += row[t];
-  // exclusive scan of the runs over the block
   uint32_t x = run;
   for (int o = 1; o < 64; o <<= 1) {
     const uint32_t y = __shfl_up(x, o, 64);
     if (lane >= o) x += y;
   }
-  __syncthreads();
   if (lane == 63) wsum[w] = x;
   __syncthreads();
-  uint32_t before = base;
+  uint32_t before = 0;
   for (int q = 0; q < w; ++q) before += wsum[q];
   before += x - run;
   for (uint32_t t = t0; t < t1; ++t) {
@@ -516,6 +473,7 @@ __global__ __launch_bounds__(kT) void sort_scan_kernel(JobSet J, uint32_t p) {
     row[t] = before;
     before += c;
   }
+  if (threadIdx.x == kT - 1) s.totals[p * 256 + d] = before;
 }
 
 // Stable scatter. Each wavefront ranks its 1,024 consecutive elements (16
@@ -591,7 +549,19 @@ __global__ __launch_bounds__(kT) void sort_scatter_kernel(JobSet J, uint32_t p) 
     uint32_t pre = xsc - c;
     for (int q = 0; q < w; ++q) pre += ws[q];
     lbase[d] = pre;
-    gbase[d] = s->hist[(size_t)d * s->ntiles_max + tile];
+    // global start: counts of smaller digits over all tiles, plus earlier tiles of this digit
+    uint32_t tot = s->totals[p * 256 + d];
+    uint32_t y = tot;
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t z = __shfl_up(y, o, 64);
+      if (lane >= o) y += z;
+    }
+    __shared__ uint32_t wt[kT / 64];
+    if (lane == 63) wt[w] = y;
+    __syncthreads();
+    uint32_t gpre = y - tot;
+    for (int q = 0; q < w; ++q) gpre += wt[q];
+    gbase[d] = gpre + s->hist[(size_t)d * s->ntiles_max + tile];
   }
   __syncthreads();
   const uint32_t cnt_tile = min(n - tb, (uint32_t)kTile);
@@ -837,7 +807,6 @@ struct DDArgs {
   odp_report* rep;
 };
 
-constexpr int kRounds = kWaveElems / 64;       // 16
 
 // Inclusive segmented scans inside one round of 64 lanes.
 template <int MODE>
@@ -1369,6 +1338,7 @@ struct Views {
   unsigned long long* bk[2];
   uint32_t* bv[2];
   uint32_t* tile_cnt;
+  uint32_t* wave_cnt;
   SubsetOut S;
   uint32_t* ad_vals1;
   uint32_t* k_vals_s1;
@@ -1395,6 +1365,7 @@ Views views(Workspace* ws) {
   v.bv[0] = static_cast<uint32_t*>(b[B_BVAL0].ptr);
   v.bv[1] = static_cast<uint32_t*>(b[B_BVAL1].ptr);
   v.tile_cnt = static_cast<uint32_t*>(b[B_TILECNT].ptr);
+  v.wave_cnt = v.tile_cnt + 2 * (size_t)v.ntc;
   const size_t cap = v.cap;
   char* pa = static_cast<char*>(b[B_AD].ptr);
   v.S.ad_idx = carve<uint32_t>(pa, cap);
@@ -1502,7 +1473,7 @@ int analyze_reserve(Workspace* ws, size_t max_events) {
   if ((e = b[B_CTL].ensure(sizeof(AnaCtl))) || (e = b[B_JOBS].ensure(sizeof(SortJob) * kNumJobs)) ||
       (e = b[B_CLS].ensure(cap)) || (e = b[B_AUX].ensure(cap)) || (e = b[B_BKEY0].ensure(cap * 8)) ||
       (e = b[B_BKEY1].ensure(cap * 8)) || (e = b[B_BVAL0].ensure(cap * 4)) || (e = b[B_BVAL1].ensure(cap * 4)) ||
-      (e = b[B_TILECNT].ensure((size_t)nt * 8)) ||
+      (e = b[B_TILECNT].ensure((size_t)nt * 8 * (1 + kT / 64))) ||
       (e = b[B_AD].ensure(cap * (4 + 8 + 8 + 4 + 4 + 4 + 1) + 64)) ||
       (e = b[B_K].ensure(cap * (4 + 8 + 8 + 8 + 4 * 4) + 64)) ||
       (e = b[B_PR].ensure(cap * (4 + 4 + 8 + 8 + 8 + 4 + 4) + 64)) ||
@@ -1556,11 +1527,11 @@ extern "C" int odp_analyze_trace(const odp_event* events, size_t n, uint8_t* out
     hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(64), 0, stream, ctl, out_report);
     return check_hip(hipGetLastError(), "odp_analyze_trace launch");
   }
-  hipLaunchKernelGGL(classify_kernel, dim3(grid_map), dim3(kT), 0, stream, events, nn, out_flags, v.cls, v.aux,
-                     v.bk[0], v.bv[0], ctl, out_report);
-  hipLaunchKernelGGL(subset_count_kernel, dim3(nt), dim3(kT), 0, stream, v.cls, nn, v.tile_cnt);
-  hipLaunchKernelGGL(scan_pairs_kernel, dim3(1), dim3(1024), 0, stream, v.tile_cnt, nt, &ctl->n_ad, &ctl->n_k);
-  hipLaunchKernelGGL(subset_scatter_kernel, dim3(nt), dim3(kT), 0, stream, events, v.cls, nn, v.tile_cnt, v.S, ctl);
+  hipLaunchKernelGGL(classify_kernel, dim3(nt), dim3(kT), 0, stream, events, nn, out_flags, v.cls, v.aux, v.bk[0],
+                     v.bv[0], v.wave_cnt, ctl, out_report);
+  hipLaunchKernelGGL(scan_pairs_kernel, dim3(1), dim3(1024), 0, stream, v.wave_cnt, nt * (kT / 64), &ctl->n_ad,
+                     &ctl->n_k);
+  hipLaunchKernelGGL(subset_scatter_kernel, dim3(nt), dim3(kT), 0, stream, events, v.cls, nn, v.wave_cnt, v.S, ctl);
 
   // Sort round 1: digests, ALLOC/DELETE, kernel starts, kernel ends.
   const JobSet J1{v.jobs, 4, nt};
