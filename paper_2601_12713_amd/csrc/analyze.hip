@@ -63,8 +63,10 @@ struct AnaCtl {
   uint32_t dev_lo[kEp], dev_hi[kEp];  // per-device ranges in the sorted kernel order
 };
 
-// One radix sort job: either "keyed" (64-bit keys move with the values) or
-// "gathered" (only values move; a digit is read from words[w][value]).
+// One radix sort job. 64-bit keys move with the values; a job lists its key
+// words least significant first. A word with words[w] != null is gathered by
+// value (words[w][value]) on the first pass that uses it; the big job's only
+// word is written into keys[0] before the sort.
 struct SortJob {
   const uint32_t* n_ptr;
   unsigned long long* keys[2];
@@ -78,6 +80,7 @@ struct SortJob {
   uint32_t* totals;                // [kMaxPasses][256]
   uint32_t npasses;                // device-computed
   uint8_t pw[kMaxPasses], ps[kMaxPasses];
+  uint8_t pg[kMaxPasses];          // 1: this pass reads its key word from words[pw] by value
 };
 
 struct JobSet {
@@ -194,14 +197,21 @@ __global__ __launch_bounds__(kT) void classify_kernel(const odp_event* __restric
   const uint32_t wb = wid * kWaveElems;
   unsigned long long n_inv = 0, n_tx = 0, n_k = 0, kor = 0, kand = ~0ull;
   uint32_t bad = kNone, mep = 0, c_ad = 0, c_k = 0;
+  // records of the next round are loaded while this round is classified; the
+  // previous record of lane 0 is lane 63 of the round before
+  odp_event e;
+  bool in = wb + lane < n;
+  if (in) e = ev[wb + lane];
+  uint64_t last_prev = (lane == 0 && in && wb > 0) ? ev[wb - 1].t_start : 0;
   for (int r = 0; r < kRounds; ++r) {
     const uint32_t i = wb + r * 64 + lane;
-    const bool in = i < n;
-    odp_event e;
-    if (in) e = ev[i];
+    const bool in_next = r + 1 < kRounds && i + 64 < n;
+    odp_event nx;
+    if (in_next) nx = ev[i + 64];
     const uint64_t ts = in ? e.t_start : 0;
     uint64_t prev_start = __shfl_up(ts, 1, 64);
-    if (lane == 0 && in && i > 0) prev_start = ev[i - 1].t_start;
+    if (lane == 0) prev_start = last_prev;
+    last_prev = __shfl(ts, 63, 64);
     if (in) {
       const bool is_tx = e.op == ODP_H2D || e.op == ODP_D2H || e.op == ODP_D2D;
       const bool valid = e.op >= ODP_ALLOC && e.op <= ODP_KERNEL && e.t_end >= e.t_start &&
@@ -235,6 +245,8 @@ __global__ __launch_bounds__(kT) void classify_kernel(const odp_event* __restric
       kor |= key;
       kand &= key;
     }
+    e = nx;
+    in = in_next;
   }
   // per-wavefront subset counts
   for (int o = 32; o >= 1; o >>= 1) {
@@ -318,17 +330,39 @@ __global__ __launch_bounds__(kT) void subset_scatter_kernel(const odp_event* __r
                                                             AnaCtl* ctl) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const uint32_t wid = blockIdx.x * (kT / 64) + w;
-  const uint32_t wb = wid * kWaveElems;
-  uint32_t p0 = wave_off[2 * wid], p1 = wave_off[2 * wid + 1];
+  // lane l owns the 16 consecutive records wid*1024 + 16l .. +15
+  const uint32_t b0 = wid * kWaveElems + lane * 16;
+  uint8_t c[16];
+  if (b0 + 16 <= n) {
+    const uint4 v = *reinterpret_cast<const uint4*>(cls + b0);
+    const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int k = 0; k < 16; ++k) c[k] = (uint8_t)(wv[k >> 2] >> (8 * (k & 3)));
+  } else {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) c[k] = b0 + k < n ? cls[b0 + k] : C_INVALID;
+  }
+  uint32_t nad = 0, nk = 0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    nad += c[k] == C_ALLOCDEL;
+    nk += c[k] == C_KERNEL;
+  }
+  // exclusive scans over the lanes
+  uint32_t xa = nad, xk = nk;
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t ya = __shfl_up(xa, o, 64), yk = __shfl_up(xk, o, 64);
+    if (lane >= o) {
+      xa += ya;
+      xk += yk;
+    }
+  }
+  uint32_t q0 = wave_off[2 * wid] + xa - nad, q1 = wave_off[2 * wid + 1] + xk - nk;
   unsigned long long o_dev = 0, a_dev = ~0ull, o_addr = 0, a_addr = ~0ull, o_ks = 0, a_ks = ~0ull, o_ke = 0,
                      a_ke = ~0ull, o_kd = 0, a_kd = ~0ull;
-  bool any_ad = false, any_k = false;
-  for (int r = 0; r < kRounds; ++r) {
-    const uint32_t i = wb + r * 64 + lane;
-    const uint8_t c = i < n ? cls[i] : C_INVALID;
-    const uint64_t bad = __ballot(c == C_ALLOCDEL), bk = __ballot(c == C_KERNEL);
-    const uint32_t q0 = p0 + __popcll(bad & lanemask_lt()), q1 = p1 + __popcll(bk & lanemask_lt());
-    if (c == C_ALLOCDEL) {
+  for (int k = 0; k < 16; ++k) {
+    const uint32_t i = b0 + k;
+    if (c[k] == C_ALLOCDEL) {
       const odp_event& e = ev[i];
       const uint64_t dv = (uint64_t)(e.dst_dev + 1), ad = e.dst_addr;
       S.ad_idx[q0] = i;
@@ -341,8 +375,8 @@ __global__ __launch_bounds__(kT) void subset_scatter_kernel(const odp_event* __r
       a_dev &= dv;
       o_addr |= ad;
       a_addr &= ad;
-      any_ad = true;
-    } else if (c == C_KERNEL) {
+      ++q0;
+    } else if (c[k] == C_KERNEL) {
       const odp_event& e = ev[i];
       const uint64_t dv = (uint64_t)(e.dst_dev + 1);
       S.k_idx[q1] = i;
@@ -357,16 +391,14 @@ __global__ __launch_bounds__(kT) void subset_scatter_kernel(const odp_event* __r
       a_ke &= e.t_end;
       o_kd |= dv;
       a_kd &= dv;
-      any_k = true;
+      ++q1;
     }
-    p0 += __popcll(bad);
-    p1 += __popcll(bk);
   }
-  block_mask(&ctl->m_ad_dev, o_dev, a_dev, any_ad);
-  block_mask(&ctl->m_ad_addr, o_addr, a_addr, any_ad);
-  block_mask(&ctl->m_k_start, o_ks, a_ks, any_k);
-  block_mask(&ctl->m_k_end, o_ke, a_ke, any_k);
-  block_mask(&ctl->m_k_dev, o_kd, a_kd, any_k);
+  block_mask(&ctl->m_ad_dev, o_dev, a_dev, nad > 0);
+  block_mask(&ctl->m_ad_addr, o_addr, a_addr, nad > 0);
+  block_mask(&ctl->m_k_start, o_ks, a_ks, nk > 0);
+  block_mask(&ctl->m_k_end, o_ke, a_ke, nk > 0);
+  block_mask(&ctl->m_k_dev, o_kd, a_kd, nk > 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -380,10 +412,13 @@ __global__ void sort_plan_kernel(JobSet J) {
   for (uint32_t w = 0; w < s.nwords; ++w) {
     // bits that are 1 in some key and 0 in another (0 when there are no keys)
     const unsigned long long var = s.masks[w]->vor & ~s.masks[w]->vand;
+    bool first = true;
     for (uint32_t b = 0; b < s.word_bytes[w]; ++b)
       if ((var >> (8 * b)) & 0xFF) {
         s.pw[np] = (uint8_t)w;
         s.ps[np] = (uint8_t)(8 * b);
+        s.pg[np] = (uint8_t)(first && s.words[w] != nullptr);
+        first = false;
         ++np;
       }
   }
@@ -402,11 +437,11 @@ __device__ __forceinline__ bool job_tile(const JobSet& J, uint32_t p, const Sort
   return p < c.npasses && (uint64_t)tile * kTile < n && tile < c.ntiles_max;
 }
 
-__device__ __forceinline__ uint32_t digit_of(const SortJob& s, uint32_t p, uint32_t src, uint32_t j) {
-  const uint32_t shift = s.ps[p];
-  if (s.keys[0]) return (uint32_t)(s.keys[src][j] >> shift) & 0xFF;
-  const uint32_t v = s.vals[src][j];
-  return (uint32_t)(s.words[s.pw[p]][v] >> shift) & 0xFF;
+// The key of element j for pass p: gathered from the pass's word on the
+// first pass of that word, else carried in keys[src].
+__device__ __forceinline__ unsigned long long key_of(const SortJob& s, uint32_t p, uint32_t src, uint32_t j) {
+  if (s.pg[p]) return s.words[s.pw[p]][s.vals[src][j]];
+  return s.keys[src][j];
 }
 
 __global__ __launch_bounds__(kT) void sort_hist_kernel(JobSet J, uint32_t p) {
@@ -419,19 +454,11 @@ __global__ __launch_bounds__(kT) void sort_hist_kernel(JobSet J, uint32_t p) {
   const uint32_t src = p & 1;
   const uint32_t b = tile * kTile;
   uint32_t d[kItems];
-  if (s->keys[0]) {
-    const uint32_t shift = s->ps[p];
+  const uint32_t shift = s->ps[p];
 #pragma unroll
-    for (int r = 0; r < kItems; ++r) {
-      const uint32_t j = b + r * kT + threadIdx.x;
-      d[r] = j < n ? (uint32_t)(s->keys[src][j] >> shift) & 0xFF : 256u;
-    }
-  } else {
-#pragma unroll
-    for (int r = 0; r < kItems; ++r) {
-      const uint32_t j = b + r * kT + threadIdx.x;
-      d[r] = j < n ? digit_of(*s, p, src, j) : 256u;
-    }
+  for (int r = 0; r < kItems; ++r) {
+    const uint32_t j = b + r * kT + threadIdx.x;
+    d[r] = j < n ? (uint32_t)(key_of(*s, p, src, j) >> shift) & 0xFF : 256u;
   }
 #pragma unroll
   for (int r = 0; r < kItems; ++r)
@@ -495,8 +522,9 @@ __global__ __launch_bounds__(kT) void sort_scatter_kernel(JobSet J, uint32_t p) 
   const uint32_t src = p & 1, dst = src ^ 1;
   const uint32_t tb = tile * kTile;
   const uint32_t wb = tb + w * kWaveElems;
-  const bool keyed = s->keys[0] != nullptr;
   const uint32_t shift = s->ps[p];
+  const bool gather = s->pg[p] != 0;
+  const uint64_t* word = s->words[s->pw[p]];
   uint32_t dg[kItems], rk[kItems], vl[kItems];
   unsigned long long ky[kItems];
 #pragma unroll
@@ -504,14 +532,20 @@ __global__ __launch_bounds__(kT) void sort_scatter_kernel(JobSet J, uint32_t p) 
     const uint32_t j = wb + r * 64 + lane;
     const bool in = j < n;
     vl[r] = in ? s->vals[src][j] : 0u;
-    ky[r] = (in && keyed) ? s->keys[src][j] : 0ull;
+    ky[r] = (in && !gather) ? s->keys[src][j] : 0ull;
+  }
+  if (gather) {
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+      const uint32_t j = wb + r * 64 + lane;
+      if (j < n) ky[r] = word[vl[r]];
+    }
   }
 #pragma unroll
   for (int r = 0; r < kItems; ++r) {
     const uint32_t j = wb + r * 64 + lane;
     const bool in = j < n;
-    uint32_t d = 0;
-    if (in) d = keyed ? (uint32_t)(ky[r] >> shift) & 0xFF : (uint32_t)(s->words[s->pw[p]][vl[r]] >> shift) & 0xFF;
+    const uint32_t d = in ? (uint32_t)(ky[r] >> shift) & 0xFF : 0u;
     uint64_t peers = __ballot(in);
 #pragma unroll
     for (int bit = 0; bit < 8; ++bit) {
@@ -580,18 +614,16 @@ __global__ __launch_bounds__(kT) void sort_scatter_kernel(JobSet J, uint32_t p) 
     const uint32_t d = sdig[i];
     s->vals[dst][gbase[d] + (i - lbase[d])] = reinterpret_cast<uint32_t*>(stage)[i];
   }
-  if (keyed) {
-    __syncthreads();
+  __syncthreads();
 #pragma unroll
-    for (int r = 0; r < kItems; ++r) {
-      const uint32_t j = wb + r * 64 + lane;
-      if (j < n) stage[lbase[dg[r]] + wcnt[w][dg[r]] + rk[r]] = ky[r];
-    }
-    __syncthreads();
-    for (uint32_t i = threadIdx.x; i < cnt_tile; i += kT) {
-      const uint32_t d = sdig[i];
-      s->keys[dst][gbase[d] + (i - lbase[d])] = stage[i];
-    }
+  for (int r = 0; r < kItems; ++r) {
+    const uint32_t j = wb + r * 64 + lane;
+    if (j < n) stage[lbase[dg[r]] + wcnt[w][dg[r]] + rk[r]] = ky[r];
+  }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < cnt_tile; i += kT) {
+    const uint32_t d = sdig[i];
+    s->keys[dst][gbase[d] + (i - lbase[d])] = stage[i];
   }
 }
 
@@ -1314,7 +1346,7 @@ __global__ void finalize_kernel(AnaCtl* ctl, odp_report* rep) {
 // ---------------------------------------------------------------------------
 enum Buf {
   B_CTL, B_JOBS, B_CLS, B_AUX, B_BKEY0, B_BKEY1, B_BVAL0, B_BVAL1, B_TILECNT, B_AD, B_K, B_PR, B_HIST,
-  B_TOTALS, B_SEG
+  B_TOTALS, B_SEG, B_SKEY
 };
 
 constexpr int kJobBig = 0, kJobAd = 1, kJobKs = 2, kJobKe = 3, kJobPr = 4, kNumJobs = 5;
@@ -1349,6 +1381,7 @@ struct Views {
   uint32_t* totals;
   WaveAgg* agg;    // per wavefront of the digest job
   WaveAgg* carry;
+  unsigned long long* skey[8];  // key ping-pong of the four subset jobs
 };
 
 Views views(Workspace* ws) {
@@ -1397,6 +1430,8 @@ Views views(Workspace* ws) {
   char* ps = static_cast<char*>(b[B_SEG].ptr);
   v.agg = carve<WaveAgg>(ps, (size_t)v.ntc * (kT / 64));
   v.carry = carve<WaveAgg>(ps, (size_t)v.ntc * (kT / 64));
+  char* pkey = static_cast<char*>(b[B_SKEY].ptr);
+  for (int i = 0; i < 8; ++i) v.skey[i] = carve<unsigned long long>(pkey, cap);
   return v;
 }
 
@@ -1455,6 +1490,10 @@ void build_jobs(const Views& v, SortJob* hj) {
   hj[kJobPr].masks[2] = &ctl->m_p_haddr;
   hj[kJobPr].word_bytes[2] = 8;
   hj[kJobPr].nwords = 3;
+  for (int j = 1; j < kNumJobs; ++j) {
+    hj[j].keys[0] = v.skey[2 * (j - 1)];
+    hj[j].keys[1] = v.skey[2 * (j - 1) + 1];
+  }
   for (int j = 0; j < kNumJobs; ++j) {
     hj[j].ntiles_max = v.ntc;
     hj[j].hist = v.hist + (size_t)j * 256 * v.ntc;
@@ -1479,7 +1518,8 @@ int analyze_reserve(Workspace* ws, size_t max_events) {
       (e = b[B_PR].ensure(cap * (4 + 4 + 8 + 8 + 8 + 4 + 4) + 64)) ||
       (e = b[B_HIST].ensure((size_t)kNumJobs * 256 * nt * 4)) ||
       (e = b[B_TOTALS].ensure((size_t)kNumJobs * kMaxPasses * 256 * 4)) ||
-      (e = b[B_SEG].ensure((size_t)nt * (kT / 64) * 2 * sizeof(WaveAgg) + 64)))
+      (e = b[B_SEG].ensure((size_t)nt * (kT / 64) * 2 * sizeof(WaveAgg) + 64)) ||
+      (e = b[B_SKEY].ensure(cap * 8 * 8 + 64)))
     return e;
   ws->a_cap_events = cap;
   SortJob hj[kNumJobs];
