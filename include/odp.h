@@ -191,6 +191,75 @@ int odp_analyze_trace(const odp_event* events, size_t n, uint8_t* out_flags, odp
                       odp_stream_t stream);
 
 /* ---------------------------------------------------------------------------
+ * Serving: mapping-event requests classified as they arrive.
+ *
+ * A request is one odp_event plus, for a transfer, the device-resident bytes it
+ * moved (the digest field is then filled from those bytes). Requests are
+ * admitted into ticks as slots and the in-flight byte budget allow; a tick is
+ * one batched digest of its payloads and one classification against
+ * device-resident per-key state, appended to a device-resident log.
+ * Flags known at arrival (DD, RT_RX, PAIRED) are exact per tick; flags that
+ * depend on later records (RT_TX, RA, UA) are resolved when the server is
+ * drained, by the analysis of the whole log in arrival order (Secs. 3.2-3.4
+ * define the rules; the paper analyses post mortem, serving is an extension).
+ * Errors: every call returns an ODP_* code; on failure the message is in
+ * odp_last_error_string(). A server belongs to one host thread.
+ * ------------------------------------------------------------------------ */
+typedef struct odp_server odp_server;
+
+enum {
+  ODP_SERVER_BATCHED = 0, /* continuous batching: ticks of up to max_tick requests */
+  ODP_SERVER_PLAIN = 1    /* one request per tick, one tick in flight, per-buffer digest launches */
+};
+
+typedef struct odp_server_config {
+  uint64_t max_events;   /* records over the server's life (log capacity), 1 .. 2^32 - 1 */
+  uint64_t budget_bytes; /* in-flight payload bytes admitted at most */
+  uint32_t max_inflight; /* in-flight requests admitted at most (slots) */
+  uint32_t max_tick;     /* records per tick, 1 .. 1024 */
+  uint32_t mode;         /* ODP_SERVER_BATCHED or ODP_SERVER_PLAIN */
+  uint32_t reserved;     /* 0 */
+} odp_server_config;
+
+typedef struct odp_server_stats {
+  double seconds;        /* wall time of the run */
+  uint64_t ticks;        /* ticks launched */
+  uint64_t max_tick;     /* largest tick */
+  uint64_t bytes;        /* payload bytes digested */
+  uint64_t budget_waits; /* requests whose admission waited for the byte budget */
+} odp_server_stats;
+
+/* Creates a server on the current device with its own stream; allocates the
+ * log (64 B per record), three state tables (32 B x 2 x max_events each,
+ * rounded up to a power of two) and the digest workspace for budget_bytes.
+ * *out is owned by the caller until odp_server_destroy. */
+int odp_server_create(const odp_server_config* cfg, odp_server** out);
+
+/* Runs an open-loop schedule to completion. All arrays are HOST arrays of n:
+ *   events         the records (arrival order)
+ *   payload_ptrs   device address of the bytes each record moved, or 0
+ *   payload_bytes  their length (a request above budget_bytes is rejected)
+ *   arrival_ns     scheduled arrival, ns after the call starts, non-decreasing
+ *   complete_ns    out: when the request's tick was seen complete, ns after start
+ * Blocks until every request is complete. Requests keep arrival order in the
+ * log across calls. */
+int odp_server_run(odp_server* s, const odp_event* events, const uint64_t* payload_ptrs, const uint64_t* payload_bytes,
+                   const uint64_t* arrival_ns, size_t n, uint64_t* complete_ns, odp_server_stats* stats);
+
+/* Waits for the server, then (each optional, DEVICE arrays of the logged count):
+ * out_imm gets the flags known at arrival; out_flags/out_report get the
+ * analysis of the whole log (both or neither). ODP_ECAPACITY if a state table
+ * ran full. */
+int odp_server_drain(odp_server* s, uint8_t* out_imm, uint8_t* out_flags, odp_report* out_report);
+
+/* Copies the logged records (digests filled in) to DEVICE out_events (may be
+ * NULL) and their count to *n. */
+int odp_server_log(odp_server* s, odp_event* out_events, size_t* n);
+
+/* Waits for the server and frees everything it holds; NULL is a no-op. */
+int odp_server_destroy(odp_server* s);
+
+/* ---------------------------------------------------------------------------
  * Helpers (workspace, tuning, status). Not part of the method.
  * ------------------------------------------------------------------------ */
 

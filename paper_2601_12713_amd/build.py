@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libodp.so")
-SOURCES = ["runtime.hip", "digest.hip", "analyze.hip"]
+SOURCES = ["runtime.hip", "digest.hip", "analyze.hip", "serve.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

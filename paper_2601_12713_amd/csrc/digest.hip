@@ -712,6 +712,18 @@ extern "C" int odp_digest_buffers(const void* const* ptrs, const uint64_t* sizes
   return ODP_OK;
 }
 
+namespace odp {
+int digest_batched_direct(const void* const* ptrs, const uint64_t* sizes, size_t n, uint64_t* out, hipStream_t stream) {
+  if (n == 0) return ODP_OK;
+  int err = 0;
+  Workspace* ws = workspace_for(stream, &err);
+  if (!ws) return err;
+  if (n > ws->cap_buffers || !ws->cap_items)
+    return set_error(ODP_ENOMEM, "digest: workspace for %zu buffers not reserved", n);
+  return enqueue_batched(ws, ptrs, sizes, n, out, stream);
+}
+}  // namespace odp
+
 extern "C" int odp_digest_buffers_plain(const void* const* host_ptrs, const uint64_t* host_sizes, size_t n,
                                         uint64_t* out, odp_stream_t stream_) {
   hipStream_t stream = static_cast<hipStream_t>(stream_);

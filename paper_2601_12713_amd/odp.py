@@ -29,7 +29,8 @@ REPORT_BYTES = 8 * len(REPORT_FIELDS) + 8
 EXPORTS = [
     "odp_digest_buffers", "odp_digest_buffers_plain", "odp_analyze_trace", "odp_version",
     "odp_last_error_string", "odp_reserve", "odp_release", "odp_device_status",
-    "odp_get_tuning", "odp_set_tuning",
+    "odp_get_tuning", "odp_set_tuning", "odp_server_create", "odp_server_run", "odp_server_drain",
+    "odp_server_log", "odp_server_destroy",
 ]
 
 
@@ -68,7 +69,7 @@ def load(path=LIB_PATH):
     L.odp_get_tuning.argtypes = [ctypes.POINTER(Tuning)]
     L.odp_set_tuning.argtypes = [ctypes.POINTER(Tuning)]
     for f in EXPORTS:
-        if f != "odp_last_error_string":
+        if f != "odp_last_error_string" and not f.startswith("odp_server"):
             getattr(L, f).restype = i32
     _lib = L
     return L
@@ -175,3 +176,95 @@ def set_tuning(blocks_per_cu=None, use_graph=None):
 
 def version():
     return int(load().odp_version())
+
+
+# ---------------------------------------------------------------------------
+# Serving
+# ---------------------------------------------------------------------------
+class _ServerConfig(ctypes.Structure):
+    _fields_ = [("max_events", ctypes.c_uint64), ("budget_bytes", ctypes.c_uint64),
+                ("max_inflight", ctypes.c_uint32), ("max_tick", ctypes.c_uint32),
+                ("mode", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+SERVER_BATCHED, SERVER_PLAIN = 0, 1
+
+
+class _ServerStats(ctypes.Structure):
+    _fields_ = [("seconds", ctypes.c_double), ("ticks", ctypes.c_uint64), ("max_tick", ctypes.c_uint64),
+                ("bytes", ctypes.c_uint64), ("budget_waits", ctypes.c_uint64)]
+
+
+def _load_server():
+    L = load()
+    if not getattr(L, "_server_ready", False):
+        p, sz = ctypes.c_void_p, ctypes.c_size_t
+        L.odp_server_create.argtypes = [ctypes.POINTER(_ServerConfig), ctypes.POINTER(ctypes.c_void_p)]
+        L.odp_server_run.argtypes = [p, p, p, p, p, sz, p, ctypes.POINTER(_ServerStats)]
+        L.odp_server_drain.argtypes = [p, p, p, p]
+        L.odp_server_log.argtypes = [p, p, ctypes.POINTER(ctypes.c_size_t)]
+        L.odp_server_destroy.argtypes = [p]
+        for f in ("odp_server_create", "odp_server_run", "odp_server_drain", "odp_server_log", "odp_server_destroy"):
+            getattr(L, f).restype = ctypes.c_int
+        L._server_ready = True
+    return L
+
+
+class Server:
+    """Request server (odp_server_*): open-loop schedules, drain, log."""
+
+    def __init__(self, max_events, budget_bytes, max_inflight=1 << 20, max_tick=1024, mode=SERVER_BATCHED):
+        L = _load_server()
+        cfg = _ServerConfig(max_events, budget_bytes, max_inflight, max_tick, mode, 0)
+        h = ctypes.c_void_p()
+        _check(L.odp_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self._n = 0
+
+    def run(self, events, payload_ptrs, payload_bytes, arrival_ns):
+        """Returns (complete_ns uint64 array, stats dict). Blocks until done."""
+        L = _load_server()
+        ev = np.ascontiguousarray(events)
+        n = ev.shape[0]
+        pp = np.ascontiguousarray(payload_ptrs, dtype=np.uint64)
+        pb = np.ascontiguousarray(payload_bytes, dtype=np.uint64)
+        an = np.ascontiguousarray(arrival_ns, dtype=np.uint64)
+        done = np.zeros(max(n, 1), dtype=np.uint64)
+        st = _ServerStats()
+        _check(L.odp_server_run(self._h, ctypes.c_void_p(ev.ctypes.data), ctypes.c_void_p(pp.ctypes.data),
+                                ctypes.c_void_p(pb.ctypes.data), ctypes.c_void_p(an.ctypes.data), n,
+                                ctypes.c_void_p(done.ctypes.data), ctypes.byref(st)))
+        self._n += n
+        return done[:n], {f: getattr(st, f) for f, _ in _ServerStats._fields_}
+
+    def drain(self):
+        """Returns (flags known at arrival, final flags, final report dict) as host arrays."""
+        import torch
+        L = _load_server()
+        n = self._n
+        imm = torch.zeros(max(n, 1), dtype=torch.uint8, device="cuda")
+        fl = torch.zeros(max(n, 1), dtype=torch.uint8, device="cuda")
+        rep = torch.zeros(REPORT_BYTES, dtype=torch.uint8, device="cuda")
+        _check(L.odp_server_drain(self._h, _ptr(imm), _ptr(fl), _ptr(rep)))
+        return imm[:n].cpu().numpy(), fl[:n].cpu().numpy(), report_to_dict(rep.cpu().numpy())
+
+    def log(self):
+        """The logged records (digests filled in) as a uint8 host array of n*64 bytes."""
+        import torch
+        L = _load_server()
+        cnt = ctypes.c_size_t()
+        _check(L.odp_server_log(self._h, None, ctypes.byref(cnt)))
+        buf = torch.zeros(max(cnt.value, 1) * 64, dtype=torch.uint8, device="cuda")
+        _check(L.odp_server_log(self._h, _ptr(buf), ctypes.byref(cnt)))
+        return buf[:cnt.value * 64].cpu().numpy()
+
+    def close(self):
+        if self._h:
+            _load_server().odp_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

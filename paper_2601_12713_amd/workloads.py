@@ -564,3 +564,99 @@ class TraceAtScale:
             "n_unpaired_alloc": 0,
             "n_unpaired_delete": 0,
         }
+
+
+# ---------------------------------------------------------------------------
+# Serving: Poisson arrivals of mapping-event requests with device payloads.
+# ---------------------------------------------------------------------------
+class ServingSchedule:
+    """``n`` requests arriving at ``rate`` per second (exponential gaps), each a
+    mapping record whose transfer moves a 256-byte aligned slice of a seeded
+    device arena (log-uniform ``lo``..``hi`` bytes). 20% of transfers re-send
+    an earlier slice to the same place (duplicates); 3% of records form
+    H2D-D2H-H2D triples of one slice (round trips); 2% are ALLOC/DELETE pairs of
+    a slot; a KERNEL follows every 16 records.
+
+    ``events`` (digest fields 0: the server fills them from the payloads),
+    ``payload_off`` / ``payload_bytes`` (into ``arena``, -1 / 0 for none),
+    ``arrival_ns``.
+    """
+
+    def __init__(self, seed=5, n=10_000, rate=10_000.0, lo=4096, hi=64 << 20, arena=None, arena_bytes=16 << 30,
+                 n_slots=10_000, device="cpu"):
+        import torch
+        rng = np.random.default_rng(seed)
+        if arena is None:
+            gen = torch.Generator(device=device)
+            gen.manual_seed(seed)
+            arena = torch.empty(arena_bytes, dtype=torch.uint8, device=device)
+            chunk = 1 << 30
+            for off in range(0, arena_bytes, chunk):
+                m = min(chunk, arena_bytes - off)
+                arena[off:off + m].copy_(torch.randint(0, 256, (m,), dtype=torch.uint8, device=device, generator=gen))
+        self.arena = arena
+        asize = arena.numel()
+        hi = min(hi, asize)
+        ev = empty_events(n)
+        off = np.full(n, -1, dtype=np.int64)
+        nb = np.zeros(n, dtype=np.uint64)
+        slots = zipf_finite(rng, 1.1, n_slots, n)
+        last_h2d = {}
+        i = 0
+        while i < n:
+            u = rng.random()
+            s = int(slots[i])
+            if i % 17 == 16:
+                ev["op"][i] = KERNEL
+                ev["dst_dev"][i], ev["src_dev"][i] = 0, HOST
+                i += 1
+                continue
+            if u < 0.02 and i + 1 < n:
+                for k, op in enumerate((ALLOC, DELETE)):
+                    ev["op"][i + k] = op
+                    ev["src_dev"][i + k], ev["dst_dev"][i + k] = HOST, 0
+                    ev["src_addr"][i + k] = HOST_BASE + s * (1 << 20)
+                    ev["dst_addr"][i + k] = DEV_BASE + s * (1 << 20)
+                    ev["bytes"][i + k] = 4096 + (s % 64) * 4096
+                i += 2
+                continue
+            if u < 0.05 and i + 2 < n:
+                size = int(np.floor(np.exp(rng.uniform(np.log(lo), np.log(hi)))))
+                o = int(rng.integers(0, (asize - size) // 256 + 1)) * 256
+                for k, (op, sd, dd) in enumerate(((H2D, HOST, 0), (D2H, 0, HOST), (H2D, HOST, 0))):
+                    ev["op"][i + k] = op
+                    ev["src_dev"][i + k], ev["dst_dev"][i + k] = sd, dd
+                    off[i + k], nb[i + k] = o, size
+                last_h2d[s] = (o, size)
+                i += 3
+                continue
+            if u < 0.25 and s in last_h2d:
+                o, size = last_h2d[s]
+                op, sd, dd = H2D, HOST, 0
+            else:
+                size = int(np.floor(np.exp(rng.uniform(np.log(lo), np.log(hi)))))
+                o = int(rng.integers(0, (asize - size) // 256 + 1)) * 256
+                if rng.random() < 0.5:
+                    op, sd, dd = H2D, HOST, 0
+                    last_h2d[s] = (o, size)
+                else:
+                    op, sd, dd = D2H, 0, HOST
+            ev["op"][i] = op
+            ev["src_dev"][i], ev["dst_dev"][i] = sd, dd
+            off[i], nb[i] = o, size
+            i += 1
+        is_tx = off >= 0
+        ev["bytes"][is_tx] = nb[is_tx]
+        ev["src_addr"] = np.where(is_tx, np.uint64(HOST_BASE) + slots.astype(np.uint64) * np.uint64(1 << 20), ev["src_addr"])
+        ev["dst_addr"] = np.where(is_tx, np.uint64(DEV_BASE) + slots.astype(np.uint64) * np.uint64(1 << 20), ev["dst_addr"])
+        gaps = rng.exponential(1e9 / rate, size=n)
+        arrival = np.cumsum(gaps).astype(np.uint64)
+        arrival -= arrival[0]
+        ev["t_start"] = arrival
+        ev["t_end"] = arrival + np.uint64(5000) + (ev["bytes"] // np.uint64(25)).astype(np.uint64)
+        ev["codeptr"] = np.uint64(0x404000)
+        self.events, self.payload_off, self.payload_bytes, self.arrival_ns = ev, off, nb, arrival
+
+    def payload_ptrs(self):
+        base = np.uint64(self.arena.data_ptr())
+        return np.where(self.payload_off >= 0, base + self.payload_off.astype(np.uint64), np.uint64(0))
