@@ -53,7 +53,40 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="approximate CPU time budget of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="before the workload, one elementwise copy kernel (torch.neg on int32) reading and "
+                         "writing BYTES: the calibration dispatch of the HBM byte counters")
     return ap.parse_args()
+
+
+def traffic_from_profile(name, sources):
+    """HBM bytes per launch of kernel `name` from its committed counter summary
+    (profiles/<name>.pmc.txt), or None when the summary is missing or was taken
+    on sources other than the current ones."""
+    import hashlib
+    path = os.path.join(HERE, "profiles", name + ".pmc.txt")
+    if not os.path.exists(path):
+        return None
+    h = hashlib.sha256()
+    for src in sources:
+        with open(os.path.join(HERE, src), "rb") as f:
+            h.update(f.read())
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line:
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+    if fields.get("source_sha256") != h.hexdigest():
+        return None
+    try:
+        return int(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+DIGEST_SOURCES = ["paper_2601_12713_amd/csrc/digest.hip", "paper_2601_12713_amd/csrc/xxh64_dev.h",
+                  "paper_2601_12713_amd/csrc/internal.h"]
 
 
 def host_info():
@@ -163,7 +196,8 @@ def run_large_arrays(args, torch, odp, W):
                                "records), per-buffer digest launch, then analysis of the 64-record log",
                    "buffers": n, "bytes_per_step": total, "events": n},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic_from_profile("digest_one_kernel.large-arrays", DIGEST_SOURCES),
                      "kernel": "digest_one_kernel (one launch per 256 MiB buffer)",
                      "kernel_ms": round(kern_ms, 5)},
         "extras": {"batched_GBps": round(total / (b_ms * 1e-3) / 1e9, 1),
@@ -360,7 +394,8 @@ def run_serve(args, torch, odp, W):
         lat_us = (done.astype(np.float64) - sched.arrival_ns[:n].astype(np.float64)) / 1e3
         return {"requests": n, "p50_us": round(float(np.percentile(lat_us, 50)), 1),
                 "p99_us": round(float(np.percentile(lat_us, 99)), 1), "GBps": round(st["bytes"] / st["seconds"] / 1e9, 1),
-                "offered_GBps": round(float(sched.payload_bytes[:n].sum()) / (float(sched.arrival_ns[n - 1]) * 1e-9) / 1e9, 1),
+                "offered_GBps": (round(float(sched.payload_bytes[:n].sum()) / float(sched.arrival_ns[n - 1]), 1)
+                                 if sched.arrival_ns[n - 1] else None),
                 "seconds": round(st["seconds"], 3), "ticks": st["ticks"], "max_tick": st["max_tick"],
                 "budget_waits": st["budget_waits"]}
 
@@ -400,8 +435,8 @@ def run_serve(args, torch, odp, W):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU; --gpus %d is not supported (multi-GPU sharding is "
-              "described in DESIGN.md, not built)" % args.gpus, file=sys.stderr)
+        print("bench.py: runs on one GPU only; --gpus %d is not supported (the multi-GPU split of the work "
+              "is not built)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():
@@ -410,6 +445,12 @@ def main():
     from paper_2601_12713_amd import odp
     from paper_2601_12713_amd import workloads as W
     odp.load()
+    if args.copy_probe:
+        src = torch.randint(0, 1 << 30, (args.copy_probe // 4,), dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     runner = {"large-arrays": run_large_arrays, "batch": run_batch, "trace": run_trace,
               "plain-small": run_plain_small, "serve": run_serve}[args.workload]
     line, cpu_sample = runner(args, torch, odp, W)

@@ -37,9 +37,17 @@ struct RowDesc {
 struct Smem {
   uint8_t slab[kWaves][kRowsPerWave * kStride];
   RowDesc rows[kRows];
-  uint64_t leafdig[kRows];
+  uint64_t leafdig[2][kRows];  // leaf digests of the current and the previous item
   uint32_t outidx[kRows];
-  uint32_t item;
+  uint32_t ring[3];            // claimed work items, two ahead of the one in progress
+};
+
+// Work record of one level-1 node item, written by the plan.
+struct NodeRec {
+  const uint8_t* base;  // first byte of the node
+  uint64_t* dst;        // where the node digest goes: out[i] for a one-node buffer, else its level-1 tree slot
+  uint32_t len;         // bytes in the node, 1 .. kNodeBytes
+  uint32_t pad;
 };
 
 __device__ __forceinline__ void wave_fence() { __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront"); }
@@ -165,6 +173,94 @@ __device__ __forceinline__ uint64_t hash_wave_full_leaves(const uint8_t* leaf_ba
   return finish_row(acc, full);
 }
 
+// Fast path as one stage of a wavefront's continuous stream of items: 16
+// whole, 16-byte aligned leaves at leaf_base + r*4096 (leaf_base wave-uniform).
+// Each step stages 512 bytes of every leaf (8 KiB per wavefront) through the
+// wavefront's LDS slab with eight 128-bit nontemporal loads per lane; load k
+// covers 128 contiguous bytes of 8 leaves (lane L: leaf L/8 + 8*(k%2), bytes
+// 128*(k/2) + 16*(L%8)), so every address is one of two per-lane offsets from
+// the uniform base plus an immediate. Lane 4r+a then folds accumulator a's
+// words of leaf r. Two steps are in flight while one is hashed.
+// On entry, `pre` says whether RA/RB already hold the first two steps (loaded
+// while the previous item was hashed). When `next` (the next item's leaves
+// for this wavefront, same shape) is non-null, its first two steps are loaded
+// during the last two steps here and `pre` is set, so the loads in flight do
+// not drain between items. Returns the leaf digest in lane 4r.
+// Buffer resource over a wave-uniform base (raw addressing, no stride, no
+// range limit below 4 GiB): keeps every address of a step as one scalar base
+// plus a 32-bit lane offset and an immediate.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t wave_rsrc(const uint8_t* base) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(base), (short)0, -1, 0x00020000);
+}
+
+template <int NL>
+__device__ __forceinline__ void fast_load(u32x4 (&R)[NL], const uint8_t* base, uint32_t step_off) {
+  const int lane = threadIdx.x & 63;
+  const __amdgpu_buffer_rsrc_t rs = wave_rsrc(base);
+  const uint32_t o = (uint32_t)(lane >> 3) * kLeaf + (uint32_t)(lane & 7) * 16;
+#pragma unroll
+  for (int k = 0; k < NL; ++k) {
+    const uint32_t vo = o + (uint32_t)(8 * (k & 1)) * kLeaf + (uint32_t)(k >> 1) * 128;
+    R[k] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)vo, (int)step_off, 2 /* nt */));
+  }
+}
+
+template <int NL>
+__device__ __forceinline__ void fast_stage(const u32x4 (&R)[NL], uint8_t* slab) {
+  const int lane = threadIdx.x & 63;
+  uint8_t* const wr = slab + (lane >> 3) * kStride + (lane & 7) * 16;
+#pragma unroll
+  for (int k = 0; k < NL; ++k) *reinterpret_cast<u32x4*>(wr + 8 * (k & 1) * kStride + (k >> 1) * 128) = R[k];
+}
+
+__device__ __forceinline__ uint64_t fast_fold(uint64_t acc, const uint8_t* slab) {
+  const int lane = threadIdx.x & 63;
+  const uint8_t* const rd = slab + (lane >> 2) * kStride + (lane & 3) * 8;
+#pragma unroll
+  for (int h2 = 0; h2 < kSlab / 128; ++h2) {
+    uint64_t w[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) w[q] = *reinterpret_cast<const uint64_t*>(rd + (h2 * 4 + q) * 32);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc = xx_round(acc, w[q]);
+  }
+  return acc;
+}
+
+template <int NL>
+__device__ __forceinline__ uint64_t hash_wave_leaves_pipe(const uint8_t* leaf_base, const uint8_t* next, bool& pre,
+                                                          u32x4 (&RA)[NL], u32x4 (&RB)[NL], uint8_t* slab) {
+  static_assert(NL == kSlab / 64, "eight 128-bit loads per lane cover one step");
+  constexpr uint32_t NS = kLeaf / kSlab;
+  const int lane = threadIdx.x & 63;
+  uint64_t acc = xx_acc_init(0, lane & 3);
+  if (!pre) {
+    fast_load(RA, leaf_base, 0);
+    fast_load(RB, leaf_base, kSlab);
+  }
+#pragma unroll 1
+  for (uint32_t s = 0; s < NS; s += 2) {
+    fast_stage(RA, slab);
+    if (s + 2 < NS) fast_load(RA, leaf_base, (s + 2) * kSlab);
+    else if (next) fast_load(RA, next, 0);
+    wave_fence();
+    acc = fast_fold(acc, slab);
+    wave_fence();
+    fast_stage(RB, slab);
+    if (s + 3 < NS) fast_load(RB, leaf_base, (s + 3) * kSlab);
+    else if (next) fast_load(RB, next, kSlab);
+    wave_fence();
+    acc = fast_fold(acc, slab);
+    wave_fence();
+  }
+  pre = next != nullptr;
+  RowDesc full;
+  full.base = leaf_base + (lane >> 2) * kLeaf;
+  full.len = kLeaf;
+  full.present = 1;
+  return finish_row(acc, full);
+}
+
 // General path: 16 rows of any length (<= 4096) and presence. 16-byte aligned
 // rows are staged through LDS with predicated loads, one step at a time;
 // otherwise every lane reads its words straight from memory at any alignment.
@@ -243,14 +339,17 @@ __device__ __forceinline__ uint64_t xx_words4_coherent(const uint64_t* w, uint32
 }
 
 // Called by one whole wavefront after it computed the digest `h` (lane 0) of
-// node m of a level holding nj nodes. Stores it, and while this wavefront
-// completes the last missing child of the parent, climbs: hashes the parent
-// (seed = its level) and repeats; the root goes to *out.
-//   tree: the buffer's node slots, level by level (level 1 first)
-//   tk:   the buffer's tickets, level 2 first; reset to 0 by their last user
-__device__ __forceinline__ void tree_up(uint64_t h, uint64_t m, uint64_t nj, uint64_t* out, uint64_t* tree, uint32_t* tk) {
+// node m of tree level `level`, which holds nj nodes. Stores it, and while
+// this wavefront completes the last missing child of the parent, climbs:
+// hashes the parent (seed = its level) and repeats; the root goes to *out.
+//   tree: the buffer's node slots, level by level (level 1 first); loff is
+//         where this level's slots start
+//   tk:   the buffer's tickets, one per node of level 2 and above, level by
+//         level; tkoff is where the tickets of this level's parents start.
+//         Each is reset to 0 by its last user.
+__device__ __forceinline__ void tree_up(uint64_t h, uint64_t m, uint64_t nj, uint64_t level, uint64_t loff,
+                                        uint64_t tkoff, uint64_t* out, uint64_t* tree, uint32_t* tk) {
   const int lane = threadIdx.x & 63;
-  uint64_t loff = 0, tkoff = 0, level = 1;
   h = __shfl(h, 0, 64);
   for (;;) {
     if (nj == 1) {
@@ -309,33 +408,12 @@ __device__ __forceinline__ void run_node(Smem& sm, const uint8_t* buf, uint64_t 
     wave_fence();
     h = hash_wave_rows(rows, sm.slab[w]);
   }
-  if ((t & 3) == 0 && (uint64_t)(w * kRowsPerWave + r) < nl) sm.leafdig[w * kRowsPerWave + r] = h;
+  if ((t & 3) == 0 && (uint64_t)(w * kRowsPerWave + r) < nl) sm.leafdig[0][w * kRowsPerWave + r] = h;
   __syncthreads();
   if (w == 0) {
-    const uint64_t d = xx_words4(sm.leafdig, nl, 1);
-    tree_up(d, node, n1, out, tree, tk);
+    const uint64_t d = xx_words4(sm.leafdig[0], nl, 1);
+    tree_up(d, node, n1, 1, 0, 0, out, tree, tk);
   }
-  __syncthreads();
-}
-
-// Up to 64 buffers of at most one leaf each (digest = XXH64 seed 0).
-__device__ __forceinline__ void run_small(Smem& sm, uint64_t group, uint64_t n_small, const uint32_t* small_list,
-                          const void* const* ptrs, const uint64_t* sizes, uint64_t* out) {
-  const int t = threadIdx.x;
-  if (t < kRows) {
-    const uint64_t k = group * kRows + t;
-    RowDesc d;
-    d.present = k < n_small;
-    uint32_t idx = d.present ? small_list[k] : 0u;
-    d.base = d.present ? static_cast<const uint8_t*>(ptrs[idx]) : nullptr;
-    d.len = d.present ? (uint32_t)sizes[idx] : 0u;
-    sm.rows[t] = d;
-    sm.outidx[t] = idx;
-  }
-  __syncthreads();
-  const int w = t >> 6, r = (t & 63) >> 2;
-  const uint64_t h = hash_wave_rows(sm.rows + w * kRowsPerWave, sm.slab[w]);
-  if ((t & 3) == 0 && sm.rows[w * kRowsPerWave + r].present) out[sm.outidx[w * kRowsPerWave + r]] = h;
   __syncthreads();
 }
 
@@ -368,7 +446,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
 // Batched form: device-side work plan, then one persistent launch.
 // ---------------------------------------------------------------------------
 struct PlanArgs {
+  const void* const* ptrs;
   const uint64_t* sizes;
+  uint64_t* out;
+  uint64_t* tree;
+  NodeRec* rec;         // [node items]
   uint64_t n;
   uint64_t* node_off;   // [n] first node item of buffer i
   uint64_t* tree_off;   // [n]
@@ -476,8 +558,9 @@ __global__ __launch_bounds__(kPlanThreads) void plan_scan_kernel(PlanArgs A) {
     c->tree_total = carry[2];
     c->tk_total = carry[3];
     c->head = 0;
+    // the queue head runs past n_items by up to three claims per workgroup
     c->overflow = (carry[0] > A.cap_items || carry[2] > A.cap_tree || carry[3] > A.cap_tk ||
-                   c->n_items >= 0xFFFFFFFFull) ? 1u : 0u;
+                   c->n_items >= 0xFFFF0000ull) ? 1u : 0u;
   }
 }
 
@@ -509,7 +592,8 @@ __global__ __launch_bounds__(kPlanThreads) void plan_write_kernel(PlanArgs A) {
   }
 }
 
-// item_buf[k] = buffer owning node item k (largest i with node_off[i] <= k).
+// item_buf[k] = buffer owning node item k (largest i with node_off[i] <= k),
+// rec[k] = the node's address, length and digest destination.
 __global__ __launch_bounds__(kPlanThreads) void plan_items_kernel(PlanArgs A, uint32_t* item_buf) {
   const DigestCtl* c = A.ctl;
   if (c->overflow) return;
@@ -521,6 +605,14 @@ __global__ __launch_bounds__(kPlanThreads) void plan_items_kernel(PlanArgs A, ui
       if (A.node_off[mid] <= k) lo = mid; else hi = mid;
     }
     item_buf[k] = (uint32_t)lo;
+    const uint64_t size = A.sizes[lo], node = k - A.node_off[lo];
+    const uint64_t n1 = ceil_div(ceil_div(size, kLeaf), kFanIn);
+    NodeRec r;
+    r.base = static_cast<const uint8_t*>(A.ptrs[lo]) + node * kNodeBytes;
+    r.dst = n1 == 1 ? A.out + lo : A.tree + A.tree_off[lo] + node;
+    r.len = (uint32_t)min<uint64_t>(kNodeBytes, size - node * kNodeBytes);
+    r.pad = 0;
+    A.rec[k] = r;
   }
 }
 
@@ -534,12 +626,40 @@ struct BatchArgs {
   const uint64_t* tk_off;
   const uint32_t* small_list;
   const uint32_t* item_buf;
+  const NodeRec* rec;
   uint64_t* tree;
   uint32_t* tickets;
   DigestCtl* ctl;
   uint32_t* status;  // host-mapped sticky status word
 };
 
+__device__ __forceinline__ bool aligned16(const uint8_t* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+// The work record of queue item `item` (node items only; zeros otherwise).
+__device__ __forceinline__ NodeRec load_rec(const BatchArgs& A, uint32_t item, uint64_t n_node) {
+  NodeRec r;
+  r.base = nullptr;
+  r.dst = nullptr;
+  r.len = 0;
+  r.pad = 0;
+  if (item < n_node) r = A.rec[item];
+  return r;
+}
+
+// First leaf of wavefront w's rows in a node when they are 16 whole, 16-byte
+// aligned leaves (the fast path), else null.
+__device__ __forceinline__ const uint8_t* fast_rows(const uint8_t* base, uint32_t len, int w) {
+  const uint32_t end = (uint32_t)(w + 1) * kRowsPerWave * kLeaf;
+  return aligned16(base) && end <= len ? base + (uint32_t)w * kRowsPerWave * kLeaf : nullptr;
+}
+
+// Persistent batched digest. Each workgroup claims items from the queue two
+// ahead of the one it hashes, so the claim and the item's record arrive while
+// the current item streams; each wavefront carries its load pipeline from one
+// node item into the next. Per item there is one barrier: after it, one
+// wavefront (rotating) folds the 64 leaf digests into the level-1 digest and
+// stores it without waiting (out[i] for one-node buffers, else the tree slot
+// that the tree kernel climbs from).
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void digest_batched_kernel(BatchArgs A) {
   __shared__ Smem sm;
   const DigestCtl* c = A.ctl;
@@ -550,18 +670,109 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
     return;
   }
   const uint64_t n_node = c->n_node_items, n_items = c->n_items, n_small = c->n_small;
-  for (;;) {
-    if (threadIdx.x == 0) sm.item = atomicAdd(&A.ctl->head, 1u);
-    __syncthreads();
-    const uint64_t item = uniform(sm.item);
-    if (item >= n_items) break;
-    if (item < n_node) {
-      const uint32_t b = uniform(A.item_buf[item]);
-      const uint64_t size = uniform(A.sizes[b]);
-      run_node(sm, uniform_ptr(static_cast<const uint8_t*>(A.ptrs[b])), size, item - uniform(A.node_off[b]), A.out + b,
-               A.tree + uniform(A.tree_off[b]), A.tickets + uniform(A.tk_off[b]));
+  const int t = threadIdx.x, w = uniform(t >> 6), lane = t & 63, r = lane >> 2;
+  if (t == 0) {
+    sm.ring[0] = atomicAdd(&A.ctl->head, 1u);
+    sm.ring[1] = atomicAdd(&A.ctl->head, 1u);
+  }
+  __syncthreads();
+  uint32_t cur = uniform(sm.ring[0]), nxt = uniform(sm.ring[1]);
+  NodeRec rc = load_rec(A, cur, n_node), rn = load_rec(A, nxt, n_node);
+  constexpr int NL = kSlab / 64;
+  u32x4 RA[NL], RB[NL];
+  bool pre = false;
+  RowDesc* rows = sm.rows + w * kRowsPerWave;
+  for (uint32_t k = 0; cur < n_items; ++k) {
+    uint32_t claim = 0;
+    if (t == 0) claim = atomicAdd(&A.ctl->head, 1u);
+    const bool is_node = cur < n_node;
+    const uint8_t* base = uniform_ptr(rc.base);
+    const uint32_t len = uniform(rc.len);
+    const uint32_t nl = (len + kLeaf - 1) / kLeaf;
+    const uint8_t* mine = is_node ? fast_rows(base, len, w) : nullptr;
+    uint64_t h;
+    if (mine) {
+      const uint8_t* next = nxt < n_node ? fast_rows(uniform_ptr(rn.base), uniform(rn.len), w) : nullptr;
+      h = hash_wave_leaves_pipe<NL>(mine, next, pre, RA, RB, sm.slab[w]);
     } else {
-      run_small(sm, item - n_node, n_small, A.small_list, A.ptrs, A.sizes, A.out);
+      // Nothing is in flight for this path (pre is false after it): constant
+      // stage registers are rematerialised instead of kept across it.
+#pragma unroll
+      for (int j = 0; j < NL; ++j) RA[j] = RB[j] = u32x4{0u, 0u, 0u, 0u};
+      // rows of a partial or unaligned node, or up to 64 buffers of at most
+      // one leaf each (digest = XXH64 seed 0), 16 per wavefront
+      if (lane < kRowsPerWave) {
+        RowDesc d;
+        if (is_node) {
+          const uint32_t leaf = w * kRowsPerWave + lane;
+          d.present = leaf < nl;
+          d.base = base + (d.present ? leaf * kLeaf : 0u);
+          d.len = d.present ? min<uint32_t>(kLeaf, len - leaf * kLeaf) : 0u;
+        } else {
+          const uint64_t q = (uint64_t)(cur - n_node) * kRows + w * kRowsPerWave + lane;
+          d.present = q < n_small;
+          const uint32_t idx = d.present ? A.small_list[q] : 0u;
+          d.base = d.present ? static_cast<const uint8_t*>(A.ptrs[idx]) : nullptr;
+          d.len = d.present ? (uint32_t)A.sizes[idx] : 0u;
+          sm.outidx[w * kRowsPerWave + lane] = idx;
+        }
+        rows[lane] = d;
+      }
+      wave_fence();
+      h = hash_wave_rows(rows, sm.slab[w]);
+      pre = false;
+    }
+    if ((lane & 3) == 0) {
+      if (is_node) {
+        if ((uint32_t)(w * kRowsPerWave + r) < nl) sm.leafdig[k & 1][w * kRowsPerWave + r] = h;
+      } else if (rows[r].present) {
+        A.out[sm.outidx[w * kRowsPerWave + r]] = h;
+      }
+    }
+    if (t == 0) sm.ring[(k + 2) % 3] = claim;
+    __syncthreads();
+    if (cur < n_node && w == (int)(k & 3)) {
+      const uint64_t d = xx_words4(sm.leafdig[k & 1], nl, 1);
+      if (lane == 0) *reinterpret_cast<uint64_t*>(uniform(reinterpret_cast<uint64_t>(rc.dst))) = d;
+    }
+    cur = nxt;
+    rc = rn;
+    nxt = uniform(sm.ring[(k + 2) % 3]);
+    rn = load_rec(A, nxt, n_node);
+  }
+}
+
+// Levels 2 and up of every buffer with more than one level-1 node: one
+// wavefront per level-2 node hashes its (up to 64) level-1 digests, then
+// climbs with tickets like the per-buffer form.
+__global__ __launch_bounds__(kThreads) void digest_tree_kernel(BatchArgs A) {
+  const DigestCtl* c = A.ctl;
+  if (c->overflow) return;
+  const uint64_t n_node = c->n_node_items;
+  const int lane = threadIdx.x & 63;
+  const uint64_t wave = (uint64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+  const uint64_t nwaves = (uint64_t)gridDim.x * kWaves;
+  for (uint64_t base = wave * 64; base < n_node; base += nwaves * 64) {
+    const uint64_t k = base + lane;
+    bool first = false;
+    if (k < n_node) {
+      const uint32_t b = A.item_buf[k];
+      const uint64_t node = k - A.node_off[b];
+      const uint64_t n1 = ceil_div(ceil_div(A.sizes[b], kLeaf), kFanIn);
+      first = n1 > 1 && node % kFanIn == 0;
+    }
+    uint64_t mask = __ballot(first);
+    while (mask) {
+      const uint64_t kk = base + (uint64_t)__builtin_ctzll(mask);
+      mask &= mask - 1;
+      const uint32_t b = uniform(A.item_buf[kk]);
+      const uint64_t n1 = ceil_div(ceil_div(uniform(A.sizes[b]), kLeaf), kFanIn);
+      const uint64_t n2 = ceil_div(n1, kFanIn);
+      const uint64_t p = (kk - uniform(A.node_off[b])) / kFanIn;
+      uint64_t* tree = A.tree + uniform(A.tree_off[b]);
+      const uint32_t nchild = (uint32_t)min<uint64_t>(kFanIn, n1 - p * kFanIn);
+      const uint64_t h = xx_words4(tree + p * kFanIn, nchild, 2);
+      tree_up(h, p, n2, 2, n1, n2, A.out + b, tree, A.tickets + uniform(A.tk_off[b]));
     }
   }
 }
@@ -598,7 +809,8 @@ int digest_reserve(Workspace* ws, size_t max_buffers, uint64_t max_total_bytes) 
     const uint64_t tree = items + items / 32 + 4 * (uint64_t)nb;
     const uint64_t tk = items / 32 + 4 * (uint64_t)nb;
     int e;
-    if ((e = ws->item_buf.ensure(items * 4)) || (e = ws->tree.ensure(tree * 8)) || (e = ws->tickets.ensure(tk * 4)))
+    if ((e = ws->item_buf.ensure(items * 4)) || (e = ws->item_rec.ensure(items * sizeof(NodeRec))) ||
+        (e = ws->tree.ensure(tree * 8)) || (e = ws->tickets.ensure(tk * 4)))
       return e;
     ODP_HIP(hipMemset(ws->tickets.ptr, 0, tk * 4));
     ws->cap_items = items;
@@ -611,7 +823,11 @@ int digest_reserve(Workspace* ws, size_t max_buffers, uint64_t max_total_bytes) 
 static int enqueue_batched(Workspace* ws, const void* const* ptrs, const uint64_t* sizes, size_t n, uint64_t* out,
                            hipStream_t stream) {
   PlanArgs P;
+  P.ptrs = ptrs;
   P.sizes = sizes;
+  P.out = out;
+  P.tree = static_cast<uint64_t*>(ws->tree.ptr);
+  P.rec = static_cast<NodeRec*>(ws->item_rec.ptr);
   P.n = n;
   P.node_off = static_cast<uint64_t*>(ws->node_off.ptr);
   P.tree_off = static_cast<uint64_t*>(ws->tree_off.ptr);
@@ -639,12 +855,14 @@ static int enqueue_batched(Workspace* ws, const void* const* ptrs, const uint64_
   B.tk_off = P.tk_off;
   B.small_list = P.small_list;
   B.item_buf = static_cast<const uint32_t*>(ws->item_buf.ptr);
+  B.rec = P.rec;
   B.tree = static_cast<uint64_t*>(ws->tree.ptr);
   B.tickets = static_cast<uint32_t*>(ws->tickets.ptr);
   B.ctl = P.ctl;
   B.status = device_status_word(ws->device);
   const uint32_t bpc = tuning().blocks_per_cu;
   hipLaunchKernelGGL(digest_batched_kernel, dim3(cus * bpc), dim3(kThreads), 0, stream, B);
+  hipLaunchKernelGGL(digest_tree_kernel, dim3(cus * 4), dim3(kThreads), 0, stream, B);
   return check_hip(hipGetLastError(), "digest launch");
 }
 

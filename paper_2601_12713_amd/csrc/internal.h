@@ -48,7 +48,7 @@ struct Workspace {
   int device = -1;
   hipStream_t stream = nullptr;
   // batched digest
-  DevBuf node_off, tree_off, tk_off, small_list, blk, ctl, item_buf, tree, tickets;
+  DevBuf node_off, tree_off, tk_off, small_list, blk, ctl, item_buf, item_rec, tree, tickets;
   size_t cap_buffers = 0;
   uint64_t cap_items = 0, cap_tree = 0, cap_tk = 0;
   // plain digest (one buffer at a time)

@@ -150,7 +150,7 @@ extern "C" int odp_release(void) {
     (void)hipDeviceSynchronize();
     if (ws->graph) (void)hipGraphExecDestroy(ws->graph);
     DevBuf* bufs[] = {&ws->node_off, &ws->tree_off, &ws->tk_off, &ws->small_list, &ws->blk, &ws->ctl,
-                      &ws->item_buf, &ws->tree, &ws->tickets, &ws->p_tree, &ws->p_tickets};
+                      &ws->item_buf, &ws->item_rec, &ws->tree, &ws->tickets, &ws->p_tree, &ws->p_tickets};
     for (DevBuf* b : bufs) b->release();
     analyze_release(ws);
     delete ws;

@@ -57,7 +57,7 @@ def check_served(odp, sched, ev_o, log, imm, fl, rep):
     bad = np.nonzero((imm & IMMEDIATE) != (fo & IMMEDIATE))[0]
     assert bad.size == 0, "arrival flags differ at %s: %s vs %s" % (
         bad[:10].tolist(), imm[bad[:10]].tolist(), fo[bad[:10]].tolist())
-    assert not (imm & ~IMMEDIATE & 0xFF).any()
+    assert not (imm & np.uint8(0xFF ^ IMMEDIATE)).any(), "only DD, RT_RX, PAIRED and INVALID are known at arrival"
     return fo, ro
 
 
