@@ -157,17 +157,17 @@ def run_large_arrays(args, torch, odp, W):
     timer = KernelTimer(torch, stream)
 
     def step(mode):
-        for i in range(n):
-            e0 = timer.start() if mode else None
-            odp.digest_buffers_plain(ptrs[i:i + 1], sizes[i:i + 1], out[i:i + 1], stream)
-            if mode:
-                timer.stop(e0)
+        # one call: the library launches the digest kernel once per buffer
+        e0 = timer.start() if mode else None
+        odp.digest_buffers_plain(ptrs, sizes, out, stream)
+        if mode:
+            timer.stop(e0)
         ev_u64[:, 0].copy_(out)  # digest field of each record
         odp.analyze_trace(d_ev, d_flags, d_rep, stream=stream, n=n)
 
     ms = timed_steps(torch, step, args.steps, args.warmup)
     rep = odp.report_to_dict(d_rep.cpu().numpy())
-    kern_ms = timer.mean_ms()
+    kern_ms = timer.mean_ms() / n  # average over the n back-to-back launches
     total = n * nbytes
     value = total / (ms * 1e-3) / 1e9
     achieved = nbytes / (kern_ms * 1e-3) / 1e9
@@ -198,7 +198,8 @@ def run_large_arrays(args, torch, odp, W):
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic_from_profile("digest_one_kernel.large-arrays", DIGEST_SOURCES),
-                     "kernel": "digest_one_kernel (one launch per 256 MiB buffer)",
+                     "kernel": "digest_one_kernel (one launch per 256 MiB buffer; HIP events around the 64 "
+                               "back-to-back launches of a step, divided by 64)",
                      "kernel_ms": round(kern_ms, 5)},
         "extras": {"batched_GBps": round(total / (b_ms * 1e-3) / 1e9, 1),
                    "batched_frac_of_peak": round(total / (b_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),

@@ -509,6 +509,21 @@ __device__ void block_scan4(uint64_t v[4], uint64_t tot[4]) {
   __syncthreads();
 }
 
+// Totals of the plan (node items, small buffers, tree and ticket slots) into
+// the control block; flags a plan that does not fit the workspace.
+__device__ void finalize_plan(const PlanArgs& A, const uint64_t carry[4]) {
+  DigestCtl* c = A.ctl;
+  c->n_node_items = carry[0];
+  c->n_small = carry[1];
+  c->n_items = carry[0] + ceil_div(carry[1], kRows);
+  c->tree_total = carry[2];
+  c->tk_total = carry[3];
+  c->head = 0;
+  // item numbers run past n_items by up to five per workgroup of at most 2^14
+  c->overflow = (carry[0] > A.cap_items || carry[2] > A.cap_tree || carry[3] > A.cap_tk ||
+                 c->n_items >= 0xFFFF0000ull - (5ull << 14)) ? 1u : 0u;
+}
+
 __global__ __launch_bounds__(kPlanThreads) void plan_count_kernel(PlanArgs A) {
   const uint64_t base = (uint64_t)blockIdx.x * kPlanTile + threadIdx.x * kPlanPer;
   uint64_t s[4] = {0, 0, 0, 0};
@@ -550,18 +565,7 @@ __global__ __launch_bounds__(kPlanThreads) void plan_scan_kernel(PlanArgs A) {
     if (threadIdx.x < 4) carry[threadIdx.x] += tot[threadIdx.x];
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    DigestCtl* c = A.ctl;
-    c->n_node_items = carry[0];
-    c->n_small = carry[1];
-    c->n_items = carry[0] + ceil_div(carry[1], kRows);
-    c->tree_total = carry[2];
-    c->tk_total = carry[3];
-    c->head = 0;
-    // the queue head runs past n_items by up to three claims per workgroup
-    c->overflow = (carry[0] > A.cap_items || carry[2] > A.cap_tree || carry[3] > A.cap_tk ||
-                   c->n_items >= 0xFFFF0000ull) ? 1u : 0u;
-  }
+  if (threadIdx.x == 0) finalize_plan(A, carry);
 }
 
 __global__ __launch_bounds__(kPlanThreads) void plan_write_kernel(PlanArgs A) {
@@ -577,8 +581,13 @@ __global__ __launch_bounds__(kPlanThreads) void plan_write_kernel(PlanArgs A) {
   }
   uint64_t tot[4];
   block_scan4(s, tot);
+  if (A.nblk == 1) {
+    // one tile: its own scan is the whole plan (no count and scan launches)
+    if (threadIdx.x == 0) finalize_plan(A, tot);
+  } else {
 #pragma unroll
-  for (int q = 0; q < 4; ++q) s[q] += A.blk[4 * blockIdx.x + q];
+    for (int q = 0; q < 4; ++q) s[q] += A.blk[4 * blockIdx.x + q];
+  }
   for (int j = 0; j < kPlanPer; ++j) {
     const uint64_t i = base + j;
     if (i < A.n) {
@@ -671,12 +680,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
   }
   const uint64_t n_node = c->n_node_items, n_items = c->n_items, n_small = c->n_small;
   const int t = threadIdx.x, w = uniform(t >> 6), lane = t & 63, r = lane >> 2;
-  if (t == 0) {
-    sm.ring[0] = atomicAdd(&A.ctl->head, 1u);
-    sm.ring[1] = atomicAdd(&A.ctl->head, 1u);
-  }
-  __syncthreads();
-  uint32_t cur = uniform(sm.ring[0]), nxt = uniform(sm.ring[1]);
+  // items blockIdx.x and blockIdx.x + gridDim.x are this workgroup's; later
+  // ones come from the queue, numbered from 2 * gridDim.x on. A workgroup
+  // with nothing to do leaves without touching the queue.
+  const uint32_t first_queued = 2u * gridDim.x;
+  uint32_t cur = blockIdx.x, nxt = blockIdx.x + gridDim.x;
   NodeRec rc = load_rec(A, cur, n_node), rn = load_rec(A, nxt, n_node);
   constexpr int NL = kSlab / 64;
   u32x4 RA[NL], RB[NL];
@@ -684,7 +692,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
   RowDesc* rows = sm.rows + w * kRowsPerWave;
   for (uint32_t k = 0; cur < n_items; ++k) {
     uint32_t claim = 0;
-    if (t == 0) claim = atomicAdd(&A.ctl->head, 1u);
+    if (t == 0) claim = first_queued + atomicAdd(&A.ctl->head, 1u);
     const bool is_node = cur < n_node;
     const uint8_t* base = uniform_ptr(rc.base);
     const uint32_t len = uniform(rc.len);
@@ -820,8 +828,10 @@ int digest_reserve(Workspace* ws, size_t max_buffers, uint64_t max_total_bytes) 
   return ODP_OK;
 }
 
+// item_hint: an upper bound on the work items when the caller knows one
+// (0: unknown), to size the grids of small batches.
 static int enqueue_batched(Workspace* ws, const void* const* ptrs, const uint64_t* sizes, size_t n, uint64_t* out,
-                           hipStream_t stream) {
+                           hipStream_t stream, uint64_t item_hint = 0) {
   PlanArgs P;
   P.ptrs = ptrs;
   P.sizes = sizes;
@@ -839,11 +849,16 @@ static int enqueue_batched(Workspace* ws, const void* const* ptrs, const uint64_
   P.cap_items = ws->cap_items;
   P.cap_tree = ws->cap_tree;
   P.cap_tk = ws->cap_tk;
-  hipLaunchKernelGGL(plan_count_kernel, dim3((unsigned)P.nblk), dim3(kPlanThreads), 0, stream, P);
-  hipLaunchKernelGGL(plan_scan_kernel, dim3(1), dim3(kPlanThreads), 0, stream, P);
+  if (P.nblk > 1) {
+    hipLaunchKernelGGL(plan_count_kernel, dim3((unsigned)P.nblk), dim3(kPlanThreads), 0, stream, P);
+    hipLaunchKernelGGL(plan_scan_kernel, dim3(1), dim3(kPlanThreads), 0, stream, P);
+  }
   hipLaunchKernelGGL(plan_write_kernel, dim3((unsigned)P.nblk), dim3(kPlanThreads), 0, stream, P);
-  const int cus = cu_count(ws->device);
-  hipLaunchKernelGGL(plan_items_kernel, dim3(cus * 4), dim3(kPlanThreads), 0, stream, P,
+  const uint64_t cus = (uint64_t)cu_count(ws->device);
+  auto sized = [&](uint64_t full, uint64_t per) {
+    return (unsigned)(item_hint ? std::max<uint64_t>(1, std::min<uint64_t>(full, ceil_div(item_hint, per))) : full);
+  };
+  hipLaunchKernelGGL(plan_items_kernel, dim3(sized(cus * 4, kPlanThreads)), dim3(kPlanThreads), 0, stream, P,
                      static_cast<uint32_t*>(ws->item_buf.ptr));
   BatchArgs B;
   B.ptrs = ptrs;
@@ -860,9 +875,9 @@ static int enqueue_batched(Workspace* ws, const void* const* ptrs, const uint64_
   B.tickets = static_cast<uint32_t*>(ws->tickets.ptr);
   B.ctl = P.ctl;
   B.status = device_status_word(ws->device);
-  const uint32_t bpc = tuning().blocks_per_cu;
-  hipLaunchKernelGGL(digest_batched_kernel, dim3(cus * bpc), dim3(kThreads), 0, stream, B);
-  hipLaunchKernelGGL(digest_tree_kernel, dim3(cus * 4), dim3(kThreads), 0, stream, B);
+  const uint64_t bpc = tuning().blocks_per_cu;
+  hipLaunchKernelGGL(digest_batched_kernel, dim3(sized(cus * bpc, 1)), dim3(kThreads), 0, stream, B);
+  hipLaunchKernelGGL(digest_tree_kernel, dim3(sized(cus * 4, 64 * kWaves)), dim3(kThreads), 0, stream, B);
   return check_hip(hipGetLastError(), "digest launch");
 }
 
@@ -931,14 +946,17 @@ extern "C" int odp_digest_buffers(const void* const* ptrs, const uint64_t* sizes
 }
 
 namespace odp {
-int digest_batched_direct(const void* const* ptrs, const uint64_t* sizes, size_t n, uint64_t* out, hipStream_t stream) {
+int digest_batched_direct(const void* const* ptrs, const uint64_t* sizes, size_t n, uint64_t* out, hipStream_t stream,
+                          uint64_t total_bytes) {
   if (n == 0) return ODP_OK;
   int err = 0;
   Workspace* ws = workspace_for(stream, &err);
   if (!ws) return err;
   if (n > ws->cap_buffers || !ws->cap_items)
     return set_error(ODP_ENOMEM, "digest: workspace for %zu buffers not reserved", n);
-  return enqueue_batched(ws, ptrs, sizes, n, out, stream);
+  // node items <= total_bytes / node + n; small groups <= n / 64 + 1
+  const uint64_t hint = total_bytes / kNodeBytes + n + n / kRows + 1;
+  return enqueue_batched(ws, ptrs, sizes, n, out, stream, hint);
 }
 }  // namespace odp
 

@@ -78,8 +78,10 @@ struct Tuning {
 Tuning& tuning();
 
 int digest_reserve(Workspace* ws, size_t max_buffers, uint64_t max_total_bytes);
-// Batched digest enqueued with direct launches (workspace reserved beforehand).
-int digest_batched_direct(const void* const* ptrs, const uint64_t* sizes, size_t n, uint64_t* out, hipStream_t stream);
+// Batched digest enqueued with direct launches (workspace reserved
+// beforehand); total_bytes, the sum of the sizes, sizes the grids.
+int digest_batched_direct(const void* const* ptrs, const uint64_t* sizes, size_t n, uint64_t* out, hipStream_t stream,
+                          uint64_t total_bytes);
 int analyze_reserve(Workspace* ws, size_t max_events);
 void analyze_release(Workspace* ws);
 

@@ -384,14 +384,14 @@ StageView stage_view(uint8_t* base, uint32_t m) {
 // Enqueues one tick: one staging copy, the digest of the payloads (one
 // persistent batched launch, or per-buffer launches in the plain mode), the
 // classification.
-static int launch_tick(odp_server* s, int b, uint32_t m) {
+static int launch_tick(odp_server* s, int b, uint32_t m, uint64_t bytes) {
   hipStream_t st = s->stream;
   ODP_HIP(hipMemcpyAsync(s->d_stage[b], s->h_stage[b], m * kStageBytes, hipMemcpyHostToDevice, st));
   const StageView hv = stage_view(s->h_stage[b], m), dv = stage_view(s->d_stage[b], m);
   // tick sizes change every tick: direct launches rather than a captured graph
   int e = s->cfg.mode == ODP_SERVER_PLAIN
               ? odp_digest_buffers_plain(reinterpret_cast<const void* const*>(hv.ptr), hv.size, m, s->d_dig[b], st)
-              : digest_batched_direct(reinterpret_cast<const void* const*>(dv.ptr), dv.size, m, s->d_dig[b], st);
+              : digest_batched_direct(reinterpret_cast<const void* const*>(dv.ptr), dv.size, m, s->d_dig[b], st, bytes);
   if (e) return e;
   TickArgs A;
   A.tick_ev = dv.ev;
@@ -492,7 +492,7 @@ extern "C" int odp_server_run(odp_server* s, const odp_event* events, const uint
         std::memmove(w.has, v.has, m);
       }
       if (m) {
-        int e = launch_tick(s, b, m);
+        int e = launch_tick(s, b, m, bytes);
         if (e) return e;
         inflight.push_back({b, first, m, bytes});
         inflight_bytes += bytes;
