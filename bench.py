@@ -53,6 +53,10 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="approximate CPU time budget of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--blocks-per-cu", type=int, default=None, help="batched digest tuning override")
+    ap.add_argument("--split-bytes", type=int, default=None, help="batched digest tuning override")
+    ap.add_argument("--tuning", default=None, metavar="JSON",
+                    help="apply a tuning file written by paper_2601_12713_amd/autotune.py")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="before the workload, one elementwise copy kernel (torch.neg on int32) reading and "
                          "writing BYTES: the calibration dispatch of the HBM byte counters")
@@ -272,7 +276,8 @@ def run_batch(args, torch, odp, W):
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "kernel": "plan + digest_batched_kernel graph", "kernel_ms": round(kern_ms, 4)},
-        "extras": {"per_buffer_GBps": round(total / (p_ms * 1e-3) / 1e9, 2), "per_buffer_ms": round(p_ms, 2),
+        "extras": {"tuning": odp.get_tuning(),
+                   "per_buffer_GBps": round(total / (p_ms * 1e-3) / 1e9, 2), "per_buffer_ms": round(p_ms, 2),
                    "speedup_vs_per_buffer": round(p_ms / kern_ms, 1)},
     }
 
@@ -446,6 +451,11 @@ def main():
     from paper_2601_12713_amd import odp
     from paper_2601_12713_amd import workloads as W
     odp.load()
+    if args.tuning:
+        from paper_2601_12713_amd import autotune
+        autotune.apply(args.tuning)
+    if args.blocks_per_cu is not None or args.split_bytes is not None:
+        odp.set_tuning(blocks_per_cu=args.blocks_per_cu, split_bytes=args.split_bytes)
     if args.copy_probe:
         src = torch.randint(0, 1 << 30, (args.copy_probe // 4,), dtype=torch.int32, device="cuda")
         dst = torch.empty_like(src)

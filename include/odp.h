@@ -288,7 +288,10 @@ int odp_device_status(void);
 typedef struct odp_tuning {
   uint32_t blocks_per_cu;   /* persistent workgroups per compute unit, 1..8 */
   uint32_t use_graph;       /* 1: replay the work plan + digest launch as a hipGraph */
-  uint32_t reserved[6];
+  uint32_t split_bytes;     /* level-1 nodes of at most this many bytes (0 or 4096..65536) are
+                               hashed and combined by one wavefront, four per work item;
+                               larger nodes take a whole workgroup */
+  uint32_t reserved[5];
 } odp_tuning;
 
 int odp_get_tuning(odp_tuning* out);

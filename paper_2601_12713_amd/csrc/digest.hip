@@ -47,7 +47,7 @@ struct NodeRec {
   const uint8_t* base;  // first byte of the node
   uint64_t* dst;        // where the node digest goes: out[i] for a one-node buffer, else its level-1 tree slot
   uint32_t len;         // bytes in the node, 1 .. kNodeBytes
-  uint32_t pad;
+  uint32_t buf;         // buffer index i
 };
 
 __device__ __forceinline__ void wave_fence() { __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront"); }
@@ -456,7 +456,9 @@ struct PlanArgs {
   uint64_t* tree_off;   // [n]
   uint64_t* tk_off;     // [n]
   uint32_t* small_list; // [n]
-  uint64_t* blk;        // [4 * nblk] per-tile sums, then exclusive prefixes
+  NodeRec* med_rec;     // [n] level-1 nodes of at most `split` bytes (one per buffer at most: its last)
+  uint32_t split;       // bytes; 0: none
+  uint64_t* blk;        // [kQ * nblk] per-tile sums, then exclusive prefixes
   uint64_t nblk;
   DigestCtl* ctl;
   uint64_t cap_items, cap_tree, cap_tk;
@@ -466,26 +468,33 @@ constexpr int kPlanThreads = 256;
 constexpr int kPlanPer = 8;  // buffers per thread
 constexpr int kPlanTile = kPlanThreads * kPlanPer;
 
-__device__ __forceinline__ void buffer_counts(uint64_t size, uint64_t c[4]) {
+// Per-buffer plan quantities: [0] level-1 nodes hashed by a whole workgroup
+// (node items), [1] 1 for a buffer of at most one leaf, [2] tree slots,
+// [3] tickets, [4] 1 when the buffer's last level-1 node has at most `split`
+// bytes and is hashed by one wavefront instead.
+constexpr int kQ = 5;
+
+__device__ __forceinline__ void buffer_counts(uint64_t size, uint32_t split, uint64_t c[kQ]) {
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) c[q] = 0;
   if (size <= kLeaf) {
-    c[0] = 0;
     c[1] = 1;
-    c[2] = 0;
-    c[3] = 0;
-  } else {
-    c[0] = ceil_div(ceil_div(size, kLeaf), kFanIn);
-    c[1] = 0;
-    tree_need(c[0], c[2], c[3]);
+    return;
   }
+  const uint64_t n1 = ceil_div(ceil_div(size, kLeaf), kFanIn);
+  const bool med = size - (n1 - 1) * kNodeBytes <= split;
+  c[0] = n1 - (med ? 1 : 0);
+  c[4] = med ? 1 : 0;
+  tree_need(n1, c[2], c[3]);
 }
 
-// Exclusive scan of 4 u64 quantities over the threads of a block; returns the
-// block totals in tot[].
-__device__ void block_scan4(uint64_t v[4], uint64_t tot[4]) {
-  __shared__ uint64_t sh[kPlanThreads / 64][4];
+// Exclusive scan of kQ u64 quantities over the threads of a block; returns
+// the block totals in tot[].
+__device__ void block_scan4(uint64_t v[kQ], uint64_t tot[kQ]) {
+  __shared__ uint64_t sh[kPlanThreads / 64][kQ];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < kQ; ++q) {
     uint64_t x = v[q];
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
@@ -497,7 +506,7 @@ __device__ void block_scan4(uint64_t v[4], uint64_t tot[4]) {
   }
   __syncthreads();
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < kQ; ++q) {
     uint64_t before = 0, all = 0;
     for (int j = 0; j < kPlanThreads / 64; ++j) {
       if (j < w) before += sh[j][q];
@@ -511,11 +520,12 @@ __device__ void block_scan4(uint64_t v[4], uint64_t tot[4]) {
 
 // Totals of the plan (node items, small buffers, tree and ticket slots) into
 // the control block; flags a plan that does not fit the workspace.
-__device__ void finalize_plan(const PlanArgs& A, const uint64_t carry[4]) {
+__device__ void finalize_plan(const PlanArgs& A, const uint64_t carry[kQ]) {
   DigestCtl* c = A.ctl;
   c->n_node_items = carry[0];
   c->n_small = carry[1];
-  c->n_items = carry[0] + ceil_div(carry[1], kRows);
+  c->n_med = carry[4];
+  c->n_items = carry[0] + ceil_div(carry[4], kWaves) + ceil_div(carry[1], kRows);
   c->tree_total = carry[2];
   c->tk_total = carry[3];
   c->head = 0;
@@ -526,43 +536,43 @@ __device__ void finalize_plan(const PlanArgs& A, const uint64_t carry[4]) {
 
 __global__ __launch_bounds__(kPlanThreads) void plan_count_kernel(PlanArgs A) {
   const uint64_t base = (uint64_t)blockIdx.x * kPlanTile + threadIdx.x * kPlanPer;
-  uint64_t s[4] = {0, 0, 0, 0};
+  uint64_t s[kQ] = {0, 0, 0, 0, 0};
   for (int j = 0; j < kPlanPer; ++j) {
     const uint64_t i = base + j;
     if (i < A.n) {
-      uint64_t c[4];
-      buffer_counts(A.sizes[i], c);
+      uint64_t c[kQ];
+      buffer_counts(A.sizes[i], A.split, c);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) s[q] += c[q];
+      for (int q = 0; q < kQ; ++q) s[q] += c[q];
     }
   }
-  uint64_t tot[4];
+  uint64_t tot[kQ];
   block_scan4(s, tot);
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) A.blk[4 * blockIdx.x + q] = tot[q];
+    for (int q = 0; q < kQ; ++q) A.blk[kQ * blockIdx.x + q] = tot[q];
   }
 }
 
 __global__ __launch_bounds__(kPlanThreads) void plan_scan_kernel(PlanArgs A) {
-  __shared__ uint64_t carry[4];
-  if (threadIdx.x < 4) carry[threadIdx.x] = 0;
+  __shared__ uint64_t carry[kQ];
+  if (threadIdx.x < kQ) carry[threadIdx.x] = 0;
   __syncthreads();
   for (uint64_t b0 = 0; b0 < A.nblk; b0 += kPlanThreads) {
     const uint64_t b = b0 + threadIdx.x;
-    uint64_t v[4] = {0, 0, 0, 0};
+    uint64_t v[kQ] = {0, 0, 0, 0, 0};
     if (b < A.nblk) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) v[q] = A.blk[4 * b + q];
+      for (int q = 0; q < kQ; ++q) v[q] = A.blk[kQ * b + q];
     }
-    uint64_t tot[4];
+    uint64_t tot[kQ];
     block_scan4(v, tot);
     if (b < A.nblk) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) A.blk[4 * b + q] = v[q] + carry[q];
+      for (int q = 0; q < kQ; ++q) A.blk[kQ * b + q] = v[q] + carry[q];
     }
     __syncthreads();
-    if (threadIdx.x < 4) carry[threadIdx.x] += tot[threadIdx.x];
+    if (threadIdx.x < kQ) carry[threadIdx.x] += tot[threadIdx.x];
     __syncthreads();
   }
   if (threadIdx.x == 0) finalize_plan(A, carry);
@@ -570,23 +580,27 @@ __global__ __launch_bounds__(kPlanThreads) void plan_scan_kernel(PlanArgs A) {
 
 __global__ __launch_bounds__(kPlanThreads) void plan_write_kernel(PlanArgs A) {
   const uint64_t base = (uint64_t)blockIdx.x * kPlanTile + threadIdx.x * kPlanPer;
-  uint64_t c[kPlanPer][4];
-  uint64_t s[4] = {0, 0, 0, 0};
+  uint64_t c[kPlanPer][kQ];
+  uint64_t s[kQ] = {0, 0, 0, 0, 0};
   for (int j = 0; j < kPlanPer; ++j) {
     const uint64_t i = base + j;
-    if (i < A.n) buffer_counts(A.sizes[i], c[j]);
-    else c[j][0] = c[j][1] = c[j][2] = c[j][3] = 0;
+    if (i < A.n) {
+      buffer_counts(A.sizes[i], A.split, c[j]);
+    } else {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) s[q] += c[j][q];
+      for (int q = 0; q < kQ; ++q) c[j][q] = 0;
+    }
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) s[q] += c[j][q];
   }
-  uint64_t tot[4];
+  uint64_t tot[kQ];
   block_scan4(s, tot);
   if (A.nblk == 1) {
     // one tile: its own scan is the whole plan (no count and scan launches)
     if (threadIdx.x == 0) finalize_plan(A, tot);
   } else {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) s[q] += A.blk[4 * blockIdx.x + q];
+    for (int q = 0; q < kQ; ++q) s[q] += A.blk[kQ * blockIdx.x + q];
   }
   for (int j = 0; j < kPlanPer; ++j) {
     const uint64_t i = base + j;
@@ -595,9 +609,18 @@ __global__ __launch_bounds__(kPlanThreads) void plan_write_kernel(PlanArgs A) {
       A.tree_off[i] = s[2];
       A.tk_off[i] = s[3];
       if (c[j][1]) A.small_list[s[1]] = (uint32_t)i;
+      if (c[j][4]) {
+        const uint64_t size = A.sizes[i], n1 = c[j][0] + 1;
+        NodeRec r;
+        r.base = static_cast<const uint8_t*>(A.ptrs[i]) + (n1 - 1) * kNodeBytes;
+        r.dst = n1 == 1 ? A.out + i : A.tree + s[2] + (n1 - 1);
+        r.len = (uint32_t)(size - (n1 - 1) * kNodeBytes);
+        r.buf = (uint32_t)i;
+        A.med_rec[s[4]] = r;
+      }
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) s[q] += c[j][q];
+    for (int q = 0; q < kQ; ++q) s[q] += c[j][q];
   }
 }
 
@@ -620,7 +643,7 @@ __global__ __launch_bounds__(kPlanThreads) void plan_items_kernel(PlanArgs A, ui
     r.base = static_cast<const uint8_t*>(A.ptrs[lo]) + node * kNodeBytes;
     r.dst = n1 == 1 ? A.out + lo : A.tree + A.tree_off[lo] + node;
     r.len = (uint32_t)min<uint64_t>(kNodeBytes, size - node * kNodeBytes);
-    r.pad = 0;
+    r.buf = (uint32_t)lo;
     A.rec[k] = r;
   }
 }
@@ -636,6 +659,7 @@ struct BatchArgs {
   const uint32_t* small_list;
   const uint32_t* item_buf;
   const NodeRec* rec;
+  const NodeRec* med_rec;
   uint64_t* tree;
   uint32_t* tickets;
   DigestCtl* ctl;
@@ -650,7 +674,7 @@ __device__ __forceinline__ NodeRec load_rec(const BatchArgs& A, uint32_t item, u
   r.base = nullptr;
   r.dst = nullptr;
   r.len = 0;
-  r.pad = 0;
+  r.buf = 0;
   if (item < n_node) r = A.rec[item];
   return r;
 }
@@ -678,7 +702,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
     if (blockIdx.x == 0 && threadIdx.x == 0 && A.status) *reinterpret_cast<volatile uint32_t*>(A.status) = (uint32_t)(-ODP_ECAPACITY);
     return;
   }
-  const uint64_t n_node = c->n_node_items, n_items = c->n_items, n_small = c->n_small;
+  const uint64_t n_node = c->n_node_items, n_items = c->n_items, n_small = c->n_small, n_med = c->n_med;
+  const uint64_t med_end = n_node + ceil_div(n_med, kWaves);
   const int t = threadIdx.x, w = uniform(t >> 6), lane = t & 63, r = lane >> 2;
   // items blockIdx.x and blockIdx.x + gridDim.x are this workgroup's; later
   // ones come from the queue, numbered from 2 * gridDim.x on. A workgroup
@@ -694,6 +719,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
     uint32_t claim = 0;
     if (t == 0) claim = first_queued + atomicAdd(&A.ctl->head, 1u);
     const bool is_node = cur < n_node;
+    const bool is_med = !is_node && cur < med_end;
     const uint8_t* base = uniform_ptr(rc.base);
     const uint32_t len = uniform(rc.len);
     const uint32_t nl = (len + kLeaf - 1) / kLeaf;
@@ -707,8 +733,20 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
       // stage registers are rematerialised instead of kept across it.
 #pragma unroll
       for (int j = 0; j < NL; ++j) RA[j] = RB[j] = u32x4{0u, 0u, 0u, 0u};
-      // rows of a partial or unaligned node, or up to 64 buffers of at most
-      // one leaf each (digest = XXH64 seed 0), 16 per wavefront
+      // This wavefront's medium node (a whole level-1 node of at most 16 leaves).
+      const uint64_t qm = (uint64_t)(cur - n_node) * kWaves + w;
+      const bool has_med = is_med && qm < n_med;
+      const uint8_t* mbase = nullptr;
+      uint64_t* mdst = nullptr;
+      uint32_t mlen = 0;
+      if (has_med) {
+        mbase = uniform_ptr(A.med_rec[qm].base);
+        mdst = reinterpret_cast<uint64_t*>(uniform(reinterpret_cast<uint64_t>(A.med_rec[qm].dst)));
+        mlen = uniform(A.med_rec[qm].len);
+      }
+      const uint32_t mnl = (mlen + kLeaf - 1) / kLeaf;
+      // rows of a partial or unaligned node, of a medium node, or of up to 64
+      // buffers of at most one leaf each (digest = XXH64 seed 0), 16 per wavefront
       if (lane < kRowsPerWave) {
         RowDesc d;
         if (is_node) {
@@ -716,8 +754,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
           d.present = leaf < nl;
           d.base = base + (d.present ? leaf * kLeaf : 0u);
           d.len = d.present ? min<uint32_t>(kLeaf, len - leaf * kLeaf) : 0u;
+        } else if (is_med) {
+          const uint32_t leaf = lane;
+          d.present = leaf < mnl;
+          d.base = d.present ? mbase + leaf * kLeaf : nullptr;
+          d.len = d.present ? min<uint32_t>(kLeaf, mlen - leaf * kLeaf) : 0u;
         } else {
-          const uint64_t q = (uint64_t)(cur - n_node) * kRows + w * kRowsPerWave + lane;
+          const uint64_t q = (uint64_t)(cur - med_end) * kRows + w * kRowsPerWave + lane;
           d.present = q < n_small;
           const uint32_t idx = d.present ? A.small_list[q] : 0u;
           d.base = d.present ? static_cast<const uint8_t*>(A.ptrs[idx]) : nullptr;
@@ -729,11 +772,21 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
       wave_fence();
       h = hash_wave_rows(rows, sm.slab[w]);
       pre = false;
+      if (is_med) {
+        // level-1 combine inside the wavefront, in its own slice of the leaf-digest buffer
+        uint64_t* ld = sm.leafdig[k & 1] + w * kRowsPerWave;
+        if ((lane & 3) == 0 && (uint32_t)r < mnl) ld[r] = h;
+        wave_fence();
+        if (has_med) {
+          const uint64_t d = xx_words4(ld, mnl, 1);
+          if (lane == 0) *mdst = d;
+        }
+      }
     }
     if ((lane & 3) == 0) {
       if (is_node) {
         if ((uint32_t)(w * kRowsPerWave + r) < nl) sm.leafdig[k & 1][w * kRowsPerWave + r] = h;
-      } else if (rows[r].present) {
+      } else if (!is_med && rows[r].present) {
         A.out[sm.outidx[w * kRowsPerWave + r]] = h;
       }
     }
@@ -783,6 +836,29 @@ __global__ __launch_bounds__(kThreads) void digest_tree_kernel(BatchArgs A) {
       tree_up(h, p, n2, 2, n1, n2, A.out + b, tree, A.tickets + uniform(A.tk_off[b]));
     }
   }
+  // a level-2 node whose only child is a buffer's last node, hashed as a medium node
+  const uint64_t n_med = c->n_med;
+  for (uint64_t base = wave * 64; base < n_med; base += nwaves * 64) {
+    const uint64_t j = base + lane;
+    bool alone = false;
+    if (j < n_med) {
+      const uint32_t b = A.med_rec[j].buf;
+      const uint64_t n1 = ceil_div(ceil_div(A.sizes[b], kLeaf), kFanIn);
+      alone = n1 > 1 && (n1 - 1) % kFanIn == 0;
+    }
+    uint64_t mask = __ballot(alone);
+    while (mask) {
+      const uint64_t jj = base + (uint64_t)__builtin_ctzll(mask);
+      mask &= mask - 1;
+      const uint32_t b = uniform(A.med_rec[jj].buf);
+      const uint64_t n1 = ceil_div(ceil_div(uniform(A.sizes[b]), kLeaf), kFanIn);
+      const uint64_t n2 = ceil_div(n1, kFanIn);
+      const uint64_t p = (n1 - 1) / kFanIn;
+      uint64_t* tree = A.tree + uniform(A.tree_off[b]);
+      const uint64_t h = xx_words4(tree + p * kFanIn, 1, 2);
+      tree_up(h, p, n2, 2, n1, n2, A.out + b, tree, A.tickets + uniform(A.tk_off[b]));
+    }
+  }
 }
 
 }  // namespace
@@ -803,7 +879,7 @@ int digest_reserve(Workspace* ws, size_t max_buffers, uint64_t max_total_bytes) 
     int e;
     if ((e = ws->node_off.ensure((nb + 1) * 8)) || (e = ws->tree_off.ensure(nb * 8)) ||
         (e = ws->tk_off.ensure(nb * 8)) || (e = ws->small_list.ensure(nb * 4)) ||
-        (e = ws->blk.ensure(nblk * 4 * 8)))
+        (e = ws->blk.ensure(nblk * kQ * 8)) || (e = ws->med_rec.ensure(nb * sizeof(NodeRec))))
       return e;
     ws->cap_buffers = nb;
   }
@@ -838,6 +914,8 @@ static int enqueue_batched(Workspace* ws, const void* const* ptrs, const uint64_
   P.out = out;
   P.tree = static_cast<uint64_t*>(ws->tree.ptr);
   P.rec = static_cast<NodeRec*>(ws->item_rec.ptr);
+  P.med_rec = static_cast<NodeRec*>(ws->med_rec.ptr);
+  P.split = tuning().split_bytes;
   P.n = n;
   P.node_off = static_cast<uint64_t*>(ws->node_off.ptr);
   P.tree_off = static_cast<uint64_t*>(ws->tree_off.ptr);
@@ -871,6 +949,7 @@ static int enqueue_batched(Workspace* ws, const void* const* ptrs, const uint64_
   B.small_list = P.small_list;
   B.item_buf = static_cast<const uint32_t*>(ws->item_buf.ptr);
   B.rec = P.rec;
+  B.med_rec = P.med_rec;
   B.tree = static_cast<uint64_t*>(ws->tree.ptr);
   B.tickets = static_cast<uint32_t*>(ws->tickets.ptr);
   B.ctl = P.ctl;
@@ -909,7 +988,7 @@ extern "C" int odp_digest_buffers(const void* const* ptrs, const uint64_t* sizes
   if (!tn.use_graph || capturing) return enqueue_batched(ws, ptrs, sizes, n, out, stream);
   const uint32_t grid = cu_count(ws->device) * tn.blocks_per_cu;
   if (!(ws->graph && ws->g_ptrs == ptrs && ws->g_sizes == sizes && ws->g_out == out && ws->g_n == n &&
-        ws->g_grid == grid)) {
+        ws->g_grid == grid && ws->g_split == tn.split_bytes)) {
     if (ws->graph) {
       ODP_HIP(hipGraphExecDestroy(ws->graph));
       ws->graph = nullptr;
@@ -940,6 +1019,7 @@ extern "C" int odp_digest_buffers(const void* const* ptrs, const uint64_t* sizes
     ws->g_out = out;
     ws->g_n = n;
     ws->g_grid = grid;
+    ws->g_split = tn.split_bytes;
   }
   ODP_HIP(hipGraphLaunch(ws->graph, stream));
   return ODP_OK;

@@ -40,6 +40,7 @@ struct DigestCtl {
   uint64_t n_items;       // node items + small groups
   uint64_t tree_total;    // tree scratch slots needed
   uint64_t tk_total;      // ticket slots needed
+  uint64_t n_med;         // level-1 nodes small enough for one wavefront
   uint32_t head;          // work-queue head
   uint32_t overflow;      // 1 when the plan did not fit the workspace
 };
@@ -48,7 +49,7 @@ struct Workspace {
   int device = -1;
   hipStream_t stream = nullptr;
   // batched digest
-  DevBuf node_off, tree_off, tk_off, small_list, blk, ctl, item_buf, item_rec, tree, tickets;
+  DevBuf node_off, tree_off, tk_off, small_list, blk, ctl, item_buf, item_rec, med_rec, tree, tickets;
   size_t cap_buffers = 0;
   uint64_t cap_items = 0, cap_tree = 0, cap_tk = 0;
   // plain digest (one buffer at a time)
@@ -64,6 +65,7 @@ struct Workspace {
   void* g_out = nullptr;
   size_t g_n = 0;
   uint32_t g_grid = 0;
+  uint32_t g_split = 0;
 };
 
 Workspace* workspace_for(hipStream_t stream, int* err);
@@ -74,6 +76,7 @@ int cu_count(int device);
 struct Tuning {
   uint32_t blocks_per_cu = 8;
   uint32_t use_graph = 1;
+  uint32_t split_bytes = 65536;
 };
 Tuning& tuning();
 

@@ -150,7 +150,7 @@ extern "C" int odp_release(void) {
     (void)hipDeviceSynchronize();
     if (ws->graph) (void)hipGraphExecDestroy(ws->graph);
     DevBuf* bufs[] = {&ws->node_off, &ws->tree_off, &ws->tk_off, &ws->small_list, &ws->blk, &ws->ctl,
-                      &ws->item_buf, &ws->item_rec, &ws->tree, &ws->tickets, &ws->p_tree, &ws->p_tickets};
+                      &ws->item_buf, &ws->item_rec, &ws->med_rec, &ws->tree, &ws->tickets, &ws->p_tree, &ws->p_tickets};
     for (DevBuf* b : bufs) b->release();
     analyze_release(ws);
     delete ws;
@@ -180,6 +180,7 @@ extern "C" int odp_get_tuning(odp_tuning* out) {
   *out = odp_tuning{};
   out->blocks_per_cu = g_tuning.blocks_per_cu;
   out->use_graph = g_tuning.use_graph;
+  out->split_bytes = g_tuning.split_bytes;
   return ODP_OK;
 }
 
@@ -188,7 +189,10 @@ extern "C" int odp_set_tuning(const odp_tuning* in) {
   if (in->blocks_per_cu < 1 || in->blocks_per_cu > 8)
     return set_error(ODP_EINVAL, "odp_set_tuning: blocks_per_cu %u outside 1..8", in->blocks_per_cu);
   if (in->use_graph > 1) return set_error(ODP_EINVAL, "odp_set_tuning: use_graph must be 0 or 1");
+  if (in->split_bytes != 0 && (in->split_bytes < 4096 || in->split_bytes > 65536))
+    return set_error(ODP_EINVAL, "odp_set_tuning: split_bytes %u not 0 or in 4096..65536", in->split_bytes);
   g_tuning.blocks_per_cu = in->blocks_per_cu;
   g_tuning.use_graph = in->use_graph;
+  g_tuning.split_bytes = in->split_bytes;
   return ODP_OK;
 }

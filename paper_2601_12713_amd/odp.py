@@ -42,7 +42,7 @@ class OdpError(RuntimeError):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("blocks_per_cu", ctypes.c_uint32), ("use_graph", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32 * 6)]
+                ("split_bytes", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 5)]
 
 
 _lib = None
@@ -55,6 +55,8 @@ def load(path=LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError("libodp.so is not built (%s); run paper_2601_12713_amd/build.py" % path)
+    # torch first: the library then binds to the HIP runtime torch already loaded
+    import torch  # noqa: F401
     L = ctypes.CDLL(path)
     p, sz, u64, i32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_uint64, ctypes.c_int
     L.odp_digest_buffers.argtypes = [p, p, sz, p, p]
@@ -72,7 +74,20 @@ def load(path=LIB_PATH):
         if f != "odp_last_error_string" and not f.startswith("odp_server"):
             getattr(L, f).restype = i32
     _lib = L
+    _apply_saved_tuning()
     return L
+
+
+def _apply_saved_tuning():
+    """Applies the autotuner's file for this GPU (tuning/<arch>.json) when present."""
+    import torch
+    if not torch.cuda.is_available():
+        return
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    path = os.path.join(HERE, "tuning", "%s.json" % arch)
+    if os.path.exists(path):
+        from . import autotune
+        autotune.apply(path)
 
 
 def _check(code):
@@ -161,16 +176,18 @@ def device_status():
 def get_tuning():
     t = Tuning()
     _check(load().odp_get_tuning(ctypes.byref(t)))
-    return {"blocks_per_cu": int(t.blocks_per_cu), "use_graph": int(t.use_graph)}
+    return {"blocks_per_cu": int(t.blocks_per_cu), "use_graph": int(t.use_graph), "split_bytes": int(t.split_bytes)}
 
 
-def set_tuning(blocks_per_cu=None, use_graph=None):
+def set_tuning(blocks_per_cu=None, use_graph=None, split_bytes=None):
     t = Tuning()
     _check(load().odp_get_tuning(ctypes.byref(t)))
     if blocks_per_cu is not None:
         t.blocks_per_cu = blocks_per_cu
     if use_graph is not None:
         t.use_graph = int(use_graph)
+    if split_bytes is not None:
+        t.split_bytes = int(split_bytes)
     _check(load().odp_set_tuning(ctypes.byref(t)))
 
 

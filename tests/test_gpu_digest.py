@@ -103,6 +103,36 @@ def test_repeated_calls_graph_and_direct(odp):
     assert odp.device_status() == 0
 
 
+# Level-1 nodes at every side of the one-wavefront split: whole buffers of
+# 2, 16 and 17 leaves, a last node of one leaf, a last node alone in its
+# level-2 group (65 and 64*64 + 1 level-1 nodes), and a full 64-node buffer.
+SPLIT_SIZES = [4097, 16 * 4096, 16 * 4096 + 1, 32 * 4096, 262144 + 4096, 262144 + 65536, 262144 + 65537,
+               64 * 262144, 64 * 262144 + 100, 65 * 262144 + 4096 * 16, 4096 * 262144 + 7]
+
+
+def test_tuning_points_same_digests(odp):
+    """Six launch configurations (workgroups per CU, graph or direct, split
+    between one-wavefront and one-workgroup nodes) give the oracle's digests."""
+    rng = np.random.default_rng(18)
+    host = [rng.integers(0, 256, size=int(s), dtype=np.uint8) for s in SPLIT_SIZES]
+    host += [rng.integers(0, 256, size=int(s), dtype=np.uint8) for s in rng.integers(1, 300_000, size=300)]
+    want = oracle.d64_many(host).tolist()
+    t = [dev_bytes(h) for h in host]
+    saved = odp.get_tuning()
+    try:
+        for bpc, graph, split in [(8, 1, 65536), (1, 1, 0), (2, 0, 4096), (4, 1, 16384), (8, 0, 32768),
+                                  (3, 1, 65536)]:
+            odp.set_tuning(blocks_per_cu=bpc, use_graph=graph, split_bytes=split)
+            for _ in range(2):
+                assert odp.digest_tensors(t).tolist() == want, (bpc, graph, split)
+        with pytest.raises(odp.OdpError):
+            odp.set_tuning(split_bytes=100)
+    finally:
+        odp.set_tuning(**saved)
+    assert odp.digest_tensors(t, plain=True).tolist() == want
+    assert odp.device_status() == 0
+
+
 def test_non_default_stream(odp):
     rng = np.random.default_rng(17)
     host = [rng.integers(0, 256, size=int(s), dtype=np.uint8) for s in [100, 70_000, 2_000_000]]
