@@ -2,16 +2,21 @@
 //
 // The paper hashes every transferred buffer with one serial 64-bit hash on the
 // host (Sec. 5.1, App. B). Here every 4096-byte leaf is hashed by four lanes of
-// a wavefront (one per XXH64 accumulator), leaves are staged through LDS from
-// coalesced 128-bit nontemporal loads, 64 leaf digests are combined inside the
-// workgroup, and the upper tree levels are finished by whichever workgroup
-// completes the last child of a node (an atomic ticket per node).
+// a wavefront (one per XXH64 accumulator); leaves are staged through LDS from
+// coalesced 128-bit nontemporal loads, and leaf digests are combined into
+// level-1 node digests (64 leaves, 256 KiB) inside the workgroup or wavefront.
 //
-// Work unit ("item"): either one level-1 node (64 leaves, 256 KiB) of a buffer
-// larger than one leaf, or a group of 64 buffers of at most one leaf each.
-// A workgroup (4 wavefronts) handles one item; each wavefront owns 16 rows
-// (leaves or small buffers) and stages, hashes and finishes them on its own,
-// so the only workgroup barriers are around the level-1 combine.
+// Plain form (one launch per buffer): one workgroup per level-1 node; the
+// upper levels are finished by whichever workgroup completes the last child of
+// a node (an atomic ticket per node).
+//
+// Batched form (one persistent launch for n buffers): a device-side plan
+// splits the buffers into work items: level-1 nodes hashed by a whole
+// workgroup, groups of four small level-1 nodes (at most `split` bytes, one per
+// wavefront), and groups of 64 buffers of at most one leaf. Workgroups claim
+// items ahead of time and carry their load pipeline from one node into the
+// next; level-1 digests are stored without waiting, and a second kernel climbs
+// the levels above.
 #include "internal.h"
 #include "xxh64_dev.h"
 
@@ -105,72 +110,6 @@ __device__ __forceinline__ uint64_t finish_row(uint64_t acc, const RowDesc& hrow
     h = xx_avalanche(h);
   }
   return h;
-}
-
-// Fast path: 16 whole, 16-byte aligned leaves at leaf_base + r*4096 (leaf_base
-// wave-uniform). Each step stages 512 bytes of every leaf (8 KiB per wavefront,
-// eight fully coalesced 1 KiB loads of 128-bit per lane) through the
-// wavefront's LDS slab; lane 4r+a then folds accumulator a's words of leaf r.
-// Two steps are in flight while one is hashed. Returns the leaf digest in
-// lane 4r.
-__device__ __forceinline__ uint64_t hash_wave_full_leaves(const uint8_t* leaf_base, uint8_t* slab) {
-  const int lane = threadIdx.x & 63;
-  constexpr int NL = kSlab / 64;    // 128-bit loads per lane per step
-  constexpr int LPR = kSlab / 16;   // lanes covering one row in a load
-  constexpr int RPI = 64 / LPR;     // rows covered by one wavefront load
-  constexpr uint32_t NS = kLeaf / kSlab;
-  const uint32_t lrow = lane / LPR, col = (lane % LPR) * 16;
-  const uint32_t goff = lrow * kLeaf + col;           // per-lane byte offset of load k = 0
-  uint8_t* const wr = slab + lrow * kStride + col;    // per-lane LDS target of load k = 0
-  const int hr = lane >> 2, a = lane & 3;
-  const uint8_t* const rd = slab + hr * kStride + a * 8;
-  uint64_t acc = xx_acc_init(0, a);
-
-  u32x4 RA[NL], RB[NL];
-#pragma unroll
-  for (int k = 0; k < NL; ++k) RA[k] = ld_global_nt(leaf_base + k * RPI * kLeaf + goff);
-#pragma unroll
-  for (int k = 0; k < NL; ++k) RB[k] = ld_global_nt(leaf_base + k * RPI * kLeaf + goff + kSlab);
-#pragma unroll 1
-  for (uint32_t s = 0; s < NS; s += 2) {
-#pragma unroll
-    for (int k = 0; k < NL; ++k) *reinterpret_cast<u32x4*>(wr + k * RPI * kStride) = RA[k];
-    if (s + 2 < NS) {
-#pragma unroll
-      for (int k = 0; k < NL; ++k) RA[k] = ld_global_nt(leaf_base + k * RPI * kLeaf + goff + (s + 2) * kSlab);
-    }
-    wave_fence();
-#pragma unroll
-    for (int h2 = 0; h2 < kSlab / 128; ++h2) {
-      uint64_t w[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) w[q] = *reinterpret_cast<const uint64_t*>(rd + (h2 * 4 + q) * 32);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) acc = xx_round(acc, w[q]);
-    }
-    wave_fence();
-#pragma unroll
-    for (int k = 0; k < NL; ++k) *reinterpret_cast<u32x4*>(wr + k * RPI * kStride) = RB[k];
-    if (s + 3 < NS) {
-#pragma unroll
-      for (int k = 0; k < NL; ++k) RB[k] = ld_global_nt(leaf_base + k * RPI * kLeaf + goff + (s + 3) * kSlab);
-    }
-    wave_fence();
-#pragma unroll
-    for (int h2 = 0; h2 < kSlab / 128; ++h2) {
-      uint64_t w[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) w[q] = *reinterpret_cast<const uint64_t*>(rd + (h2 * 4 + q) * 32);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) acc = xx_round(acc, w[q]);
-    }
-    wave_fence();
-  }
-  RowDesc full;
-  full.base = leaf_base + hr * kLeaf;
-  full.len = kLeaf;
-  full.present = 1;
-  return finish_row(acc, full);
 }
 
 // Fast path as one stage of a wavefront's continuous stream of items: 16
@@ -324,17 +263,21 @@ __device__ __forceinline__ uint64_t load_coherent(const uint64_t* p) {
 }
 __device__ __forceinline__ void wait_stores_done() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
-// XXH64 of `nw` child digests written by other workgroups (see xx_words4).
-__device__ __forceinline__ uint64_t xx_words4_coherent(const uint64_t* w, uint32_t nw, uint64_t seed) {
-  const int a = threadIdx.x & 3;
+// XXH64 of `nw` (<= 64) child digests written by other workgroups, by one
+// whole wavefront: lane i fetches child i (all fetches in flight at once),
+// then lanes 4g+a fold accumulator a's words, taken by cross-lane shuffles.
+// Every lane returns the digest.
+__device__ __forceinline__ uint64_t xx_words64_coherent(const uint64_t* w, uint32_t nw, uint64_t seed) {
+  const int lane = threadIdx.x & 63, a = lane & 3;
+  const uint64_t v = (uint32_t)lane < nw ? load_coherent(w + lane) : 0ull;
   const uint32_t nstripes = nw / 4;
   uint64_t acc = xx_acc_init(seed, a);
-  for (uint32_t s = 0; s < nstripes; ++s) acc = xx_round(acc, load_coherent(w + s * 4 + a));
+  for (uint32_t s = 0; s < nstripes; ++s) acc = xx_round(acc, __shfl(v, (int)(s * 4) + a, 64));
   uint64_t v1, v2, v3, v4;
   xx_gather4(acc, v1, v2, v3, v4);
   uint64_t h = nstripes ? xx_converge(v1, v2, v3, v4) : seed + kP5;
   h += uint64_t(nw) * 8;
-  for (uint32_t i = nstripes * 4; i < nw; ++i) h = xx_step8(h, load_coherent(w + i));
+  for (uint32_t i = nstripes * 4; i < nw; ++i) h = xx_step8(h, __shfl(v, (int)i, 64));
   return xx_avalanche(h);
 }
 
@@ -366,7 +309,7 @@ __device__ __forceinline__ void tree_up(uint64_t h, uint64_t m, uint64_t nj, uin
     old = __shfl(old, 0, 64);
     if (old != nchild - 1) return;
     if (lane == 0) __hip_atomic_store(tk + tkoff + p, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    h = xx_words4_coherent(tree + loff + p * kFanIn, nchild, level + 1);
+    h = xx_words64_coherent(tree + loff + p * kFanIn, nchild, level + 1);
     h = __shfl(h, 0, 64);
     ++level;
     m = p;
@@ -392,7 +335,10 @@ __device__ __forceinline__ void run_node(Smem& sm, const uint8_t* buf, uint64_t 
                          (wfirst + kRowsPerWave) * kLeaf <= size;
   uint64_t h;
   if (wave_full) {
-    h = hash_wave_full_leaves(buf + wfirst * kLeaf, sm.slab[w]);
+    constexpr int NL = kSlab / 64;
+    u32x4 RA[NL], RB[NL];
+    bool pre = false;
+    h = hash_wave_leaves_pipe<NL>(uniform_ptr(buf + wfirst * kLeaf), nullptr, pre, RA, RB, sm.slab[w]);
   } else {
     RowDesc* rows = sm.rows + w * kRowsPerWave;
     if ((t & 63) < kRowsPerWave) {

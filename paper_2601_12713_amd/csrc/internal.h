@@ -73,10 +73,12 @@ uint32_t* device_status_word(int device);  // device-visible sticky status (host
 int current_device(int* dev);
 int cu_count(int device);
 
+// Defaults: the autotuner's choice on MI355X (LDS admits four of the digest's
+// workgroups per compute unit, so more only queue).
 struct Tuning {
-  uint32_t blocks_per_cu = 8;
+  uint32_t blocks_per_cu = 4;
   uint32_t use_graph = 1;
-  uint32_t split_bytes = 65536;
+  uint32_t split_bytes = 32768;
 };
 Tuning& tuning();
 
