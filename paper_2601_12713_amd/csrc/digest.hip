@@ -200,16 +200,26 @@ __device__ __forceinline__ uint64_t hash_wave_leaves_pipe(const uint8_t* leaf_ba
   return finish_row(acc, full);
 }
 
-// General path: 16 rows of any length (<= 4096) and presence. 16-byte aligned
-// rows are staged through LDS with predicated loads, one step at a time;
-// otherwise every lane reads its words straight from memory at any alignment.
-// Returns the row digest in lane 4r.
+// General path: 16 rows of any length (<= 4096) and presence. When every
+// present row is 16-byte aligned, rows are staged through LDS like the fast
+// path (same lane mapping, two steps in flight) with loads predicated on each
+// row's length; a 16-byte load that crosses a row's end stays inside the
+// row's last 16-byte granule, so inside the same page. Otherwise every lane
+// reads its words straight from memory at any alignment, eight stripes per
+// batch of independent loads. Returns the row digest in lane 4r.
+__device__ __forceinline__ void rows_load(u32x4 (&R)[kSlab / 64], const RowDesc& ra, const RowDesc& rb, uint32_t step_off) {
+  const int lane = threadIdx.x & 63;
+  const uint32_t lc = (uint32_t)(lane & 7) * 16;
+#pragma unroll
+  for (int k = 0; k < kSlab / 64; ++k) {
+    const RowDesc& d = (k & 1) ? rb : ra;
+    const uint32_t o = step_off + (uint32_t)(k >> 1) * 128 + lc;
+    if (o < d.len) R[k] = ld_global_nt(d.base + o);
+  }
+}
+
 __device__ __forceinline__ uint64_t hash_wave_rows(const RowDesc* rows, uint8_t* slab) {
   const int lane = threadIdx.x & 63;
-  constexpr int LPR = kSlab / 16;
-  constexpr int RPI = 64 / LPR;
-  const uint32_t lrow = lane / LPR, col = (lane % LPR) * 16;
-
   const RowDesc mine = rows[lane & 15];
   const bool aligned = !mine.present || ((reinterpret_cast<uintptr_t>(mine.base) & 15) == 0);
   const bool all_aligned = __all(aligned);
@@ -224,27 +234,48 @@ __device__ __forceinline__ uint64_t hash_wave_rows(const RowDesc* rows, uint8_t*
   uint64_t acc = xx_acc_init(0, a);
 
   if (all_aligned) {
+    // lane L loads for rows L/8 and L/8 + 8 (absent rows count as length 0)
+    RowDesc ra = rows[lane >> 3], rb = rows[(lane >> 3) + 8];
+    if (!ra.present) ra.len = 0;
+    if (!rb.present) rb.len = 0;
     const uint8_t* rd = slab + hr * kStride + a * 8;
     const uint32_t nslab = (mlen + kSlab - 1) / kSlab;
+    u32x4 R0[kSlab / 64], R1[kSlab / 64];
+#pragma unroll
+    for (int k = 0; k < kSlab / 64; ++k) R0[k] = R1[k] = u32x4{0u, 0u, 0u, 0u};
+    rows_load(R0, ra, rb, 0);
+    rows_load(R1, ra, rb, kSlab);
 #pragma unroll 1
-    for (uint32_t s = 0; s < nslab; ++s) {
-      const uint32_t o = s * kSlab + col;
-#pragma unroll 1
-      for (int k = 0; k < kSlab / 64; ++k) {
-        const RowDesc d = rows[k * RPI + lrow];
-        if (d.present && o < d.len)
-          *reinterpret_cast<u32x4*>(slab + (k * RPI + lrow) * kStride + col) = ld_global_nt(d.base + o);
-      }
+    for (uint32_t s = 0; s < nslab; s += 2) {
+      fast_stage(R0, slab);
+      if (s + 2 < nslab) rows_load(R0, ra, rb, (s + 2) * kSlab);
       wave_fence();
-      const uint32_t q0 = s * (kSlab / 32);
-#pragma unroll 1
+      uint32_t q0 = s * (kSlab / 32);
+#pragma unroll
       for (int q = 0; q < kSlab / 32; ++q)
         if (q0 + q < nstripes) acc = xx_round(acc, *reinterpret_cast<const uint64_t*>(rd + q * 32));
       wave_fence();
+      if (s + 1 < nslab) {
+        fast_stage(R1, slab);
+        if (s + 3 < nslab) rows_load(R1, ra, rb, (s + 3) * kSlab);
+        wave_fence();
+        q0 += kSlab / 32;
+#pragma unroll
+        for (int q = 0; q < kSlab / 32; ++q)
+          if (q0 + q < nstripes) acc = xx_round(acc, *reinterpret_cast<const uint64_t*>(rd + q * 32));
+        wave_fence();
+      }
     }
   } else {
 #pragma unroll 1
-    for (uint32_t s = 0; s < nstripes; ++s) acc = xx_round(acc, load64_any(hrow.base + s * 32 + a * 8));
+    for (uint32_t s0 = 0; s0 < nstripes; s0 += 8) {
+      uint64_t wv[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) wv[j] = s0 + j < nstripes ? load64_any(hrow.base + (s0 + j) * 32 + a * 8) : 0ull;
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (s0 + j < nstripes) acc = xx_round(acc, wv[j]);
+    }
   }
   return finish_row(acc, hrow);
 }
