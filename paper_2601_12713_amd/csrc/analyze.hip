@@ -124,6 +124,52 @@ __device__ __forceinline__ void mask_update(WordMask* m, unsigned long long vor,
   atomicAnd(&m->vand, vand);
 }
 
+// Per-block partials of the grid-wide reductions of the big launches
+// (classification, subset compaction, DD/RT): every block stores its own
+// slot entry and one small kernel reduces each slot afterwards, so no two
+// blocks touch the same word (same-address atomics from thousands of blocks
+// serialise at one L2 channel).
+enum Slot : uint32_t {
+  S_N_INVALID, S_N_TRANSFERS, S_N_KERNELS, S_DIG_OR, S_DIG_AND, S_FIRST_BAD, S_MAX_EP,
+  S_AD_DEV_OR, S_AD_DEV_AND, S_AD_ADDR_OR, S_AD_ADDR_AND, S_KS_OR, S_KS_AND, S_KE_OR, S_KE_AND, S_KD_OR, S_KD_AND,
+  S_DD_EVENTS, S_DD_GROUPS, S_DD_BYTES, S_DD_TIME, S_RT_PAIRS, S_RT_RX, S_RT_BYTES, S_RT_TIME,
+  kSlots
+};
+constexpr uint32_t kSlotsPhase1 = S_DD_EVENTS;  // slots reduced before the sorts
+
+struct Parts {
+  unsigned long long* p;  // [kSlots][stride]
+  uint32_t stride;        // tiles of the capacity
+  __device__ unsigned long long* at(uint32_t slot) const { return p + (size_t)slot * stride + blockIdx.x; }
+};
+
+enum RedOp : int { R_ADD, R_OR, R_AND, R_MIN, R_MAX };
+
+template <RedOp OP>
+__device__ __forceinline__ unsigned long long red2(unsigned long long a, unsigned long long b) {
+  if constexpr (OP == R_ADD) return a + b;
+  if constexpr (OP == R_OR) return a | b;
+  if constexpr (OP == R_AND) return a & b;
+  if constexpr (OP == R_MIN) return a < b ? a : b;
+  return a > b ? a : b;
+}
+
+// Reduces v over the block; thread 0 stores the result to *dst.
+template <RedOp OP>
+__device__ void block_store(unsigned long long* dst, unsigned long long v) {
+  __shared__ unsigned long long sh[kT / 64];
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = red2<OP>(v, __shfl_xor(v, o, 64));
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long r = sh[0];
+    for (int w = 1; w < kT / 64; ++w) r = red2<OP>(r, sh[w]);
+    *dst = r;
+  }
+  __syncthreads();
+}
+
 __device__ void block_mask(WordMask* m, unsigned long long vor, unsigned long long vand, bool any) {
   __shared__ unsigned long long so[kT / 64], sa[kT / 64];
   __shared__ int sany[kT / 64];
@@ -191,7 +237,7 @@ __device__ __forceinline__ bool dev_ok(int d) { return d >= -1 && d <= ODP_MAX_D
 __global__ __launch_bounds__(kT) void classify_kernel(const odp_event* __restrict__ ev, uint32_t n, uint8_t* __restrict__ flags,
                                                       uint8_t* __restrict__ cls, uint8_t* __restrict__ aux,
                                                       unsigned long long* __restrict__ keys, uint32_t* __restrict__ vals,
-                                                      uint32_t* __restrict__ wave_cnt, AnaCtl* ctl, odp_report* rep) {
+                                                      uint32_t* __restrict__ wave_cnt, Parts parts) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const uint32_t wid = blockIdx.x * (kT / 64) + w;
   const uint32_t wb = wid * kWaveElems;
@@ -257,14 +303,13 @@ __global__ __launch_bounds__(kT) void classify_kernel(const odp_event* __restric
     wave_cnt[2 * wid] = c_ad;
     wave_cnt[2 * wid + 1] = c_k;
   }
-  block_add(&rep->n_invalid, n_inv);
-  block_add(&rep->n_transfers, n_tx);
-  block_add(&rep->n_kernels, n_k);
-  block_mask(&ctl->m_digest, kor, kand, true);
-  for (int o = 32; o >= 1; o >>= 1) bad = min(bad, (uint32_t)__shfl_xor((int)bad, o, 64));
-  if (lane == 0 && bad != kNone) atomicMin(&ctl->first_bad, bad);
-  for (int o = 32; o >= 1; o >>= 1) mep = max(mep, (uint32_t)__shfl_xor((int)mep, o, 64));
-  if (lane == 0 && mep) atomicMax(&ctl->max_ep, mep);
+  block_store<R_ADD>(parts.at(S_N_INVALID), n_inv);
+  block_store<R_ADD>(parts.at(S_N_TRANSFERS), n_tx);
+  block_store<R_ADD>(parts.at(S_N_KERNELS), n_k);
+  block_store<R_OR>(parts.at(S_DIG_OR), kor);
+  block_store<R_AND>(parts.at(S_DIG_AND), kand);
+  block_store<R_MIN>(parts.at(S_FIRST_BAD), bad);
+  block_store<R_MAX>(parts.at(S_MAX_EP), mep);
 }
 
 // ---------------------------------------------------------------------------
@@ -327,7 +372,7 @@ struct SubsetOut {
 // per-wavefront counts, so no workgroup barrier is needed between rounds.
 __global__ __launch_bounds__(kT) void subset_scatter_kernel(const odp_event* __restrict__ ev, const uint8_t* __restrict__ cls,
                                                             uint32_t n, const uint32_t* __restrict__ wave_off, SubsetOut S,
-                                                            AnaCtl* ctl) {
+                                                            Parts parts) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const uint32_t wid = blockIdx.x * (kT / 64) + w;
   // lane l owns the 16 consecutive records wid*1024 + 16l .. +15
@@ -394,11 +439,79 @@ __global__ __launch_bounds__(kT) void subset_scatter_kernel(const odp_event* __r
       ++q1;
     }
   }
-  block_mask(&ctl->m_ad_dev, o_dev, a_dev, nad > 0);
-  block_mask(&ctl->m_ad_addr, o_addr, a_addr, nad > 0);
-  block_mask(&ctl->m_k_start, o_ks, a_ks, nk > 0);
-  block_mask(&ctl->m_k_end, o_ke, a_ke, nk > 0);
-  block_mask(&ctl->m_k_dev, o_kd, a_kd, nk > 0);
+  // (identity values where a lane saw no such record)
+  block_store<R_OR>(parts.at(S_AD_DEV_OR), o_dev);
+  block_store<R_AND>(parts.at(S_AD_DEV_AND), a_dev);
+  block_store<R_OR>(parts.at(S_AD_ADDR_OR), o_addr);
+  block_store<R_AND>(parts.at(S_AD_ADDR_AND), a_addr);
+  block_store<R_OR>(parts.at(S_KS_OR), o_ks);
+  block_store<R_AND>(parts.at(S_KS_AND), a_ks);
+  block_store<R_OR>(parts.at(S_KE_OR), o_ke);
+  block_store<R_AND>(parts.at(S_KE_AND), a_ke);
+  block_store<R_OR>(parts.at(S_KD_OR), o_kd);
+  block_store<R_AND>(parts.at(S_KD_AND), a_kd);
+}
+
+// One block per slot: reduces the blocks' partials of slots [first, first +
+// gridDim.x) into the control block and the report.
+__global__ __launch_bounds__(kT) void reduce_parts_kernel(Parts parts, uint32_t nb, uint32_t first, AnaCtl* ctl,
+                                                          odp_report* rep) {
+  const uint32_t slot = first + blockIdx.x;
+  const unsigned long long* p = parts.p + (size_t)slot * parts.stride;
+  int op = R_ADD;
+  switch (slot) {
+    case S_DIG_OR: case S_AD_DEV_OR: case S_AD_ADDR_OR: case S_KS_OR: case S_KE_OR: case S_KD_OR: op = R_OR; break;
+    case S_DIG_AND: case S_AD_DEV_AND: case S_AD_ADDR_AND: case S_KS_AND: case S_KE_AND: case S_KD_AND: op = R_AND; break;
+    case S_FIRST_BAD: op = R_MIN; break;
+    case S_MAX_EP: op = R_MAX; break;
+    default: break;
+  }
+  unsigned long long v = op == R_AND || op == R_MIN ? ~0ull : 0ull;
+  for (uint32_t b = threadIdx.x; b < nb; b += kT) {
+    const unsigned long long x = p[b];
+    v = op == R_ADD ? v + x : op == R_OR ? (v | x) : op == R_AND ? (v & x) : op == R_MIN ? min(v, x) : max(v, x);
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const unsigned long long x = __shfl_xor(v, o, 64);
+    v = op == R_ADD ? v + x : op == R_OR ? (v | x) : op == R_AND ? (v & x) : op == R_MIN ? min(v, x) : max(v, x);
+  }
+  __shared__ unsigned long long sh[kT / 64];
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  for (int t = 1; t < kT / 64; ++t) {
+    const unsigned long long x = sh[t];
+    v = op == R_ADD ? v + x : op == R_OR ? (v | x) : op == R_AND ? (v & x) : op == R_MIN ? min(v, x) : max(v, x);
+  }
+  switch (slot) {
+    case S_N_INVALID: rep->n_invalid = v; break;
+    case S_N_TRANSFERS: rep->n_transfers = v; break;
+    case S_N_KERNELS: rep->n_kernels = v; break;
+    case S_DIG_OR: ctl->m_digest.vor = v; break;
+    case S_DIG_AND: ctl->m_digest.vand = v; break;
+    case S_FIRST_BAD: ctl->first_bad = (uint32_t)min(v, (unsigned long long)kNone); break;
+    case S_MAX_EP: ctl->max_ep = (uint32_t)v; break;
+    case S_AD_DEV_OR: ctl->m_ad_dev.vor = v; break;
+    case S_AD_DEV_AND: ctl->m_ad_dev.vand = v; break;
+    case S_AD_ADDR_OR: ctl->m_ad_addr.vor = v; break;
+    case S_AD_ADDR_AND: ctl->m_ad_addr.vand = v; break;
+    case S_KS_OR: ctl->m_k_start.vor = v; break;
+    case S_KS_AND: ctl->m_k_start.vand = v; break;
+    case S_KE_OR: ctl->m_k_end.vor = v; break;
+    case S_KE_AND: ctl->m_k_end.vand = v; break;
+    case S_KD_OR: ctl->m_k_dev.vor = v; break;
+    case S_KD_AND: ctl->m_k_dev.vand = v; break;
+    case S_DD_EVENTS: rep->dd_events = v; break;
+    case S_DD_GROUPS: rep->dd_groups = v; break;
+    case S_DD_BYTES: rep->dd_bytes = v; break;
+    case S_DD_TIME: rep->dd_time_ns = v; break;
+    case S_RT_PAIRS: rep->rt_pairs = v; break;
+    case S_RT_RX: rep->rt_rx_events = v; break;
+    case S_RT_BYTES: rep->rt_bytes = v; break;
+    case S_RT_TIME: rep->rt_time_ns = v; break;
+    default: break;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -837,6 +950,7 @@ struct DDArgs {
   WaveAgg* carry;      // per wavefront: forward carry-in / backward carry-in
   uint8_t* flags;
   odp_report* rep;
+  Parts parts;
 };
 
 
@@ -870,25 +984,51 @@ __device__ __forceinline__ void wave_bscan(uint32_t& f, BS<MODE>& v) {
   }
 }
 
-// Loads of one round: value, endpoint code, group start / end flags.
-__device__ __forceinline__ void load_round(const unsigned long long* k, const uint32_t* v, const uint8_t* aux,
-                                           uint32_t n, uint32_t j, uint32_t& val, uint8_t& a, bool& head,
-                                           bool& tail) {
+// Orders this wavefront's LDS writes before its later LDS reads by other lanes.
+__device__ __forceinline__ void wave_lds_fence() { __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront"); }
+
+// All 16 rounds of a wavefront at once: keys and values (coalesced), then
+// the endpoint codes gathered by value, all loads in flight together. Values
+// and codes go to the wavefront's LDS rows; bit r of heads / tails says
+// whether this lane's element of round r starts / ends its digest group.
+__device__ __forceinline__ void load_wave(const unsigned long long* k, const uint32_t* v, const uint8_t* aux,
+                                          uint32_t n, uint32_t wb, uint32_t* s_val, uint8_t* s_code,
+                                          uint32_t& heads, uint32_t& tails) {
   const int lane = threadIdx.x & 63;
-  const bool in = j < n;
-  const unsigned long long key = in ? k[j] : 0ull;
-  unsigned long long prev = __shfl_up(key, 1, 64);
-  unsigned long long next = __shfl_down(key, 1, 64);
-  if (lane == 0 && in && j > 0) prev = k[j - 1];
-  if (lane == 63 && in && j + 1 < n) next = k[j + 1];
-  head = in && (j == 0 || prev != key);
-  tail = in && (j + 1 == n || next != key);
-  val = in ? v[j] : 0u;
-  a = in ? aux[val] : kNotTransfer;
+  unsigned long long key[kRounds];
+  uint32_t val[kRounds];
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) {
+    const uint32_t j = wb + r * 64 + lane;
+    key[r] = j < n ? k[j] : 0ull;
+    val[r] = j < n ? v[j] : 0u;
+  }
+  const unsigned long long before = (lane == 0 && wb > 0 && wb < n) ? k[wb - 1] : 0ull;
+  const unsigned long long after = (lane == 63 && wb + kWaveElems < n) ? k[wb + kWaveElems] : 0ull;
+  uint8_t a[kRounds];
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) a[r] = wb + r * 64 + lane < n ? aux[val[r]] : kNotTransfer;
+  heads = tails = 0;
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) {
+    const uint32_t j = wb + r * 64 + lane;
+    const bool in = j < n;
+    unsigned long long prev = __shfl_up(key[r], 1, 64);
+    unsigned long long next = __shfl_down(key[r], 1, 64);
+    const unsigned long long last_before = r > 0 ? __shfl(key[r > 0 ? r - 1 : 0], 63, 64) : before;
+    const unsigned long long first_after = r + 1 < kRounds ? __shfl(key[r + 1 < kRounds ? r + 1 : r], 0, 64) : after;
+    if (lane == 0) prev = last_before;
+    if (lane == 63) next = first_after;
+    heads |= (uint32_t)(in && (j == 0 || prev != key[r])) << r;
+    tails |= (uint32_t)(in && (j + 1 == n || next != key[r])) << r;
+    s_val[r * 64 + lane] = val[r];
+    s_code[r * 64 + lane] = a[r];
+  }
+  wave_lds_fence();
 }
 
 template <int MODE>
-__device__ void ddrt_agg_body(const DDArgs& A) {
+__device__ void ddrt_agg_body(const DDArgs& A, uint32_t (*s_val)[kWaveElems], uint8_t (*s_code)[kWaveElems]) {
   using S = St<MODE>;
   const SortJob& s = *A.job;
   const uint32_t buf = s.npasses & 1;
@@ -897,16 +1037,16 @@ __device__ void ddrt_agg_body(const DDArgs& A) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const uint32_t wid = blockIdx.x * (kT / 64) + w;
   const uint32_t wb = wid * kWaveElems;
+  uint32_t heads, tails;
+  load_wave(k, v, A.aux, A.n, wb, s_val[w], s_code[w], heads, tails);
   uint32_t cf = 0, cb = 0;
   FS<MODE> fv = S::fid();
   BS<MODE> bv = S::bid();
   bool first_tail_seen = false;
+#pragma unroll 1
   for (int r = 0; r < kRounds; ++r) {
-    const uint32_t j = wb + r * 64 + lane;
-    uint32_t val;
-    uint8_t a;
-    bool head, tail;
-    load_round(k, v, A.aux, A.n, j, val, a, head, tail);
+    const uint8_t a = s_code[w][r * 64 + lane];
+    const bool head = (heads >> r) & 1, tail = (tails >> r) & 1;
     uint32_t f = head;
     FS<MODE> x = S::flift(a);
     wave_fscan<MODE>(f, x);
@@ -938,7 +1078,9 @@ __device__ void ddrt_agg_body(const DDArgs& A) {
 }
 
 __global__ __launch_bounds__(kT) void ddrt_agg_kernel(DDArgs A) {
-  if (A.ctl->max_ep < 4) ddrt_agg_body<0>(A); else ddrt_agg_body<1>(A);
+  __shared__ uint32_t s_val[kT / 64][kWaveElems];
+  __shared__ uint8_t s_code[kT / 64][kWaveElems];
+  if (A.ctl->max_ep < 4) ddrt_agg_body<0>(A, s_val, s_code); else ddrt_agg_body<1>(A, s_val, s_code);
 }
 
 // Carries between wavefronts (one block): forward carry-in of wavefront i
@@ -955,11 +1097,13 @@ __device__ void ddrt_carry_body(const DDArgs& A, uint32_t nw) {
   uint32_t ff = 0, bf = 0;
   FS<MODE> fv = S::fid();
   BS<MODE> bv = S::bid();
+#pragma unroll 8
   for (uint32_t t = t0; t < t1; ++t) {
     const WaveAgg& g = A.agg[t];
     fv = g.ff ? get_f<MODE>(g.fs) : S::fop(fv, get_f<MODE>(g.fs));
     ff |= g.ff;
   }
+#pragma unroll 8
   for (uint32_t t = t1; t > t0; --t) {
     const WaveAgg& g = A.agg[t - 1];
     if (g.bf) {
@@ -1000,12 +1144,14 @@ __device__ void ddrt_carry_body(const DDArgs& A, uint32_t nw) {
   }
   __syncthreads();
   FS<MODE> run = get_f<MODE>(exfv[threadIdx.x]);
+#pragma unroll 8
   for (uint32_t t = t0; t < t1; ++t) {
     put_f<MODE>(A.carry[t].fs, run);
     const WaveAgg& g = A.agg[t];
     run = g.ff ? get_f<MODE>(g.fs) : S::fop(run, get_f<MODE>(g.fs));
   }
   BS<MODE> runb = get_b<MODE>(exbv[threadIdx.x]);
+#pragma unroll 8
   for (uint32_t t = t1; t > t0; --t) {
     put_b<MODE>(A.carry[t - 1].bs, runb);
     const WaveAgg& g = A.agg[t - 1];
@@ -1020,7 +1166,7 @@ __global__ __launch_bounds__(kT) void ddrt_carry_kernel(DDArgs A, uint32_t nw) {
 }
 
 template <int MODE>
-__device__ void ddrt_final_body(const DDArgs& A) {
+__device__ void ddrt_final_body(const DDArgs& A, uint32_t (*s_val)[kWaveElems], uint8_t (*s_code)[kWaveElems]) {
   using S = St<MODE>;
   const SortJob& s = *A.job;
   const uint32_t buf = s.npasses & 1;
@@ -1030,20 +1176,13 @@ __device__ void ddrt_final_body(const DDArgs& A) {
   const uint32_t wid = blockIdx.x * (kT / 64) + w;
   const uint32_t wb = wid * kWaveElems;
   // per round: value and endpoint code (LDS), start/end flags and forward results (bits)
-  __shared__ uint32_t s_val[kT / 64][kWaveElems];
-  __shared__ uint8_t s_code[kT / 64][kWaveElems];
-  uint32_t tails = 0, fres = 0;
+  uint32_t heads, tails, fres = 0;
+  load_wave(k, v, A.aux, A.n, wb, s_val[w], s_code[w], heads, tails);
   FS<MODE> carry = get_f<MODE>(A.carry[wid].fs);
 #pragma unroll 1
   for (int r = 0; r < kRounds; ++r) {
-    const uint32_t j = wb + r * 64 + lane;
-    uint32_t val;
-    uint8_t a;
-    bool head, tail;
-    load_round(k, v, A.aux, A.n, j, val, a, head, tail);
-    s_val[w][r * 64 + lane] = val;
-    s_code[w][r * 64 + lane] = a;
-    tails |= (uint32_t)tail << r;
+    const uint8_t a = s_code[w][r * 64 + lane];
+    const bool head = (heads >> r) & 1;
     uint32_t f = head;
     FS<MODE> x = S::flift(a);
     wave_fscan<MODE>(f, x);
@@ -1085,37 +1224,57 @@ __device__ void ddrt_final_body(const DDArgs& A) {
       c_dd += (res & ODP_F_DD) != 0;
       c_tx += (res & ODP_F_RT_TX) != 0;
       c_rx += (res & ODP_F_RT_RX) != 0;
-      const uint32_t idx = s_val[w][r * 64 + lane];
-      if (res & (ODP_F_DD | ODP_F_RT_RX)) {
-        const odp_event& e = A.ev[idx];
-        const uint64_t du = e.t_end - e.t_start;
-        if (res & ODP_F_DD) {
-          b_dd += e.bytes;
-          t_dd += du;
-        }
-        if (res & ODP_F_RT_RX) {
-          b_rx += e.bytes;
-          t_rx += du;
-        }
-      }
-      A.flags[idx] = res;
+      A.flags[s_val[w][r * 64 + lane]] = res;
+      s_code[w][r * 64 + lane] = res;  // the code is not read again
+    } else {
+      s_code[w][r * 64 + lane] = 0;
     }
     const uint32_t g0 = (uint32_t)__shfl((int)g, 0, 64);
     const BS<MODE> y0 = S::shfl(y, 0);
     bcarry = g0 ? y0 : S::bop(y0, bcarry);
   }
-  block_add(&A.rep->dd_events, c_dd);
-  block_add(&A.rep->dd_groups, c_grp);
-  block_add(&A.rep->dd_bytes, b_dd);
-  block_add(&A.rep->dd_time_ns, t_dd);
-  block_add(&A.rep->rt_pairs, c_tx);
-  block_add(&A.rep->rt_rx_events, c_rx);
-  block_add(&A.rep->rt_bytes, b_rx);
-  block_add(&A.rep->rt_time_ns, t_rx);
+  // bytes and durations of the flagged records, four rounds of gathers in flight at a time
+  wave_lds_fence();
+#pragma unroll 1
+  for (int r0 = 0; r0 < kRounds; r0 += 4) {
+    uint64_t eb[4], ed[4];
+    uint8_t rs[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      rs[q] = s_code[w][(r0 + q) * 64 + lane];
+      eb[q] = ed[q] = 0;
+      if (rs[q] & (ODP_F_DD | ODP_F_RT_RX)) {
+        const odp_event& e = A.ev[s_val[w][(r0 + q) * 64 + lane]];
+        eb[q] = e.bytes;
+        ed[q] = e.t_end - e.t_start;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (rs[q] & ODP_F_DD) {
+        b_dd += eb[q];
+        t_dd += ed[q];
+      }
+      if (rs[q] & ODP_F_RT_RX) {
+        b_rx += eb[q];
+        t_rx += ed[q];
+      }
+    }
+  }
+  block_store<R_ADD>(A.parts.at(S_DD_EVENTS), c_dd);
+  block_store<R_ADD>(A.parts.at(S_DD_GROUPS), c_grp);
+  block_store<R_ADD>(A.parts.at(S_DD_BYTES), b_dd);
+  block_store<R_ADD>(A.parts.at(S_DD_TIME), t_dd);
+  block_store<R_ADD>(A.parts.at(S_RT_PAIRS), c_tx);
+  block_store<R_ADD>(A.parts.at(S_RT_RX), c_rx);
+  block_store<R_ADD>(A.parts.at(S_RT_BYTES), b_rx);
+  block_store<R_ADD>(A.parts.at(S_RT_TIME), t_rx);
 }
 
 __global__ __launch_bounds__(kT) void ddrt_final_kernel(DDArgs A) {
-  if (A.ctl->max_ep < 4) ddrt_final_body<0>(A); else ddrt_final_body<1>(A);
+  __shared__ uint32_t s_val[kT / 64][kWaveElems];
+  __shared__ uint8_t s_code[kT / 64][kWaveElems];
+  if (A.ctl->max_ep < 4) ddrt_final_body<0>(A, s_val, s_code); else ddrt_final_body<1>(A, s_val, s_code);
 }
 
 // ---------------------------------------------------------------------------
@@ -1346,7 +1505,7 @@ __global__ void finalize_kernel(AnaCtl* ctl, odp_report* rep) {
 // ---------------------------------------------------------------------------
 enum Buf {
   B_CTL, B_JOBS, B_CLS, B_AUX, B_BKEY0, B_BKEY1, B_BVAL0, B_BVAL1, B_TILECNT, B_AD, B_K, B_PR, B_HIST,
-  B_TOTALS, B_SEG, B_SKEY
+  B_TOTALS, B_SEG, B_SKEY, B_PARTS
 };
 
 constexpr int kJobBig = 0, kJobAd = 1, kJobKs = 2, kJobKe = 3, kJobPr = 4, kNumJobs = 5;
@@ -1382,6 +1541,7 @@ struct Views {
   WaveAgg* agg;    // per wavefront of the digest job
   WaveAgg* carry;
   unsigned long long* skey[8];  // key ping-pong of the four subset jobs
+  Parts parts;                  // per-block partials of the grid-wide reductions
 };
 
 Views views(Workspace* ws) {
@@ -1432,6 +1592,8 @@ Views views(Workspace* ws) {
   v.carry = carve<WaveAgg>(ps, (size_t)v.ntc * (kT / 64));
   char* pkey = static_cast<char*>(b[B_SKEY].ptr);
   for (int i = 0; i < 8; ++i) v.skey[i] = carve<unsigned long long>(pkey, cap);
+  v.parts.p = static_cast<unsigned long long*>(b[B_PARTS].ptr);
+  v.parts.stride = v.ntc;
   return v;
 }
 
@@ -1519,7 +1681,7 @@ int analyze_reserve(Workspace* ws, size_t max_events) {
       (e = b[B_HIST].ensure((size_t)kNumJobs * 256 * nt * 4)) ||
       (e = b[B_TOTALS].ensure((size_t)kNumJobs * kMaxPasses * 256 * 4)) ||
       (e = b[B_SEG].ensure((size_t)nt * (kT / 64) * 2 * sizeof(WaveAgg) + 64)) ||
-      (e = b[B_SKEY].ensure(cap * 8 * 8 + 64)))
+      (e = b[B_SKEY].ensure(cap * 8 * 8 + 64)) || (e = b[B_PARTS].ensure((size_t)kSlots * nt * 8)))
     return e;
   ws->a_cap_events = cap;
   SortJob hj[kNumJobs];
@@ -1568,10 +1730,11 @@ extern "C" int odp_analyze_trace(const odp_event* events, size_t n, uint8_t* out
     return check_hip(hipGetLastError(), "odp_analyze_trace launch");
   }
   hipLaunchKernelGGL(classify_kernel, dim3(nt), dim3(kT), 0, stream, events, nn, out_flags, v.cls, v.aux, v.bk[0],
-                     v.bv[0], v.wave_cnt, ctl, out_report);
+                     v.bv[0], v.wave_cnt, v.parts);
   hipLaunchKernelGGL(scan_pairs_kernel, dim3(1), dim3(1024), 0, stream, v.wave_cnt, nt * (kT / 64), &ctl->n_ad,
                      &ctl->n_k);
-  hipLaunchKernelGGL(subset_scatter_kernel, dim3(nt), dim3(kT), 0, stream, events, v.cls, nn, v.wave_cnt, v.S, ctl);
+  hipLaunchKernelGGL(subset_scatter_kernel, dim3(nt), dim3(kT), 0, stream, events, v.cls, nn, v.wave_cnt, v.S, v.parts);
+  hipLaunchKernelGGL(reduce_parts_kernel, dim3(kSlotsPhase1), dim3(kT), 0, stream, v.parts, nt, 0u, ctl, out_report);
 
   // Sort round 1: digests, ALLOC/DELETE, kernel starts, kernel ends.
   const JobSet J1{v.jobs, 4, nt};
@@ -1593,9 +1756,12 @@ extern "C" int odp_analyze_trace(const odp_event* events, size_t n, uint8_t* out
   D.carry = v.carry;
   D.flags = out_flags;
   D.rep = out_report;
+  D.parts = v.parts;
   hipLaunchKernelGGL(ddrt_agg_kernel, dim3(nt), dim3(kT), 0, stream, D);
   hipLaunchKernelGGL(ddrt_carry_kernel, dim3(1), dim3(kT), 0, stream, D, nt * (kT / 64));
   hipLaunchKernelGGL(ddrt_final_kernel, dim3(nt), dim3(kT), 0, stream, D);
+  hipLaunchKernelGGL(reduce_parts_kernel, dim3(kSlots - kSlotsPhase1), dim3(kT), 0, stream, v.parts, nt, kSlotsPhase1,
+                     ctl, out_report);
 
   // Pairing and the pair list.
   PairArgs P;
