@@ -17,6 +17,10 @@
  *                        App. B; here the digest is ODP-D64 v1, defined below)
  *   odp_analyze_trace    one pass over the event log that flags the four
  *                        patterns from those digests and addresses
+ *   odp_server_*         the two combined for requests that arrive over
+ *                        time: each is digested and classified as it comes,
+ *                        with continuous batching (an extension; the paper
+ *                        analyses post mortem)
  *
  * Conventions for every entry point
  *   - All pointers marked DEVICE must be device-accessible: hipMalloc memory,
@@ -200,8 +204,9 @@ int odp_analyze_trace(const odp_event* events, size_t n, uint8_t* out_flags, odp
  * device-resident per-key state, appended to a device-resident log.
  * Flags known at arrival (DD, RT_RX, PAIRED) are exact per tick; flags that
  * depend on later records (RT_TX, RA, UA) are resolved when the server is
- * drained, by the analysis of the whole log in arrival order (Secs. 3.2-3.4
- * define the rules; the paper analyses post mortem, serving is an extension).
+ * drained, by the analysis of the whole log in arrival order (the rules of
+ * Sec. 4, Defs. 1-4, and Sec. 5; the paper analyses post mortem, serving is an
+ * extension).
  * Errors: every call returns an ODP_* code; on failure the message is in
  * odp_last_error_string(). A server belongs to one host thread.
  * ------------------------------------------------------------------------ */

@@ -1736,7 +1736,7 @@ extern "C" int odp_analyze_trace(const odp_event* events, size_t n, uint8_t* out
   hipLaunchKernelGGL(subset_scatter_kernel, dim3(nt), dim3(kT), 0, stream, events, v.cls, nn, v.wave_cnt, v.S, v.parts);
   hipLaunchKernelGGL(reduce_parts_kernel, dim3(kSlotsPhase1), dim3(kT), 0, stream, v.parts, nt, 0u, ctl, out_report);
 
-  // Sort round 1: digests, ALLOC/DELETE, kernel starts, kernel ends.
+  // First sorts: digests, ALLOC/DELETE, kernel starts, kernel ends.
   const JobSet J1{v.jobs, 4, nt};
   hipLaunchKernelGGL(sort_plan_kernel, dim3(1), dim3(64), 0, stream, J1);
   for (uint32_t p = 0; p < 9; ++p) {
@@ -1790,7 +1790,7 @@ extern "C" int odp_analyze_trace(const odp_event* events, size_t n, uint8_t* out
   hipLaunchKernelGGL(kernel_ranges_kernel, dim3(grid_map), dim3(kT), 0, stream, v.jobs + kJobKs, v.S.k_w_dev,
                      &ctl->n_k, ctl);
 
-  // Sort round 2: pairs by (host address, device, bytes).
+  // Second sort: pairs by (host address, device, bytes).
   const JobSet J2{v.jobs + kJobPr, 1, nt};
   hipLaunchKernelGGL(sort_plan_kernel, dim3(1), dim3(64), 0, stream, J2);
   for (uint32_t p = 0; p < 17; ++p) {
