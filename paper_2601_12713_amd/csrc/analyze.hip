@@ -135,7 +135,6 @@ enum Slot : uint32_t {
   S_DD_EVENTS, S_DD_GROUPS, S_DD_BYTES, S_DD_TIME, S_RT_PAIRS, S_RT_RX, S_RT_BYTES, S_RT_TIME,
   kSlots
 };
-constexpr uint32_t kSlotsPhase1 = S_DD_EVENTS;  // slots reduced before the sorts
 
 struct Parts {
   unsigned long long* p;  // [kSlots][stride]
@@ -1683,6 +1682,11 @@ int analyze_reserve(Workspace* ws, size_t max_events) {
       (e = b[B_SEG].ensure((size_t)nt * (kT / 64) * 2 * sizeof(WaveAgg) + 64)) ||
       (e = b[B_SKEY].ensure(cap * 8 * 8 + 64)) || (e = b[B_PARTS].ensure((size_t)kSlots * nt * 8)))
     return e;
+  if (!ws->a_side) {
+    ODP_HIP(hipStreamCreateWithFlags(&ws->a_side, hipStreamNonBlocking));
+    ODP_HIP(hipEventCreateWithFlags(&ws->a_fork, hipEventDisableTiming));
+    ODP_HIP(hipEventCreateWithFlags(&ws->a_join, hipEventDisableTiming));
+  }
   ws->a_cap_events = cap;
   SortJob hj[kNumJobs];
   build_jobs(views(ws), hj);
@@ -1693,6 +1697,14 @@ int analyze_reserve(Workspace* ws, size_t max_events) {
 void analyze_release(Workspace* ws) {
   for (DevBuf& b : ws->a_bufs) b.release();
   ws->a_cap_events = 0;
+  if (ws->a_side) {
+    (void)hipStreamSynchronize(ws->a_side);
+    (void)hipEventDestroy(ws->a_fork);
+    (void)hipEventDestroy(ws->a_join);
+    (void)hipStreamDestroy(ws->a_side);
+    ws->a_side = nullptr;
+    ws->a_fork = ws->a_join = nullptr;
+  }
 }
 
 }  // namespace odp
@@ -1731,21 +1743,24 @@ extern "C" int odp_analyze_trace(const odp_event* events, size_t n, uint8_t* out
   }
   hipLaunchKernelGGL(classify_kernel, dim3(nt), dim3(kT), 0, stream, events, nn, out_flags, v.cls, v.aux, v.bk[0],
                      v.bv[0], v.wave_cnt, v.parts);
-  hipLaunchKernelGGL(scan_pairs_kernel, dim3(1), dim3(1024), 0, stream, v.wave_cnt, nt * (kT / 64), &ctl->n_ad,
-                     &ctl->n_k);
-  hipLaunchKernelGGL(subset_scatter_kernel, dim3(nt), dim3(kT), 0, stream, events, v.cls, nn, v.wave_cnt, v.S, v.parts);
-  hipLaunchKernelGGL(reduce_parts_kernel, dim3(kSlotsPhase1), dim3(kT), 0, stream, v.parts, nt, 0u, ctl, out_report);
+  // the classification's counts, digest masks, first rejected record and endpoint range
+  hipLaunchKernelGGL(reduce_parts_kernel, dim3(S_AD_DEV_OR), dim3(kT), 0, stream, v.parts, nt, 0u, ctl, out_report);
 
-  // First sorts: digests, ALLOC/DELETE, kernel starts, kernel ends.
-  const JobSet J1{v.jobs, 4, nt};
-  hipLaunchKernelGGL(sort_plan_kernel, dim3(1), dim3(64), 0, stream, J1);
-  for (uint32_t p = 0; p < 9; ++p) {
-    hipLaunchKernelGGL(sort_hist_kernel, dim3(J1.njobs * nt), dim3(kT), 0, stream, J1, p);
-    hipLaunchKernelGGL(sort_scan_kernel, dim3(256 * J1.njobs), dim3(kT), 0, stream, J1, p);
-    hipLaunchKernelGGL(sort_scatter_kernel, dim3(J1.njobs * nt), dim3(kT), 0, stream, J1, p);
+  // Fork: the allocation path (subsets, their sorts, pairing, RA/UA) runs on
+  // the workspace's side stream while the digest groups are sorted and
+  // scanned on the caller's stream; joined before the report is finished.
+  hipStream_t side = ws->a_side;
+  ODP_HIP(hipEventRecord(ws->a_fork, stream));
+  ODP_HIP(hipStreamWaitEvent(side, ws->a_fork, 0));
+
+  // Records by digest (up to 8 passes), then duplicates and round trips.
+  const JobSet Jb{v.jobs + kJobBig, 1, nt};
+  hipLaunchKernelGGL(sort_plan_kernel, dim3(1), dim3(64), 0, stream, Jb);
+  for (uint32_t p = 0; p < 8; ++p) {
+    hipLaunchKernelGGL(sort_hist_kernel, dim3(nt), dim3(kT), 0, stream, Jb, p);
+    hipLaunchKernelGGL(sort_scan_kernel, dim3(256), dim3(kT), 0, stream, Jb, p);
+    hipLaunchKernelGGL(sort_scatter_kernel, dim3(nt), dim3(kT), 0, stream, Jb, p);
   }
-
-  // Duplicates and round trips.
   DDArgs D;
   D.ev = events;
   D.n = nn;
@@ -1760,9 +1775,24 @@ extern "C" int odp_analyze_trace(const odp_event* events, size_t n, uint8_t* out
   hipLaunchKernelGGL(ddrt_agg_kernel, dim3(nt), dim3(kT), 0, stream, D);
   hipLaunchKernelGGL(ddrt_carry_kernel, dim3(1), dim3(kT), 0, stream, D, nt * (kT / 64));
   hipLaunchKernelGGL(ddrt_final_kernel, dim3(nt), dim3(kT), 0, stream, D);
-  hipLaunchKernelGGL(reduce_parts_kernel, dim3(kSlots - kSlotsPhase1), dim3(kT), 0, stream, v.parts, nt, kSlotsPhase1,
-                     ctl, out_report);
+  hipLaunchKernelGGL(reduce_parts_kernel, dim3(kSlots - S_DD_EVENTS), dim3(kT), 0, stream, v.parts, nt,
+                     (uint32_t)S_DD_EVENTS, ctl, out_report);
 
+  // The allocation path on the side stream (enqueued after the digest path,
+  // whose chain is the longer one, so that one starts first).
+  hipLaunchKernelGGL(scan_pairs_kernel, dim3(1), dim3(1024), 0, side, v.wave_cnt, nt * (kT / 64), &ctl->n_ad,
+                     &ctl->n_k);
+  hipLaunchKernelGGL(subset_scatter_kernel, dim3(nt), dim3(kT), 0, side, events, v.cls, nn, v.wave_cnt, v.S, v.parts);
+  hipLaunchKernelGGL(reduce_parts_kernel, dim3(S_DD_EVENTS - S_AD_DEV_OR), dim3(kT), 0, side, v.parts, nt,
+                     (uint32_t)S_AD_DEV_OR, ctl, out_report);
+  // ALLOC/DELETE by (device, address), kernels by (device, start) and (device, end)
+  const JobSet Js{v.jobs + kJobAd, 3, nt};
+  hipLaunchKernelGGL(sort_plan_kernel, dim3(1), dim3(64), 0, side, Js);
+  for (uint32_t p = 0; p < 9; ++p) {
+    hipLaunchKernelGGL(sort_hist_kernel, dim3(Js.njobs * nt), dim3(kT), 0, side, Js, p);
+    hipLaunchKernelGGL(sort_scan_kernel, dim3(256 * Js.njobs), dim3(kT), 0, side, Js, p);
+    hipLaunchKernelGGL(sort_scatter_kernel, dim3(Js.njobs * nt), dim3(kT), 0, side, Js, p);
+  }
   // Pairing and the pair list.
   PairArgs P;
   P.ev = events;
@@ -1783,20 +1813,20 @@ extern "C" int odp_analyze_trace(const odp_event* events, size_t n, uint8_t* out
   P.flags = out_flags;
   P.ctl = ctl;
   P.rep = out_report;
-  hipLaunchKernelGGL(pair_kernel, dim3(grid_map), dim3(kT), 0, stream, P);
-  hipLaunchKernelGGL(pair_count_kernel, dim3(nt), dim3(kT), 0, stream, P);
-  hipLaunchKernelGGL(scan_pairs_kernel, dim3(1), dim3(1024), 0, stream, v.tile_cnt, nt, &ctl->n_pairs, nullptr);
-  hipLaunchKernelGGL(pair_scatter_kernel, dim3(nt), dim3(kT), 0, stream, P);
-  hipLaunchKernelGGL(kernel_ranges_kernel, dim3(grid_map), dim3(kT), 0, stream, v.jobs + kJobKs, v.S.k_w_dev,
+  hipLaunchKernelGGL(pair_kernel, dim3(grid_map), dim3(kT), 0, side, P);
+  hipLaunchKernelGGL(pair_count_kernel, dim3(nt), dim3(kT), 0, side, P);
+  hipLaunchKernelGGL(scan_pairs_kernel, dim3(1), dim3(1024), 0, side, v.tile_cnt, nt, &ctl->n_pairs, nullptr);
+  hipLaunchKernelGGL(pair_scatter_kernel, dim3(nt), dim3(kT), 0, side, P);
+  hipLaunchKernelGGL(kernel_ranges_kernel, dim3(grid_map), dim3(kT), 0, side, v.jobs + kJobKs, v.S.k_w_dev,
                      &ctl->n_k, ctl);
 
   // Second sort: pairs by (host address, device, bytes).
   const JobSet J2{v.jobs + kJobPr, 1, nt};
-  hipLaunchKernelGGL(sort_plan_kernel, dim3(1), dim3(64), 0, stream, J2);
+  hipLaunchKernelGGL(sort_plan_kernel, dim3(1), dim3(64), 0, side, J2);
   for (uint32_t p = 0; p < 17; ++p) {
-    hipLaunchKernelGGL(sort_hist_kernel, dim3(nt), dim3(kT), 0, stream, J2, p);
-    hipLaunchKernelGGL(sort_scan_kernel, dim3(256), dim3(kT), 0, stream, J2, p);
-    hipLaunchKernelGGL(sort_scatter_kernel, dim3(nt), dim3(kT), 0, stream, J2, p);
+    hipLaunchKernelGGL(sort_hist_kernel, dim3(nt), dim3(kT), 0, side, J2, p);
+    hipLaunchKernelGGL(sort_scan_kernel, dim3(256), dim3(kT), 0, side, J2, p);
+    hipLaunchKernelGGL(sort_scatter_kernel, dim3(nt), dim3(kT), 0, side, J2, p);
   }
 
   RaArgs R;
@@ -1816,7 +1846,10 @@ extern "C" int odp_analyze_trace(const odp_event* events, size_t n, uint8_t* out
   R.ctl = ctl;
   R.flags = out_flags;
   R.rep = out_report;
-  hipLaunchKernelGGL(ra_ua_kernel, dim3(grid_map), dim3(kT), 0, stream, R);
+  hipLaunchKernelGGL(ra_ua_kernel, dim3(grid_map), dim3(kT), 0, side, R);
+  ODP_HIP(hipEventRecord(ws->a_join, side));
+
+  ODP_HIP(hipStreamWaitEvent(stream, ws->a_join, 0));
   hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(64), 0, stream, ctl, out_report);
   return check_hip(hipGetLastError(), "odp_analyze_trace launch");
 }

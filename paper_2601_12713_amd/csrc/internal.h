@@ -55,9 +55,12 @@ struct Workspace {
   // plain digest (one buffer at a time)
   DevBuf p_tree, p_tickets;
   uint64_t p_cap_tree = 0, p_cap_tk = 0;
-  // analysis
+  // analysis: the allocation path runs on a second stream of this workspace,
+  // forked from and joined to the caller's stream with events
   DevBuf a_bufs[24];
   size_t a_cap_events = 0;
+  hipStream_t a_side = nullptr;
+  hipEvent_t a_fork = nullptr, a_join = nullptr;
   // graph cache of the batched digest
   hipGraphExec_t graph = nullptr;
   const void* g_ptrs = nullptr;

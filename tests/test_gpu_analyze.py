@@ -160,3 +160,32 @@ def test_null_report_rejected(odp):
     import ctypes
     rc = odp.load().odp_analyze_trace(None, 0, None, None, None)
     assert rc == odp.ODP_EINVAL
+
+
+def test_analysis_replayed_from_a_graph(odp):
+    """A captured analysis (its side-stream fork and join included) replays
+    correctly several times, with eager work on the buffers between replays."""
+    tr = W.TraceAtScale(seed=9, n_map=200_000, n_slots=5_000)
+    ev = tr.events
+    n = len(ev)
+    fr, rr = oracle.analyze(ev)
+    s = torch.cuda.Stream()
+    d_ev = torch.from_numpy(ev.view(np.uint8).reshape(-1).copy()).to("cuda")
+    d_flags = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    d_rep = torch.zeros(odp.REPORT_BYTES, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        odp.reserve(max_events=n, stream=s)
+        odp.analyze_trace(d_ev, d_flags, d_rep, stream=s, n=n)
+    s.synchronize()
+    compare(d_flags.cpu().numpy(), odp.report_to_dict(d_rep.cpu().numpy()), fr, rr)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        odp.analyze_trace(d_ev, d_flags, d_rep, stream=s, n=n)
+    for _ in range(3):
+        d_flags.fill_(0xAA)
+        d_rep.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        compare(d_flags.cpu().numpy(), odp.report_to_dict(d_rep.cpu().numpy()), fr, rr)

@@ -176,3 +176,31 @@ def test_large_arrays_full_size(odp):
         prev = [j for j in range(i) if la.array_of[j] == la.array_of[i]]
         if prev:
             assert (got[i] == got[prev[-1]]) == la.identical[i], i
+
+
+def test_batched_digest_replayed_from_a_graph(odp):
+    """The batched digest captured by the caller (plan and digest kernels, no
+    memset nodes) replays correctly several times."""
+    rng = np.random.default_rng(19)
+    host = [rng.integers(0, 256, size=int(s), dtype=np.uint8) for s in [0, 100, 5000, 70_000, 262_145, 3_000_000]]
+    want = oracle.d64_many(host).tolist()
+    t = [dev_bytes(h) for h in host]
+    n = len(t)
+    dp = torch.tensor(np.array([x.data_ptr() for x in t], dtype=np.uint64).view(np.int64), device="cuda")
+    ds = torch.tensor(np.array([x.numel() for x in t], dtype=np.uint64).view(np.int64), device="cuda")
+    out = torch.zeros(n, dtype=torch.int64, device="cuda")
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        odp.reserve(max_buffers=n, max_total_bytes=1 << 24, stream=s)
+    s.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        odp.digest_buffers(dp, ds, out, stream=s)
+    for _ in range(3):
+        out.fill_(7)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert out.cpu().numpy().view(np.uint64).tolist() == want
+    assert odp.device_status() == 0
