@@ -1003,6 +1003,24 @@ extern "C" int odp_digest_buffers(const void* const* ptrs, const uint64_t* sizes
 }
 
 namespace odp {
+// Tree and ticket slots of the per-buffer form (grow-only; tickets zeroed).
+int plain_reserve_slots(Workspace* ws, uint64_t need_tree, uint64_t need_tk) {
+  if (need_tree <= ws->p_cap_tree && need_tk <= ws->p_cap_tk && ws->p_tickets.ptr) return ODP_OK;
+  const uint64_t tr = std::max<uint64_t>(need_tree, 1024), tk = std::max<uint64_t>(need_tk, 256);
+  int e;
+  if ((e = ws->p_tree.ensure(tr * 8)) || (e = ws->p_tickets.ensure(tk * 4))) return e;
+  ODP_HIP(hipMemset(ws->p_tickets.ptr, 0, tk * 4));
+  ws->p_cap_tree = tr;
+  ws->p_cap_tk = tk;
+  return ODP_OK;
+}
+
+int digest_plain_reserve(Workspace* ws, uint64_t max_bytes) {
+  uint64_t tr = 0, tk = 0;
+  if (max_bytes > kLeaf) tree_need(ceil_div(ceil_div(max_bytes, kLeaf), kFanIn), tr, tk);
+  return plain_reserve_slots(ws, tr, tk);
+}
+
 int digest_batched_direct(const void* const* ptrs, const uint64_t* sizes, size_t n, uint64_t* out, hipStream_t stream,
                           uint64_t total_bytes) {
   if (n == 0) return ODP_OK;
@@ -1041,12 +1059,8 @@ extern "C" int odp_digest_buffers_plain(const void* const* host_ptrs, const uint
   if (!ws) return err;
   if (need_tree > ws->p_cap_tree || need_tk > ws->p_cap_tk || !ws->p_tickets.ptr) {
     ODP_HIP(hipStreamSynchronize(stream));
-    const uint64_t tr = std::max<uint64_t>(need_tree, 1024), tk = std::max<uint64_t>(need_tk, 256);
-    int e;
-    if ((e = ws->p_tree.ensure(tr * 8)) || (e = ws->p_tickets.ensure(tk * 4))) return e;
-    ODP_HIP(hipMemset(ws->p_tickets.ptr, 0, tk * 4));
-    ws->p_cap_tree = tr;
-    ws->p_cap_tk = tk;
+    int e = plain_reserve_slots(ws, need_tree, need_tk);
+    if (e) return e;
   }
   uint64_t* tree = static_cast<uint64_t*>(ws->p_tree.ptr);
   uint32_t* tk = static_cast<uint32_t*>(ws->p_tickets.ptr);

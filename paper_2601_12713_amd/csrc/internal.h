@@ -86,6 +86,8 @@ struct Tuning {
 Tuning& tuning();
 
 int digest_reserve(Workspace* ws, size_t max_buffers, uint64_t max_total_bytes);
+// Workspace of the per-buffer form for buffers of up to max_bytes (grow-only).
+int digest_plain_reserve(Workspace* ws, uint64_t max_bytes);
 // Batched digest enqueued with direct launches (workspace reserved
 // beforehand); total_bytes, the sum of the sizes, sizes the grids.
 int digest_batched_direct(const void* const* ptrs, const uint64_t* sizes, size_t n, uint64_t* out, hipStream_t stream,

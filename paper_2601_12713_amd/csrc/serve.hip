@@ -347,6 +347,8 @@ extern "C" int odp_server_create(const odp_server_config* cfg, odp_server** out)
     int err = 0;
     Workspace* ws = workspace_for(s->stream, &err);
     e = ws ? digest_reserve(ws, kTickMax, cfg->budget_bytes + (uint64_t)kTickMax * kNodeBytes) : err;
+    // one-request ticks take the per-buffer launch: its workspace too, up front
+    if (!e) e = digest_plain_reserve(ws, cfg->budget_bytes);
   }
   if (e) {
     server_free(s);
@@ -388,8 +390,10 @@ static int launch_tick(odp_server* s, int b, uint32_t m, uint64_t bytes) {
   hipStream_t st = s->stream;
   ODP_HIP(hipMemcpyAsync(s->d_stage[b], s->h_stage[b], m * kStageBytes, hipMemcpyHostToDevice, st));
   const StageView hv = stage_view(s->h_stage[b], m), dv = stage_view(s->d_stage[b], m);
-  // tick sizes change every tick: direct launches rather than a captured graph
-  int e = s->cfg.mode == ODP_SERVER_PLAIN
+  // Tick sizes change every tick: direct launches rather than a captured
+  // graph. A tick of one request takes the per-buffer launch (one kernel
+  // instead of the plan, the persistent digest and the tree kernels).
+  int e = s->cfg.mode == ODP_SERVER_PLAIN || m == 1
               ? odp_digest_buffers_plain(reinterpret_cast<const void* const*>(hv.ptr), hv.size, m, s->d_dig[b], st)
               : digest_batched_direct(reinterpret_cast<const void* const*>(dv.ptr), dv.size, m, s->d_dig[b], st, bytes);
   if (e) return e;
