@@ -1026,8 +1026,29 @@ __device__ __forceinline__ void load_wave(const unsigned long long* k, const uin
   wave_lds_fence();
 }
 
+// One round of 64 sorted elements: endpoint code (gathered by value) and
+// whether the element starts / ends its digest group.
+__device__ __forceinline__ void load_round(const unsigned long long* k, const uint32_t* v, const uint8_t* aux,
+                                           uint32_t n, uint32_t j, uint8_t& a, bool& head, bool& tail) {
+  const int lane = threadIdx.x & 63;
+  const bool in = j < n;
+  const unsigned long long key = in ? k[j] : 0ull;
+  unsigned long long prev = __shfl_up(key, 1, 64);
+  unsigned long long next = __shfl_down(key, 1, 64);
+  if (lane == 0 && in && j > 0) prev = k[j - 1];
+  if (lane == 63 && in && j + 1 < n) next = k[j + 1];
+  head = in && (j == 0 || prev != key);
+  tail = in && (j + 1 == n || next != key);
+  a = in ? aux[v[j]] : kNotTransfer;
+}
+
+// Per-wavefront aggregates. The forward one folds the elements after the
+// wavefront's last group start, the backward one those before its first
+// group end, so rounds are read from each end only until such a boundary
+// turns up (one round each for typical groups; all 16 for a group that
+// spans the wavefront).
 template <int MODE>
-__device__ void ddrt_agg_body(const DDArgs& A, uint32_t (*s_val)[kWaveElems], uint8_t (*s_code)[kWaveElems]) {
+__device__ void ddrt_agg_body(const DDArgs& A) {
   using S = St<MODE>;
   const SortJob& s = *A.job;
   const uint32_t buf = s.npasses & 1;
@@ -1036,35 +1057,39 @@ __device__ void ddrt_agg_body(const DDArgs& A, uint32_t (*s_val)[kWaveElems], ui
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const uint32_t wid = blockIdx.x * (kT / 64) + w;
   const uint32_t wb = wid * kWaveElems;
-  uint32_t heads, tails;
-  load_wave(k, v, A.aux, A.n, wb, s_val[w], s_code[w], heads, tails);
   uint32_t cf = 0, cb = 0;
   FS<MODE> fv = S::fid();
   BS<MODE> bv = S::bid();
-  bool first_tail_seen = false;
 #pragma unroll 1
-  for (int r = 0; r < kRounds; ++r) {
-    const uint8_t a = s_code[w][r * 64 + lane];
-    const bool head = (heads >> r) & 1, tail = (tails >> r) & 1;
+  for (int r = kRounds - 1; r >= 0; --r) {
+    uint8_t a;
+    bool head, tail;
+    load_round(k, v, A.aux, A.n, wb + r * 64 + lane, a, head, tail);
     uint32_t f = head;
     FS<MODE> x = S::flift(a);
     wave_fscan<MODE>(f, x);
     const uint32_t f63 = (uint32_t)__shfl((int)f, 63, 64);
     const FS<MODE> x63 = S::shfl(x, 63);
-    fv = f63 ? x63 : S::fop(fv, x63);
-    cf |= f63;
-    // backward aggregate: elements from the wave start up to its first group end
-    if (!first_tail_seen) {
-      uint32_t g = tail;
-      BS<MODE> y = S::blift(a);
-      wave_bscan<MODE>(g, y);
-      const uint32_t g0 = (uint32_t)__shfl((int)g, 0, 64);
-      const BS<MODE> y0 = S::shfl(y, 0);
-      bv = S::bop(bv, y0);
-      if (g0) {
-        cb = 1;
-        first_tail_seen = true;
-      }
+    fv = S::fop(x63, fv);  // this round, then the later ones
+    if (f63) {
+      cf = 1;
+      break;
+    }
+  }
+#pragma unroll 1
+  for (int r = 0; r < kRounds; ++r) {
+    uint8_t a;
+    bool head, tail;
+    load_round(k, v, A.aux, A.n, wb + r * 64 + lane, a, head, tail);
+    uint32_t g = tail;
+    BS<MODE> y = S::blift(a);
+    wave_bscan<MODE>(g, y);
+    const uint32_t g0 = (uint32_t)__shfl((int)g, 0, 64);
+    const BS<MODE> y0 = S::shfl(y, 0);
+    bv = S::bop(bv, y0);
+    if (g0) {
+      cb = 1;
+      break;
     }
   }
   if (lane == 0) {
@@ -1077,9 +1102,7 @@ __device__ void ddrt_agg_body(const DDArgs& A, uint32_t (*s_val)[kWaveElems], ui
 }
 
 __global__ __launch_bounds__(kT) void ddrt_agg_kernel(DDArgs A) {
-  __shared__ uint32_t s_val[kT / 64][kWaveElems];
-  __shared__ uint8_t s_code[kT / 64][kWaveElems];
-  if (A.ctl->max_ep < 4) ddrt_agg_body<0>(A, s_val, s_code); else ddrt_agg_body<1>(A, s_val, s_code);
+  if (A.ctl->max_ep < 4) ddrt_agg_body<0>(A); else ddrt_agg_body<1>(A);
 }
 
 // Carries between wavefronts (one block): forward carry-in of wavefront i
