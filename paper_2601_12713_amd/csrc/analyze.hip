@@ -81,7 +81,12 @@ struct SortJob {
   uint32_t npasses;                // device-computed
   uint8_t pw[kMaxPasses], ps[kMaxPasses];
   uint8_t pg[kMaxPasses];          // 1: this pass reads its key word from words[pw] by value
+  // A word already non-decreasing in input order whenever *first_bad is kNone
+  // (no record rejected), so its passes are skipped then; kNoWord if none.
+  const uint32_t* first_bad;
+  uint32_t mono_word;
 };
+constexpr uint32_t kNoWord = 0xFFFFFFFFu;
 
 struct JobSet {
   SortJob* jobs;
@@ -521,7 +526,9 @@ __global__ void sort_plan_kernel(JobSet J) {
   if (j >= J.njobs) return;
   SortJob& s = J.jobs[j];
   uint32_t np = 0;
+  const uint32_t skip = (s.first_bad && *s.first_bad == kNone) ? s.mono_word : kNoWord;
   for (uint32_t w = 0; w < s.nwords; ++w) {
+    if (w == skip) continue;
     // bits that are 1 in some key and 0 in another (0 when there are no keys)
     const unsigned long long var = s.masks[w]->vor & ~s.masks[w]->vand;
     bool first = true;
@@ -1623,6 +1630,7 @@ Views views(Workspace* ws) {
 // inside are refilled on the device by every call).
 void build_jobs(const Views& v, SortJob* hj) {
   std::memset(static_cast<void*>(hj), 0, sizeof(SortJob) * kNumJobs);
+  for (int j = 0; j < kNumJobs; ++j) hj[j].mono_word = kNoWord;
   AnaCtl* ctl = v.ctl;
   // all records by digest (keyed; non-transfers carry an all-ones key and contribute nothing)
   hj[kJobBig].n_ptr = &ctl->n;
@@ -1656,6 +1664,11 @@ void build_jobs(const Views& v, SortJob* hj) {
   hj[kJobKs].word_bytes[1] = 1;
   hj[kJobKs].nwords = 2;
   hj[kJobKe] = hj[kJobKs];
+  // Valid records are in non-decreasing t_start order when no record was
+  // rejected (a rejected record can hide a decrease), so the kernels' starts
+  // then need no sorting: a stable sort by device keeps them in order.
+  hj[kJobKs].first_bad = &ctl->first_bad;
+  hj[kJobKs].mono_word = 0;
   hj[kJobKe].vals[0] = v.S.k_vals_e;
   hj[kJobKe].vals[1] = v.k_vals_e1;
   hj[kJobKe].words[0] = v.S.k_w_end;
