@@ -622,32 +622,39 @@ __global__ __launch_bounds__(kT) void sort_scan_kernel(JobSet J, uint32_t p) {
   if (threadIdx.x == kT - 1) s.totals[p * 256 + d] = before;
 }
 
-// Stable scatter. Each wavefront ranks its 1,024 consecutive elements (16
-// rounds of 64) by digit with ballots; the tile is then placed in digit
-// order in LDS and written out in that order, so the global writes form one
-// contiguous run per digit.
-__global__ __launch_bounds__(kT) void sort_scatter_kernel(JobSet J, uint32_t p) {
+// Stable scatter, 512 threads per tile (twice the wavefronts of the other
+// sort kernels, for latency hiding at this kernel's LDS footprint). Each
+// wavefront ranks its 512 consecutive elements (8 rounds of 64) by digit with
+// ballots; the tile is then placed in digit order in LDS and written out in
+// that order, so the global writes form one contiguous run per digit.
+constexpr int kST = 512;                      // threads of the scatter
+constexpr int kSW = kST / 64;                 // its wavefronts
+constexpr int kSElems = kTile / kSW;          // elements per wavefront
+constexpr int kSRounds = kSElems / 64;        // rounds of 64 per wavefront
+
+__global__ __launch_bounds__(kST) void sort_scatter_kernel(JobSet J, uint32_t p) {
   const SortJob* s;
   uint32_t tile, n;
   if (!job_tile(J, p, s, tile, n)) return;
-  __shared__ uint32_t wcnt[kT / 64][256];
+  __shared__ uint32_t wcnt[kSW][256];
   __shared__ uint32_t lbase[256];   // tile-local start of each digit
   __shared__ uint32_t gbase[256];   // global start of each digit's run of this tile
   __shared__ unsigned long long stage[kTile];
   __shared__ uint8_t sdig[kTile];
+  __shared__ uint32_t ws[4], wt[4];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   for (int x = 0; x < 256; x += 64) wcnt[w][x + lane] = 0;
   __syncthreads();
   const uint32_t src = p & 1, dst = src ^ 1;
   const uint32_t tb = tile * kTile;
-  const uint32_t wb = tb + w * kWaveElems;
+  const uint32_t wb = tb + w * kSElems;
   const uint32_t shift = s->ps[p];
   const bool gather = s->pg[p] != 0;
   const uint64_t* word = s->words[s->pw[p]];
-  uint32_t dg[kItems], rk[kItems], vl[kItems];
-  unsigned long long ky[kItems];
+  uint32_t dg[kSRounds], rk[kSRounds], vl[kSRounds];
+  unsigned long long ky[kSRounds];
 #pragma unroll
-  for (int r = 0; r < kItems; ++r) {
+  for (int r = 0; r < kSRounds; ++r) {
     const uint32_t j = wb + r * 64 + lane;
     const bool in = j < n;
     vl[r] = in ? s->vals[src][j] : 0u;
@@ -655,13 +662,13 @@ __global__ __launch_bounds__(kT) void sort_scatter_kernel(JobSet J, uint32_t p) 
   }
   if (gather) {
 #pragma unroll
-    for (int r = 0; r < kItems; ++r) {
+    for (int r = 0; r < kSRounds; ++r) {
       const uint32_t j = wb + r * 64 + lane;
       if (j < n) ky[r] = word[vl[r]];
     }
   }
 #pragma unroll
-  for (int r = 0; r < kItems; ++r) {
+  for (int r = 0; r < kSRounds; ++r) {
     const uint32_t j = wb + r * 64 + lane;
     const bool in = j < n;
     const uint32_t d = in ? (uint32_t)(ky[r] >> shift) & 0xFF : 0u;
@@ -681,11 +688,11 @@ __global__ __launch_bounds__(kT) void sort_scatter_kernel(JobSet J, uint32_t p) 
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
   }
   __syncthreads();
-  {
-    // per digit: counts of the wavefronts before, tile-local and global bases
+  if (threadIdx.x < 256) {
+    // per digit (threads 0..255): counts of the wavefronts before, tile-local and global bases
     const uint32_t d = threadIdx.x;
     uint32_t c = 0;
-    for (int x = 0; x < kT / 64; ++x) {
+    for (int x = 0; x < kSW; ++x) {
       const uint32_t t = wcnt[x][d];
       wcnt[x][d] = c;
       c += t;
@@ -696,31 +703,34 @@ __global__ __launch_bounds__(kT) void sort_scatter_kernel(JobSet J, uint32_t p) 
       const uint32_t y = __shfl_up(xsc, o, 64);
       if (lane >= o) xsc += y;
     }
-    __shared__ uint32_t ws[kT / 64];
     if (lane == 63) ws[w] = xsc;
-    __syncthreads();
-    uint32_t pre = xsc - c;
-    for (int q = 0; q < w; ++q) pre += ws[q];
-    lbase[d] = pre;
     // global start: counts of smaller digits over all tiles, plus earlier tiles of this digit
-    uint32_t tot = s->totals[p * 256 + d];
+    const uint32_t tot = s->totals[p * 256 + d];
     uint32_t y = tot;
     for (int o = 1; o < 64; o <<= 1) {
       const uint32_t z = __shfl_up(y, o, 64);
       if (lane >= o) y += z;
     }
-    __shared__ uint32_t wt[kT / 64];
     if (lane == 63) wt[w] = y;
-    __syncthreads();
-    uint32_t gpre = y - tot;
-    for (int q = 0; q < w; ++q) gpre += wt[q];
-    gbase[d] = gpre + s->hist[(size_t)d * s->ntiles_max + tile];
+    lbase[d] = xsc - c;  // completed below with the sums of earlier wavefronts
+    gbase[d] = y - tot + s->hist[(size_t)d * s->ntiles_max + tile];
+  }
+  __syncthreads();
+  if (threadIdx.x < 256) {
+    const uint32_t d = threadIdx.x;
+    uint32_t pre = 0, gpre = 0;
+    for (int q = 0; q < w; ++q) {
+      pre += ws[q];
+      gpre += wt[q];
+    }
+    lbase[d] += pre;
+    gbase[d] += gpre;
   }
   __syncthreads();
   const uint32_t cnt_tile = min(n - tb, (uint32_t)kTile);
   // pass 1: values (and digits) into tile-local digit order
 #pragma unroll
-  for (int r = 0; r < kItems; ++r) {
+  for (int r = 0; r < kSRounds; ++r) {
     const uint32_t j = wb + r * 64 + lane;
     if (j < n) {
       const uint32_t lp = lbase[dg[r]] + wcnt[w][dg[r]] + rk[r];
@@ -729,18 +739,18 @@ __global__ __launch_bounds__(kT) void sort_scatter_kernel(JobSet J, uint32_t p) 
     }
   }
   __syncthreads();
-  for (uint32_t i = threadIdx.x; i < cnt_tile; i += kT) {
+  for (uint32_t i = threadIdx.x; i < cnt_tile; i += kST) {
     const uint32_t d = sdig[i];
     s->vals[dst][gbase[d] + (i - lbase[d])] = reinterpret_cast<uint32_t*>(stage)[i];
   }
   __syncthreads();
 #pragma unroll
-  for (int r = 0; r < kItems; ++r) {
+  for (int r = 0; r < kSRounds; ++r) {
     const uint32_t j = wb + r * 64 + lane;
     if (j < n) stage[lbase[dg[r]] + wcnt[w][dg[r]] + rk[r]] = ky[r];
   }
   __syncthreads();
-  for (uint32_t i = threadIdx.x; i < cnt_tile; i += kT) {
+  for (uint32_t i = threadIdx.x; i < cnt_tile; i += kST) {
     const uint32_t d = sdig[i];
     s->keys[dst][gbase[d] + (i - lbase[d])] = stage[i];
   }
@@ -1795,7 +1805,7 @@ extern "C" int odp_analyze_trace(const odp_event* events, size_t n, uint8_t* out
   for (uint32_t p = 0; p < 8; ++p) {
     hipLaunchKernelGGL(sort_hist_kernel, dim3(nt), dim3(kT), 0, stream, Jb, p);
     hipLaunchKernelGGL(sort_scan_kernel, dim3(256), dim3(kT), 0, stream, Jb, p);
-    hipLaunchKernelGGL(sort_scatter_kernel, dim3(nt), dim3(kT), 0, stream, Jb, p);
+    hipLaunchKernelGGL(sort_scatter_kernel, dim3(nt), dim3(kST), 0, stream, Jb, p);
   }
   DDArgs D;
   D.ev = events;
@@ -1827,7 +1837,7 @@ extern "C" int odp_analyze_trace(const odp_event* events, size_t n, uint8_t* out
   for (uint32_t p = 0; p < 9; ++p) {
     hipLaunchKernelGGL(sort_hist_kernel, dim3(Js.njobs * nt), dim3(kT), 0, side, Js, p);
     hipLaunchKernelGGL(sort_scan_kernel, dim3(256 * Js.njobs), dim3(kT), 0, side, Js, p);
-    hipLaunchKernelGGL(sort_scatter_kernel, dim3(Js.njobs * nt), dim3(kT), 0, side, Js, p);
+    hipLaunchKernelGGL(sort_scatter_kernel, dim3(Js.njobs * nt), dim3(kST), 0, side, Js, p);
   }
   // Pairing and the pair list.
   PairArgs P;
@@ -1862,7 +1872,7 @@ extern "C" int odp_analyze_trace(const odp_event* events, size_t n, uint8_t* out
   for (uint32_t p = 0; p < 17; ++p) {
     hipLaunchKernelGGL(sort_hist_kernel, dim3(nt), dim3(kT), 0, side, J2, p);
     hipLaunchKernelGGL(sort_scan_kernel, dim3(256), dim3(kT), 0, side, J2, p);
-    hipLaunchKernelGGL(sort_scatter_kernel, dim3(nt), dim3(kT), 0, side, J2, p);
+    hipLaunchKernelGGL(sort_scatter_kernel, dim3(nt), dim3(kST), 0, side, J2, p);
   }
 
   RaArgs R;
