@@ -1122,85 +1122,97 @@ __global__ __launch_bounds__(kT) void ddrt_agg_kernel(DDArgs A) {
   if (A.ctl->max_ep < 4) ddrt_agg_body<0>(A); else ddrt_agg_body<1>(A);
 }
 
-// Carries between wavefronts (one block): forward carry-in of wavefront i
-// combines wavefronts < i; backward carry-in combines wavefronts > i.
+// Carries between wavefronts (one block of 1,024 threads): the forward
+// carry-in of wavefront i folds wavefronts < i, the backward carry-in folds
+// wavefronts > i. Each thread folds a run of consecutive wavefronts; the runs'
+// folds are scanned across the block (shuffles inside a wavefront, then the
+// wavefront totals), and each thread walks its run again writing the carries.
+// Forward element (ff, fs): a later element with ff set replaces the state.
+// Backward element (bf, bs): an earlier element with bf set blocks what
+// comes after it.
+constexpr int kCT = 1024;
+
+template <int MODE>
+struct FwdEl {
+  uint32_t f;
+  FS<MODE> v;
+};
+template <int MODE>
+struct BwdEl {
+  uint32_t f;
+  BS<MODE> v;
+};
+
+template <int MODE>
+__device__ __forceinline__ FwdEl<MODE> fcomb(const FwdEl<MODE>& a, const FwdEl<MODE>& b) {  // a earlier
+  return FwdEl<MODE>{a.f | b.f, b.f ? b.v : St<MODE>::fop(a.v, b.v)};
+}
+template <int MODE>
+__device__ __forceinline__ BwdEl<MODE> bcomb(const BwdEl<MODE>& a, const BwdEl<MODE>& b) {  // a earlier
+  return BwdEl<MODE>{a.f | b.f, a.f ? a.v : St<MODE>::bop(a.v, b.v)};
+}
+
 template <int MODE>
 __device__ void ddrt_carry_body(const DDArgs& A, uint32_t nw) {
   using S = St<MODE>;
-  __shared__ uint32_t shf[kT];
-  __shared__ uint32_t shb[kT];
-  __shared__ uint32_t shfv[kT][5];
-  __shared__ uint32_t shbv[kT][5];
-  const uint32_t per = ceil_div32(nw, kT);
-  const uint32_t t0 = threadIdx.x * per, t1 = min(nw, t0 + per);
-  uint32_t ff = 0, bf = 0;
-  FS<MODE> fv = S::fid();
-  BS<MODE> bv = S::bid();
-#pragma unroll 8
+  __shared__ FwdEl<MODE> wf[kCT / 64];
+  __shared__ BwdEl<MODE> wbk[kCT / 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint32_t per = ceil_div32(nw, kCT);
+  const uint32_t t0 = min(nw, threadIdx.x * per), t1 = min(nw, t0 + per);
+  // this thread's run: forward fold left to right, backward fold right to left
+  FwdEl<MODE> F{0, S::fid()};
+  BwdEl<MODE> B{0, S::bid()};
+#pragma unroll 4
   for (uint32_t t = t0; t < t1; ++t) {
     const WaveAgg& g = A.agg[t];
-    fv = g.ff ? get_f<MODE>(g.fs) : S::fop(fv, get_f<MODE>(g.fs));
-    ff |= g.ff;
+    F = fcomb<MODE>(F, FwdEl<MODE>{g.ff, get_f<MODE>(g.fs)});
   }
-#pragma unroll 8
+#pragma unroll 4
   for (uint32_t t = t1; t > t0; --t) {
     const WaveAgg& g = A.agg[t - 1];
-    if (g.bf) {
-      bv = get_b<MODE>(g.bs);
-      bf = 1;
-    } else {
-      bv = S::bop(get_b<MODE>(g.bs), bv);
-    }
+    B = bcomb<MODE>(BwdEl<MODE>{g.bf, get_b<MODE>(g.bs)}, B);
   }
-  shf[threadIdx.x] = ff;
-  shb[threadIdx.x] = bf;
-  put_f<MODE>(shfv[threadIdx.x], fv);
-  put_b<MODE>(shbv[threadIdx.x], bv);
-  __syncthreads();
-  // serial exclusive scans over the 256 run aggregates (thread 0 forward, thread 64 backward)
-  __shared__ uint32_t exf[kT], exb[kT];
-  __shared__ uint32_t exfv[kT][5], exbv[kT][5];
-  if (threadIdx.x == 0) {
-    uint32_t c = 0;
-    FS<MODE> cv = S::fid();
-    for (int t = 0; t < kT; ++t) {
-      exf[t] = c;
-      put_f<MODE>(exfv[t], cv);
-      const FS<MODE> x = get_f<MODE>(shfv[t]);
-      cv = shf[t] ? x : S::fop(cv, x);
-      c |= shf[t];
-    }
-  } else if (threadIdx.x == 64) {
-    uint32_t c = 0;
-    BS<MODE> cv = S::bid();
-    for (int t = kT - 1; t >= 0; --t) {
-      exb[t] = c;
-      put_b<MODE>(exbv[t], cv);
-      const BS<MODE> x = get_b<MODE>(shbv[t]);
-      cv = shb[t] ? x : S::bop(x, cv);
-      c |= shb[t];
-    }
+  // inclusive scans inside the wavefront: forward over lower lanes, backward over higher lanes
+  FwdEl<MODE> xf = F;
+  BwdEl<MODE> xb = B;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const FwdEl<MODE> yf{(uint32_t)__shfl_up((int)xf.f, o, 64), S::shfl_up(xf.v, o)};
+    const BwdEl<MODE> yb{(uint32_t)__shfl_down((int)xb.f, o, 64), S::shfl_down(xb.v, o)};
+    if (lane >= o) xf = fcomb<MODE>(yf, xf);
+    if (lane + o < 64) xb = bcomb<MODE>(xb, yb);
   }
+  if (lane == 63) wf[w] = xf;
+  if (lane == 0) wbk[w] = xb;
+  // exclusive within the wavefront
+  FwdEl<MODE> ef{(uint32_t)__shfl_up((int)xf.f, 1, 64), S::shfl_up(xf.v, 1)};
+  BwdEl<MODE> eb{(uint32_t)__shfl_down((int)xb.f, 1, 64), S::shfl_down(xb.v, 1)};
+  if (lane == 0) ef = FwdEl<MODE>{0, S::fid()};
+  if (lane == 63) eb = BwdEl<MODE>{0, S::bid()};
   __syncthreads();
-  FS<MODE> run = get_f<MODE>(exfv[threadIdx.x]);
-#pragma unroll 8
+  // fold in the wavefront totals before (forward) and after (backward) this one
+  FwdEl<MODE> pf{0, S::fid()};
+  for (int q = 0; q < w; ++q) pf = fcomb<MODE>(pf, wf[q]);
+  BwdEl<MODE> pb{0, S::bid()};
+  for (int q = kCT / 64 - 1; q > w; --q) pb = bcomb<MODE>(wbk[q], pb);
+  FwdEl<MODE> run = fcomb<MODE>(pf, ef);
+  BwdEl<MODE> runb = bcomb<MODE>(eb, pb);
+#pragma unroll 4
   for (uint32_t t = t0; t < t1; ++t) {
-    put_f<MODE>(A.carry[t].fs, run);
+    put_f<MODE>(A.carry[t].fs, run.v);
     const WaveAgg& g = A.agg[t];
-    run = g.ff ? get_f<MODE>(g.fs) : S::fop(run, get_f<MODE>(g.fs));
+    run = fcomb<MODE>(run, FwdEl<MODE>{g.ff, get_f<MODE>(g.fs)});
   }
-  BS<MODE> runb = get_b<MODE>(exbv[threadIdx.x]);
-#pragma unroll 8
+#pragma unroll 4
   for (uint32_t t = t1; t > t0; --t) {
-    put_b<MODE>(A.carry[t - 1].bs, runb);
+    put_b<MODE>(A.carry[t - 1].bs, runb.v);
     const WaveAgg& g = A.agg[t - 1];
-    runb = g.bf ? get_b<MODE>(g.bs) : S::bop(get_b<MODE>(g.bs), runb);
+    runb = bcomb<MODE>(BwdEl<MODE>{g.bf, get_b<MODE>(g.bs)}, runb);
   }
-  (void)exf;
-  (void)exb;
 }
 
-__global__ __launch_bounds__(kT) void ddrt_carry_kernel(DDArgs A, uint32_t nw) {
+__global__ __launch_bounds__(kCT) void ddrt_carry_kernel(DDArgs A, uint32_t nw) {
   if (A.ctl->max_ep < 4) ddrt_carry_body<0>(A, nw); else ddrt_carry_body<1>(A, nw);
 }
 
@@ -1819,7 +1831,7 @@ extern "C" int odp_analyze_trace(const odp_event* events, size_t n, uint8_t* out
   D.rep = out_report;
   D.parts = v.parts;
   hipLaunchKernelGGL(ddrt_agg_kernel, dim3(nt), dim3(kT), 0, stream, D);
-  hipLaunchKernelGGL(ddrt_carry_kernel, dim3(1), dim3(kT), 0, stream, D, nt * (kT / 64));
+  hipLaunchKernelGGL(ddrt_carry_kernel, dim3(1), dim3(kCT), 0, stream, D, nt * (kT / 64));
   hipLaunchKernelGGL(ddrt_final_kernel, dim3(nt), dim3(kT), 0, stream, D);
   hipLaunchKernelGGL(reduce_parts_kernel, dim3(kSlots - S_DD_EVENTS), dim3(kT), 0, stream, v.parts, nt,
                      (uint32_t)S_DD_EVENTS, ctl, out_report);
