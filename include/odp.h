@@ -190,6 +190,9 @@ typedef struct odp_report {
  * Data-dependent problems do not fail the call: rejected records get
  * ODP_F_INVALID, take part in no rule, and set report.status.
  * n = 0 writes an empty report. n > 2^32 - 1 returns ODP_ERANGE.
+ * Internally the allocation rules run on a side stream of the workspace that
+ * is forked from `stream` and joined back before the report is written, so
+ * the call remains ordered on `stream` (and capturable as one unit).
  * Capture-safe once odp_reserve covered n. */
 int odp_analyze_trace(const odp_event* events, size_t n, uint8_t* out_flags, odp_report* out_report,
                       odp_stream_t stream);
@@ -276,12 +279,15 @@ const char* odp_last_error_string(void);
 
 /* Pre-size the workspace of the current device for `stream`: up to max_buffers
  * buffers totalling max_total_bytes for odp_digest_buffers, and up to
- * max_events records for odp_analyze_trace. Synchronous; allocates. Call it
- * before capturing calls into a hipGraph. */
+ * max_events records for odp_analyze_trace (which also creates the
+ * workspace's side stream and the two events that fork and join it).
+ * Synchronous; allocates. Call it before capturing calls into a hipGraph. */
 int odp_reserve(size_t max_buffers, uint64_t max_total_bytes, size_t max_events, odp_stream_t stream);
 
-/* Frees every workspace the library holds (all devices and streams). Waits for
- * the device first. */
+/* Frees every workspace the library holds (all devices and streams), the
+ * analysis side streams included. Waits for the device first. Graphs that
+ * captured library calls and live servers keep pointers into these
+ * workspaces: destroy them first (a later call simply reserves again). */
 int odp_release(void);
 
 /* Sticky device-side status of the current device: ODP_OK or ODP_ECAPACITY
