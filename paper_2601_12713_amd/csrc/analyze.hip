@@ -372,76 +372,65 @@ struct SubsetOut {
   uint32_t* k_vals_e;
 };
 
-// Wavefront w writes its records' subset entries at offsets from the scanned
-// per-wavefront counts, so no workgroup barrier is needed between rounds.
+// Ordered compaction of the ALLOC/DELETE and KERNEL records. Wavefront w
+// takes its 1,024 records in 16 coalesced rounds of 64 (lane l: record
+// wb + 64r + l); a ballot per round gives each matching lane its rank, so the
+// entries land in record order at the wavefront's scanned offsets, and the
+// records of a round are read together.
 __global__ __launch_bounds__(kT) void subset_scatter_kernel(const odp_event* __restrict__ ev, const uint8_t* __restrict__ cls,
                                                             uint32_t n, const uint32_t* __restrict__ wave_off, SubsetOut S,
                                                             Parts parts) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const uint32_t wid = blockIdx.x * (kT / 64) + w;
-  // lane l owns the 16 consecutive records wid*1024 + 16l .. +15
-  const uint32_t b0 = wid * kWaveElems + lane * 16;
-  uint8_t c[16];
-  if (b0 + 16 <= n) {
-    const uint4 v = *reinterpret_cast<const uint4*>(cls + b0);
-    const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
+  const uint32_t wb = wid * kWaveElems;
+  uint8_t c[kRounds];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) c[k] = (uint8_t)(wv[k >> 2] >> (8 * (k & 3)));
-  } else {
-#pragma unroll
-    for (int k = 0; k < 16; ++k) c[k] = b0 + k < n ? cls[b0 + k] : C_INVALID;
+  for (int r = 0; r < kRounds; ++r) {
+    const uint32_t i = wb + r * 64 + lane;
+    c[r] = i < n ? cls[i] : C_INVALID;
   }
-  uint32_t nad = 0, nk = 0;
-#pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    nad += c[k] == C_ALLOCDEL;
-    nk += c[k] == C_KERNEL;
-  }
-  // exclusive scans over the lanes
-  uint32_t xa = nad, xk = nk;
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t ya = __shfl_up(xa, o, 64), yk = __shfl_up(xk, o, 64);
-    if (lane >= o) {
-      xa += ya;
-      xk += yk;
-    }
-  }
-  uint32_t q0 = wave_off[2 * wid] + xa - nad, q1 = wave_off[2 * wid + 1] + xk - nk;
+  uint32_t q0 = wave_off[2 * wid], q1 = wave_off[2 * wid + 1];
   unsigned long long o_dev = 0, a_dev = ~0ull, o_addr = 0, a_addr = ~0ull, o_ks = 0, a_ks = ~0ull, o_ke = 0,
                      a_ke = ~0ull, o_kd = 0, a_kd = ~0ull;
-  for (int k = 0; k < 16; ++k) {
-    const uint32_t i = b0 + k;
-    if (c[k] == C_ALLOCDEL) {
+  const uint64_t lt = lanemask_lt();
+#pragma unroll 4
+  for (int r = 0; r < kRounds; ++r) {
+    const uint32_t i = wb + r * 64 + lane;
+    const bool is_ad = c[r] == C_ALLOCDEL, is_k = c[r] == C_KERNEL;
+    const uint64_t bad = __ballot(is_ad), bk = __ballot(is_k);
+    if (is_ad) {
       const odp_event& e = ev[i];
+      const uint32_t q = q0 + (uint32_t)__popcll(bad & lt);
       const uint64_t dv = (uint64_t)(e.dst_dev + 1), ad = e.dst_addr;
-      S.ad_idx[q0] = i;
-      S.ad_op[q0] = e.op;
-      S.ad_w_dev[q0] = dv;
-      S.ad_w_addr[q0] = ad;
-      S.ad_vals[q0] = q0;
-      S.ad_alloc_partner[q0] = kNone;
+      S.ad_idx[q] = i;
+      S.ad_op[q] = e.op;
+      S.ad_w_dev[q] = dv;
+      S.ad_w_addr[q] = ad;
+      S.ad_vals[q] = q;
+      S.ad_alloc_partner[q] = kNone;
       o_dev |= dv;
       a_dev &= dv;
       o_addr |= ad;
       a_addr &= ad;
-      ++q0;
-    } else if (c[k] == C_KERNEL) {
+    } else if (is_k) {
       const odp_event& e = ev[i];
+      const uint32_t q = q1 + (uint32_t)__popcll(bk & lt);
       const uint64_t dv = (uint64_t)(e.dst_dev + 1);
-      S.k_idx[q1] = i;
-      S.k_w_start[q1] = e.t_start;
-      S.k_w_end[q1] = e.t_end;
-      S.k_w_dev[q1] = dv;
-      S.k_vals_s[q1] = q1;
-      S.k_vals_e[q1] = q1;
+      S.k_idx[q] = i;
+      S.k_w_start[q] = e.t_start;
+      S.k_w_end[q] = e.t_end;
+      S.k_w_dev[q] = dv;
+      S.k_vals_s[q] = q;
+      S.k_vals_e[q] = q;
       o_ks |= e.t_start;
       a_ks &= e.t_start;
       o_ke |= e.t_end;
       a_ke &= e.t_end;
       o_kd |= dv;
       a_kd &= dv;
-      ++q1;
     }
+    q0 += (uint32_t)__popcll(bad);
+    q1 += (uint32_t)__popcll(bk);
   }
   // (identity values where a lane saw no such record)
   block_store<R_OR>(parts.at(S_AD_DEV_OR), o_dev);
