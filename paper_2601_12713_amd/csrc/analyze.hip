@@ -745,6 +745,101 @@ __global__ __launch_bounds__(kST) void sort_scatter_kernel(JobSet J, uint32_t p)
   }
 }
 
+// Small logs: every pass of a job in one workgroup, keys and values held in
+// LDS (ping-pong), one launch per sort instead of three per pass. Used when
+// the log has at most kSmallMax records (so every job has at most that many
+// elements). The result lands in keys/vals[npasses & 1], as with the passes.
+constexpr uint32_t kSmallMax = 2048;
+constexpr int kQT = 512;                         // threads
+constexpr int kQW = kQT / 64;                    // wavefronts
+constexpr int kQElems = kSmallMax / kQW;         // elements per wavefront (256)
+constexpr int kQRounds = kQElems / 64;           // rounds of 64 per wavefront
+
+__global__ __launch_bounds__(kQT) void sort_small_kernel(JobSet J) {
+  const SortJob& s = J.jobs[blockIdx.x];
+  const uint32_t n = *s.n_ptr;
+  const uint32_t np = s.npasses;
+  __shared__ unsigned long long lk[2][kSmallMax];
+  __shared__ uint32_t lv[2][kSmallMax];
+  __shared__ uint32_t wcnt[kQW][256];
+  __shared__ uint32_t base[256];
+  __shared__ uint32_t wsum[4];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (uint32_t i = threadIdx.x; i < n; i += kQT) {
+    lk[0][i] = s.keys[0][i];
+    lv[0][i] = s.vals[0][i];
+  }
+  __syncthreads();
+  uint32_t cur = 0;
+  for (uint32_t p = 0; p < np; ++p) {
+    for (int x = 0; x < 256; x += 64) wcnt[w][x + lane] = 0;
+    __syncthreads();
+    const uint32_t shift = s.ps[p];
+    const bool gather = s.pg[p] != 0;
+    const uint64_t* word = s.words[s.pw[p]];
+    uint32_t dg[kQRounds], rk[kQRounds];
+    unsigned long long ky[kQRounds];
+#pragma unroll
+    for (int r = 0; r < kQRounds; ++r) {
+      const uint32_t i = w * kQElems + r * 64 + lane;
+      const bool in = i < n;
+      ky[r] = in ? (gather ? word[lv[cur][i]] : lk[cur][i]) : 0ull;
+      const uint32_t d = in ? (uint32_t)(ky[r] >> shift) & 0xFF : 0u;
+      uint64_t peers = __ballot(in);
+#pragma unroll
+      for (int bit = 0; bit < 8; ++bit) {
+        const uint64_t bb = __ballot((d >> bit) & 1);
+        peers &= ((d >> bit) & 1) ? bb : ~bb;
+      }
+      const uint32_t before = in ? wcnt[w][d] : 0;
+      dg[r] = d;
+      rk[r] = before + (uint32_t)__popcll(peers & lanemask_lt());
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      if (in && (peers >> lane) == 1ull) wcnt[w][d] = before + (uint32_t)__popcll(peers);
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    }
+    __syncthreads();
+    if (threadIdx.x < 256) {
+      const uint32_t d = threadIdx.x;
+      uint32_t c = 0;
+      for (int x = 0; x < kQW; ++x) {
+        const uint32_t t = wcnt[x][d];
+        wcnt[x][d] = c;
+        c += t;
+      }
+      uint32_t xs = c;
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(xs, o, 64);
+        if (lane >= o) xs += y;
+      }
+      if (lane == 63) wsum[w] = xs;
+      base[d] = xs - c;
+    }
+    __syncthreads();
+    if (threadIdx.x < 256) {
+      uint32_t pre = 0;
+      for (int q = 0; q < w; ++q) pre += wsum[q];
+      base[threadIdx.x] += pre;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kQRounds; ++r) {
+      const uint32_t i = w * kQElems + r * 64 + lane;
+      if (i < n) {
+        const uint32_t pos = base[dg[r]] + wcnt[w][dg[r]] + rk[r];
+        lk[cur ^ 1][pos] = ky[r];
+        lv[cur ^ 1][pos] = lv[cur][i];
+      }
+    }
+    __syncthreads();
+    cur ^= 1;
+  }
+  for (uint32_t i = threadIdx.x; i < n; i += kQT) {
+    s.keys[np & 1][i] = lk[cur][i];
+    s.vals[np & 1][i] = lv[cur][i];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // 4. Duplicate and round-trip transfers: segmented scans per digest group.
 //
@@ -1802,11 +1897,16 @@ extern "C" int odp_analyze_trace(const odp_event* events, size_t n, uint8_t* out
 
   // Records by digest (up to 8 passes), then duplicates and round trips.
   const JobSet Jb{v.jobs + kJobBig, 1, nt};
+  const bool small = n <= kSmallMax;  // every job then has at most kSmallMax elements
   hipLaunchKernelGGL(sort_plan_kernel, dim3(1), dim3(64), 0, stream, Jb);
-  for (uint32_t p = 0; p < 8; ++p) {
-    hipLaunchKernelGGL(sort_hist_kernel, dim3(nt), dim3(kT), 0, stream, Jb, p);
-    hipLaunchKernelGGL(sort_scan_kernel, dim3(256), dim3(kT), 0, stream, Jb, p);
-    hipLaunchKernelGGL(sort_scatter_kernel, dim3(nt), dim3(kST), 0, stream, Jb, p);
+  if (small) {
+    hipLaunchKernelGGL(sort_small_kernel, dim3(Jb.njobs), dim3(kQT), 0, stream, Jb);
+  } else {
+    for (uint32_t p = 0; p < 8; ++p) {
+      hipLaunchKernelGGL(sort_hist_kernel, dim3(nt), dim3(kT), 0, stream, Jb, p);
+      hipLaunchKernelGGL(sort_scan_kernel, dim3(256), dim3(kT), 0, stream, Jb, p);
+      hipLaunchKernelGGL(sort_scatter_kernel, dim3(nt), dim3(kST), 0, stream, Jb, p);
+    }
   }
   DDArgs D;
   D.ev = events;
@@ -1835,10 +1935,14 @@ extern "C" int odp_analyze_trace(const odp_event* events, size_t n, uint8_t* out
   // ALLOC/DELETE by (device, address), kernels by (device, start) and (device, end)
   const JobSet Js{v.jobs + kJobAd, 3, nt};
   hipLaunchKernelGGL(sort_plan_kernel, dim3(1), dim3(64), 0, side, Js);
-  for (uint32_t p = 0; p < 9; ++p) {
-    hipLaunchKernelGGL(sort_hist_kernel, dim3(Js.njobs * nt), dim3(kT), 0, side, Js, p);
-    hipLaunchKernelGGL(sort_scan_kernel, dim3(256 * Js.njobs), dim3(kT), 0, side, Js, p);
-    hipLaunchKernelGGL(sort_scatter_kernel, dim3(Js.njobs * nt), dim3(kST), 0, side, Js, p);
+  if (small) {
+    hipLaunchKernelGGL(sort_small_kernel, dim3(Js.njobs), dim3(kQT), 0, side, Js);
+  } else {
+    for (uint32_t p = 0; p < 9; ++p) {
+      hipLaunchKernelGGL(sort_hist_kernel, dim3(Js.njobs * nt), dim3(kT), 0, side, Js, p);
+      hipLaunchKernelGGL(sort_scan_kernel, dim3(256 * Js.njobs), dim3(kT), 0, side, Js, p);
+      hipLaunchKernelGGL(sort_scatter_kernel, dim3(Js.njobs * nt), dim3(kST), 0, side, Js, p);
+    }
   }
   // Pairing and the pair list.
   PairArgs P;
@@ -1870,10 +1974,14 @@ extern "C" int odp_analyze_trace(const odp_event* events, size_t n, uint8_t* out
   // Second sort: pairs by (host address, device, bytes).
   const JobSet J2{v.jobs + kJobPr, 1, nt};
   hipLaunchKernelGGL(sort_plan_kernel, dim3(1), dim3(64), 0, side, J2);
-  for (uint32_t p = 0; p < 17; ++p) {
-    hipLaunchKernelGGL(sort_hist_kernel, dim3(nt), dim3(kT), 0, side, J2, p);
-    hipLaunchKernelGGL(sort_scan_kernel, dim3(256), dim3(kT), 0, side, J2, p);
-    hipLaunchKernelGGL(sort_scatter_kernel, dim3(nt), dim3(kST), 0, side, J2, p);
+  if (small) {
+    hipLaunchKernelGGL(sort_small_kernel, dim3(J2.njobs), dim3(kQT), 0, side, J2);
+  } else {
+    for (uint32_t p = 0; p < 17; ++p) {
+      hipLaunchKernelGGL(sort_hist_kernel, dim3(nt), dim3(kT), 0, side, J2, p);
+      hipLaunchKernelGGL(sort_scan_kernel, dim3(256), dim3(kT), 0, side, J2, p);
+      hipLaunchKernelGGL(sort_scatter_kernel, dim3(nt), dim3(kST), 0, side, J2, p);
+    }
   }
 
   RaArgs R;
