@@ -7,8 +7,8 @@
 // level-1 node digests (64 leaves, 256 KiB) inside the workgroup or wavefront.
 //
 // Plain form (one launch per buffer): one workgroup per level-1 node; the
-// upper levels are finished by whichever workgroup completes the last child of
-// a node (an atomic ticket per node).
+// upper levels are finished by whichever workgroup completes the last level-1
+// node (one atomic ticket per buffer up to 1 GiB, one per node above that).
 //
 // Batched form (one persistent launch for n buffers): a device-side plan
 // splits the buffers into work items: level-1 nodes hashed by a whole
@@ -350,6 +350,44 @@ __device__ __forceinline__ void tree_up(uint64_t h, uint64_t m, uint64_t nj, uin
   }
 }
 
+// Buffers of up to kOneTicketNodes level-1 nodes (1 GiB) share one ticket:
+// the workgroup that completes the last level-1 node reads all of their
+// digests into LDS (every load in flight at once) and hashes the levels above
+// there, level 2 with four lanes per node and the root (level 3) with four
+// lanes, instead of a store, a wait, a ticket and a coherent load per level.
+constexpr uint32_t kOneTicketNodes = kFanIn * kFanIn;
+constexpr int kGatherPer = kOneTicketNodes / kThreads;
+
+__device__ __forceinline__ void finish_upper(Smem& sm, uint32_t n1, uint64_t* tree, uint32_t* tk, uint64_t* out) {
+  static_assert(sizeof(sm.slab) >= kOneTicketNodes * sizeof(uint64_t), "level-1 digests fit the staging slabs");
+  uint64_t* lv1 = reinterpret_cast<uint64_t*>(&sm.slab[0][0]);
+  const int t = threadIdx.x;
+  if (t == 0) __hip_atomic_store(tk, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  uint64_t v[kGatherPer];
+#pragma unroll
+  for (int k = 0; k < kGatherPer; ++k) {
+    const uint32_t i = (uint32_t)t + (uint32_t)k * kThreads;
+    v[k] = i < n1 ? load_coherent(tree + i) : 0ull;
+  }
+#pragma unroll
+  for (int k = 0; k < kGatherPer; ++k) {
+    const uint32_t i = (uint32_t)t + (uint32_t)k * kThreads;
+    if (i < n1) lv1[i] = v[k];
+  }
+  __syncthreads();
+  const uint32_t n2 = (n1 + kFanIn - 1) / kFanIn;
+  const uint32_t g = (uint32_t)t >> 2;
+  if (g < n2) {
+    const uint64_t h2 = xx_words4(lv1 + g * kFanIn, min<uint32_t>(kFanIn, n1 - g * kFanIn), 2);
+    if ((t & 3) == 0) sm.leafdig[1][g] = h2;
+  }
+  __syncthreads();
+  if (t < 64) {
+    const uint64_t root = n2 == 1 ? sm.leafdig[1][0] : xx_words4(sm.leafdig[1], n2, 3);
+    if (t == 0) *out = root;
+  }
+}
+
 // One level-1 node of a buffer larger than one leaf. `buf`, `size`, `node`
 // and the tree pointers are wave-uniform.
 __device__ __forceinline__ void run_node(Smem& sm, const uint8_t* buf, uint64_t size, uint64_t node, uint64_t* out,
@@ -387,11 +425,29 @@ __device__ __forceinline__ void run_node(Smem& sm, const uint8_t* buf, uint64_t 
   }
   if ((t & 3) == 0 && (uint64_t)(w * kRowsPerWave + r) < nl) sm.leafdig[0][w * kRowsPerWave + r] = h;
   __syncthreads();
+  if (n1 > kOneTicketNodes) {
+    if (w == 0) {
+      const uint64_t d = xx_words4(sm.leafdig[0], nl, 1);
+      tree_up(d, node, n1, 1, 0, 0, out, tree, tk);
+    }
+    __syncthreads();
+    return;
+  }
   if (w == 0) {
-    const uint64_t d = xx_words4(sm.leafdig[0], nl, 1);
-    tree_up(d, node, n1, 1, 0, 0, out, tree, tk);
+    const int lane = t & 63;
+    const uint64_t d = __shfl(xx_words4(sm.leafdig[0], nl, 1), 0, 64);
+    uint32_t last = 0;
+    if (n1 == 1) {
+      if (lane == 0) *out = d;
+    } else {
+      if (lane == 0) store_coherent(tree + node, d);
+      wait_stores_done();
+      if (lane == 0) last = __hip_atomic_fetch_add(tk, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == n1 - 1;
+    }
+    if (lane == 0) sm.outidx[0] = last;
   }
   __syncthreads();
+  if (sm.outidx[0]) finish_upper(sm, (uint32_t)n1, tree, tk, out);
 }
 
 // ---------------------------------------------------------------------------

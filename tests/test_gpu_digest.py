@@ -62,14 +62,17 @@ def test_same_bytes_same_digest_any_alignment(odp):
 
 
 def test_four_level_tree(odp):
-    # 2^30 + 4097 bytes: 262146 leaves -> 4097 level-1 -> 65 -> 2 -> root at level 4
+    # 2^30 + 4097 bytes: 262146 leaves -> 4097 level-1 -> 65 -> 2 -> root at level 4.
+    # Its first 2^30 bytes: 4096 level-1 -> 64 -> root at level 3, the largest
+    # buffer whose upper levels the per-buffer form finishes under one ticket.
     n = (1 << 30) + 4097
     g = torch.Generator(device="cuda")
     g.manual_seed(14)
     t = torch.randint(0, 256, (n,), dtype=torch.uint8, device="cuda", generator=g)
-    want = oracle.d64(t.cpu().numpy())
-    b, p = both_forms(odp, [t])
-    assert int(b[0]) == want and int(p[0]) == want
+    host = t.cpu().numpy()
+    want = [oracle.d64(host), oracle.d64(host[:1 << 30])]
+    b, p = both_forms(odp, [t, t[:1 << 30]])
+    assert b.tolist() == want and p.tolist() == want
 
 
 def test_mixed_batch_random_sizes(odp):
