@@ -378,7 +378,8 @@ __device__ __forceinline__ void finish_upper(Smem& sm, uint32_t n1, uint64_t* tr
   const uint32_t n2 = (n1 + kFanIn - 1) / kFanIn;
   const uint32_t g = (uint32_t)t >> 2;
   if (g < n2) {
-    const uint64_t h2 = xx_words4(lv1 + g * kFanIn, min<uint32_t>(kFanIn, n1 - g * kFanIn), 2);
+    const uint64_t h2 = n1 % kFanIn == 0 ? xx_words4_full64(lv1 + g * kFanIn, 2)
+                                         : xx_words4(lv1 + g * kFanIn, min<uint32_t>(kFanIn, n1 - g * kFanIn), 2);
     if ((t & 3) == 0) sm.leafdig[1][g] = h2;
   }
   __syncthreads();
@@ -435,7 +436,8 @@ __device__ __forceinline__ void run_node(Smem& sm, const uint8_t* buf, uint64_t 
   }
   if (w == 0) {
     const int lane = t & 63;
-    const uint64_t d = __shfl(xx_words4(sm.leafdig[0], nl, 1), 0, 64);
+    const uint64_t d =
+        __shfl(nl == kFanIn ? xx_words4_full64(sm.leafdig[0], 1) : xx_words4(sm.leafdig[0], nl, 1), 0, 64);
     uint32_t last = 0;
     if (n1 == 1) {
       if (lane == 0) *out = d;

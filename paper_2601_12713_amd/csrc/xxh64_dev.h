@@ -127,4 +127,27 @@ __device__ __forceinline__ uint64_t xx_words4(const uint64_t* w, uint32_t nw, ui
   return xx_avalanche(h);
 }
 
+// XXH64 of exactly 64 words (a full tree node) by lanes 4g..4g+3; every lane
+// returns the digest. One four-lane chain is bound by latency, not issue, so
+// every stripe word and its product with P2 are formed before the chain
+// starts, and only the add, the rotation and the multiply by P1 wait on the
+// previous round. Same result as xx_words4(w, 64, seed).
+__device__ __forceinline__ uint64_t xx_words4_full64(const uint64_t* w, uint64_t seed) {
+  const int a = threadIdx.x & 3;
+  uint64_t t[16];
+#pragma unroll
+  for (int s = 0; s < 16; ++s) t[s] = w[s * 4 + a];
+#pragma unroll
+  for (int s = 0; s < 16; ++s) {
+    t[s] *= kP2;
+    asm volatile("" : "+v"(t[s]));  // keeps the product out of the accumulator's multiply-add
+  }
+  uint64_t acc = xx_acc_init(seed, a);
+#pragma unroll
+  for (int s = 0; s < 16; ++s) acc = rotl64(acc + t[s], 31) * kP1;
+  uint64_t v1, v2, v3, v4;
+  xx_gather4(acc, v1, v2, v3, v4);
+  return xx_avalanche(xx_converge(v1, v2, v3, v4) + 64 * 8);
+}
+
 }  // namespace odp
