@@ -23,6 +23,8 @@
 // Sort keys are 64-bit words; a job lists its words least significant first,
 // and digit passes whose byte is the same in every key are skipped on the
 // device, so the launches are fixed while the work follows the data.
+#include <algorithm>
+#include <cmath>
 #include <cstring>
 
 #include "internal.h"
@@ -78,7 +80,12 @@ struct SortJob {
   uint32_t ntiles_max;             // row length of `hist` (tiles of the capacity)
   uint32_t* hist;                  // [256][ntiles_max]
   uint32_t* totals;                // [kMaxPasses][256]
-  uint32_t npasses;                // device-computed
+  uint32_t npasses;                // device-computed: the passes that run
+  // The digest job may sort on its least significant varying bytes first
+  // (np_first passes) and run each further pass (up to np_full) only when a
+  // check finds two different keys that agree on the bytes sorted so far;
+  // other jobs: all equal.
+  uint32_t np_first, np_full;
   uint8_t pw[kMaxPasses], ps[kMaxPasses];
   uint8_t pg[kMaxPasses];          // 1: this pass reads its key word from words[pw] by value
   // A word already non-decreasing in input order whenever *first_bad is kNone
@@ -510,7 +517,9 @@ __global__ __launch_bounds__(kT) void reduce_parts_kernel(Parts parts, uint32_t 
 // ---------------------------------------------------------------------------
 // 3. LSD radix sort, 8-bit digits, several independent jobs per launch.
 // ---------------------------------------------------------------------------
-__global__ void sort_plan_kernel(JobSet J) {
+// first_passes: when nonzero, the passes after that many are deferred to the
+// collision check (digest job only).
+__global__ void sort_plan_kernel(JobSet J, uint32_t first_passes) {
   const uint32_t j = threadIdx.x;
   if (j >= J.njobs) return;
   SortJob& s = J.jobs[j];
@@ -530,7 +539,45 @@ __global__ void sort_plan_kernel(JobSet J) {
         ++np;
       }
   }
-  s.npasses = np;
+  s.np_full = np;
+  s.np_first = first_passes ? min(np, first_passes) : np;
+  s.npasses = s.np_first;
+}
+
+// Before deferred pass p (p >= np_first): the keys, sorted on the bytes of
+// passes 0..p-1, are grouped by those bytes only. Adjacent keys that agree on
+// them but differ elsewhere mean two digests share them (their groups may then
+// interleave), and pass p is switched on; the check before pass p+1 then looks
+// again. Otherwise equal sorted bytes already imply equal keys, so each group
+// of equal keys is contiguous and in input order, which is all the duplicate
+// and round-trip scans use, and the remaining passes stay off. Runs only while
+// every pass before p ran (npasses == p).
+__global__ __launch_bounds__(kT) void sort_collide_kernel(SortJob* job, uint32_t p) {
+  SortJob& s = *job;
+  if (s.npasses != p || p >= s.np_full) return;
+  const uint32_t n = *s.n_ptr;
+  unsigned long long mask = 0;
+  for (uint32_t q = 0; q < p; ++q) mask |= 0xFFull << s.ps[q];
+  const unsigned long long* k = s.keys[p & 1];
+  const int lane = threadIdx.x & 63;
+  const uint32_t wb = (blockIdx.x * (kT / 64) + (threadIdx.x >> 6)) * kWaveElems;
+  unsigned long long key[kRounds];
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) {
+    const uint32_t j = wb + r * 64 + lane;
+    key[r] = j < n ? k[j] : 0ull;
+  }
+  const unsigned long long before = (lane == 0 && wb > 0 && wb < n) ? k[wb - 1] : key[0];
+  bool hit = false;
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) {
+    const uint32_t j = wb + r * 64 + lane;
+    unsigned long long prev = __shfl_up(key[r], 1, 64);
+    const unsigned long long last = __shfl(key[r > 0 ? r - 1 : 0], 63, 64);
+    if (lane == 0) prev = r > 0 ? last : before;
+    if (j < n && j > 0) hit |= (((key[r] ^ prev) & mask) == 0) && key[r] != prev;
+  }
+  if (__syncthreads_or(hit) && threadIdx.x == 0) s.npasses = p + 1;
 }
 
 // Locates this block's job and tile; returns false when the block has no work
@@ -1849,6 +1896,30 @@ void analyze_release(Workspace* ws) {
   }
 }
 
+// Digest passes to run before the first collision check, for n records (at
+// most n distinct digests, uniformly distributed): the k in 4..8 with the least
+// expected cost in passes, where a check costs a fifth of a pass, pass j (j >=
+// k) runs only when two distinct digests agree on their low j bytes, with
+// probability at most P(j) = n^2 / 2^(8j+1), and is preceded by a check.
+// 8 means no check.
+uint32_t first_digest_passes(size_t n) {
+  const double nn = (double)n * (double)n;
+  constexpr double kCheck = 0.2;
+  // tail[j]: expected cost from just after pass j-1 on, checks included
+  double tail[9];
+  tail[8] = 0.0;
+  for (int j = 7; j >= 4; --j)
+    tail[j] = kCheck + std::min(1.0, std::ldexp(nn, -(8 * j + 1))) * (1.0 + tail[j + 1]);
+  uint32_t best = 8;
+  double best_cost = 8.0;
+  for (uint32_t k = 4; k < 8; ++k)
+    if (k + tail[k] < best_cost) {
+      best_cost = k + tail[k];
+      best = k;
+    }
+  return best;
+}
+
 }  // namespace odp
 
 using namespace odp;
@@ -1898,11 +1969,13 @@ extern "C" int odp_analyze_trace(const odp_event* events, size_t n, uint8_t* out
   // Records by digest (up to 8 passes), then duplicates and round trips.
   const JobSet Jb{v.jobs + kJobBig, 1, nt};
   const bool small = n <= kSmallMax;  // every job then has at most kSmallMax elements
-  hipLaunchKernelGGL(sort_plan_kernel, dim3(1), dim3(64), 0, stream, Jb);
+  const uint32_t kfirst = small ? 0u : first_digest_passes(n);
+  hipLaunchKernelGGL(sort_plan_kernel, dim3(1), dim3(64), 0, stream, Jb, kfirst);
   if (small) {
     hipLaunchKernelGGL(sort_small_kernel, dim3(Jb.njobs), dim3(kQT), 0, stream, Jb);
   } else {
     for (uint32_t p = 0; p < 8; ++p) {
+      if (kfirst && p >= kfirst) hipLaunchKernelGGL(sort_collide_kernel, dim3(nt), dim3(kT), 0, stream, v.jobs + kJobBig, p);
       hipLaunchKernelGGL(sort_hist_kernel, dim3(nt), dim3(kT), 0, stream, Jb, p);
       hipLaunchKernelGGL(sort_scan_kernel, dim3(256), dim3(kT), 0, stream, Jb, p);
       hipLaunchKernelGGL(sort_scatter_kernel, dim3(nt), dim3(kST), 0, stream, Jb, p);
@@ -1934,7 +2007,7 @@ extern "C" int odp_analyze_trace(const odp_event* events, size_t n, uint8_t* out
                      (uint32_t)S_AD_DEV_OR, ctl, out_report);
   // ALLOC/DELETE by (device, address), kernels by (device, start) and (device, end)
   const JobSet Js{v.jobs + kJobAd, 3, nt};
-  hipLaunchKernelGGL(sort_plan_kernel, dim3(1), dim3(64), 0, side, Js);
+  hipLaunchKernelGGL(sort_plan_kernel, dim3(1), dim3(64), 0, side, Js, 0u);
   if (small) {
     hipLaunchKernelGGL(sort_small_kernel, dim3(Js.njobs), dim3(kQT), 0, side, Js);
   } else {
@@ -1973,7 +2046,7 @@ extern "C" int odp_analyze_trace(const odp_event* events, size_t n, uint8_t* out
 
   // Second sort: pairs by (host address, device, bytes).
   const JobSet J2{v.jobs + kJobPr, 1, nt};
-  hipLaunchKernelGGL(sort_plan_kernel, dim3(1), dim3(64), 0, side, J2);
+  hipLaunchKernelGGL(sort_plan_kernel, dim3(1), dim3(64), 0, side, J2, 0u);
   if (small) {
     hipLaunchKernelGGL(sort_small_kernel, dim3(J2.njobs), dim3(kQT), 0, side, J2);
   } else {

@@ -201,3 +201,36 @@ def test_one_workgroup_sort_threshold(odp, n):
     check(odp, ev)
     clean, payloads, payload_of = W.tiny_trace(400 + n, n_events=n, n_devices=2, n_payloads=6)
     check(odp, with_digests(clean, payloads, payload_of))
+
+
+@pytest.mark.parametrize("m,seed", [(30_000, 1), (1_000_000, 2)])
+def test_digests_sharing_low_bytes(odp, m, seed):
+    """The digest sort first orders by the low bytes only (4 of them at 30,000
+    records, 5 at a million); before each further pass a check switches that
+    pass on only when two different digests still agree on every byte sorted
+    so far. Planted digests that differ from another only in byte 6 or 7,
+    interleaved in time with it, need every pass (else their groups interleave
+    and the flags go wrong); planted ones that differ only in byte 4 need the
+    passes up to byte 4 and no more; unrelated random digests take whatever
+    the checks find. Every case must give the oracle's result."""
+    rng = np.random.default_rng(seed)
+    ev = W.empty_events(m)
+    ev["op"] = rng.choice([W.H2D, W.D2H, W.D2D], size=m)
+    ev["src_dev"] = rng.integers(-1, 3, size=m)
+    ev["dst_dev"] = rng.integers(-1, 3, size=m)
+    ev["t_start"] = np.arange(m, dtype=np.uint64) * 3
+    ev["t_end"] = ev["t_start"] + 2
+    top = np.uint64(0xFFFFFFFFFFFFFFFE)
+    base = rng.integers(0, top, size=m // 4, dtype=np.uint64, endpoint=True)
+    dig = rng.choice(base, size=m)
+    flip = rng.random(m) < 0.2
+    which = rng.integers(0, 2, size=m)
+    high = np.where(flip & (which == 0), dig ^ np.uint64(0x5A << 56), dig)
+    high = np.where(flip & (which == 1), high ^ np.uint64(1 << 48), high)
+    for digests in (high, np.where(flip, dig ^ np.uint64(1 << 32), dig),
+                    rng.integers(0, top, size=m, dtype=np.uint64, endpoint=True)):
+        ev["digest"] = digests
+        fg, rg = check(odp, ev)
+    ev["digest"] = high
+    fg, rg = check(odp, ev)
+    assert rg["dd_events"] > m // 4 and rg["rt_pairs"] > 0
