@@ -109,6 +109,26 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
   return lane ? (~0ull >> (64 - lane)) : 0ull;
 }
 
+// Cross-lane moves on the VALU (DPP) instead of LDS permutes: the segmented
+// scans below are chains of dependent moves, so their latency is what counts.
+// Controls (GCN / CDNA encodings): row_shr:n, lane i of a row of 16 reads lane
+// i-n of the row; row_shl:n reads lane i+n; wave_shr:1 reads lane i-1 of the
+// wavefront, wave_shl:1 lane i+1. A lane whose source falls outside keeps `old`.
+constexpr int kDppRowShr = 0x110, kDppRowShl = 0x100, kDppWaveShr1 = 0x138, kDppWaveShl1 = 0x130;
+
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp32(uint32_t old, uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)x, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ uint64_t dpp64(uint64_t old, uint64_t x) {
+  return (uint64_t)dpp32<CTRL>((uint32_t)old, (uint32_t)x) | ((uint64_t)dpp32<CTRL>((uint32_t)(old >> 32), (uint32_t)(x >> 32)) << 32);
+}
+__device__ __forceinline__ uint32_t lane32(uint32_t x, int l) { return (uint32_t)__builtin_amdgcn_readlane((int)x, l); }
+__device__ __forceinline__ uint64_t lane64(uint64_t x, int l) {
+  return (uint64_t)lane32((uint32_t)x, l) | ((uint64_t)lane32((uint32_t)(x >> 32), l) << 32);
+}
+
 __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -983,6 +1003,12 @@ struct St<0> {
   __device__ static BS<0> shfl_down(BS<0> x, int o) { return BS<0>{(uint32_t)__shfl_down((int)x.w, o, 64)}; }
   __device__ static FS<0> shfl(FS<0> x, int l) { return FS<0>{(uint32_t)__shfl((int)x.w, l, 64)}; }
   __device__ static BS<0> shfl(BS<0> x, int l) { return BS<0>{(uint32_t)__shfl((int)x.w, l, 64)}; }
+  template <int C>
+  __device__ static FS<0> dpp(FS<0> old, FS<0> x) { return FS<0>{dpp32<C>(old.w, x.w)}; }
+  template <int C>
+  __device__ static BS<0> dpp(BS<0> old, BS<0> x) { return BS<0>{dpp32<C>(old.w, x.w)}; }
+  __device__ static FS<0> lane(FS<0> x, int l) { return FS<0>{lane32(x.w, l)}; }
+  __device__ static BS<0> lane(BS<0> x, int l) { return BS<0>{lane32(x.w, l)}; }
 };
 
 template <>
@@ -1037,6 +1063,16 @@ struct St<1> {
   __device__ static BS<1> shfl(const BS<1>& x, int l) {
     return BS<1>{(uint32_t)__shfl((int)x.dst, l, 64), __shfl(x.lo, l, 64), __shfl(x.hi, l, 64)};
   }
+  template <int C>
+  __device__ static FS<1> dpp(const FS<1>& old, const FS<1>& x) {
+    return FS<1>{dpp32<C>(old.dst, x.dst), dpp64<C>(old.pres, x.pres), dpp64<C>(old.dir, x.dir)};
+  }
+  template <int C>
+  __device__ static BS<1> dpp(const BS<1>& old, const BS<1>& x) {
+    return BS<1>{dpp32<C>(old.dst, x.dst), dpp64<C>(old.lo, x.lo), dpp64<C>(old.hi, x.hi)};
+  }
+  __device__ static FS<1> lane(const FS<1>& x, int l) { return FS<1>{lane32(x.dst, l), lane64(x.pres, l), lane64(x.dir, l)}; }
+  __device__ static BS<1> lane(const BS<1>& x, int l) { return BS<1>{lane32(x.dst, l), lane64(x.lo, l), lane64(x.hi, l)}; }
 };
 
 // Carry records per wavefront (1,024 consecutive sorted elements).
@@ -1101,33 +1137,76 @@ struct DDArgs {
 };
 
 
-// Inclusive segmented scans inside one round of 64 lanes.
+// Inclusive segmented scans inside one round of 64 lanes: (f, v) pairs where
+// f marks a segment start at or before the lane (forward) or a segment end at
+// or after it (backward). Four DPP steps scan each row of 16 lanes; the row
+// totals, read into scalars, then carry across rows.
+template <int MODE, int CTRL>
+__device__ __forceinline__ void fstep(uint32_t& f, FS<MODE>& v) {
+  using S = St<MODE>;
+  const uint32_t fo = dpp32<CTRL>(0u, f);
+  const FS<MODE> vo = S::template dpp<CTRL>(S::fid(), v);
+  if (!f) v = S::fop(vo, v);
+  f |= fo;
+}
+template <int MODE, int CTRL>
+__device__ __forceinline__ void bstep(uint32_t& f, BS<MODE>& v) {
+  using S = St<MODE>;
+  const uint32_t fo = dpp32<CTRL>(0u, f);
+  const BS<MODE> vo = S::template dpp<CTRL>(S::bid(), v);
+  if (!f) v = S::bop(v, vo);
+  f |= fo;
+}
 template <int MODE>
 __device__ __forceinline__ void wave_fscan(uint32_t& f, FS<MODE>& v) {
   using S = St<MODE>;
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t fo = (uint32_t)__shfl_up((int)f, o, 64);
-    const FS<MODE> vo = S::shfl_up(v, o);
-    if (lane >= o) {
-      if (!f) v = S::fop(vo, v);
-      f |= fo;
-    }
+  fstep<MODE, kDppRowShr + 1>(f, v);
+  fstep<MODE, kDppRowShr + 2>(f, v);
+  fstep<MODE, kDppRowShr + 4>(f, v);
+  fstep<MODE, kDppRowShr + 8>(f, v);
+  // prefixes of rows 1..3: the totals of the rows before, in order
+  uint32_t pf = lane32(f, 15);
+  FS<MODE> pv = S::lane(v, 15);
+  const uint32_t f31 = lane32(f, 31), f47 = lane32(f, 47);
+  const FS<MODE> v31 = S::lane(v, 31), v47 = S::lane(v, 47);
+  const int row = (threadIdx.x & 63) >> 4;
+  if (row >= 2) {
+    pv = f31 ? v31 : S::fop(pv, v31);
+    pf |= f31;
+  }
+  if (row == 3) {
+    pv = f47 ? v47 : S::fop(pv, v47);
+    pf |= f47;
+  }
+  if (row >= 1) {
+    if (!f) v = S::fop(pv, v);
+    f |= pf;
   }
 }
 template <int MODE>
 __device__ __forceinline__ void wave_bscan(uint32_t& f, BS<MODE>& v) {
   using S = St<MODE>;
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t fo = (uint32_t)__shfl_down((int)f, o, 64);
-    const BS<MODE> vo = S::shfl_down(v, o);
-    if (lane + o < 64) {
-      if (!f) v = S::bop(v, vo);
-      f |= fo;
-    }
+  bstep<MODE, kDppRowShl + 1>(f, v);
+  bstep<MODE, kDppRowShl + 2>(f, v);
+  bstep<MODE, kDppRowShl + 4>(f, v);
+  bstep<MODE, kDppRowShl + 8>(f, v);
+  // suffixes of rows 0..2: the totals of the rows after, in order
+  uint32_t qf = lane32(f, 48);
+  BS<MODE> qv = S::lane(v, 48);
+  const uint32_t f32 = lane32(f, 32), f16 = lane32(f, 16);
+  const BS<MODE> v32 = S::lane(v, 32), v16 = S::lane(v, 16);
+  const int row = (threadIdx.x & 63) >> 4;
+  if (row <= 1) {
+    qv = f32 ? v32 : S::bop(v32, qv);
+    qf |= f32;
+  }
+  if (row == 0) {
+    qv = f16 ? v16 : S::bop(v16, qv);
+    qf |= f16;
+  }
+  if (row <= 2) {
+    if (!f) v = S::bop(v, qv);
+    f |= qf;
   }
 }
 
@@ -1406,7 +1485,8 @@ __device__ void ddrt_final_body(const DDArgs& A, uint32_t (*s_val)[kWaveElems], 
       c_dd += (res & ODP_F_DD) != 0;
       c_tx += (res & ODP_F_RT_TX) != 0;
       c_rx += (res & ODP_F_RT_RX) != 0;
-      A.flags[s_val[w][r * 64 + lane]] = res;
+      // classification stored 0 for every valid record: only set flags are written
+      if (res) A.flags[s_val[w][r * 64 + lane]] = res;
       s_code[w][r * 64 + lane] = res;  // the code is not read again
     } else {
       s_code[w][r * 64 + lane] = 0;
