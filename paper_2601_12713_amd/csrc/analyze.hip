@@ -1362,63 +1362,76 @@ __device__ __forceinline__ BwdEl<MODE> bcomb(const BwdEl<MODE>& a, const BwdEl<M
   return BwdEl<MODE>{a.f | b.f, a.f ? a.v : St<MODE>::bop(a.v, b.v)};
 }
 
+// The wavefront aggregates are split into kCT/64 contiguous ranges, one per
+// wavefront, read in coalesced rounds of 64 and scanned with the segmented
+// wavefront scans: a first sweep gives each wavefront's forward and backward
+// totals, LDS carries them across wavefronts, and a second sweep writes every
+// element's exclusive forward prefix and backward suffix.
+template <int MODE>
+__device__ __forceinline__ void load_agg(const DDArgs& A, uint32_t e, uint32_t end, FwdEl<MODE>& x, BwdEl<MODE>& y) {
+  using S = St<MODE>;
+  if (e < end) {
+    const WaveAgg& g = A.agg[e];
+    x = FwdEl<MODE>{g.ff, get_f<MODE>(g.fs)};
+    y = BwdEl<MODE>{g.bf, get_b<MODE>(g.bs)};
+  } else {
+    x = FwdEl<MODE>{0, S::fid()};
+    y = BwdEl<MODE>{0, S::bid()};
+  }
+}
+
 template <int MODE>
 __device__ void ddrt_carry_body(const DDArgs& A, uint32_t nw) {
   using S = St<MODE>;
-  __shared__ FwdEl<MODE> wf[kCT / 64];
-  __shared__ BwdEl<MODE> wbk[kCT / 64];
+  constexpr int kW = kCT / 64;
+  __shared__ FwdEl<MODE> wf[kW];
+  __shared__ BwdEl<MODE> wbk[kW];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const uint32_t per = ceil_div32(nw, kCT);
-  const uint32_t t0 = min(nw, threadIdx.x * per), t1 = min(nw, t0 + per);
-  // this thread's run: forward fold left to right, backward fold right to left
-  FwdEl<MODE> F{0, S::fid()};
-  BwdEl<MODE> B{0, S::bid()};
-#pragma unroll 4
-  for (uint32_t t = t0; t < t1; ++t) {
-    const WaveAgg& g = A.agg[t];
-    F = fcomb<MODE>(F, FwdEl<MODE>{g.ff, get_f<MODE>(g.fs)});
+  const uint32_t rounds = ceil_div32(nw, kCT);
+  const uint32_t c0 = min(nw, (uint32_t)w * rounds * 64), c1 = min(nw, c0 + rounds * 64);
+  // sweep 1: this wavefront's totals
+  FwdEl<MODE> tf{0, S::fid()};
+  BwdEl<MODE> tb{0, S::bid()};
+  for (uint32_t r = 0; r < rounds; ++r) {
+    FwdEl<MODE> x;
+    BwdEl<MODE> y;
+    load_agg<MODE>(A, c0 + r * 64 + lane, c1, x, y);
+    wave_fscan<MODE>(x.f, x.v);
+    wave_bscan<MODE>(y.f, y.v);
+    tf = fcomb<MODE>(tf, FwdEl<MODE>{lane32(x.f, 63), S::lane(x.v, 63)});
+    tb = bcomb<MODE>(tb, BwdEl<MODE>{lane32(y.f, 0), S::lane(y.v, 0)});  // rounds in order: earlier first
   }
-#pragma unroll 4
-  for (uint32_t t = t1; t > t0; --t) {
-    const WaveAgg& g = A.agg[t - 1];
-    B = bcomb<MODE>(BwdEl<MODE>{g.bf, get_b<MODE>(g.bs)}, B);
+  if (lane == 0) {
+    wf[w] = tf;
+    wbk[w] = tb;
   }
-  // inclusive scans inside the wavefront: forward over lower lanes, backward over higher lanes
-  FwdEl<MODE> xf = F;
-  BwdEl<MODE> xb = B;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const FwdEl<MODE> yf{(uint32_t)__shfl_up((int)xf.f, o, 64), S::shfl_up(xf.v, o)};
-    const BwdEl<MODE> yb{(uint32_t)__shfl_down((int)xb.f, o, 64), S::shfl_down(xb.v, o)};
-    if (lane >= o) xf = fcomb<MODE>(yf, xf);
-    if (lane + o < 64) xb = bcomb<MODE>(xb, yb);
-  }
-  if (lane == 63) wf[w] = xf;
-  if (lane == 0) wbk[w] = xb;
-  // exclusive within the wavefront
-  FwdEl<MODE> ef{(uint32_t)__shfl_up((int)xf.f, 1, 64), S::shfl_up(xf.v, 1)};
-  BwdEl<MODE> eb{(uint32_t)__shfl_down((int)xb.f, 1, 64), S::shfl_down(xb.v, 1)};
-  if (lane == 0) ef = FwdEl<MODE>{0, S::fid()};
-  if (lane == 63) eb = BwdEl<MODE>{0, S::bid()};
   __syncthreads();
-  // fold in the wavefront totals before (forward) and after (backward) this one
-  FwdEl<MODE> pf{0, S::fid()};
-  for (int q = 0; q < w; ++q) pf = fcomb<MODE>(pf, wf[q]);
-  BwdEl<MODE> pb{0, S::bid()};
-  for (int q = kCT / 64 - 1; q > w; --q) pb = bcomb<MODE>(wbk[q], pb);
-  FwdEl<MODE> run = fcomb<MODE>(pf, ef);
-  BwdEl<MODE> runb = bcomb<MODE>(eb, pb);
-#pragma unroll 4
-  for (uint32_t t = t0; t < t1; ++t) {
-    put_f<MODE>(A.carry[t].fs, run.v);
-    const WaveAgg& g = A.agg[t];
-    run = fcomb<MODE>(run, FwdEl<MODE>{g.ff, get_f<MODE>(g.fs)});
+  FwdEl<MODE> run{0, S::fid()};
+  for (int q = 0; q < w; ++q) run = fcomb<MODE>(run, wf[q]);
+  BwdEl<MODE> runb{0, S::bid()};
+  for (int q = kW - 1; q > w; --q) runb = bcomb<MODE>(wbk[q], runb);
+  // sweep 2: exclusive prefixes (forward, in order) and suffixes (backward)
+  for (uint32_t r = 0; r < rounds; ++r) {
+    const uint32_t e = c0 + r * 64 + lane;
+    FwdEl<MODE> x;
+    BwdEl<MODE> y;
+    load_agg<MODE>(A, e, c1, x, y);
+    wave_fscan<MODE>(x.f, x.v);
+    const FwdEl<MODE> xp{dpp32<kDppWaveShr1>(0u, x.f), S::template dpp<kDppWaveShr1>(S::fid(), x.v)};
+    const FwdEl<MODE> ex = lane == 0 ? run : fcomb<MODE>(run, xp);
+    if (e < c1) put_f<MODE>(A.carry[e].fs, ex.v);
+    run = fcomb<MODE>(run, FwdEl<MODE>{lane32(x.f, 63), S::lane(x.v, 63)});
   }
-#pragma unroll 4
-  for (uint32_t t = t1; t > t0; --t) {
-    put_b<MODE>(A.carry[t - 1].bs, runb.v);
-    const WaveAgg& g = A.agg[t - 1];
-    runb = bcomb<MODE>(BwdEl<MODE>{g.bf, get_b<MODE>(g.bs)}, runb);
+  for (uint32_t r = rounds; r-- > 0;) {
+    const uint32_t e = c0 + r * 64 + lane;
+    FwdEl<MODE> x;
+    BwdEl<MODE> y;
+    load_agg<MODE>(A, e, c1, x, y);
+    wave_bscan<MODE>(y.f, y.v);
+    const BwdEl<MODE> yn{dpp32<kDppWaveShl1>(0u, y.f), S::template dpp<kDppWaveShl1>(S::bid(), y.v)};
+    const BwdEl<MODE> ex = lane == 63 ? runb : bcomb<MODE>(yn, runb);
+    if (e < c1) put_b<MODE>(A.carry[e].bs, ex.v);
+    runb = bcomb<MODE>(BwdEl<MODE>{lane32(y.f, 0), S::lane(y.v, 0)}, runb);
   }
 }
 
