@@ -600,8 +600,10 @@ __global__ __launch_bounds__(kT) void sort_collide_kernel(SortJob* job, uint32_t
   if (__syncthreads_or(hit) && threadIdx.x == 0) s.npasses = p + 1;
 }
 
-// Locates this block's job and tile; returns false when the block has no work
-// in pass p.
+// Locates this block's job and first tile; returns false when the block has
+// no work in pass p. A job's blocks (J.stride of them) take its tiles
+// tile, tile + stride, ... (next_tile), so a launch may have fewer blocks per
+// job than the job has tiles.
 __device__ __forceinline__ bool job_tile(const JobSet& J, uint32_t p, const SortJob*& s, uint32_t& tile, uint32_t& n) {
   const uint32_t j = blockIdx.x / J.stride;
   if (j >= J.njobs) return false;
@@ -610,6 +612,10 @@ __device__ __forceinline__ bool job_tile(const JobSet& J, uint32_t p, const Sort
   tile = blockIdx.x % J.stride;
   n = *c.n_ptr;
   return p < c.npasses && (uint64_t)tile * kTile < n && tile < c.ntiles_max;
+}
+__device__ __forceinline__ bool next_tile(const JobSet& J, const SortJob* s, uint32_t& tile, uint32_t n) {
+  tile += J.stride;
+  return (uint64_t)tile * kTile < n && tile < s->ntiles_max;
 }
 
 // The key of element j for pass p: gathered from the pass's word on the
@@ -624,6 +630,7 @@ __global__ __launch_bounds__(kT) void sort_hist_kernel(JobSet J, uint32_t p) {
   uint32_t tile, n;
   if (!job_tile(J, p, s, tile, n)) return;
   __shared__ uint32_t h[256];
+  do {
   h[threadIdx.x] = 0;
   __syncthreads();
   const uint32_t src = p & 1;
@@ -640,6 +647,8 @@ __global__ __launch_bounds__(kT) void sort_hist_kernel(JobSet J, uint32_t p) {
     if (d[r] < 256u) atomicAdd(&h[d[r]], 1u);
   __syncthreads();
   s->hist[threadIdx.x * s->ntiles_max + tile] = h[threadIdx.x];
+  __syncthreads();
+  } while (next_tile(J, s, tile, n));
 }
 
 // One block per (job, digit): exclusive scan of the digit's row over tiles;
@@ -699,6 +708,7 @@ __global__ __launch_bounds__(kST) void sort_scatter_kernel(JobSet J, uint32_t p)
   __shared__ uint8_t sdig[kTile];
   __shared__ uint32_t ws[4], wt[4];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  do {
   for (int x = 0; x < 256; x += 64) wcnt[w][x + lane] = 0;
   __syncthreads();
   const uint32_t src = p & 1, dst = src ^ 1;
@@ -810,6 +820,8 @@ __global__ __launch_bounds__(kST) void sort_scatter_kernel(JobSet J, uint32_t p)
     const uint32_t d = sdig[i];
     s->keys[dst][gbase[d] + (i - lbase[d])] = stage[i];
   }
+  __syncthreads();
+  } while (next_tile(J, s, tile, n));
 }
 
 // Small logs: every pass of a job in one workgroup, keys and values held in
@@ -2099,15 +2111,18 @@ extern "C" int odp_analyze_trace(const odp_event* events, size_t n, uint8_t* out
   hipLaunchKernelGGL(reduce_parts_kernel, dim3(S_DD_EVENTS - S_AD_DEV_OR), dim3(kT), 0, side, v.parts, nt,
                      (uint32_t)S_AD_DEV_OR, ctl, out_report);
   // ALLOC/DELETE by (device, address), kernels by (device, start) and (device, end)
-  const JobSet Js{v.jobs + kJobAd, 3, nt};
+  // The subsets are usually far smaller than the log: a capped number of
+  // blocks per job loops over its tiles instead of a block per log tile.
+  const uint32_t side_blocks = std::min<uint32_t>(nt, (uint32_t)cus * 2);
+  const JobSet Js{v.jobs + kJobAd, 3, side_blocks};
   hipLaunchKernelGGL(sort_plan_kernel, dim3(1), dim3(64), 0, side, Js, 0u);
   if (small) {
     hipLaunchKernelGGL(sort_small_kernel, dim3(Js.njobs), dim3(kQT), 0, side, Js);
   } else {
     for (uint32_t p = 0; p < 9; ++p) {
-      hipLaunchKernelGGL(sort_hist_kernel, dim3(Js.njobs * nt), dim3(kT), 0, side, Js, p);
+      hipLaunchKernelGGL(sort_hist_kernel, dim3(Js.njobs * side_blocks), dim3(kT), 0, side, Js, p);
       hipLaunchKernelGGL(sort_scan_kernel, dim3(256 * Js.njobs), dim3(kT), 0, side, Js, p);
-      hipLaunchKernelGGL(sort_scatter_kernel, dim3(Js.njobs * nt), dim3(kST), 0, side, Js, p);
+      hipLaunchKernelGGL(sort_scatter_kernel, dim3(Js.njobs * side_blocks), dim3(kST), 0, side, Js, p);
     }
   }
   // Pairing and the pair list.
@@ -2138,15 +2153,15 @@ extern "C" int odp_analyze_trace(const odp_event* events, size_t n, uint8_t* out
                      &ctl->n_k, ctl);
 
   // Second sort: pairs by (host address, device, bytes).
-  const JobSet J2{v.jobs + kJobPr, 1, nt};
+  const JobSet J2{v.jobs + kJobPr, 1, side_blocks};
   hipLaunchKernelGGL(sort_plan_kernel, dim3(1), dim3(64), 0, side, J2, 0u);
   if (small) {
     hipLaunchKernelGGL(sort_small_kernel, dim3(J2.njobs), dim3(kQT), 0, side, J2);
   } else {
     for (uint32_t p = 0; p < 17; ++p) {
-      hipLaunchKernelGGL(sort_hist_kernel, dim3(nt), dim3(kT), 0, side, J2, p);
+      hipLaunchKernelGGL(sort_hist_kernel, dim3(side_blocks), dim3(kT), 0, side, J2, p);
       hipLaunchKernelGGL(sort_scan_kernel, dim3(256), dim3(kT), 0, side, J2, p);
-      hipLaunchKernelGGL(sort_scatter_kernel, dim3(nt), dim3(kST), 0, side, J2, p);
+      hipLaunchKernelGGL(sort_scatter_kernel, dim3(side_blocks), dim3(kST), 0, side, J2, p);
     }
   }
 

@@ -234,3 +234,45 @@ def test_digests_sharing_low_bytes(odp, m, seed):
     ev["digest"] = high
     fg, rg = check(odp, ev)
     assert rg["dd_events"] > m // 4 and rg["rt_pairs"] > 0
+
+
+def big_subset_log(rng, m, kind):
+    """m records, nearly all KERNELs (kind "kernel") or nearly all ALLOC/DELETE
+    records (kind "alloc"), over host + 3 devices, with some transfers: each
+    of the allocation-path sorts then has more than 512 tiles of 4,096."""
+    ev = W.empty_events(m)
+    t = np.cumsum(rng.integers(0, 3, size=m)).astype(np.uint64)
+    ev["t_start"] = t
+    ev["t_end"] = t + rng.integers(0, 3, size=m).astype(np.uint64)
+    dev = rng.integers(0, 3, size=m)
+    if kind == "kernel":
+        op = np.where(rng.random(m) < 0.96, W.KERNEL, 0)
+        op = np.where((op == 0) & (rng.random(m) < 0.5), W.ALLOC, op)
+        op = np.where(op == 0, W.DELETE, op)
+    else:
+        op = np.where(rng.random(m) < 0.5, W.ALLOC, W.DELETE)
+        op = np.where(rng.random(m) < 0.03, W.KERNEL, op)
+    tx = rng.random(m) < 0.01
+    op = np.where(tx, W.H2D, op)
+    ev["op"] = op
+    ev["src_dev"] = np.where(tx, W.HOST, W.HOST)
+    ev["dst_dev"] = dev
+    var = rng.integers(0, 5000, size=m).astype(np.uint64)
+    ev["src_addr"] = np.uint64(W.HOST_BASE) + var * np.uint64(4096)
+    ev["dst_addr"] = np.uint64(W.DEV_BASE) + var * np.uint64(4096)
+    ev["bytes"] = np.where(op == W.KERNEL, 0, rng.choice([64, 128, 4096], size=m)).astype(np.uint64)
+    ev["digest"] = np.where(tx, rng.integers(0, 1 << 20, size=m).astype(np.uint64), np.uint64(0))
+    return ev
+
+
+@pytest.mark.parametrize("kind", ["kernel", "alloc"])
+def test_allocation_path_sorts_loop_over_tiles(odp, kind):
+    """The allocation-path sorts run a capped number of blocks per job (twice
+    the compute units) that loop over the job's tiles; logs whose KERNEL or
+    ALLOC/DELETE subset spans more tiles than that must match the oracle."""
+    ev = big_subset_log(np.random.default_rng(31 if kind == "kernel" else 32), 2_400_000, kind)
+    fg, rg = check(odp, ev)
+    if kind == "kernel":
+        assert rg["n_kernels"] > 2_100_000
+    else:
+        assert rg["n_alloc_pairs"] > 100_000 and rg["ra_events"] > 0
