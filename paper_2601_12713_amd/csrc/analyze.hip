@@ -41,6 +41,11 @@ constexpr int kMaxWords = 3;
 constexpr int kMaxPasses = 24;
 constexpr int kEp = 11;                 // endpoints: host (0) and devices 0..9 (1..10)
 constexpr uint8_t kNotTransfer = 0xFF;
+// Logs of fewer than 2^24 records carry each record's endpoint code in the
+// top byte of its digest-sort value (the record index in the low 24 bits), so
+// the scans over the sorted order need no gather of the code by index.
+constexpr uint32_t kPackLimit = 1u << 24;
+constexpr uint32_t kIdxMask = kPackLimit - 1;
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 
 enum : uint8_t { C_INVALID = 0, C_TRANSFER = 1, C_ALLOCDEL = 2, C_KERNEL = 3 };
@@ -318,7 +323,7 @@ __global__ __launch_bounds__(kT) void classify_kernel(const odp_event* __restric
       cls[i] = c;
       aux[i] = a;
       keys[i] = key;
-      vals[i] = i;
+      vals[i] = n < kPackLimit ? i | ((uint32_t)a << 24) : i;
       kor |= key;
       kand &= key;
     }
@@ -1244,8 +1249,16 @@ __device__ __forceinline__ void load_wave(const unsigned long long* k, const uin
   const unsigned long long before = (lane == 0 && wb > 0 && wb < n) ? k[wb - 1] : 0ull;
   const unsigned long long after = (lane == 63 && wb + kWaveElems < n) ? k[wb + kWaveElems] : 0ull;
   uint8_t a[kRounds];
+  if (n < kPackLimit) {
 #pragma unroll
-  for (int r = 0; r < kRounds; ++r) a[r] = wb + r * 64 + lane < n ? aux[val[r]] : kNotTransfer;
+    for (int r = 0; r < kRounds; ++r) {
+      a[r] = wb + r * 64 + lane < n ? (uint8_t)(val[r] >> 24) : kNotTransfer;
+      val[r] &= kIdxMask;
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) a[r] = wb + r * 64 + lane < n ? aux[val[r]] : kNotTransfer;
+  }
   heads = tails = 0;
 #pragma unroll
   for (int r = 0; r < kRounds; ++r) {
@@ -1278,7 +1291,7 @@ __device__ __forceinline__ void load_round(const unsigned long long* k, const ui
   if (lane == 63 && in && j + 1 < n) next = k[j + 1];
   head = in && (j == 0 || prev != key);
   tail = in && (j + 1 == n || next != key);
-  a = in ? aux[v[j]] : kNotTransfer;
+  a = !in ? kNotTransfer : n < kPackLimit ? (uint8_t)(v[j] >> 24) : aux[v[j]];
 }
 
 // Per-wavefront aggregates. The forward one folds the elements after the

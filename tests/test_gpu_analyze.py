@@ -276,3 +276,33 @@ def test_allocation_path_sorts_loop_over_tiles(odp, kind):
         assert rg["n_kernels"] > 2_100_000
     else:
         assert rg["n_alloc_pairs"] > 100_000 and rg["ra_events"] > 0
+
+
+def test_log_above_packed_index_limit(odp):
+    """Logs of fewer than 2^24 records carry the endpoint code in the top byte
+    of the digest sort's values; a longer log keeps plain indices and gathers
+    the codes. 2^24 + 70,000 records of transfers (repeated digests, three
+    devices), kernels and ALLOC/DELETE records must match the oracle."""
+    m = (1 << 24) + 70_000
+    rng = np.random.default_rng(33)
+    ev = W.empty_events(m)
+    t = np.cumsum(rng.integers(0, 3, size=m)).astype(np.uint64)
+    ev["t_start"] = t
+    ev["t_end"] = t + 1
+    op = rng.choice([W.H2D, W.D2H, W.D2D, W.KERNEL, W.ALLOC, W.DELETE], size=m,
+                    p=[0.4, 0.3, 0.1, 0.1, 0.05, 0.05])
+    ev["op"] = op
+    src = rng.integers(-1, 3, size=m)
+    dst = rng.integers(-1, 3, size=m)
+    src = np.where(op == W.H2D, -1, np.where(op == W.D2H, np.maximum(src, 0), np.maximum(src, 0)))
+    dst = np.where(op == W.D2H, -1, np.maximum(dst, 0))
+    ev["src_dev"], ev["dst_dev"] = src, dst
+    pool = rng.integers(0, np.uint64(0xFFFFFFFFFFFFFFFE), size=m // 3, dtype=np.uint64, endpoint=True)
+    is_tx = np.isin(op, [W.H2D, W.D2H, W.D2D])
+    ev["digest"] = np.where(is_tx, rng.choice(pool, size=m), np.uint64(0))
+    var = rng.integers(0, 20_000, size=m).astype(np.uint64)
+    ev["src_addr"] = np.uint64(W.HOST_BASE) + var * np.uint64(4096)
+    ev["dst_addr"] = np.uint64(W.DEV_BASE) + var * np.uint64(4096)
+    ev["bytes"] = np.where(op == W.KERNEL, 0, 4096).astype(np.uint64)
+    fg, rg = check(odp, ev)
+    assert rg["n_events"] == m and rg["dd_events"] > 1_000_000 and rg["rt_pairs"] > 1000
