@@ -2088,13 +2088,16 @@ extern "C" int odp_analyze_trace(const odp_event* events, size_t n, uint8_t* out
   const JobSet Jb{v.jobs + kJobBig, 1, nt};
   const bool small = n <= kSmallMax;  // every job then has at most kSmallMax elements
   const uint32_t kfirst = small ? 0u : first_digest_passes(n);
+  // the digest histograms take two tiles per block on long logs (measured a
+  // little faster than one: the per-block start-up is amortised)
+  const JobSet Jh{v.jobs + kJobBig, 1, nt > 4u * (uint32_t)cus ? (nt + 1) / 2 : nt};
   hipLaunchKernelGGL(sort_plan_kernel, dim3(1), dim3(64), 0, stream, Jb, kfirst);
   if (small) {
     hipLaunchKernelGGL(sort_small_kernel, dim3(Jb.njobs), dim3(kQT), 0, stream, Jb);
   } else {
     for (uint32_t p = 0; p < 8; ++p) {
       if (kfirst && p >= kfirst) hipLaunchKernelGGL(sort_collide_kernel, dim3(nt), dim3(kT), 0, stream, v.jobs + kJobBig, p);
-      hipLaunchKernelGGL(sort_hist_kernel, dim3(nt), dim3(kT), 0, stream, Jb, p);
+      hipLaunchKernelGGL(sort_hist_kernel, dim3(Jh.stride), dim3(kT), 0, stream, Jh, p);
       hipLaunchKernelGGL(sort_scan_kernel, dim3(256), dim3(kT), 0, stream, Jb, p);
       hipLaunchKernelGGL(sort_scatter_kernel, dim3(nt), dim3(kST), 0, stream, Jb, p);
     }
