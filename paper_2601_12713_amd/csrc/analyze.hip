@@ -2014,6 +2014,239 @@ void analyze_release(Workspace* ws) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Logs of at most kTinyMax records: the whole analysis in one workgroup, one
+// thread per record, each rule written out as its definition. The records sit
+// in LDS, compacted into per-class lists (transfers, ALLOC/DELETE, kernels);
+// a thread walks the list its rule needs in a loop that is the same for the
+// whole wavefront, so every LDS read is a broadcast. One launch instead of the
+// sort and scan pipeline (two dozen launches on two streams) that longer logs
+// take.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kTinyMax = 512;
+
+struct TinyLds {
+  unsigned long long dig[kTinyMax], saddr[kTinyMax], daddr[kTinyMax], bytes[kTinyMax], ts[kTinyMax], te[kTinyMax];
+  uint16_t list[3][kTinyMax];   // record indices of each class in log order: transfers, ALLOC/DELETE, kernels
+  uint16_t del_of[kTinyMax];    // the DELETE paired with an ALLOC
+  int8_t src[kTinyMax], dst[kTinyMax];
+  uint8_t op[kTinyMax], cls[kTinyMax], paired[kTinyMax];
+  uint32_t wcnt[kTinyMax / 64][3];
+  unsigned long long acc[kTinyMax / 64][24];
+};
+
+enum TinyAcc {
+  TA_INV, TA_TX, TA_K, TA_PAIRS, TA_UNP_A, TA_UNP_D, TA_DD, TA_DD_GRP, TA_DD_B, TA_DD_T, TA_RT_TX, TA_RT_RX, TA_RT_B,
+  TA_RT_T, TA_RA, TA_RA_GRP, TA_RA_B, TA_RA_T, TA_UA, TA_UA_B, TA_UA_T, TA_BAD, TA_COUNT
+};
+
+__global__ __launch_bounds__(kTinyMax) void analyze_tiny_kernel(const odp_event* __restrict__ ev, uint32_t n,
+                                                               uint8_t* __restrict__ flags, odp_report* __restrict__ rep) {
+  __shared__ TinyLds L;
+  const uint32_t i = threadIdx.x;
+  const int lane = i & 63, w = i >> 6;
+  const bool in = i < n;
+  if (in) {
+    const odp_event& e = ev[i];
+    L.dig[i] = e.digest;
+    L.saddr[i] = e.src_addr;
+    L.daddr[i] = e.dst_addr;
+    L.bytes[i] = e.bytes;
+    L.ts[i] = e.t_start;
+    L.te[i] = e.t_end;
+    L.op[i] = e.op;
+    L.src[i] = (int8_t)max(-128, min(127, (int)e.src_dev));
+    L.dst[i] = (int8_t)max(-128, min(127, (int)e.dst_dev));
+    L.paired[i] = 0;
+  }
+  __syncthreads();
+  // validity (as the classification of longer logs) and the class lists
+  uint8_t c = C_INVALID;
+  if (in) {
+    const uint8_t op = L.op[i];
+    const bool tx = op == ODP_H2D || op == ODP_D2H || op == ODP_D2D;
+    const bool valid = op >= ODP_ALLOC && op <= ODP_KERNEL && L.te[i] >= L.ts[i] && (i == 0 || L.ts[i] >= L.ts[i - 1]) &&
+                       dev_ok(ev[i].dst_dev) && (!tx || dev_ok(ev[i].src_dev));
+    if (valid) c = tx ? C_TRANSFER : op == ODP_KERNEL ? C_KERNEL : C_ALLOCDEL;
+    L.cls[i] = c;
+  }
+  uint32_t pos[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const uint64_t m = __ballot(c == C_TRANSFER + k);
+    pos[k] = (uint32_t)__popcll(m & lanemask_lt());
+    if (lane == 0) L.wcnt[w][k] = (uint32_t)__popcll(m);
+  }
+  __syncthreads();
+  uint32_t cnt[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    uint32_t before = 0, all = 0;
+    for (int x = 0; x < (int)(kTinyMax / 64); ++x) {
+      if (x < w) before += L.wcnt[x][k];
+      all += L.wcnt[x][k];
+    }
+    cnt[k] = all;
+    if (c == C_TRANSFER + k) L.list[k][before + pos[k]] = (uint16_t)i;
+  }
+  __syncthreads();
+  unsigned long long a[TA_COUNT];
+#pragma unroll
+  for (int k = 0; k < TA_COUNT; ++k) a[k] = 0;
+  a[TA_BAD] = in && c == C_INVALID ? i : kNone;
+  a[TA_INV] = in && c == C_INVALID;
+  a[TA_TX] = c == C_TRANSFER;
+  a[TA_K] = c == C_KERNEL;
+  uint8_t f = in && c == C_INVALID ? ODP_F_INVALID : 0;
+  // duplicates and round trips: one walk over the transfers
+  if (c == C_TRANSFER) {
+    const unsigned long long dg = L.dig[i];
+    const int sr = L.src[i], ds = L.dst[i];
+    bool dd = false, later = false, tx = false, rx = false;
+    for (uint32_t q = 0; q < cnt[0]; ++q) {
+      const uint32_t j = L.list[0][q];
+      if (L.dig[j] != dg) continue;
+      const int sj = L.src[j], dj = L.dst[j];
+      if (j < i) {
+        dd |= dj == ds;
+        // the latest earlier transfer between the same two endpoints (the walk is in log order)
+        if (sr != ds && sj != dj && ((sj == sr && dj == ds) || (sj == ds && dj == sr))) rx = sj == ds;
+      } else if (j > i) {
+        later |= dj == ds;
+        tx |= sr != ds && sj == ds && dj == sr;
+      }
+    }
+    const unsigned long long b = L.bytes[i], d = L.te[i] - L.ts[i];
+    if (dd) {
+      f |= ODP_F_DD;
+      a[TA_DD] = 1;
+      a[TA_DD_B] = b;
+      a[TA_DD_T] = d;
+    } else {
+      a[TA_DD_GRP] = later;
+    }
+    if (tx) {
+      f |= ODP_F_RT_TX;
+      a[TA_RT_TX] = 1;
+    }
+    if (rx) {
+      f |= ODP_F_RT_RX;
+      a[TA_RT_RX] = 1;
+      a[TA_RT_B] = b;
+      a[TA_RT_T] = d;
+    }
+  }
+  // pairing: a DELETE pairs with the record just before it in its (device,
+  // device address) group when that record is an ALLOC
+  if (c == C_ALLOCDEL && L.op[i] == ODP_DELETE) {
+    const int ds = L.dst[i];
+    const unsigned long long da = L.daddr[i];
+    uint32_t prev = kNone;
+    for (uint32_t q = 0; q < cnt[1]; ++q) {
+      const uint32_t j = L.list[1][q];
+      if (j < i && L.dst[j] == ds && L.daddr[j] == da) prev = j;
+    }
+    if (prev != kNone && L.op[prev] == ODP_ALLOC) {
+      L.paired[prev] = 1;
+      L.del_of[prev] = (uint16_t)i;
+      L.paired[i] = 1;
+    }
+  }
+  __syncthreads();
+  if (c == C_ALLOCDEL) {
+    if (L.paired[i]) {
+      f |= ODP_F_PAIRED;
+    } else if (L.op[i] == ODP_ALLOC) {
+      a[TA_UNP_A] = 1;
+    } else {
+      a[TA_UNP_D] = 1;
+    }
+  }
+  // repeated and unused allocations, over the paired ALLOCs
+  if (c == C_ALLOCDEL && L.paired[i] && L.op[i] == ODP_ALLOC) {
+    const uint32_t del = L.del_of[i];
+    const int ds = L.dst[i];
+    const unsigned long long ha = L.saddr[i], b = L.bytes[i];
+    bool ra = false, later = false;
+    for (uint32_t q = 0; q < cnt[1]; ++q) {
+      const uint32_t j = L.list[1][q];
+      if (j == i || L.op[j] != ODP_ALLOC || !L.paired[j]) continue;
+      if (L.saddr[j] == ha && L.dst[j] == ds && L.bytes[j] == b) {
+        ra |= j < i;
+        later |= j > i;
+      }
+    }
+    const unsigned long long t0 = L.ts[i], t1 = L.te[del];
+    bool used = false;
+    for (uint32_t q = 0; q < cnt[2]; ++q) {
+      const uint32_t k = L.list[2][q];
+      used |= L.dst[k] == ds && L.ts[k] <= t1 && L.te[k] >= t0;
+    }
+    const unsigned long long d = (L.te[i] - L.ts[i]) + (L.te[del] - L.ts[del]);
+    a[TA_PAIRS] = 1;
+    if (ra) {
+      f |= ODP_F_RA;
+      a[TA_RA] = 1;
+      a[TA_RA_B] = b;
+      a[TA_RA_T] = d;
+    } else {
+      a[TA_RA_GRP] = later;
+    }
+    if (!used) {
+      f |= ODP_F_UA;
+      a[TA_UA] = 1;
+      a[TA_UA_B] = b;
+      a[TA_UA_T] = d;
+    }
+  }
+  if (in) flags[i] = f;
+  // the report: sums (the first rejected record: minimum) over the workgroup
+#pragma unroll
+  for (int k = 0; k < TA_COUNT; ++k) {
+    unsigned long long v = a[k];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      const unsigned long long y = __shfl_xor(v, o, 64);
+      v = k == TA_BAD ? min(v, y) : v + y;
+    }
+    if (lane == 0) L.acc[w][k] = v;
+  }
+  __syncthreads();
+  if (i == 0) {
+    unsigned long long t[TA_COUNT];
+    for (int k = 0; k < TA_COUNT; ++k) {
+      t[k] = k == TA_BAD ? (unsigned long long)kNone : 0ull;
+      for (int x = 0; x < (int)(kTinyMax / 64); ++x) t[k] = k == TA_BAD ? min(t[k], L.acc[x][k]) : t[k] + L.acc[x][k];
+    }
+    rep->n_events = n;
+    rep->n_invalid = t[TA_INV];
+    rep->n_transfers = t[TA_TX];
+    rep->n_kernels = t[TA_K];
+    rep->n_alloc_pairs = t[TA_PAIRS];
+    rep->n_unpaired_alloc = t[TA_UNP_A];
+    rep->n_unpaired_delete = t[TA_UNP_D];
+    rep->dd_events = t[TA_DD];
+    rep->dd_groups = t[TA_DD_GRP];
+    rep->dd_members = t[TA_DD] + t[TA_DD_GRP];
+    rep->dd_bytes = t[TA_DD_B];
+    rep->dd_time_ns = t[TA_DD_T];
+    rep->rt_pairs = t[TA_RT_TX];
+    rep->rt_rx_events = t[TA_RT_RX];
+    rep->rt_bytes = t[TA_RT_B];
+    rep->rt_time_ns = t[TA_RT_T];
+    rep->ra_events = t[TA_RA];
+    rep->ra_groups = t[TA_RA_GRP];
+    rep->ra_members = t[TA_RA] + t[TA_RA_GRP];
+    rep->ra_bytes = t[TA_RA_B];
+    rep->ra_time_ns = t[TA_RA_T];
+    rep->ua_events = t[TA_UA];
+    rep->ua_bytes = t[TA_UA_B];
+    rep->ua_time_ns = t[TA_UA_T];
+    rep->first_bad_event = (uint32_t)t[TA_BAD];
+    rep->status = t[TA_BAD] != kNone ? 1 : 0;
+  }
+}
+
 // Digest passes to run before the first collision check, for n records (at
 // most n distinct digests, uniformly distributed): the k in 4..8 with the least
 // expected cost in passes, where a check costs a fifth of a pass, pass j (j >=
@@ -2048,6 +2281,12 @@ extern "C" int odp_analyze_trace(const odp_event* events, size_t n, uint8_t* out
   if (n > 0xFFFFFFFFull) return set_error(ODP_ERANGE, "odp_analyze_trace: n = %zu above 2^32 - 1", n);
   if (!out_report) return set_error(ODP_EINVAL, "odp_analyze_trace: null report");
   if (n > 0 && (!events || !out_flags)) return set_error(ODP_EINVAL, "odp_analyze_trace: null array with n = %zu", n);
+  if (n <= kTinyMax) {
+    // one workgroup, no workspace
+    hipLaunchKernelGGL(analyze_tiny_kernel, dim3(1), dim3(kTinyMax), 0, stream, events, (uint32_t)n, out_flags,
+                       out_report);
+    return check_hip(hipGetLastError(), "odp_analyze_trace launch");
+  }
   int err = 0;
   Workspace* ws = workspace_for(stream, &err);
   if (!ws) return err;

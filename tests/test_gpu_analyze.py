@@ -191,11 +191,12 @@ def test_analysis_replayed_from_a_graph(odp):
         compare(d_flags.cpu().numpy(), odp.report_to_dict(d_rep.cpu().numpy()), fr, rr)
 
 
-@pytest.mark.parametrize("n", [1, 2047, 2048, 2049, 4200])
+@pytest.mark.parametrize("n", [1, 511, 512, 513, 2047, 2048, 2049, 4200])
 def test_one_workgroup_sort_threshold(odp, n):
-    """Logs of at most 2,048 records take the one-workgroup sort, longer ones
-    the multi-launch passes; both sides of the threshold match the oracle
-    (three devices, rejected records, multi-word keys)."""
+    """Logs of at most 512 records are analysed by one workgroup (each rule
+    written out per record), up to 2,048 records take the one-workgroup sorts,
+    longer ones the multi-launch passes; every side of both thresholds matches
+    the oracle (three devices, rejected records, multi-word keys)."""
     ev, payloads, payload_of = W.tiny_trace(300 + n, n_events=n, n_devices=3, n_payloads=6, invalid_rate=0.01)
     ev = with_digests(ev, payloads, payload_of)
     check(odp, ev)
