@@ -102,13 +102,23 @@ __device__ __forceinline__ uint64_t xx_tail_bytes(uint64_t h, const uint8_t* p, 
   return h;
 }
 
+// Lane k of each group of four lanes, broadcast to the group (DPP quad_perm,
+// a VALU move: no LDS round trip on the accumulator chain). Every lane of the
+// group must be active.
+template <int K>
+__device__ __forceinline__ uint64_t xx_quad_bcast(uint64_t x) {
+  constexpr int ctrl = K * 0x55;  // quad_perm:[K,K,K,K]
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)x, ctrl, 0xF, 0xF, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(x >> 32), ctrl, 0xF, 0xF, false);
+  return ((uint64_t)hi << 32) | lo;
+}
+
 // Gathers the accumulator of lanes 4g..4g+3 into all four lanes.
 __device__ __forceinline__ void xx_gather4(uint64_t acc, uint64_t& v1, uint64_t& v2, uint64_t& v3, uint64_t& v4) {
-  int base = (threadIdx.x & 63) & ~3;
-  v1 = __shfl(acc, base + 0, 64);
-  v2 = __shfl(acc, base + 1, 64);
-  v3 = __shfl(acc, base + 2, 64);
-  v4 = __shfl(acc, base + 3, 64);
+  v1 = xx_quad_bcast<0>(acc);
+  v2 = xx_quad_bcast<1>(acc);
+  v3 = xx_quad_bcast<2>(acc);
+  v4 = xx_quad_bcast<3>(acc);
 }
 
 // XXH64 of `nw` little-endian u64 words (a tree node's children), computed by
