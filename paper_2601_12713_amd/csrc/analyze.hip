@@ -2103,6 +2103,7 @@ __global__ __launch_bounds__(kTinyMax) void analyze_tiny_kernel(const odp_event*
     const unsigned long long dg = L.dig[i];
     const int sr = L.src[i], ds = L.dst[i];
     bool dd = false, later = false, tx = false, rx = false;
+#pragma unroll 4
     for (uint32_t q = 0; q < cnt[0]; ++q) {
       const uint32_t j = L.list[0][q];
       if (L.dig[j] != dg) continue;
@@ -2142,6 +2143,7 @@ __global__ __launch_bounds__(kTinyMax) void analyze_tiny_kernel(const odp_event*
     const int ds = L.dst[i];
     const unsigned long long da = L.daddr[i];
     uint32_t prev = kNone;
+#pragma unroll 4
     for (uint32_t q = 0; q < cnt[1]; ++q) {
       const uint32_t j = L.list[1][q];
       if (j < i && L.dst[j] == ds && L.daddr[j] == da) prev = j;
@@ -2168,6 +2170,7 @@ __global__ __launch_bounds__(kTinyMax) void analyze_tiny_kernel(const odp_event*
     const int ds = L.dst[i];
     const unsigned long long ha = L.saddr[i], b = L.bytes[i];
     bool ra = false, later = false;
+#pragma unroll 4
     for (uint32_t q = 0; q < cnt[1]; ++q) {
       const uint32_t j = L.list[1][q];
       if (j == i || L.op[j] != ODP_ALLOC || !L.paired[j]) continue;
@@ -2178,6 +2181,7 @@ __global__ __launch_bounds__(kTinyMax) void analyze_tiny_kernel(const odp_event*
     }
     const unsigned long long t0 = L.ts[i], t1 = L.te[del];
     bool used = false;
+#pragma unroll 4
     for (uint32_t q = 0; q < cnt[2]; ++q) {
       const uint32_t k = L.list[2][q];
       used |= L.dst[k] == ds && L.ts[k] <= t1 && L.te[k] >= t0;
@@ -2212,12 +2216,15 @@ __global__ __launch_bounds__(kTinyMax) void analyze_tiny_kernel(const odp_event*
     if (lane == 0) L.acc[w][k] = v;
   }
   __syncthreads();
+  if (i < TA_COUNT) {  // one thread per field folds the wavefronts' partials
+    unsigned long long v = i == TA_BAD ? (unsigned long long)kNone : 0ull;
+#pragma unroll
+    for (int x = 0; x < (int)(kTinyMax / 64); ++x) v = i == TA_BAD ? min(v, L.acc[x][i]) : v + L.acc[x][i];
+    L.acc[0][i] = v;
+  }
+  __syncthreads();
   if (i == 0) {
-    unsigned long long t[TA_COUNT];
-    for (int k = 0; k < TA_COUNT; ++k) {
-      t[k] = k == TA_BAD ? (unsigned long long)kNone : 0ull;
-      for (int x = 0; x < (int)(kTinyMax / 64); ++x) t[k] = k == TA_BAD ? min(t[k], L.acc[x][k]) : t[k] + L.acc[x][k];
-    }
+    const unsigned long long* t = L.acc[0];
     rep->n_events = n;
     rep->n_invalid = t[TA_INV];
     rep->n_transfers = t[TA_TX];
