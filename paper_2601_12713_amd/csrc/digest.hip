@@ -27,9 +27,12 @@ constexpr int kWaves = 4;
 constexpr int kThreads = 64 * kWaves;
 constexpr int kRows = 64;                  // rows per item
 constexpr int kRowsPerWave = kRows / kWaves;
-constexpr int kSlab = 512;                 // bytes of each row staged per step
 constexpr int kPad = 16;                   // LDS row padding (bank spread)
-constexpr int kStride = kSlab + kPad;
+// Bytes of each row staged per step: 512 in the one-launch-per-buffer kernel,
+// 256 in the persistent batched kernel, whose loop keeps more state live (the
+// smaller step frees the load registers that the larger one spills there).
+constexpr int kSlabOne = 512;
+constexpr int kSlabBatch = 256;
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
@@ -39,8 +42,9 @@ struct RowDesc {
   uint32_t present;
 };
 
+template <int SLAB>
 struct Smem {
-  uint8_t slab[kWaves][kRowsPerWave * kStride];
+  uint8_t slab[kWaves][kRowsPerWave * (SLAB + kPad)];
   RowDesc rows[kRows];
   uint64_t leafdig[2][kRows];  // leaf digests of the current and the previous item
   uint32_t outidx[kRows];
@@ -114,8 +118,9 @@ __device__ __forceinline__ uint64_t finish_row(uint64_t acc, const RowDesc& hrow
 
 // Fast path as one stage of a wavefront's continuous stream of items: 16
 // whole, 16-byte aligned leaves at leaf_base + r*4096 (leaf_base wave-uniform).
-// Each step stages 512 bytes of every leaf (8 KiB per wavefront) through the
-// wavefront's LDS slab with eight 128-bit nontemporal loads per lane; load k
+// Each step stages 64*NL bytes of every leaf (512 bytes, 8 KiB per wavefront,
+// in the per-buffer kernel; 256 in the batched one) through the wavefront's
+// LDS slab with NL 128-bit nontemporal loads per lane; load k
 // covers 128 contiguous bytes of 8 leaves (lane L: leaf L/8 + 8*(k%2), bytes
 // 128*(k/2) + 16*(L%8)), so every address is one of two per-lane offsets from
 // the uniform base plus an immediate. Lane 4r+a then folds accumulator a's
@@ -146,17 +151,20 @@ __device__ __forceinline__ void fast_load(u32x4 (&R)[NL], const uint8_t* base, u
 
 template <int NL>
 __device__ __forceinline__ void fast_stage(const u32x4 (&R)[NL], uint8_t* slab) {
+  constexpr int kStride = NL * 64 + kPad;
   const int lane = threadIdx.x & 63;
   uint8_t* const wr = slab + (lane >> 3) * kStride + (lane & 7) * 16;
 #pragma unroll
   for (int k = 0; k < NL; ++k) *reinterpret_cast<u32x4*>(wr + 8 * (k & 1) * kStride + (k >> 1) * 128) = R[k];
 }
 
+template <int SLAB>
 __device__ __forceinline__ uint64_t fast_fold(uint64_t acc, const uint8_t* slab) {
+  constexpr int kStride = SLAB + kPad;
   const int lane = threadIdx.x & 63;
   const uint8_t* const rd = slab + (lane >> 2) * kStride + (lane & 3) * 8;
 #pragma unroll
-  for (int h2 = 0; h2 < kSlab / 128; ++h2) {
+  for (int h2 = 0; h2 < SLAB / 128; ++h2) {
     uint64_t w[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) w[q] = *reinterpret_cast<const uint64_t*>(rd + (h2 * 4 + q) * 32);
@@ -169,7 +177,7 @@ __device__ __forceinline__ uint64_t fast_fold(uint64_t acc, const uint8_t* slab)
 template <int NL>
 __device__ __forceinline__ uint64_t hash_wave_leaves_pipe(const uint8_t* leaf_base, const uint8_t* next, bool& pre,
                                                           u32x4 (&RA)[NL], u32x4 (&RB)[NL], uint8_t* slab) {
-  static_assert(NL == kSlab / 64, "eight 128-bit loads per lane cover one step");
+  constexpr int kSlab = NL * 64;  // NL 128-bit loads per lane cover one step
   constexpr uint32_t NS = kLeaf / kSlab;
   const int lane = threadIdx.x & 63;
   uint64_t acc = xx_acc_init(0, lane & 3);
@@ -183,13 +191,13 @@ __device__ __forceinline__ uint64_t hash_wave_leaves_pipe(const uint8_t* leaf_ba
     if (s + 2 < NS) fast_load(RA, leaf_base, (s + 2) * kSlab);
     else if (next) fast_load(RA, next, 0);
     wave_fence();
-    acc = fast_fold(acc, slab);
+    acc = fast_fold<kSlab>(acc, slab);
     wave_fence();
     fast_stage(RB, slab);
     if (s + 3 < NS) fast_load(RB, leaf_base, (s + 3) * kSlab);
     else if (next) fast_load(RB, next, kSlab);
     wave_fence();
-    acc = fast_fold(acc, slab);
+    acc = fast_fold<kSlab>(acc, slab);
     wave_fence();
   }
   pre = next != nullptr;
@@ -207,6 +215,7 @@ __device__ __forceinline__ uint64_t hash_wave_leaves_pipe(const uint8_t* leaf_ba
 // row's last 16-byte granule, so inside the same page. Otherwise every lane
 // reads its words straight from memory at any alignment, eight stripes per
 // batch of independent loads. Returns the row digest in lane 4r.
+template <int kSlab>
 __device__ __forceinline__ void rows_load(u32x4 (&R)[kSlab / 64], const RowDesc& ra, const RowDesc& rb, uint32_t step_off) {
   const int lane = threadIdx.x & 63;
   const uint32_t lc = (uint32_t)(lane & 7) * 16;
@@ -218,7 +227,9 @@ __device__ __forceinline__ void rows_load(u32x4 (&R)[kSlab / 64], const RowDesc&
   }
 }
 
+template <int kSlab>
 __device__ __forceinline__ uint64_t hash_wave_rows(const RowDesc* rows, uint8_t* slab) {
+  constexpr int kStride = kSlab + kPad;
   const int lane = threadIdx.x & 63;
   const RowDesc mine = rows[lane & 15];
   const bool aligned = !mine.present || ((reinterpret_cast<uintptr_t>(mine.base) & 15) == 0);
@@ -243,12 +254,12 @@ __device__ __forceinline__ uint64_t hash_wave_rows(const RowDesc* rows, uint8_t*
     u32x4 R0[kSlab / 64], R1[kSlab / 64];
 #pragma unroll
     for (int k = 0; k < kSlab / 64; ++k) R0[k] = R1[k] = u32x4{0u, 0u, 0u, 0u};
-    rows_load(R0, ra, rb, 0);
-    rows_load(R1, ra, rb, kSlab);
+    rows_load<kSlab>(R0, ra, rb, 0);
+    rows_load<kSlab>(R1, ra, rb, kSlab);
 #pragma unroll 1
     for (uint32_t s = 0; s < nslab; s += 2) {
       fast_stage(R0, slab);
-      if (s + 2 < nslab) rows_load(R0, ra, rb, (s + 2) * kSlab);
+      if (s + 2 < nslab) rows_load<kSlab>(R0, ra, rb, (s + 2) * kSlab);
       wave_fence();
       uint32_t q0 = s * (kSlab / 32);
 #pragma unroll
@@ -257,7 +268,7 @@ __device__ __forceinline__ uint64_t hash_wave_rows(const RowDesc* rows, uint8_t*
       wave_fence();
       if (s + 1 < nslab) {
         fast_stage(R1, slab);
-        if (s + 3 < nslab) rows_load(R1, ra, rb, (s + 3) * kSlab);
+        if (s + 3 < nslab) rows_load<kSlab>(R1, ra, rb, (s + 3) * kSlab);
         wave_fence();
         q0 += kSlab / 32;
 #pragma unroll
@@ -358,7 +369,7 @@ __device__ __forceinline__ void tree_up(uint64_t h, uint64_t m, uint64_t nj, uin
 constexpr uint32_t kOneTicketNodes = kFanIn * kFanIn;
 constexpr int kGatherPer = kOneTicketNodes / kThreads;
 
-__device__ __forceinline__ void finish_upper(Smem& sm, uint32_t n1, uint64_t* tree, uint32_t* tk, uint64_t* out) {
+__device__ __forceinline__ void finish_upper(Smem<kSlabOne>& sm, uint32_t n1, uint64_t* tree, uint32_t* tk, uint64_t* out) {
   static_assert(sizeof(sm.slab) >= kOneTicketNodes * sizeof(uint64_t), "level-1 digests fit the staging slabs");
   uint64_t* lv1 = reinterpret_cast<uint64_t*>(&sm.slab[0][0]);
   const int t = threadIdx.x;
@@ -391,7 +402,7 @@ __device__ __forceinline__ void finish_upper(Smem& sm, uint32_t n1, uint64_t* tr
 
 // One level-1 node of a buffer larger than one leaf. `buf`, `size`, `node`
 // and the tree pointers are wave-uniform.
-__device__ __forceinline__ void run_node(Smem& sm, const uint8_t* buf, uint64_t size, uint64_t node, uint64_t* out,
+__device__ __forceinline__ void run_node(Smem<kSlabOne>& sm, const uint8_t* buf, uint64_t size, uint64_t node, uint64_t* out,
                          uint64_t* tree, uint32_t* tk) {
   const int t = threadIdx.x;
   const int w = t >> 6, r = (t & 63) >> 2;
@@ -405,7 +416,7 @@ __device__ __forceinline__ void run_node(Smem& sm, const uint8_t* buf, uint64_t 
                          (wfirst + kRowsPerWave) * kLeaf <= size;
   uint64_t h;
   if (wave_full) {
-    constexpr int NL = kSlab / 64;
+    constexpr int NL = kSlabOne / 64;
     u32x4 RA[NL], RB[NL];
     bool pre = false;
     h = hash_wave_leaves_pipe<NL>(uniform_ptr(buf + wfirst * kLeaf), nullptr, pre, RA, RB, sm.slab[w]);
@@ -422,7 +433,7 @@ __device__ __forceinline__ void run_node(Smem& sm, const uint8_t* buf, uint64_t 
       rows[rr] = d;
     }
     wave_fence();
-    h = hash_wave_rows(rows, sm.slab[w]);
+    h = hash_wave_rows<kSlabOne>(rows, sm.slab[w]);
   }
   if ((t & 3) == 0 && (uint64_t)(w * kRowsPerWave + r) < nl) sm.leafdig[0][w * kRowsPerWave + r] = h;
   __syncthreads();
@@ -457,7 +468,7 @@ __device__ __forceinline__ void run_node(Smem& sm, const uint8_t* buf, uint64_t 
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void digest_one_kernel(const uint8_t* p, uint64_t size, uint64_t* out,
                                                              uint64_t* tree, uint32_t* tk) {
-  __shared__ Smem sm;
+  __shared__ Smem<kSlabOne> sm;
   if (size <= kLeaf) {
     const int t = threadIdx.x;
     if (t < kRows) {
@@ -469,7 +480,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
     }
     __syncthreads();
     if (t < 64) {
-      const uint64_t h = hash_wave_rows(sm.rows, sm.slab[0]);
+      const uint64_t h = hash_wave_rows<kSlabOne>(sm.rows, sm.slab[0]);
       if (t == 0) *out = h;
     }
     return;
@@ -729,7 +740,7 @@ __device__ __forceinline__ const uint8_t* fast_rows(const uint8_t* base, uint32_
 // stores it without waiting (out[i] for one-node buffers, else the tree slot
 // that the tree kernel climbs from).
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void digest_batched_kernel(BatchArgs A) {
-  __shared__ Smem sm;
+  __shared__ Smem<kSlabBatch> sm;
   const DigestCtl* c = A.ctl;
   if (c->overflow) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < A.n; i += (uint64_t)gridDim.x * blockDim.x)
@@ -746,7 +757,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
   const uint32_t first_queued = 2u * gridDim.x;
   uint32_t cur = blockIdx.x, nxt = blockIdx.x + gridDim.x;
   NodeRec rc = load_rec(A, cur, n_node), rn = load_rec(A, nxt, n_node);
-  constexpr int NL = kSlab / 64;
+  constexpr int NL = kSlabBatch / 64;
   u32x4 RA[NL], RB[NL];
   bool pre = false;
   RowDesc* rows = sm.rows + w * kRowsPerWave;
@@ -805,7 +816,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
         rows[lane] = d;
       }
       wave_fence();
-      h = hash_wave_rows(rows, sm.slab[w]);
+      h = hash_wave_rows<kSlabBatch>(rows, sm.slab[w]);
       pre = false;
       if (is_med) {
         // level-1 combine inside the wavefront, in its own slice of the leaf-digest buffer

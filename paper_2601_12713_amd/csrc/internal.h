@@ -76,12 +76,14 @@ uint32_t* device_status_word(int device);  // device-visible sticky status (host
 int current_device(int* dev);
 int cu_count(int device);
 
-// Defaults: the autotuner's choice on MI355X (LDS admits four of the digest's
-// workgroups per compute unit, so more only queue).
+// Defaults: the autotuner's choice on MI355X (registers admit four of the
+// batched digest's workgroups per compute unit, so more only queue; with the
+// batched kernel's 256-byte steps, small level-1 nodes are no faster on one
+// wavefront than on a whole workgroup).
 struct Tuning {
   uint32_t blocks_per_cu = 4;
   uint32_t use_graph = 1;
-  uint32_t split_bytes = 32768;
+  uint32_t split_bytes = 0;
 };
 Tuning& tuning();
 
