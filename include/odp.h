@@ -190,10 +190,12 @@ typedef struct odp_report {
  * Data-dependent problems do not fail the call: rejected records get
  * ODP_F_INVALID, take part in no rule, and set report.status.
  * n = 0 writes an empty report. n > 2^32 - 1 returns ODP_ERANGE.
- * Internally the allocation rules run on a side stream of the workspace that
- * is forked from `stream` and joined back before the report is written, so
- * the call remains ordered on `stream` (and capturable as one unit).
- * Capture-safe once odp_reserve covered n. */
+ * Logs of at most 512 records are analysed by one workgroup in one launch and
+ * need no workspace. For longer logs the allocation rules run on a side
+ * stream of the workspace that is forked from `stream` and joined back before
+ * the report is written, so the call remains ordered on `stream` (and
+ * capturable as one unit). Capture-safe once odp_reserve covered n (always for
+ * n <= 512). */
 int odp_analyze_trace(const odp_event* events, size_t n, uint8_t* out_flags, odp_report* out_report,
                       odp_stream_t stream);
 
