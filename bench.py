@@ -91,6 +91,7 @@ def traffic_from_profile(name, sources):
 
 DIGEST_SOURCES = ["paper_2601_12713_amd/csrc/digest.hip", "paper_2601_12713_amd/csrc/xxh64_dev.h",
                   "paper_2601_12713_amd/csrc/internal.h"]
+ANALYSIS_SOURCES = ["paper_2601_12713_amd/csrc/analyze.hip", "paper_2601_12713_amd/csrc/internal.h"]
 
 
 def host_info():
@@ -328,10 +329,14 @@ def run_trace(args, torch, odp, W):
         "ms_per_step": round(ms, 4),
         "config": {"workload": "trace: 10^7 map records over 10^5 Zipf(1.1) slots + kernel records", "events": n},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "whole analysis (65 algorithmic bytes per record)", "kernel_ms": round(kern_ms, 4)},
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic_from_profile("analysis.trace", ANALYSIS_SOURCES),
+                     "kernel": "whole analysis (65 algorithmic bytes per record; traffic: HBM bytes of all its "
+                               "kernels per call)", "kernel_ms": round(kern_ms, 4)},
         "extras": {k: rep[k] for k in ("dd_events", "rt_pairs", "ra_events", "ua_events")},
     }
+    if line["roofline"]["traffic"]:
+        line["extras"]["measured_GBps"] = round(line["roofline"]["traffic"] / (kern_ms * 1e-3) / 1e9, 1)
 
     def cpu_sample(budget_s):
         import oracle
