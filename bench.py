@@ -45,7 +45,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="large-arrays",
-                    choices=["large-arrays", "batch", "trace", "plain-small", "serve"])
+                    choices=["large-arrays", "batch", "trace", "plain-small", "serve", "rate-vs-size"])
     ap.add_argument("--serve-seconds", type=float, default=4.0,
                     help="serve: schedule length per rate (at most 200,000 requests)")
     ap.add_argument("--plain-requests", type=int, default=20_000,
@@ -298,6 +298,63 @@ def run_batch(args, torch, odp, W):
     return line, cpu_sample
 
 
+def run_rate_vs_size(args, torch, odp, W):
+    """Per-buffer digest rate against buffer size, beside the host<->device copy
+    rates of the same sizes (pinned host memory, one copy per call): whether
+    fingerprinting a transfer on the device costs less than the transfer."""
+    sizes = [1, 64, 4096, 1 << 16, 1 << 20, 1 << 24, 1 << 28, 1 << 30]
+    big = sizes[-1]
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(7)
+    dev = torch.randint(0, 256, (big,), dtype=torch.uint8, device="cuda", generator=gen)
+    host = torch.empty(big, dtype=torch.uint8, pin_memory=True)
+    stream = torch.cuda.current_stream()
+    out = torch.zeros(1, dtype=torch.int64, device="cuda")
+    ptr = dev.data_ptr()
+
+    def per_call_us(fn, reps):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1000.0 / reps
+
+    rows = {}
+    t0 = time.perf_counter()
+    for sz in sizes:
+        reps = max(5, min(400, (1 << 31) // (sz * 4) if sz >= 4096 else 400))
+        d_us = per_call_us(lambda: odp.digest_buffers_plain([ptr], [sz], out, stream), reps)
+        h_us = per_call_us(lambda: dev[:sz].copy_(host[:sz], non_blocking=True), reps)
+        g_us = per_call_us(lambda: host[:sz].copy_(dev[:sz], non_blocking=True), reps)
+        rows[str(sz)] = {"digest_us": round(d_us, 2), "digest_GBps": round(sz / d_us / 1e3, 3),
+                         "h2d_us": round(h_us, 2), "h2d_GBps": round(sz / h_us / 1e3, 3),
+                         "d2h_us": round(g_us, 2), "d2h_GBps": round(sz / g_us / 1e3, 3),
+                         "digest_vs_h2d": round(h_us / d_us, 2)}
+    wall_ms = (time.perf_counter() - t0) * 1000.0
+    top = rows[str(big)]
+    achieved = top["digest_GBps"]
+    line = {
+        "metric": "per-buffer digest GB/s at 1 GiB (digest and copy rates by size in extras)",
+        "value": achieved,
+        "unit": "GB/s",
+        "ms_per_step": round(wall_ms, 3),
+        "config": {"workload": "rate-vs-size: one buffer of 1 B-1 GiB per call, digest vs pinned H2D/D2H copy",
+                   "sizes": sizes},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "digest_one_kernel, one launch over 1 GiB (HIP events per call)",
+                     "kernel_ms": round(top["digest_us"] / 1000.0, 4)},
+        "extras": rows,
+    }
+    return line, None
+
+
 def run_trace(args, torch, odp, W):
     tr = W.TraceAtScale(seed=4)
     n = len(tr.events)
@@ -468,7 +525,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     runner = {"large-arrays": run_large_arrays, "batch": run_batch, "trace": run_trace,
-              "plain-small": run_plain_small, "serve": run_serve}[args.workload]
+              "plain-small": run_plain_small, "serve": run_serve, "rate-vs-size": run_rate_vs_size}[args.workload]
     line, cpu_sample = runner(args, torch, odp, W)
     out = {"metric": line["metric"], "value": line["value"], "unit": line["unit"], "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": line["ms_per_step"],
