@@ -490,6 +490,60 @@ __device__ __forceinline__ void run_node(Smem<kSlabOne>& sm, const uint8_t* buf,
   if (sm.outidx[0]) finish_upper(sm, (uint32_t)n1, tree, tk, out);
 }
 
+// XXH64 (seed 0) of a buffer of at most one leaf at a 16-byte aligned address,
+// by one whole wavefront. Every lane issues its four 16-byte loads at once
+// (lane L, load k: bytes 1024k + 16L), so the leaf arrives in one memory round
+// trip instead of eight staged steps; a load starting below `len` may end past
+// it, inside the same aligned 16-byte granule. The leaf lands contiguously in
+// the LDS slab, lanes 4g+a fold accumulator a's words sixteen stripes per LDS
+// wait, and the remainder bytes are read from the slab too. Returns the
+// digest in lane 0 (and every lane 4g).
+__device__ __forceinline__ uint64_t hash_one_leaf(const uint8_t* p, uint32_t len, uint8_t* slab) {
+  const int lane = threadIdx.x & 63, a = lane & 3;
+  u32x4 R[kLeaf / 1024];
+#pragma unroll
+  for (int k = 0; k < kLeaf / 1024; ++k) {
+    const uint32_t o = (uint32_t)k * 1024 + (uint32_t)lane * 16;
+    if (o < len) R[k] = ld_global_nt(p + o);
+  }
+#pragma unroll
+  for (int k = 0; k < kLeaf / 1024; ++k) {
+    const uint32_t o = (uint32_t)k * 1024 + (uint32_t)lane * 16;
+    if (o < len) *reinterpret_cast<u32x4*>(slab + o) = R[k];
+  }
+  wave_fence();
+  const uint32_t nstripes = len >> 5;
+  uint64_t acc = xx_acc_init(0, a);
+  const uint8_t* rd = slab + a * 8;
+  // whole chunks of 16 stripes (one LDS wait each), then the remaining
+  // stripes with selects
+  constexpr uint32_t kChunk = 16;
+  uint32_t s = 0;
+#pragma unroll 1
+  for (; s + kChunk <= nstripes; s += kChunk) {
+    uint64_t w[kChunk];
+#pragma unroll
+    for (uint32_t q = 0; q < kChunk; ++q) w[q] = *reinterpret_cast<const uint64_t*>(rd + (s + q) * 32);
+#pragma unroll
+    for (uint32_t q = 0; q < kChunk; ++q) acc = xx_round(acc, w[q]);
+  }
+  if (s < nstripes) {
+    uint64_t w[kChunk];
+#pragma unroll
+    for (uint32_t q = 0; q < kChunk; ++q) w[q] = *reinterpret_cast<const uint64_t*>(rd + (s + q) * 32);
+#pragma unroll
+    for (uint32_t q = 0; q < kChunk; ++q) {
+      const uint64_t folded = xx_round(acc, w[q]);
+      acc = s + q < nstripes ? folded : acc;
+    }
+  }
+  RowDesc staged;
+  staged.base = slab;
+  staged.len = len;
+  staged.present = 1;
+  return finish_row(acc, staged);
+}
+
 // ---------------------------------------------------------------------------
 // Plain form: one launch per buffer, one workgroup per level-1 node.
 // ---------------------------------------------------------------------------
@@ -498,6 +552,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
   __shared__ Smem<kSlabOne> sm;
   if (size <= kLeaf) {
     const int t = threadIdx.x;
+    if ((reinterpret_cast<uintptr_t>(p) & 15) == 0) {
+      if (t < 64) {
+        const uint64_t h = hash_one_leaf(p, (uint32_t)size, sm.slab[0]);
+        if (t == 0) *out = h;
+      }
+      return;
+    }
     if (t < kRows) {
       RowDesc d;
       d.present = t == 0;

@@ -48,6 +48,25 @@ def test_unaligned_starts(odp):
     assert p.tolist() == want
 
 
+def test_one_leaf_buffers_at_aligned_offsets(odp):
+    # Buffers of at most one leaf at 16-byte aligned starts take the per-buffer
+    # path that loads the whole leaf at once and reads its remainder from LDS:
+    # every remainder class of the 32-byte stripe and of the 16-byte loads,
+    # and lengths around the 1 KiB load boundaries.
+    rng = np.random.default_rng(18)
+    base = dev_bytes(rng.integers(0, 256, size=3 * 4096 + 64, dtype=np.uint8))
+    host = base.cpu().numpy()
+    sizes = list(range(0, 70)) + [95, 96, 97, 127, 128, 129, 1008, 1023, 1024, 1025, 1040, 2047, 2048, 2049,
+                                  3071, 3072, 3073, 4063, 4064, 4065, 4080, 4095, 4096]
+    views, want = [], []
+    for off in [0, 16, 48, 4096 + 32]:
+        for size in sizes:
+            views.append(base[off:off + size])
+            want.append(oracle.d64(host[off:off + size]))
+    assert odp.digest_tensors(views, plain=True).tolist() == want
+    assert odp.digest_tensors(views).tolist() == want
+
+
 def test_same_bytes_same_digest_any_alignment(odp):
     rng = np.random.default_rng(13)
     src = rng.integers(0, 256, size=270_000, dtype=np.uint8)
