@@ -15,6 +15,11 @@ Parity status of each function (how it is pinned, see tests/test_oracle_*.py):
   alg1..alg4   the paper's Algorithms 1-4 step by step; checked against
                ``analyze`` on the traces where the paper's algorithms and the
                rule readings provably coincide.
+  unused_transfers, alg5
+               unused transfers (Def. 4, Alg. 5): the rule and the algorithm
+               step by step. Pinned by hand-worked traces, an O(n^2) brute
+               force over the rule on random tiny traces, and agreement of the
+               two where kernels do not overlap. Not computed on the GPU yet.
   The counts in the paper's issue table are not reproducible here (the
   applications are absent): parity unpinned for those.
 """
@@ -68,6 +73,10 @@ def lib():
         L.orc_alg3.argtypes = [p, p, p, u64, p]
         L.orc_alg4.restype = None
         L.orc_alg4.argtypes = [p, p, u64, p, p, u64, p]
+        L.orc_unused_transfers.restype = ctypes.c_int64
+        L.orc_unused_transfers.argtypes = [p, u64, p]
+        L.orc_alg5.restype = None
+        L.orc_alg5.argtypes = [p, p, u64, p, u64, p]
         _lib = L
     return _lib
 
@@ -162,3 +171,21 @@ def alg4(events, kernel_idx, alloc_idx, delete_idx):
     u = np.zeros(ai.size, dtype=np.uint8)
     lib().orc_alg4(a.ctypes.data, ki.ctypes.data, ki.size, ai.ctypes.data, di.ctypes.data, ai.size, u.ctypes.data)
     return u
+
+
+def unused_transfers(events):
+    """Unused transfers (Def. 4, transfer half): uint8 per record, 1 when flagged."""
+    a = _events(events)
+    u = np.zeros(max(len(a), 1), dtype=np.uint8)
+    lib().orc_unused_transfers(a.ctypes.data, len(a), u.ctypes.data)
+    return u[:len(a)]
+
+
+def alg5(events, kernel_idx, tx_idx):
+    """Algorithm 5 over the given kernels and transfers (both in log order): 1 per unused transfer."""
+    a = _events(events)
+    ki = np.ascontiguousarray(kernel_idx, dtype=np.uint64)
+    ti = np.ascontiguousarray(tx_idx, dtype=np.uint64)
+    u = np.zeros(max(ti.size, 1), dtype=np.uint8)
+    lib().orc_alg5(a.ctypes.data, ki.ctypes.data, ki.size, ti.ctypes.data, ti.size, u.ctypes.data)
+    return u[:ti.size]

@@ -19,6 +19,9 @@
 //                  passes over per-key state.
 //   * alg1..alg4 : the paper's Algorithms 1-4 taken step by step with ordered
 //                  maps and queues, kept to cross-check the rules above.
+//   * unused_transfers, alg5 : unused transfers (Def. 4, Alg. 5), the rule and
+//                  the algorithm step by step; the GPU path does not compute
+//                  this pattern yet.
 // Parity status of each part is listed in the header of oracle/__init__.py.
 #include <algorithm>
 #include <cstdint>
@@ -460,6 +463,104 @@ void orc_alg4(const orc_event* ev, const uint64_t* kernel_idx, uint64_t nk,
       const orc_event& d = ev[delete_idx[p]];
       while (t < tgt.size() && ev[tgt[t]].t_end < a.t_start) t++;
       unused[p] = (t == tgt.size() || ev[tgt[t]].t_start > d.t_end) ? 1 : 0;
+    }
+  }
+}
+
+// Unused transfers (Def. 4, transfer half; the rule behind Alg. 5). Not part
+// of orc_analyze: a separate output, ut[i] in {0, 1}. Readings:
+//   * a transfer belongs to the device it writes: dst_dev of an H2D or D2D.
+//     A D2H writes host memory, which the definition (data mapped to a
+//     device) does not cover, so it is never flagged and changes no state;
+//   * the address a later transfer overwrites is keyed by the source
+//     endpoint and address (src_dev, src_addr); Alg. 5 keys by the host
+//     address alone, which is the same key when every such transfer comes
+//     from the host;
+//   * the kernels a transfer has passed on its device are counted, as for
+//     UA: e = #kernels on the device with t_end < the transfer's t_start
+//     (Alg. 5's pointer gives the same count when kernels do not overlap).
+// With K the device's valid kernels in log order, a transfer is unused when
+//   (i)  e = |K|: no kernel on its device is left to read it, or
+//   (ii) K[e] starts after it (it lies in the gap before K[e]) and a later
+//        transfer of the same (device, e, src_dev, src_addr) also lies in
+//        that gap: it is overwritten before any kernel can read it.
+// A transfer that overlaps K[e] (K[e].t_start <= t_start) is neither; every
+// later transfer of the same e overlaps K[e] as well (the log is ordered by
+// t_start), so it ends the gap's candidates as Alg. 5's clearing does.
+// Invalid records take part in nothing. Returns the number flagged.
+int64_t orc_unused_transfers(const orc_event* ev, uint64_t n, uint8_t* ut) {
+  std::vector<bool> ok(n);
+  for (uint64_t i = 0; i < n; ++i) ok[i] = event_valid(ev, i);
+  std::map<int, std::vector<uint64_t>> kernels;  // device -> kernel records in log order
+  std::map<int, std::vector<uint64_t>> ends;     // device -> sorted kernel t_end
+  for (uint64_t i = 0; i < n; ++i)
+    if (ok[i] && ev[i].op == OP_KERNEL) {
+      kernels[ev[i].dst_dev].push_back(i);
+      ends[ev[i].dst_dev].push_back(ev[i].t_end);
+    }
+  for (auto& kv : ends) std::sort(kv.second.begin(), kv.second.end());
+  // (device, e, src_dev, src_addr) -> the latest gap transfer seen so far
+  std::map<std::tuple<int, uint64_t, int, uint64_t>, uint64_t> last_in_gap;
+  int64_t count = 0;
+  for (uint64_t i = 0; i < n; ++i) ut[i] = 0;
+  for (uint64_t i = 0; i < n; ++i) {
+    const orc_event& t = ev[i];
+    if (!ok[i] || !(t.op == OP_H2D || t.op == OP_D2D) || t.dst_dev < 0) continue;
+    const std::vector<uint64_t>& K = kernels[t.dst_dev];
+    const std::vector<uint64_t>& E = ends[t.dst_dev];
+    const uint64_t e = (uint64_t)(std::lower_bound(E.begin(), E.end(), t.t_start) - E.begin());
+    if (e == K.size()) {
+      ut[i] = 1;
+      continue;
+    }
+    if (ev[K[e]].t_start > t.t_start) {
+      const auto key = std::make_tuple((int)t.dst_dev, e, (int)t.src_dev, t.src_addr);
+      auto it = last_in_gap.find(key);
+      if (it != last_in_gap.end()) ut[it->second] = 1;
+      last_in_gap[key] = i;
+    }
+  }
+  for (uint64_t i = 0; i < n; ++i) count += ut[i];
+  return count;
+}
+
+// Algorithm 5 step by step: per device, a pointer over that device's kernels
+// (log order) and a map of candidate transfers by source address. Moving the
+// pointer past a kernel, or a transfer that overlaps the kernel it points to,
+// empties the map; with no kernel left the transfer is unused; in a gap before
+// the pointed kernel, a candidate at the same address is unused and the
+// transfer replaces it. Transfers (tx_idx, log order) are grouped by dst_dev
+// and keyed by (src_dev, src_addr), the readings of orc_unused_transfers.
+// Output: unused[t] in {0, 1} for tx_idx[t].
+void orc_alg5(const orc_event* ev, const uint64_t* kernel_idx, uint64_t nk, const uint64_t* tx_idx, uint64_t m,
+              uint8_t* unused) {
+  std::map<int, std::vector<uint64_t>> dev_kernels;
+  for (uint64_t k = 0; k < nk; ++k) dev_kernels[ev[kernel_idx[k]].dst_dev].push_back(kernel_idx[k]);
+  std::map<int, std::vector<uint64_t>> dev_tx;
+  for (uint64_t t = 0; t < m; ++t) {
+    unused[t] = 0;
+    dev_tx[ev[tx_idx[t]].dst_dev].push_back(t);
+  }
+  for (auto& dt : dev_tx) {
+    const std::vector<uint64_t>& tgt = dev_kernels[dt.first];
+    size_t p = 0;
+    std::map<std::pair<int, uint64_t>, uint64_t> candidates;
+    for (uint64_t t : dt.second) {
+      const orc_event& tx = ev[tx_idx[t]];
+      while (p < tgt.size() && ev[tgt[p]].t_end < tx.t_start) {
+        p++;
+        candidates.clear();
+      }
+      if (p == tgt.size()) {
+        unused[t] = 1;
+      } else if (ev[tgt[p]].t_start > tx.t_start) {
+        const std::pair<int, uint64_t> key((int)tx.src_dev, tx.src_addr);
+        auto it = candidates.find(key);
+        if (it != candidates.end()) unused[it->second] = 1;
+        candidates[key] = t;
+      } else {
+        candidates.clear();
+      }
     }
   }
 }
