@@ -215,6 +215,16 @@ __device__ __forceinline__ uint64_t hash_wave_leaves_pipe(const uint8_t* leaf_ba
 // row's last 16-byte granule, so inside the same page. Otherwise every lane
 // reads its words straight from memory at any alignment, eight stripes per
 // batch of independent loads. Returns the row digest in lane 4r.
+// A 16-byte granule that row loads past a row's end read instead.
+__device__ __align__(16) uint8_t g_no_row[16];
+
+// In the per-buffer kernel every lane issues every load of the step, without
+// a branch: a load under a branch makes the compiler wait for all loads in
+// flight at the next stage, which serialised the two steps kept in flight (a
+// partial node of 2-16 leaves took 9.8 us per launch). An offset at or past
+// the row's end (or an absent row) reads g_no_row instead; those bytes are
+// staged but never folded. The batched kernel keeps predicated loads: the
+// address selects cost it a register spill.
 template <int kSlab>
 __device__ __forceinline__ void rows_load(u32x4 (&R)[kSlab / 64], const RowDesc& ra, const RowDesc& rb, uint32_t step_off) {
   const int lane = threadIdx.x & 63;
@@ -223,7 +233,11 @@ __device__ __forceinline__ void rows_load(u32x4 (&R)[kSlab / 64], const RowDesc&
   for (int k = 0; k < kSlab / 64; ++k) {
     const RowDesc& d = (k & 1) ? rb : ra;
     const uint32_t o = step_off + (uint32_t)(k >> 1) * 128 + lc;
-    if (o < d.len) R[k] = ld_global_nt(d.base + o);
+    if constexpr (kSlab == kSlabOne) {
+      R[k] = ld_global_nt(o < d.len ? d.base + o : g_no_row);
+    } else {
+      if (o < d.len) R[k] = ld_global_nt(d.base + o);
+    }
   }
 }
 
@@ -286,6 +300,9 @@ __device__ __forceinline__ uint64_t hash_wave_rows(const RowDesc* rows, uint8_t*
 #pragma unroll
     for (int k = 0; k < kSlab / 64; ++k) R0[k] = R1[k] = u32x4{0u, 0u, 0u, 0u};
     rows_load<kSlab>(R0, ra, rb, 0);
+    // keeps the first step's loads ahead of the second's, so the first stage
+    // can wait for its own loads only
+    if constexpr (kSlab == kSlabOne) __builtin_amdgcn_sched_barrier(0);
     rows_load<kSlab>(R1, ra, rb, kSlab);
 #pragma unroll 1
     for (uint32_t s = 0; s < nslab; s += 2) {
