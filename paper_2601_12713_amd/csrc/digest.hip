@@ -250,13 +250,23 @@ __device__ __forceinline__ void rows_load(u32x4 (&R)[kSlab / 64], const RowDesc&
 // batched kernel keeps one read per round: there the held words push it past
 // its register budget, and it ran 2% slower.
 template <int kSlab>
-__device__ __forceinline__ uint64_t rows_fold(uint64_t acc, const uint8_t* rd, uint32_t q0, uint32_t nstripes) {
+__device__ __forceinline__ uint64_t rows_fold(uint64_t acc, const uint8_t* rd, uint32_t q0, uint32_t nstripes,
+                                              bool whole) {
   if constexpr (kSlab != kSlabOne) {
 #pragma unroll
     for (int q = 0; q < kSlab / 32; ++q)
       if (q0 + q < nstripes) acc = xx_round(acc, *reinterpret_cast<const uint64_t*>(rd + q * 32));
     return acc;
   } else {
+    if (whole) {
+      // every present row covers the whole step: no per-round predicate
+      uint64_t w[kSlab / 32];
+#pragma unroll
+      for (int q = 0; q < kSlab / 32; ++q) w[q] = *reinterpret_cast<const uint64_t*>(rd + q * 32);
+#pragma unroll
+      for (int q = 0; q < kSlab / 32; ++q) acc = xx_round(acc, w[q]);
+      return acc;
+    }
 #pragma unroll
     for (int g = 0; g < kSlab / 128; ++g) {
       uint64_t w[4];
@@ -310,14 +320,16 @@ __device__ __forceinline__ uint64_t hash_wave_rows(const RowDesc* rows, uint8_t*
       if (s + 2 < nslab) rows_load<kSlab>(R0, ra, rb, (s + 2) * kSlab);
       wave_fence();
       uint32_t q0 = s * (kSlab / 32);
-      acc = rows_fold<kSlab>(acc, rd, q0, nstripes);
+      bool whole = false;
+      if constexpr (kSlab == kSlabOne) whole = __all(!hrow.present || nstripes >= q0 + 2 * (kSlab / 32));
+      acc = rows_fold<kSlab>(acc, rd, q0, nstripes, whole);
       wave_fence();
       if (s + 1 < nslab) {
         fast_stage(R1, slab);
         if (s + 3 < nslab) rows_load<kSlab>(R1, ra, rb, (s + 3) * kSlab);
         wave_fence();
         q0 += kSlab / 32;
-        acc = rows_fold<kSlab>(acc, rd, q0, nstripes);
+        acc = rows_fold<kSlab>(acc, rd, q0, nstripes, whole);
         wave_fence();
       }
     }
@@ -444,69 +456,6 @@ __device__ __forceinline__ void finish_upper(Smem<kSlabOne>& sm, uint32_t n1, ui
   }
 }
 
-// One level-1 node of a buffer larger than one leaf. `buf`, `size`, `node`
-// and the tree pointers are wave-uniform.
-__device__ __forceinline__ void run_node(Smem<kSlabOne>& sm, const uint8_t* buf, uint64_t size, uint64_t node, uint64_t* out,
-                         uint64_t* tree, uint32_t* tk) {
-  const int t = threadIdx.x;
-  const int w = t >> 6, r = (t & 63) >> 2;
-  const uint64_t nleaves = ceil_div(size, kLeaf);
-  const uint64_t n1 = ceil_div(nleaves, kFanIn);
-  const uint64_t first = node * kFanIn;
-  const uint32_t nl = (uint32_t)min<uint64_t>(kFanIn, nleaves - first);
-  // leaves [first + 16w, first + 16w + 16) belong to this wavefront
-  const uint64_t wfirst = first + (uint64_t)w * kRowsPerWave;
-  const bool wave_full = ((reinterpret_cast<uintptr_t>(buf) & 15) == 0) &&
-                         (wfirst + kRowsPerWave) * kLeaf <= size;
-  uint64_t h;
-  if (wave_full) {
-    constexpr int NL = kSlabOne / 64;
-    u32x4 RA[NL], RB[NL];
-    bool pre = false;
-    h = hash_wave_leaves_pipe<NL>(uniform_ptr(buf + wfirst * kLeaf), nullptr, pre, RA, RB, sm.slab[w]);
-  } else {
-    RowDesc* rows = sm.rows + w * kRowsPerWave;
-    if ((t & 63) < kRowsPerWave) {
-      const uint32_t rr = t & 63;
-      RowDesc d;
-      const uint64_t leaf = wfirst + rr;
-      const uint64_t off = leaf * kLeaf;
-      d.present = leaf < first + nl;
-      d.base = buf + (d.present ? off : 0);
-      d.len = d.present ? (uint32_t)min<uint64_t>(kLeaf, size - off) : 0u;
-      rows[rr] = d;
-    }
-    wave_fence();
-    h = hash_wave_rows<kSlabOne>(rows, sm.slab[w]);
-  }
-  if ((t & 3) == 0 && (uint64_t)(w * kRowsPerWave + r) < nl) sm.leafdig[0][w * kRowsPerWave + r] = h;
-  __syncthreads();
-  if (n1 > kOneTicketNodes) {
-    if (w == 0) {
-      const uint64_t d = xx_words4(sm.leafdig[0], nl, 1);
-      tree_up(d, node, n1, 1, 0, 0, out, tree, tk);
-    }
-    __syncthreads();
-    return;
-  }
-  if (w == 0) {
-    const int lane = t & 63;
-    const uint64_t d =
-        __shfl(nl == kFanIn ? xx_words4_full64(sm.leafdig[0], 1) : xx_words4(sm.leafdig[0], nl, 1), 0, 64);
-    uint32_t last = 0;
-    if (n1 == 1) {
-      if (lane == 0) *out = d;
-    } else {
-      if (lane == 0) store_coherent(tree + node, d);
-      wait_stores_done();
-      if (lane == 0) last = __hip_atomic_fetch_add(tk, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == n1 - 1;
-    }
-    if (lane == 0) sm.outidx[0] = last;
-  }
-  __syncthreads();
-  if (sm.outidx[0]) finish_upper(sm, (uint32_t)n1, tree, tk, out);
-}
-
 // XXH64 (seed 0) of a buffer of at most one leaf at a 16-byte aligned address,
 // by one whole wavefront. Every lane issues its four 16-byte loads at once
 // (lane L, load k: bytes 1024k + 16L), so the leaf arrives in one memory round
@@ -559,6 +508,83 @@ __device__ __forceinline__ uint64_t hash_one_leaf(const uint8_t* p, uint32_t len
   staged.len = len;
   staged.present = 1;
   return finish_row(acc, staged);
+}
+
+// One level-1 node of a buffer larger than one leaf. `buf`, `size`, `node`
+// and the tree pointers are wave-uniform.
+__device__ __forceinline__ void run_node(Smem<kSlabOne>& sm, const uint8_t* buf, uint64_t size, uint64_t node, uint64_t* out,
+                         uint64_t* tree, uint32_t* tk) {
+  const int t = threadIdx.x;
+  const int w = t >> 6, r = (t & 63) >> 2;
+  const uint64_t nleaves = ceil_div(size, kLeaf);
+  const uint64_t n1 = ceil_div(nleaves, kFanIn);
+  const uint64_t first = node * kFanIn;
+  const uint32_t nl = (uint32_t)min<uint64_t>(kFanIn, nleaves - first);
+  // leaves [first + 16w, first + 16w + 16) belong to this wavefront
+  const uint64_t wfirst = first + (uint64_t)w * kRowsPerWave;
+  const bool wave_full = ((reinterpret_cast<uintptr_t>(buf) & 15) == 0) &&
+                         (wfirst + kRowsPerWave) * kLeaf <= size;
+  // The buffer's last leaf, when shorter than a leaf (and the buffer 16-byte
+  // aligned), is hashed on its own by hash_one_leaf, so that every row the
+  // wavefronts fold is a whole leaf and folds without per-round predicates:
+  // wavefront 3 takes it when it holds no leaves of this node, else the
+  // wavefront that owns it, after its rows.
+  const bool has_short = ((reinterpret_cast<uintptr_t>(buf) & 15) == 0) && (size % kLeaf) != 0 && node == n1 - 1;
+  const uint32_t short_row = (uint32_t)(nleaves - 1 - first);  // its index in the node
+  const int short_wave = !has_short ? -1 : nl <= 3 * kRowsPerWave ? 3 : (int)(short_row / kRowsPerWave);
+  uint64_t h;
+  if (wave_full) {
+    constexpr int NL = kSlabOne / 64;
+    u32x4 RA[NL], RB[NL];
+    bool pre = false;
+    h = hash_wave_leaves_pipe<NL>(uniform_ptr(buf + wfirst * kLeaf), nullptr, pre, RA, RB, sm.slab[w]);
+  } else {
+    RowDesc* rows = sm.rows + w * kRowsPerWave;
+    if ((t & 63) < kRowsPerWave) {
+      const uint32_t rr = t & 63;
+      RowDesc d;
+      const uint64_t leaf = wfirst + rr;
+      const uint64_t off = leaf * kLeaf;
+      d.present = leaf < first + nl && !(has_short && leaf == nleaves - 1);
+      d.base = buf + (d.present ? off : 0);
+      d.len = d.present ? (uint32_t)min<uint64_t>(kLeaf, size - off) : 0u;
+      rows[rr] = d;
+    }
+    wave_fence();
+    h = hash_wave_rows<kSlabOne>(rows, sm.slab[w]);
+    if (w == short_wave) {
+      const uint64_t off = (nleaves - 1) * kLeaf;
+      const uint64_t hs = hash_one_leaf(buf + off, (uint32_t)(size - off), sm.slab[w]);
+      if ((t & 63) == 0) sm.leafdig[0][short_row] = hs;
+    }
+  }
+  const uint32_t my_row = (uint32_t)(w * kRowsPerWave + r);
+  if ((t & 3) == 0 && my_row < nl && !(has_short && my_row == short_row)) sm.leafdig[0][my_row] = h;
+  __syncthreads();
+  if (n1 > kOneTicketNodes) {
+    if (w == 0) {
+      const uint64_t d = xx_words4(sm.leafdig[0], nl, 1);
+      tree_up(d, node, n1, 1, 0, 0, out, tree, tk);
+    }
+    __syncthreads();
+    return;
+  }
+  if (w == 0) {
+    const int lane = t & 63;
+    const uint64_t d =
+        __shfl(nl == kFanIn ? xx_words4_full64(sm.leafdig[0], 1) : xx_words4(sm.leafdig[0], nl, 1), 0, 64);
+    uint32_t last = 0;
+    if (n1 == 1) {
+      if (lane == 0) *out = d;
+    } else {
+      if (lane == 0) store_coherent(tree + node, d);
+      wait_stores_done();
+      if (lane == 0) last = __hip_atomic_fetch_add(tk, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == n1 - 1;
+    }
+    if (lane == 0) sm.outidx[0] = last;
+  }
+  __syncthreads();
+  if (sm.outidx[0]) finish_upper(sm, (uint32_t)n1, tree, tk, out);
 }
 
 // ---------------------------------------------------------------------------
