@@ -9,17 +9,14 @@ Parity status of each function (how it is pinned, see tests/test_oracle_*.py):
   d64          pinned: an independent composition of ``xxhash`` calls written
                in the test, over one-, two- and three-level trees; invariants.
   analyze      pinned: O(n^2) brute force over Defs. 1-4 using byte equality of
-               real payloads on random tiny traces; hand traces of the paper's
-               Listings 1 and 2; closed forms for alternating round-trip chains;
-               planted counts of the synthetic workload generators.
-  alg1..alg4   the paper's Algorithms 1-4 step by step; checked against
-               ``analyze`` on the traces where the paper's algorithms and the
-               rule readings provably coincide.
-  unused_transfers, alg5
-               unused transfers (Def. 4, Alg. 5): the rule and the algorithm
-               step by step. Pinned by hand-worked traces, an O(n^2) brute
-               force over the rule on random tiny traces, and agreement of the
-               two where kernels do not overlap. Not computed on the GPU yet.
+               real payloads on random tiny traces (every flag and every count
+               and sum of the report, unused transfers and the
+               optimization-potential figures included); hand traces of the
+               paper's Listings 1 and 2 and of each unused-transfer case;
+               closed forms for alternating round-trip chains and repeated
+               copies; planted counts and sums of the synthetic generators.
+  alg2_pairs   the pairs Algorithm 2 records; pinned by hand traces and by
+               its agreement with the round-trip rule on two endpoints.
   The counts in the paper's issue table are not reproducible here (the
   applications are absent): parity unpinned for those.
 """
@@ -30,7 +27,7 @@ import numpy as np
 
 from . import build as _build
 
-F_DD, F_RT_TX, F_RT_RX, F_RA, F_UA, F_PAIRED, F_INVALID = 1, 2, 4, 8, 16, 32, 128
+F_DD, F_RT_TX, F_RT_RX, F_RA, F_UA, F_PAIRED, F_UT, F_INVALID = 1, 2, 4, 8, 16, 32, 64, 128
 OP_ALLOC, OP_H2D, OP_D2H, OP_D2D, OP_DELETE, OP_KERNEL = 1, 2, 3, 4, 5, 6
 
 REPORT_FIELDS = [
@@ -40,12 +37,14 @@ REPORT_FIELDS = [
     "rt_pairs", "rt_rx_events", "rt_bytes", "rt_time_ns",
     "ra_events", "ra_groups", "ra_members", "ra_bytes", "ra_time_ns",
     "ua_events", "ua_bytes", "ua_time_ns",
+    "ut_events", "ut_bytes", "ut_time_ns",
+    "span_ns", "elim_ns",
 ]
 
 
 class _Report(ctypes.Structure):
     _fields_ = [(f, ctypes.c_uint64) for f in REPORT_FIELDS] + [
-        ("status", ctypes.c_int32), ("first_bad_event", ctypes.c_uint32)]
+        ("predicted_speedup", ctypes.c_double), ("status", ctypes.c_int32), ("first_bad_event", ctypes.c_uint32)]
 
 
 _lib = None
@@ -65,18 +64,8 @@ def lib():
         L.orc_d64_many.argtypes = [p, p, u64, p]
         L.orc_analyze.restype = ctypes.c_int
         L.orc_analyze.argtypes = [p, u64, p, ctypes.POINTER(_Report)]
-        L.orc_alg1.restype = ctypes.c_int64
-        L.orc_alg1.argtypes = [p, p, u64, p]
-        L.orc_alg2.restype = ctypes.c_int64
-        L.orc_alg2.argtypes = [p, p, u64, p, p]
-        L.orc_alg3.restype = ctypes.c_int64
-        L.orc_alg3.argtypes = [p, p, p, u64, p]
-        L.orc_alg4.restype = None
-        L.orc_alg4.argtypes = [p, p, u64, p, p, u64, p]
-        L.orc_unused_transfers.restype = ctypes.c_int64
-        L.orc_unused_transfers.argtypes = [p, u64, p]
-        L.orc_alg5.restype = None
-        L.orc_alg5.argtypes = [p, p, u64, p, u64, p]
+        L.orc_alg2_pairs.restype = ctypes.c_int64
+        L.orc_alg2_pairs.argtypes = [p, p, u64, p, p]
         _lib = L
     return _lib
 
@@ -128,64 +117,23 @@ def analyze(events):
     rep = _Report()
     lib().orc_analyze(a.ctypes.data, n, flags.ctypes.data, ctypes.byref(rep))
     d = {f: int(getattr(rep, f)) for f in REPORT_FIELDS}
+    d["predicted_speedup"] = float(rep.predicted_speedup)
     d["status"] = int(rep.status)
     d["first_bad_event"] = int(rep.first_bad_event)
     return flags, d
 
 
-def alg1(events, idx):
-    """Algorithm 1 over the records ``idx``: per position, its duplicate-group number or -1."""
-    a = _events(events)
-    idx = np.ascontiguousarray(idx, dtype=np.uint64)
-    g = np.zeros(idx.size, dtype=np.int64)
-    ng = lib().orc_alg1(a.ctypes.data, idx.ctypes.data, idx.size, g.ctypes.data)
-    return int(ng), g
-
-
-def alg2(events, idx):
-    """Algorithm 2 over the records ``idx``: list of (tx_position, rx_position) pairs."""
+def alg2_pairs(events, idx):
+    """The pairs Algorithm 2 records over the transfers ``idx``: list of (tx_position, rx_position)."""
     a = _events(events)
     idx = np.ascontiguousarray(idx, dtype=np.uint64)
     tx = np.zeros(max(idx.size, 1), dtype=np.int64)
     rx = np.zeros(max(idx.size, 1), dtype=np.int64)
-    npairs = lib().orc_alg2(a.ctypes.data, idx.ctypes.data, idx.size, tx.ctypes.data, rx.ctypes.data)
+    npairs = lib().orc_alg2_pairs(a.ctypes.data, idx.ctypes.data, idx.size, tx.ctypes.data, rx.ctypes.data)
     return list(zip(tx[:npairs].tolist(), rx[:npairs].tolist()))
-
-
-def alg3(events, alloc_idx, delete_idx):
-    """Algorithm 3 over (alloc, delete) pairs: per pair, its rank in a kept group or -1."""
-    a = _events(events)
-    ai = np.ascontiguousarray(alloc_idx, dtype=np.uint64)
-    di = np.ascontiguousarray(delete_idx, dtype=np.uint64)
-    r = np.zeros(ai.size, dtype=np.int64)
-    ng = lib().orc_alg3(a.ctypes.data, ai.ctypes.data, di.ctypes.data, ai.size, r.ctypes.data)
-    return int(ng), r
-
-
-def alg4(events, kernel_idx, alloc_idx, delete_idx):
-    """Algorithm 4: per (alloc, delete) pair, 1 when no kernel on its device can have used it."""
-    a = _events(events)
-    ki = np.ascontiguousarray(kernel_idx, dtype=np.uint64)
-    ai = np.ascontiguousarray(alloc_idx, dtype=np.uint64)
-    di = np.ascontiguousarray(delete_idx, dtype=np.uint64)
-    u = np.zeros(ai.size, dtype=np.uint8)
-    lib().orc_alg4(a.ctypes.data, ki.ctypes.data, ki.size, ai.ctypes.data, di.ctypes.data, ai.size, u.ctypes.data)
-    return u
 
 
 def unused_transfers(events):
     """Unused transfers (Def. 4, transfer half): uint8 per record, 1 when flagged."""
-    a = _events(events)
-    u = np.zeros(max(len(a), 1), dtype=np.uint8)
-    lib().orc_unused_transfers(a.ctypes.data, len(a), u.ctypes.data)
-    return u[:len(a)]
-
-
-def alg5(events, kernel_idx, tx_idx):
-    """Algorithm 5 over the given kernels and transfers (both in log order): 1 per unused transfer."""
-    a = _events(events)
-    ki = np.ascontiguousarray(kernel_idx, dtype=np.uint64)
-    ti = np.ascontiguousarray(tx_idx, dtype=np.uint64)
-    u = np.zeros(max(ti.size, 1), dtype=np.uint8)
-    lib().orc_alg5(a.ctypes.data, ki.ctypes.data, ki.size, ti.ctypes.data, ti.size, u.ctypes.data)
-    return u[:ti.size]
+    flags, _ = analyze(events)
+    return ((flags & F_UT) != 0).astype(np.uint8)

@@ -15,20 +15,18 @@
 //                  paper hashes each transfer whole (Sec. 5.1 and App. B); the
 //                  tree form is this project's parallel definition.
 //   * analyze    : the detection rules of Sec. 5 (Defs. 1-4 of Sec. 4 with the
-//                  keys of Algorithms 1-4), computed by single chronological
-//                  passes over per-key state.
-//   * alg1..alg4 : the paper's Algorithms 1-4 taken step by step with ordered
-//                  maps and queues, kept to cross-check the rules above.
-//   * unused_transfers, alg5 : unused transfers (Def. 4, Alg. 5), the rule and
-//                  the algorithm step by step; the GPU path does not compute
-//                  this pattern yet.
+//                  keys of Algorithms 1-5), computed by chronological passes
+//                  over per-key state, and the optimization-potential sums of
+//                  Sec. 7.6.
+//   * alg2_pairs : the pairs Alg. 2 records, restated over per-endpoint
+//                  arrival lists, to compare that algorithm with the
+//                  round-trip rule where they differ (three or more endpoints).
 // Parity status of each part is listed in the header of oracle/__init__.py.
 #include <algorithm>
+#include <cmath>
 #include <cstdint>
 #include <cstring>
-#include <deque>
 #include <map>
-#include <set>
 #include <tuple>
 #include <unordered_map>
 #include <unordered_set>
@@ -176,12 +174,16 @@ struct orc_report {
   uint64_t rt_pairs, rt_rx_events, rt_bytes, rt_time_ns;
   uint64_t ra_events, ra_groups, ra_members, ra_bytes, ra_time_ns;
   uint64_t ua_events, ua_bytes, ua_time_ns;
+  uint64_t ut_events, ut_bytes, ut_time_ns;
+  uint64_t span_ns, elim_ns;
+  double predicted_speedup;
   int32_t status;
   uint32_t first_bad_event;
 };
+static_assert(sizeof(orc_report) == 248, "report is 248 bytes");
 
 enum { OP_ALLOC = 1, OP_H2D = 2, OP_D2H = 3, OP_D2D = 4, OP_DELETE = 5, OP_KERNEL = 6 };
-enum { F_DD = 1, F_RT_TX = 2, F_RT_RX = 4, F_RA = 8, F_UA = 16, F_PAIRED = 32, F_INVALID = 128 };
+enum { F_DD = 1, F_RT_TX = 2, F_RT_RX = 4, F_RA = 8, F_UA = 16, F_PAIRED = 32, F_UT = 64, F_INVALID = 128 };
 const int MAX_DEVICE = 9;  // device numbers -1 (host) .. 9 are accepted
 
 uint64_t orc_xxh64(const uint8_t* p, uint64_t n, uint64_t seed) { return xxh64(p, n, seed); }
@@ -199,6 +201,9 @@ struct KeyHash {
   }
   size_t operator()(const std::tuple<uint64_t, int, uint64_t>& k) const {
     return mix(std::get<0>(k), (uint64_t)std::get<1>(k), std::get<2>(k));
+  }
+  size_t operator()(const std::tuple<int, int, uint64_t>& k) const {
+    return mix((uint64_t)std::get<0>(k), (uint64_t)std::get<1>(k), std::get<2>(k));
   }
   static size_t mix(uint64_t a, uint64_t b, uint64_t c) {
     uint64_t h = a * 0x9E3779B97F4A7C15ULL;
@@ -224,6 +229,21 @@ static bool event_valid(const orc_event* ev, uint64_t i) {
   if (is_transfer(e.op) && !dev_ok(e.src_dev)) return false;
   return true;
 }
+
+// Kernel intervals of one device, as two sorted lists. The number of kernels
+// whose closed interval [t_start, t_end] meets the closed interval [lo, hi]
+// (lo <= hi) is
+//   #{kernels with t_start <= hi} - #{kernels with t_end < lo},
+// because a kernel that ends before lo also starts before hi; what remains
+// are the kernels that start by hi and end at or after lo.
+struct DeviceKernels {
+  std::vector<uint64_t> starts, ends;
+  uint64_t meeting(uint64_t lo, uint64_t hi) const {
+    const uint64_t started = std::upper_bound(starts.begin(), starts.end(), hi) - starts.begin();
+    const uint64_t ended = std::lower_bound(ends.begin(), ends.end(), lo) - ends.begin();
+    return started - ended;
+  }
+};
 
 // The detection rules, one chronological pass per rule. flags[i] receives the
 // F_* bits of record i; *rep receives the counts and sums.
@@ -326,7 +346,8 @@ int orc_analyze(const orc_event* ev, uint64_t n, uint8_t* flags, orc_report* rep
   }
 
   // Repeated allocation (Def. 3, key <host address, device, bytes> of Alg. 3):
-  // every paired allocation after the first of its key.
+  // every paired allocation after the first of its key. Its bytes are the
+  // ALLOC's; its time is the ALLOC's and the paired DELETE's durations.
   {
     std::unordered_map<std::tuple<uint64_t, int, uint64_t>, uint64_t, KeyHash> count;
     for (auto& pr : pairs) {
@@ -344,225 +365,132 @@ int orc_analyze(const orc_event* ev, uint64_t n, uint8_t* flags, orc_report* rep
       if (kv.second >= 2) { rep->ra_groups++; rep->ra_members += kv.second; }
   }
 
+  // Kernel intervals per device, for both unused-mapping rules.
+  std::map<int, DeviceKernels> dk;
+  for (uint64_t k : kernels) {
+    dk[ev[k].dst_dev].starts.push_back(ev[k].t_start);
+    dk[ev[k].dst_dev].ends.push_back(ev[k].t_end);
+  }
+  for (auto& kv : dk) {
+    std::sort(kv.second.starts.begin(), kv.second.starts.end());
+    std::sort(kv.second.ends.begin(), kv.second.ends.end());
+  }
+  auto kernels_meeting = [&](int dev, uint64_t lo, uint64_t hi) -> uint64_t {
+    auto it = dk.find(dev);
+    return it == dk.end() ? 0 : it->second.meeting(lo, hi);
+  };
+
   // Unused allocation (Def. 4, allocation half; Alg. 4): the closed interval
-  // [alloc.t_start, delete.t_end] meets no kernel's [t_start, t_end] on the same
-  // device. The number of kernels meeting it is
-  //   #{kernels with t_start <= delete.t_end} - #{kernels with t_end < alloc.t_start},
-  // because every kernel ending before the allocation also starts before the
-  // deletion ends.
+  // [alloc.t_start, delete.t_end] meets no kernel's [t_start, t_end] on the
+  // same device.
+  for (auto& pr : pairs) {
+    const orc_event& a = ev[pr.first];
+    const orc_event& d = ev[pr.second];
+    if (kernels_meeting(a.dst_dev, a.t_start, d.t_end) == 0) {
+      flags[pr.first] |= F_UA;
+      rep->ua_events++;
+      rep->ua_bytes += a.bytes;
+      rep->ua_time_ns += dur(a) + dur(d);
+    }
+  }
+
+  // Unused transfer (Def. 4, transfer half; Alg. 5): data copied into device
+  // memory that no kernel on that device can read before the next copy to the
+  // same place overwrites it, or ever, when no such copy follows. Readings:
+  //   * the device a transfer writes is its dst_dev, for an H2D or a D2D; a
+  //     D2H writes host memory, which the definition does not cover;
+  //   * "the same place" is the transfer's (dst_dev, src_dev, src_addr):
+  //     Alg. 5 keys by the host address, the same key when every copy into a
+  //     device comes from the host; a D2D source address is device memory;
+  //   * a kernel can read the copy when its closed interval meets
+  //     [copy.t_start, next.t_start], where next is the next copy of the same
+  //     key in log order (no upper end when there is none): the kernel is
+  //     still running or not yet started when the copy begins, and starts no
+  //     later than the overwrite begins. With kernels that do not overlap
+  //     this is Alg. 5's pointer and candidate rule; it also holds when
+  //     kernels on a device overlap (the count form above).
   {
-    std::map<int, std::vector<uint64_t>> starts, ends;
-    for (uint64_t k : kernels) {
-      starts[ev[k].dst_dev].push_back(ev[k].t_start);
-      ends[ev[k].dst_dev].push_back(ev[k].t_end);
+    std::unordered_map<std::tuple<int, int, uint64_t>, uint64_t, KeyHash> next_of_key;
+    std::vector<uint64_t> nxt(n, UINT64_MAX);
+    for (size_t k = transfers.size(); k-- > 0;) {
+      const uint64_t i = transfers[k];
+      const orc_event& t = ev[i];
+      if (!(t.op == OP_H2D || t.op == OP_D2D) || t.dst_dev < 0) continue;
+      const auto key = std::make_tuple((int)t.dst_dev, (int)t.src_dev, t.src_addr);
+      auto it = next_of_key.find(key);
+      if (it != next_of_key.end()) nxt[i] = it->second;
+      next_of_key[key] = i;
     }
-    for (auto& kv : starts) std::sort(kv.second.begin(), kv.second.end());
-    for (auto& kv : ends) std::sort(kv.second.begin(), kv.second.end());
-    for (auto& pr : pairs) {
-      const orc_event& a = ev[pr.first];
-      const orc_event& d = ev[pr.second];
-      uint64_t meets = 0;
-      auto s = starts.find(a.dst_dev);
-      if (s != starts.end()) {
-        const std::vector<uint64_t>& st = s->second;
-        const std::vector<uint64_t>& en = ends[a.dst_dev];
-        uint64_t started = std::upper_bound(st.begin(), st.end(), d.t_end) - st.begin();
-        uint64_t ended = std::lower_bound(en.begin(), en.end(), a.t_start) - en.begin();
-        meets = started - ended;
-      }
-      if (meets == 0) {
-        flags[pr.first] |= F_UA;
-        rep->ua_events++;
-        rep->ua_bytes += a.bytes;
-        rep->ua_time_ns += dur(a) + dur(d);
+    for (uint64_t i : transfers) {
+      const orc_event& t = ev[i];
+      if (!(t.op == OP_H2D || t.op == OP_D2D) || t.dst_dev < 0) continue;
+      const uint64_t hi = nxt[i] == UINT64_MAX ? UINT64_MAX : ev[nxt[i]].t_start;
+      if (kernels_meeting(t.dst_dev, t.t_start, hi) == 0) {
+        flags[i] |= F_UT;
+        rep->ut_events++;
+        rep->ut_bytes += t.bytes;
+        rep->ut_time_ns += dur(t);
       }
     }
+  }
+
+  // Optimization potential (Sec. 7.6): the time that removing the flagged
+  // mappings would save, each record counted once whatever flags it carries.
+  // A transfer flagged as a duplicate, a round-trip return leg or unused is
+  // removable; a repeated or unused allocation removes its ALLOC and its
+  // DELETE. The run's total time is the log's span, from the first valid
+  // record's start to the latest valid end; the predicted speedup is
+  // span / (span - eliminable), +infinity when nothing would be left, 1 for an
+  // empty span.
+  {
+    for (uint64_t i : transfers)
+      if (flags[i] & (F_DD | F_RT_RX | F_UT)) rep->elim_ns += dur(ev[i]);
+    for (auto& pr : pairs)
+      if (flags[pr.first] & (F_RA | F_UA)) rep->elim_ns += dur(ev[pr.first]) + dur(ev[pr.second]);
+    bool any = false;
+    uint64_t first = 0, last = 0;
+    for (uint64_t i = 0; i < n; ++i) {
+      if (!valid[i]) continue;
+      if (!any) first = ev[i].t_start;
+      last = any ? std::max(last, ev[i].t_end) : ev[i].t_end;
+      any = true;
+    }
+    rep->span_ns = any ? last - first : 0;
+    if (rep->span_ns == 0) rep->predicted_speedup = 1.0;
+    else if (rep->elim_ns >= rep->span_ns) rep->predicted_speedup = INFINITY;
+    else rep->predicted_speedup = (double)rep->span_ns / (double)(rep->span_ns - rep->elim_ns);
   }
   return 0;
 }
 
-// ----------------------------------------------------------------------------
-// The paper's Algorithms 1-4, step by step, for cross-checking. Each takes the
-// indices of the records it is given (already restricted to the kind of record
-// the algorithm expects) and returns what the algorithm returns, flattened.
-// ----------------------------------------------------------------------------
-
-// Algorithm 1: map <hash, destination device> -> events; groups of size >= 2.
-// Output: group_of[i] = group number (0-based, in order of first member) for
-// members of returned groups, else -1. Returns the number of groups.
-int64_t orc_alg1(const orc_event* ev, const uint64_t* idx, uint64_t m, int64_t* group_of) {
-  std::map<std::pair<uint64_t, int>, std::vector<uint64_t>> received;
-  for (uint64_t k = 0; k < m; ++k)
-    received[std::make_pair(ev[idx[k]].digest, (int)ev[idx[k]].dst_dev)].push_back(k);
-  std::vector<std::vector<uint64_t>> dup;
-  for (auto& kv : received)
-    if (kv.second.size() >= 2) dup.push_back(kv.second);
-  std::sort(dup.begin(), dup.end(), [](const std::vector<uint64_t>& x, const std::vector<uint64_t>& y) { return x[0] < y[0]; });
-  for (uint64_t k = 0; k < m; ++k) group_of[k] = -1;
-  for (size_t g = 0; g < dup.size(); ++g)
-    for (uint64_t k : dup[g]) group_of[k] = (int64_t)g;
-  return (int64_t)dup.size();
-}
-
-// Algorithm 2: queues of received events per <hash, destination>; for each
-// transfer, peek the queue of its source; record <tx, rx>; dequeue the queue
-// of its destination. Output: tx_pos[p], rx_pos[p] (positions in idx), in the
-// order the algorithm records them. Returns the number of pairs.
-int64_t orc_alg2(const orc_event* ev, const uint64_t* idx, uint64_t m, int64_t* tx_pos, int64_t* rx_pos) {
-  std::map<std::pair<uint64_t, int>, std::deque<uint64_t>> received;
-  for (uint64_t k = 0; k < m; ++k)
-    received[std::make_pair(ev[idx[k]].digest, (int)ev[idx[k]].dst_dev)].push_back(k);
+// The pairs Alg. 2 records, for comparing that algorithm with the round-trip
+// rule above (they differ with three or more endpoints; see the readings).
+// Alg. 2 matches each transfer, in log order, against the transfers received
+// by its source endpoint: for a digest h and an endpoint d, let R(h, d) be
+// the transfers of h received by d, in log order, and c(h, d) how many of
+// them have been used up. A transfer tx of h is matched to element
+// c(h, tx.src) of R(h, tx.src) when that exists; a matched transfer uses up
+// one element of R(h, tx.dst), the list that holds tx itself.
+// `idx` lists the transfers (positions in the event array, log order).
+// Output: tx_pos[p], rx_pos[p] (positions in idx) in match order. Returns the
+// number of pairs.
+int64_t orc_alg2_pairs(const orc_event* ev, const uint64_t* idx, uint64_t m, int64_t* tx_pos, int64_t* rx_pos) {
+  std::map<std::pair<uint64_t, int>, std::vector<uint64_t>> received;  // R(h, d): positions in idx
+  std::map<std::pair<uint64_t, int>, uint64_t> used;                   // c(h, d)
+  for (uint64_t k = 0; k < m; ++k) received[std::make_pair(ev[idx[k]].digest, (int)ev[idx[k]].dst_dev)].push_back(k);
   int64_t np = 0;
   for (uint64_t k = 0; k < m; ++k) {
     const orc_event& tx = ev[idx[k]];
-    auto rx_it = received.find(std::make_pair(tx.digest, (int)tx.src_dev));
-    if (rx_it == received.end() || rx_it->second.empty()) continue;
+    const auto from = std::make_pair(tx.digest, (int)tx.src_dev);
+    auto r = received.find(from);
+    const uint64_t c = used[from];
+    if (r == received.end() || c >= r->second.size()) continue;
     tx_pos[np] = (int64_t)k;
-    rx_pos[np] = (int64_t)rx_it->second.front();
+    rx_pos[np] = (int64_t)r->second[c];
     np++;
-    received[std::make_pair(tx.digest, (int)tx.dst_dev)].pop_front();
+    used[std::make_pair(tx.digest, (int)tx.dst_dev)]++;
   }
   return np;
-}
-
-// Algorithm 3 over given <alloc, delete> pairs (positions in the event array):
-// map <host address, device, bytes> -> pairs; keep groups of size >= 2.
-// Output: rank[p] = position of pair p inside its kept group (0 = first), or
-// -1 when its group was removed. Returns the number of kept groups.
-int64_t orc_alg3(const orc_event* ev, const uint64_t* alloc_idx, const uint64_t* delete_idx, uint64_t m, int64_t* rank) {
-  (void)delete_idx;
-  std::map<std::tuple<uint64_t, int, uint64_t>, std::vector<uint64_t>> repeated;
-  for (uint64_t p = 0; p < m; ++p) {
-    const orc_event& a = ev[alloc_idx[p]];
-    repeated[std::make_tuple(a.src_addr, (int)a.dst_dev, a.bytes)].push_back(p);
-  }
-  for (auto it = repeated.begin(); it != repeated.end();) {
-    if (it->second.size() < 2) it = repeated.erase(it); else ++it;
-  }
-  for (uint64_t p = 0; p < m; ++p) rank[p] = -1;
-  for (auto& kv : repeated)
-    for (size_t r = 0; r < kv.second.size(); ++r) rank[kv.second[r]] = (int64_t)r;
-  return (int64_t)repeated.size();
-}
-
-// Algorithm 4: per device, a pointer over that device's kernels (in log
-// order) skips kernels that end before the allocation starts; the pair is
-// unused when no kernel is left or the next one starts after the deletion ends.
-// Pairs must be in allocation order. Output: unused[p] in {0, 1}.
-void orc_alg4(const orc_event* ev, const uint64_t* kernel_idx, uint64_t nk,
-              const uint64_t* alloc_idx, const uint64_t* delete_idx, uint64_t m, uint8_t* unused) {
-  std::map<int, std::vector<uint64_t>> dev_kernels;
-  for (uint64_t k = 0; k < nk; ++k) dev_kernels[ev[kernel_idx[k]].dst_dev].push_back(kernel_idx[k]);
-  std::map<int, std::vector<uint64_t>> dev_pairs;
-  for (uint64_t p = 0; p < m; ++p) dev_pairs[ev[alloc_idx[p]].dst_dev].push_back(p);
-  for (auto& dp : dev_pairs) {
-    const std::vector<uint64_t>& tgt = dev_kernels[dp.first];
-    size_t t = 0;
-    for (uint64_t p : dp.second) {
-      const orc_event& a = ev[alloc_idx[p]];
-      const orc_event& d = ev[delete_idx[p]];
-      while (t < tgt.size() && ev[tgt[t]].t_end < a.t_start) t++;
-      unused[p] = (t == tgt.size() || ev[tgt[t]].t_start > d.t_end) ? 1 : 0;
-    }
-  }
-}
-
-// Unused transfers (Def. 4, transfer half; the rule behind Alg. 5). Not part
-// of orc_analyze: a separate output, ut[i] in {0, 1}. Readings:
-//   * a transfer belongs to the device it writes: dst_dev of an H2D or D2D.
-//     A D2H writes host memory, which the definition (data mapped to a
-//     device) does not cover, so it is never flagged and changes no state;
-//   * the address a later transfer overwrites is keyed by the source
-//     endpoint and address (src_dev, src_addr); Alg. 5 keys by the host
-//     address alone, which is the same key when every such transfer comes
-//     from the host;
-//   * the kernels a transfer has passed on its device are counted, as for
-//     UA: e = #kernels on the device with t_end < the transfer's t_start
-//     (Alg. 5's pointer gives the same count when kernels do not overlap).
-// With K the device's valid kernels in log order, a transfer is unused when
-//   (i)  e = |K|: no kernel on its device is left to read it, or
-//   (ii) K[e] starts after it (it lies in the gap before K[e]) and a later
-//        transfer of the same (device, e, src_dev, src_addr) also lies in
-//        that gap: it is overwritten before any kernel can read it.
-// A transfer that overlaps K[e] (K[e].t_start <= t_start) is neither; every
-// later transfer of the same e overlaps K[e] as well (the log is ordered by
-// t_start), so it ends the gap's candidates as Alg. 5's clearing does.
-// Invalid records take part in nothing. Returns the number flagged.
-int64_t orc_unused_transfers(const orc_event* ev, uint64_t n, uint8_t* ut) {
-  std::vector<bool> ok(n);
-  for (uint64_t i = 0; i < n; ++i) ok[i] = event_valid(ev, i);
-  std::map<int, std::vector<uint64_t>> kernels;  // device -> kernel records in log order
-  std::map<int, std::vector<uint64_t>> ends;     // device -> sorted kernel t_end
-  for (uint64_t i = 0; i < n; ++i)
-    if (ok[i] && ev[i].op == OP_KERNEL) {
-      kernels[ev[i].dst_dev].push_back(i);
-      ends[ev[i].dst_dev].push_back(ev[i].t_end);
-    }
-  for (auto& kv : ends) std::sort(kv.second.begin(), kv.second.end());
-  // (device, e, src_dev, src_addr) -> the latest gap transfer seen so far
-  std::map<std::tuple<int, uint64_t, int, uint64_t>, uint64_t> last_in_gap;
-  int64_t count = 0;
-  for (uint64_t i = 0; i < n; ++i) ut[i] = 0;
-  for (uint64_t i = 0; i < n; ++i) {
-    const orc_event& t = ev[i];
-    if (!ok[i] || !(t.op == OP_H2D || t.op == OP_D2D) || t.dst_dev < 0) continue;
-    const std::vector<uint64_t>& K = kernels[t.dst_dev];
-    const std::vector<uint64_t>& E = ends[t.dst_dev];
-    const uint64_t e = (uint64_t)(std::lower_bound(E.begin(), E.end(), t.t_start) - E.begin());
-    if (e == K.size()) {
-      ut[i] = 1;
-      continue;
-    }
-    if (ev[K[e]].t_start > t.t_start) {
-      const auto key = std::make_tuple((int)t.dst_dev, e, (int)t.src_dev, t.src_addr);
-      auto it = last_in_gap.find(key);
-      if (it != last_in_gap.end()) ut[it->second] = 1;
-      last_in_gap[key] = i;
-    }
-  }
-  for (uint64_t i = 0; i < n; ++i) count += ut[i];
-  return count;
-}
-
-// Algorithm 5 step by step: per device, a pointer over that device's kernels
-// (log order) and a map of candidate transfers by source address. Moving the
-// pointer past a kernel, or a transfer that overlaps the kernel it points to,
-// empties the map; with no kernel left the transfer is unused; in a gap before
-// the pointed kernel, a candidate at the same address is unused and the
-// transfer replaces it. Transfers (tx_idx, log order) are grouped by dst_dev
-// and keyed by (src_dev, src_addr), the readings of orc_unused_transfers.
-// Output: unused[t] in {0, 1} for tx_idx[t].
-void orc_alg5(const orc_event* ev, const uint64_t* kernel_idx, uint64_t nk, const uint64_t* tx_idx, uint64_t m,
-              uint8_t* unused) {
-  std::map<int, std::vector<uint64_t>> dev_kernels;
-  for (uint64_t k = 0; k < nk; ++k) dev_kernels[ev[kernel_idx[k]].dst_dev].push_back(kernel_idx[k]);
-  std::map<int, std::vector<uint64_t>> dev_tx;
-  for (uint64_t t = 0; t < m; ++t) {
-    unused[t] = 0;
-    dev_tx[ev[tx_idx[t]].dst_dev].push_back(t);
-  }
-  for (auto& dt : dev_tx) {
-    const std::vector<uint64_t>& tgt = dev_kernels[dt.first];
-    size_t p = 0;
-    std::map<std::pair<int, uint64_t>, uint64_t> candidates;
-    for (uint64_t t : dt.second) {
-      const orc_event& tx = ev[tx_idx[t]];
-      while (p < tgt.size() && ev[tgt[p]].t_end < tx.t_start) {
-        p++;
-        candidates.clear();
-      }
-      if (p == tgt.size()) {
-        unused[t] = 1;
-      } else if (ev[tgt[p]].t_start > tx.t_start) {
-        const std::pair<int, uint64_t> key((int)tx.src_dev, tx.src_addr);
-        auto it = candidates.find(key);
-        if (it != candidates.end()) unused[it->second] = 1;
-        candidates[key] = t;
-      } else {
-        candidates.clear();
-      }
-    }
-  }
 }
 
 }  // extern "C"

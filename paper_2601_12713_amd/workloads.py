@@ -552,15 +552,58 @@ class TraceAtScale:
         self.n_map = n_map
         n_rep_final = int(rep.sum())
         pair_slots = slots[(kinds == 4) | (kinds == 5)]
+        # What the generator planted, record by record. Every interval is
+        # disjoint from the others and they increase with the index, so "a
+        # KERNEL record lies between two records" is the same as "a kernel runs
+        # between them in time".
+        dur = (ev["t_end"] - ev["t_start"]).astype(np.uint64)
+        rec_dd = ((k == 2) & (pos_in_unit == 0)) | (tri_pos == 2)
+        rec_rx = (tri_pos == 1) | (tri_pos == 2)
+        pair_units = np.nonzero((kinds == 4) | (kinds == 5))[0]  # in time order
+        first_of_slot = np.zeros(pair_units.size, dtype=bool)
+        _, first = np.unique(slots[pair_units], return_index=True)
+        first_of_slot[first] = True
+        alloc_rec = rec_start[pair_units]
+        delete_rec = alloc_rec + np.where(kinds[pair_units] == 4, 2, 1)
+        pair_dur = dur[alloc_rec] + dur[delete_rec]
+        pair_bytes = nbytes[alloc_rec]
+        ra = ~first_of_slot
+        ua = kinds[pair_units] == 5
+        # A host-to-device copy is never read when no KERNEL record follows it
+        # before the next copy of its slot (or at all, when none follows).
+        kc = np.cumsum(is_k)
+        h_idx = np.nonzero(h2d)[0]
+        o = np.lexsort((h_idx, s[h_idx]))
+        hi, hs = h_idx[o], s[h_idx][o]
+        has_next = np.zeros(hi.size, dtype=bool)
+        has_next[:-1] = hs[1:] == hs[:-1]
+        nxt = np.where(has_next, np.roll(hi, -1), 0)
+        between = np.where(has_next, kc[np.maximum(nxt - 1, 0)] - kc[hi], kc[-1] - kc[hi])
+        rec_ut = np.zeros(total, dtype=bool)
+        rec_ut[hi[between == 0]] = True
+        removable = rec_dd | rec_rx | rec_ut
         self.planted = {
             "n_transfers": int(is_tx.sum()),
             "n_kernels": int(is_k.sum()),
             "n_alloc_pairs": n_pair,
             "dd_events": n_rep_final + n_tri,
+            "dd_bytes": int(nbytes[rec_dd].sum()),
+            "dd_time_ns": int(dur[rec_dd].sum()),
             "rt_pairs": 2 * n_tri,
             "rt_rx_events": 2 * n_tri,
+            "rt_bytes": int(nbytes[rec_rx].sum()),
+            "rt_time_ns": int(dur[rec_rx].sum()),
             "ra_events": n_pair - int(np.unique(pair_slots).size),
+            "ra_bytes": int(pair_bytes[ra].sum()),
+            "ra_time_ns": int(pair_dur[ra].sum()),
             "ua_events": n_pair - n_pair // 2,
+            "ua_bytes": int(pair_bytes[ua].sum()),
+            "ua_time_ns": int(pair_dur[ua].sum()),
+            "ut_events": int(rec_ut.sum()),
+            "ut_bytes": int(nbytes[rec_ut].sum()),
+            "ut_time_ns": int(dur[rec_ut].sum()),
+            "elim_ns": int(dur[removable].sum()) + int(pair_dur[ra | ua].sum()),
+            "span_ns": int(ev["t_end"][-1] - ev["t_start"][0]),
             "n_unpaired_alloc": 0,
             "n_unpaired_delete": 0,
         }

@@ -1,10 +1,11 @@
 """Pins of the oracle's unused-transfer rule (Def. 4, transfer half; Alg. 5).
 
-Three independent routes: traces worked by hand from the definition, an
-O(n^2) brute force that decides "overwritten before any kernel can read it" by
-scanning every later transfer, and the paper's Algorithm 5 taken step by step
-(pointer and candidate map), which must agree with the rule wherever kernels
-on a device do not overlap.
+Two independent routes: traces worked by hand from the definition (each case
+of the paper's description of Alg. 5: a copy overwritten in the gap before a
+kernel, a kernel in between, a copy after the last kernel, a device without
+kernels, a copy overlapping a running kernel), and the brute force of
+tests/brute.py, which decides "read by some kernel before a later copy to the
+same place begins" by quantifying over every kernel and every later copy.
 """
 import numpy as np
 from hypothesis import given, settings, strategies as st
@@ -12,43 +13,12 @@ from hypothesis import given, settings, strategies as st
 import oracle
 from paper_2601_12713_amd import workloads as W
 
-from brute import _valid, H2D, D2D, KERNEL
+from brute import brute, F_UT
 
 
 def brute_ut(ev):
-    n = len(ev)
-    valid = [_valid(ev, i) for i in range(n)]
-    op = [int(ev[i]["op"]) for i in range(n)]
-    dst = [int(ev[i]["dst_dev"]) for i in range(n)]
-    src = [int(ev[i]["src_dev"]) for i in range(n)]
-    saddr = [int(ev[i]["src_addr"]) for i in range(n)]
-    ts = [int(ev[i]["t_start"]) for i in range(n)]
-    te = [int(ev[i]["t_end"]) for i in range(n)]
-    kernels = {}
-    for i in range(n):
-        if valid[i] and op[i] == KERNEL:
-            kernels.setdefault(dst[i], []).append(i)
-    into = [i for i in range(n) if valid[i] and op[i] in (H2D, D2D) and dst[i] >= 0]
-
-    def passed(i):  # kernels on the transfer's device that ended before it started
-        return sum(1 for k in kernels.get(dst[i], []) if te[k] < ts[i])
-
-    def in_gap(i, e):
-        K = kernels.get(dst[i], [])
-        return e < len(K) and ts[K[e]] > ts[i]
-
-    ut = [0] * n
-    for i in into:
-        e = passed(i)
-        if e == len(kernels.get(dst[i], [])):
-            ut[i] = 1
-        elif in_gap(i, e):
-            for j in into:
-                if (j > i and dst[j] == dst[i] and src[j] == src[i] and saddr[j] == saddr[i]
-                        and passed(j) == e and in_gap(j, e)):
-                    ut[i] = 1
-                    break
-    return ut
+    flags, _ = brute(ev, lambda i: b"")
+    return [1 if f & F_UT else 0 for f in flags]
 
 
 def trace(rows):
@@ -149,35 +119,30 @@ def test_rule_matches_brute_force_invalid_and_overlapping(seed):
     assert oracle.unused_transfers(ev).tolist() == brute_ut(ev)
 
 
-def _kernels_overlap(ev, K):
-    by_dev = {}
-    for k in K:
-        by_dev.setdefault(int(ev["dst_dev"][k]), []).append(k)
-    for ks in by_dev.values():
-        for a, b in zip(ks, ks[1:]):
-            if int(ev["t_start"][b]) <= int(ev["t_end"][a]):
-                return True
-    return False
+def test_overlapping_kernels():
+    # Two kernels on device 0 overlap: [10, 100] and [20, 30]. A copy at 40
+    # is read by the long kernel still running (it meets [40, 50]); the copy
+    # at 50 is overwritten at 60 with no kernel starting in between, but the
+    # long kernel runs across both, so it may read either: used.
+    ev = trace([(W.KERNEL, -1, 0, 0, 10, 100), (W.KERNEL, -1, 0, 0, 20, 30), (W.H2D, -1, 0, A, 40, 45),
+                (W.H2D, -1, 0, A, 50, 55), (W.H2D, -1, 0, A, 60, 65), (W.H2D, -1, 0, B, 110, 115)])
+    assert oracle.unused_transfers(ev).tolist() == [0, 0, 0, 0, 0, 1]
 
 
-@settings(max_examples=200, deadline=None)
-@given(seed=st.integers(0, 2**32 - 1), n_dev=st.integers(1, 3))
-def test_algorithm5_matches_rule_without_overlapping_kernels(seed, n_dev):
-    ev, _, _ = W.tiny_trace(seed, n_events=60, n_devices=n_dev, n_vars=3)
-    valid = [_valid(ev, i) for i in range(len(ev))]
-    K = [i for i in range(len(ev)) if valid[i] and int(ev["op"][i]) == KERNEL]
-    if _kernels_overlap(ev, K):
-        return
-    T = [i for i in range(len(ev)) if valid[i] and int(ev["op"][i]) in (H2D, D2D) and int(ev["dst_dev"][i]) >= 0]
-    rule = oracle.unused_transfers(ev)
-    alg = oracle.alg5(ev, np.array(K, dtype=np.uint64), np.array(T, dtype=np.uint64))
-    assert alg.tolist() == [int(rule[i]) for i in T]
+def test_touching_ends_count_as_use():
+    # A kernel ending exactly when the copy starts, or starting exactly when
+    # the overwrite starts, may read the copy (closed intervals).
+    ev = trace([(W.KERNEL, -1, 0, 0, 0, 10), (W.H2D, -1, 0, A, 10, 12), (W.H2D, -1, 0, A, 14, 16),
+                (W.KERNEL, -1, 0, 0, 14, 20)])
+    assert oracle.unused_transfers(ev).tolist() == [0, 0, 0, 0]
+    ev = trace([(W.KERNEL, -1, 0, 0, 0, 9), (W.H2D, -1, 0, A, 10, 12), (W.H2D, -1, 0, A, 14, 16),
+                (W.KERNEL, -1, 0, 0, 15, 20)])
+    assert oracle.unused_transfers(ev).tolist() == [0, 1, 0, 0]
 
 
-def test_algorithm5_and_rule_on_planted_trace():
-    # The hand trace of the first case, through the step-by-step algorithm.
-    ev = trace([(W.H2D, -1, 0, A, 0, 5), (W.H2D, -1, 0, A, 10, 15), (W.KERNEL, -1, 0, 0, 20, 30),
-                (W.H2D, -1, 0, A, 40, 45)])
-    alg = oracle.alg5(ev, np.array([2], dtype=np.uint64), np.array([0, 1, 3], dtype=np.uint64))
-    assert alg.tolist() == [1, 0, 1]
-    assert oracle.unused_transfers(ev).tolist() == [1, 0, 0, 1]
+def test_report_counts_and_sums_of_unused_transfers():
+    ev = trace([(W.H2D, -1, 0, A, 0, 5), (W.H2D, -1, 0, A, 10, 17), (W.KERNEL, -1, 0, 0, 20, 30),
+                (W.H2D, -1, 0, B, 40, 49)])
+    ev["bytes"] = [100, 200, 0, 300]
+    flags, rep = oracle.analyze(ev)
+    assert rep["ut_events"] == 2 and rep["ut_bytes"] == 400 and rep["ut_time_ns"] == 5 + 9
