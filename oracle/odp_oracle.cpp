@@ -438,8 +438,8 @@ int orc_analyze(const orc_event* ev, uint64_t n, uint8_t* flags, orc_report* rep
   // mappings would save, each record counted once whatever flags it carries.
   // A transfer flagged as a duplicate, a round-trip return leg or unused is
   // removable; a repeated or unused allocation removes its ALLOC and its
-  // DELETE. The run's total time is the log's span, from the first valid
-  // record's start to the latest valid end; the predicted speedup is
+  // DELETE. The run's total time is the log's span, from the earliest valid
+  // start to the latest valid end; the predicted speedup is
   // span / (span - eliminable), +infinity when nothing would be left, 1 for an
   // empty span.
   {
@@ -451,7 +451,7 @@ int orc_analyze(const orc_event* ev, uint64_t n, uint8_t* flags, orc_report* rep
     uint64_t first = 0, last = 0;
     for (uint64_t i = 0; i < n; ++i) {
       if (!valid[i]) continue;
-      if (!any) first = ev[i].t_start;
+      first = any ? std::min(first, ev[i].t_start) : ev[i].t_start;
       last = any ? std::max(last, ev[i].t_end) : ev[i].t_end;
       any = true;
     }

@@ -8,10 +8,10 @@ Every count and sum of the report is recomputed here from the definitions:
     Defs. 1-4, with bytes and durations summed over the flagged records (a
     repeated or unused allocation adds its DELETE's duration: the allocation's
     whole lifetime is the mapping the pattern concerns);
-  * unused transfers by quantifying over kernels and later copies: a copy into
-    device memory is used when some kernel on that device is still running or
-    not yet started when the copy begins, and starts before any later copy to
-    the same place has begun to overwrite it (closed intervals: touching
+  * unused transfers by quantifying over kernels: a copy into device memory is
+    used when some kernel on that device is still running or not yet started
+    when the copy begins, and starts no later than the next copy to the same
+    place (in log order) begins to overwrite it (closed intervals: touching
     counts as use).
 """
 ALLOC, H2D, D2H, D2D, DELETE, KERNEL = 1, 2, 3, 4, 5, 6
@@ -137,9 +137,9 @@ def brute(ev, data_of):
         return (dst[i], src[i], int(ev[i]["src_addr"]))
 
     for i in into:
-        overwrites = [j for j in into if j > i and place(j) == place(i)]
-        read = any(dst[k] == dst[i] and te[k] >= ts[i] and not any(ts[j] < ts[k] for j in overwrites)
-                   for k in K)
+        overwrites = [j for j in into if j > i and place(j) == place(i)]  # later copies, log order
+        nxt = overwrites[0] if overwrites else None
+        read = any(dst[k] == dst[i] and te[k] >= ts[i] and (nxt is None or ts[k] <= ts[nxt]) for k in K)
         if not read:
             flags[i] |= F_UT
             c["ut_events"] += 1
@@ -149,7 +149,7 @@ def brute(ev, data_of):
     elim = sum(dur[i] for i in T if flags[i] & (F_DD | F_RT_RX | F_UT))
     elim += sum(dur[a] + dur[d] for a, d in pairs if flags[a] & (F_RA | F_UA))
     V = [i for i in range(n) if valid[i]]
-    span = (max(te[i] for i in V) - ts[V[0]]) if V else 0
+    span = (max(te[i] for i in V) - min(ts[i] for i in V)) if V else 0
     c["span_ns"] = span
     c["elim_ns"] = elim
     c["predicted_speedup"] = 1.0 if span == 0 else (float("inf") if elim >= span else span / (span - elim))
