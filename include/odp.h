@@ -16,7 +16,10 @@
  *                        buffer (the paper hashes each transfer, Sec. 5.1 and
  *                        App. B; here the digest is ODP-D64 v1, defined below)
  *   odp_analyze_trace    one pass over the event log that flags the four
- *                        patterns from those digests and addresses
+ *                        patterns from those digests and addresses (both
+ *                        halves of Def. 4: unused allocations and unused
+ *                        transfers), and the optimization-potential estimate
+ *                        of Sec. 7.6
  *   odp_server_*         the two combined for requests that arrive over
  *                        time: each is digested and classified as it comes,
  *                        with continuous batching (an extension; the paper
@@ -149,14 +152,25 @@ enum {
   ODP_F_UA = 16,     /* unused allocation: no kernel on the device meets the closed interval
                         [ALLOC.t_start, DELETE.t_end] (Def. 4, Alg. 4) */
   ODP_F_PAIRED = 32, /* ALLOC/DELETE matched into a pair (see below) */
+  ODP_F_UT = 64,     /* unused transfer: no kernel on the receiving device can read the copy before
+                        the next copy to the same place begins (Def. 4, Alg. 5) */
   ODP_F_INVALID = 128 /* record rejected: unknown op, t_end < t_start, t_start below the
                          previous record's, or a device number outside -1..ODP_MAX_DEVICE */
 };
 
-/* Counts and sums over one log. Filled on the device; valid after the stream
- * completes. *_bytes and *_time_ns sum `bytes` and (t_end - t_start) over the
- * flagged records (round trips: over return legs; RA/UA: the ALLOC plus its
- * DELETE's duration), the inputs of the paper's savings estimate (Sec. 7.6). */
+/* Counts and sums over one log (248 bytes). Filled on the device; valid after
+ * the stream completes. *_bytes and *_time_ns sum `bytes` and
+ * (t_end - t_start) over the flagged records (round trips: over return legs;
+ * RA/UA: the ALLOC plus its DELETE's duration), the inputs of the paper's
+ * savings estimate (Sec. 7.6), which the last three fields complete:
+ *   span_ns            latest t_end minus earliest t_start over the valid
+ *                      records (0 when there is none): the run's total time
+ *   elim_ns            the time removing the flagged mappings would save, each
+ *                      record counted once whatever flags it carries: a
+ *                      transfer flagged DD, RT_RX or UT, and the ALLOC and
+ *                      DELETE of a pair flagged RA or UA
+ *   predicted_speedup  span_ns / (span_ns - elim_ns); 1.0 when span_ns is 0,
+ *                      +infinity when elim_ns >= span_ns */
 typedef struct odp_report {
   uint64_t n_events, n_invalid, n_transfers, n_kernels;
   uint64_t n_alloc_pairs, n_unpaired_alloc, n_unpaired_delete;
@@ -164,11 +178,14 @@ typedef struct odp_report {
   uint64_t rt_pairs, rt_rx_events, rt_bytes, rt_time_ns;
   uint64_t ra_events, ra_groups, ra_members, ra_bytes, ra_time_ns;
   uint64_t ua_events, ua_bytes, ua_time_ns;
+  uint64_t ut_events, ut_bytes, ut_time_ns;
+  uint64_t span_ns, elim_ns;
+  double predicted_speedup;
   int32_t status;           /* 0, or 1 when some record was rejected */
   uint32_t first_bad_event; /* index of the first rejected record, 0xFFFFFFFF if none */
 } odp_report;
 
-/* Mapping-trace analysis (Sec. 5, Algs. 1-4) over a chronological log.
+/* Mapping-trace analysis (Sec. 5, Algs. 1-5; Sec. 7.6) over a chronological log.
  *   events      DEVICE, n records in log order (array order is time order; the
  *               index breaks ties).
  *   out_flags   DEVICE, n bytes: ODP_F_* bits of each record.
@@ -187,6 +204,11 @@ typedef struct odp_report {
  *          (src_addr, dst_dev, bytes).
  *   UA     a paired ALLOC on device d whose [t_start, DELETE.t_end] meets no
  *          KERNEL record's [t_start, t_end] on d (closed intervals).
+ *   UT     a transfer with op H2D or D2D into device d = dst_dev >= 0 whose
+ *          [t_start, next.t_start] meets no KERNEL record's [t_start, t_end]
+ *          on d, where next is the next such transfer in log order with the
+ *          same (dst_dev, src_dev, src_addr), the copy that overwrites it (no
+ *          upper end when there is none).
  * Data-dependent problems do not fail the call: rejected records get
  * ODP_F_INVALID, take part in no rule, and set report.status.
  * n = 0 writes an empty report. n > 2^32 - 1 returns ODP_ERANGE.
@@ -208,7 +230,7 @@ int odp_analyze_trace(const odp_event* events, size_t n, uint8_t* out_flags, odp
  * one batched digest of its payloads and one classification against
  * device-resident per-key state, appended to a device-resident log.
  * Flags known at arrival (DD, RT_RX, PAIRED) are exact per tick; flags that
- * depend on later records (RT_TX, RA, UA) are resolved when the server is
+ * depend on later records (RT_TX, RA, UA, UT) are resolved when the server is
  * drained, by the analysis of the whole log in arrival order (the rules of
  * Sec. 4, Defs. 1-4, and Sec. 5; the paper analyses post mortem, serving is an
  * extension).

@@ -1,24 +1,32 @@
-// Mapping-trace analysis on gfx950 (the paper's Sec. 5, Algorithms 1-4).
+// Mapping-trace analysis on gfx950 (the paper's Sec. 5, Algorithms 1-5, and
+// the optimization-potential estimate of Sec. 7.6).
 //
 // The paper groups records with host-side maps: <hash, destination> for
 // duplicates (Alg. 1), queues per <hash, destination> for round trips
-// (Alg. 2), <host address, device, bytes> for repeated allocations (Alg. 3)
-// and a two-pointer sweep per device for unused allocations (Alg. 4). Here the
-// grouping is a stable LSD radix sort and the per-group logic is a pass over
-// the sorted order:
+// (Alg. 2), <host address, device, bytes> for repeated allocations (Alg. 3),
+// a two-pointer sweep per device for unused allocations (Alg. 4) and a
+// per-device kernel pointer with candidate copies for unused transfers
+// (Alg. 5). Here the grouping is a stable LSD radix sort and the per-group
+// logic is a pass over the sorted order:
 //
 //   classify   one read of the 64-byte records: validity, per-record flags,
 //              the digest sort keys, and a 1-byte class / endpoint code
-//   subsets    ordered compaction of ALLOC/DELETE and KERNEL records
+//   subsets    ordered compaction of ALLOC/DELETE, KERNEL and copy-in (H2D or
+//              D2D into a device) records
 //   sort #1    (all in the same launches) records by digest; ALLOC/DELETE by
 //              (device, device address); KERNELs by (device, start) and by
-//              (device, end)
+//              (device, end); copy-ins by (endpoints, source address)
 //   DD/RT      forward and backward segmented scans over each digest group
 //   pairing    a DELETE pairs with its predecessor in its (device, address)
 //              group when that is an ALLOC; paired ALLOCs compacted in order
 //   sort #2    pairs by (bytes, device, host address)
 //   RA/UA      RA = not first of its key group; UA by two binary searches in
 //              the device's sorted kernel starts and ends
+//   UT         a copy-in and the next one of its group (the copy that
+//              overwrites it) bound the window a kernel must meet; the same
+//              two binary searches
+//   estimate   removable time per record over the union of its flags, the
+//              log's span, the predicted speedup
 //
 // Sort keys are 64-bit words; a job lists its words least significant first,
 // and digit passes whose byte is the same in every key are skipped on the
@@ -48,7 +56,9 @@ constexpr uint32_t kPackLimit = 1u << 24;
 constexpr uint32_t kIdxMask = kPackLimit - 1;
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 
-enum : uint8_t { C_INVALID = 0, C_TRANSFER = 1, C_ALLOCDEL = 2, C_KERNEL = 3 };
+// C_COPYIN: a transfer that writes device memory (H2D or D2D, dst_dev >= 0),
+// the records the unused-transfer rule looks at.
+enum : uint8_t { C_INVALID = 0, C_TRANSFER = 1, C_ALLOCDEL = 2, C_KERNEL = 3, C_COPYIN = 4 };
 
 __host__ __device__ inline uint32_t ceil_div32(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
 
@@ -64,11 +74,19 @@ struct AnaCtl {
   uint32_t n_ad;        // ALLOC/DELETE records
   uint32_t n_k;         // KERNEL records
   uint32_t n_pairs;     // paired allocations
+  uint32_t n_ut;        // copy-in records
   uint32_t first_bad;
   uint32_t max_ep;      // largest endpoint code among valid transfers
-  WordMask m_digest, m_ad_dev, m_ad_addr, m_k_start, m_k_end, m_k_dev, m_p_bytes, m_p_dev, m_p_haddr;
+  WordMask m_digest, m_ad_dev, m_ad_addr, m_k_start, m_k_end, m_k_dev, m_p_bytes, m_p_dev, m_p_haddr, m_ut_addr,
+      m_ut_code;
   uint32_t dev_lo[kEp], dev_hi[kEp];  // per-device ranges in the sorted kernel order
+  uint64_t t_min, t_max;              // earliest start and latest end of the valid records
+  // removable time (Sec. 7.6), in three parts written by different stages:
+  // transfers flagged DD or RT_RX; pairs flagged RA or UA; transfers flagged
+  // UT only
+  uint64_t elim_tx, elim_pairs, elim_ut;
 };
+constexpr int kNumMasks = 11;
 
 // One radix sort job. 64-bit keys move with the values; a job lists its key
 // words least significant first. A word with words[w] != null is gathered by
@@ -167,9 +185,10 @@ __device__ __forceinline__ void mask_update(WordMask* m, unsigned long long vor,
 // blocks touch the same word (same-address atomics from thousands of blocks
 // serialise at one L2 channel).
 enum Slot : uint32_t {
-  S_N_INVALID, S_N_TRANSFERS, S_N_KERNELS, S_DIG_OR, S_DIG_AND, S_FIRST_BAD, S_MAX_EP,
+  S_N_INVALID, S_N_TRANSFERS, S_N_KERNELS, S_DIG_OR, S_DIG_AND, S_FIRST_BAD, S_MAX_EP, S_TMIN, S_TMAX,
   S_AD_DEV_OR, S_AD_DEV_AND, S_AD_ADDR_OR, S_AD_ADDR_AND, S_KS_OR, S_KS_AND, S_KE_OR, S_KE_AND, S_KD_OR, S_KD_AND,
-  S_DD_EVENTS, S_DD_GROUPS, S_DD_BYTES, S_DD_TIME, S_RT_PAIRS, S_RT_RX, S_RT_BYTES, S_RT_TIME,
+  S_UT_ADDR_OR, S_UT_ADDR_AND, S_UT_CODE_OR, S_UT_CODE_AND,
+  S_DD_EVENTS, S_DD_GROUPS, S_DD_BYTES, S_DD_TIME, S_RT_PAIRS, S_RT_RX, S_RT_BYTES, S_RT_TIME, S_ELIM_TX,
   kSlots
 };
 
@@ -242,16 +261,20 @@ __global__ void init_kernel(AnaCtl* ctl, odp_report* rep, uint32_t* totals, uint
   for (uint32_t i = t; i < ntotals; i += gridDim.x * blockDim.x) totals[i] = 0;
   if (t == 0) {
     unsigned long long* r = reinterpret_cast<unsigned long long*>(rep);
-    for (int i = 0; i < 24; ++i) r[i] = 0;
+    for (int i = 0; i < (int)(offsetof(odp_report, predicted_speedup) / 8); ++i) r[i] = 0;
     rep->n_events = n;
+    rep->predicted_speedup = 1.0;
     rep->status = 0;
     rep->first_bad_event = kNone;
     ctl->n = n;
-    ctl->n_ad = ctl->n_k = ctl->n_pairs = 0;
+    ctl->n_ad = ctl->n_k = ctl->n_pairs = ctl->n_ut = 0;
     ctl->first_bad = kNone;
     ctl->max_ep = 0;
+    ctl->t_min = ~0ull;
+    ctl->t_max = 0;
+    ctl->elim_tx = ctl->elim_pairs = ctl->elim_ut = 0;
     WordMask* m = &ctl->m_digest;
-    for (int i = 0; i < 9; ++i) {
+    for (int i = 0; i < kNumMasks; ++i) {
       m[i].vor = 0;
       m[i].vand = ~0ull;
     }
@@ -269,7 +292,8 @@ __device__ __forceinline__ bool dev_ok(int d) { return d >= -1 && d <= ODP_MAX_D
 
 // One block per tile of kTile records; wavefront w takes the 1,024
 // consecutive records [tile*kTile + w*1024, ...) in 16 rounds of 64 and also
-// counts the ALLOC/DELETE and KERNEL records it sees (for the compaction).
+// counts the ALLOC/DELETE, KERNEL and copy-in records it sees (for the
+// compaction).
 __global__ __launch_bounds__(kT) void classify_kernel(const odp_event* __restrict__ ev, uint32_t n, uint8_t* __restrict__ flags,
                                                       uint8_t* __restrict__ cls, uint8_t* __restrict__ aux,
                                                       unsigned long long* __restrict__ keys, uint32_t* __restrict__ vals,
@@ -277,8 +301,8 @@ __global__ __launch_bounds__(kT) void classify_kernel(const odp_event* __restric
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const uint32_t wid = blockIdx.x * (kT / 64) + w;
   const uint32_t wb = wid * kWaveElems;
-  unsigned long long n_inv = 0, n_tx = 0, n_k = 0, kor = 0, kand = ~0ull;
-  uint32_t bad = kNone, mep = 0, c_ad = 0, c_k = 0;
+  unsigned long long n_inv = 0, n_tx = 0, n_k = 0, kor = 0, kand = ~0ull, tmin = ~0ull, tmax = 0;
+  uint32_t bad = kNone, mep = 0, c_ad = 0, c_k = 0, c_ut = 0;
   // records of the next round are loaded while this round is classified; the
   // previous record of lane 0 is lane 63 of the round before
   odp_event e;
@@ -301,8 +325,12 @@ __global__ __launch_bounds__(kT) void classify_kernel(const odp_event* __restric
       uint8_t c = C_INVALID, a = kNotTransfer;
       unsigned long long key = ~0ull;
       if (valid) {
+        tmin = min(tmin, (unsigned long long)e.t_start);
+        tmax = max(tmax, (unsigned long long)e.t_end);
         if (is_tx) {
-          c = C_TRANSFER;
+          const bool copyin = e.op != ODP_D2H && e.dst_dev >= 0;
+          c = copyin ? C_COPYIN : C_TRANSFER;
+          c_ut += copyin;
           a = (uint8_t)(((e.src_dev + 1) << 4) | (e.dst_dev + 1));
           mep = max(mep, (uint32_t)max(e.src_dev + 1, e.dst_dev + 1));
           key = e.digest;
@@ -334,10 +362,12 @@ __global__ __launch_bounds__(kT) void classify_kernel(const odp_event* __restric
   for (int o = 32; o >= 1; o >>= 1) {
     c_ad += __shfl_xor(c_ad, o, 64);
     c_k += __shfl_xor(c_k, o, 64);
+    c_ut += __shfl_xor(c_ut, o, 64);
   }
   if (lane == 0) {
-    wave_cnt[2 * wid] = c_ad;
-    wave_cnt[2 * wid + 1] = c_k;
+    wave_cnt[3 * wid] = c_ad;
+    wave_cnt[3 * wid + 1] = c_k;
+    wave_cnt[3 * wid + 2] = c_ut;
   }
   block_store<R_ADD>(parts.at(S_N_INVALID), n_inv);
   block_store<R_ADD>(parts.at(S_N_TRANSFERS), n_tx);
@@ -346,50 +376,62 @@ __global__ __launch_bounds__(kT) void classify_kernel(const odp_event* __restric
   block_store<R_AND>(parts.at(S_DIG_AND), kand);
   block_store<R_MIN>(parts.at(S_FIRST_BAD), bad);
   block_store<R_MAX>(parts.at(S_MAX_EP), mep);
+  block_store<R_MIN>(parts.at(S_TMIN), tmin);
+  block_store<R_MAX>(parts.at(S_TMAX), tmax);
 }
 
 // ---------------------------------------------------------------------------
 // 2. Ordered compaction of the ALLOC/DELETE and KERNEL subsets.
 // ---------------------------------------------------------------------------
-// Exclusive scan of pairs of u32 counters over `ntiles` tiles (one block).
-__global__ __launch_bounds__(1024) void scan_pairs_kernel(uint32_t* tile_cnt, uint32_t ntiles, uint32_t* tot0,
-                                                          uint32_t* tot1) {
-  __shared__ uint32_t sh0[1024], sh1[1024];
-  __shared__ uint32_t c0, c1;
-  if (threadIdx.x == 0) c0 = c1 = 0;
+// Exclusive scan of K interleaved u32 counters (cnt[K*t + c]) over `ntiles`
+// entries (one block); the totals go to tot[c] where that is not null.
+template <int K>
+__global__ __launch_bounds__(1024) void scan_counts_kernel(uint32_t* cnt, uint32_t ntiles, uint32_t* tot0,
+                                                           uint32_t* tot1, uint32_t* tot2) {
+  __shared__ uint32_t sh[K][1024];
+  __shared__ uint32_t carry[K];
+  if (threadIdx.x < K) carry[threadIdx.x] = 0;
   __syncthreads();
   for (uint32_t base = 0; base < ntiles; base += 1024) {
     const uint32_t t = base + threadIdx.x;
-    const uint32_t a = t < ntiles ? tile_cnt[2 * t] : 0, b = t < ntiles ? tile_cnt[2 * t + 1] : 0;
-    sh0[threadIdx.x] = a;
-    sh1[threadIdx.x] = b;
+    uint32_t own[K];
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+      own[c] = t < ntiles ? cnt[K * t + c] : 0;
+      sh[c][threadIdx.x] = own[c];
+    }
     __syncthreads();
     for (int o = 1; o < 1024; o <<= 1) {
-      uint32_t x = threadIdx.x >= (uint32_t)o ? sh0[threadIdx.x - o] : 0;
-      uint32_t y = threadIdx.x >= (uint32_t)o ? sh1[threadIdx.x - o] : 0;
+      uint32_t x[K];
+#pragma unroll
+      for (int c = 0; c < K; ++c) x[c] = threadIdx.x >= (uint32_t)o ? sh[c][threadIdx.x - o] : 0;
       __syncthreads();
-      sh0[threadIdx.x] += x;
-      sh1[threadIdx.x] += y;
+#pragma unroll
+      for (int c = 0; c < K; ++c) sh[c][threadIdx.x] += x[c];
       __syncthreads();
     }
     if (t < ntiles) {
-      tile_cnt[2 * t] = c0 + sh0[threadIdx.x] - a;
-      tile_cnt[2 * t + 1] = c1 + sh1[threadIdx.x] - b;
+#pragma unroll
+      for (int c = 0; c < K; ++c) cnt[K * t + c] = carry[c] + sh[c][threadIdx.x] - own[c];
     }
     __syncthreads();
-    if (threadIdx.x == 1023) {
-      c0 += sh0[1023];
-      c1 += sh1[1023];
-    }
+    if (threadIdx.x < K) carry[threadIdx.x] += sh[threadIdx.x][1023];
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    if (tot0) *tot0 = c0;
-    if (tot1) *tot1 = c1;
+    uint32_t* tot[3] = {tot0, tot1, tot2};
+#pragma unroll
+    for (int c = 0; c < K; ++c)
+      if (tot[c]) *tot[c] = carry[c];
   }
 }
 
 struct SubsetOut {
+  uint32_t* ut_idx;     // copy-ins: record index
+  uint64_t* ut_w_addr;  // source address
+  uint64_t* ut_w_code;  // endpoint code (src_dev + 1) << 4 | (dst_dev + 1)
+  uint64_t* ut_ts;      // t_start
+  uint32_t* ut_vals;
   uint32_t* ad_idx;
   uint8_t* ad_op;
   uint64_t* ad_w_dev;
@@ -404,7 +446,7 @@ struct SubsetOut {
   uint32_t* k_vals_e;
 };
 
-// Ordered compaction of the ALLOC/DELETE and KERNEL records. Wavefront w
+// Ordered compaction of the ALLOC/DELETE, KERNEL and copy-in records. Wavefront w
 // takes its 1,024 records in 16 coalesced rounds of 64 (lane l: record
 // wb + 64r + l); a ballot per round gives each matching lane its rank, so the
 // entries land in record order at the wavefront's scanned offsets, and the
@@ -421,16 +463,29 @@ __global__ __launch_bounds__(kT) void subset_scatter_kernel(const odp_event* __r
     const uint32_t i = wb + r * 64 + lane;
     c[r] = i < n ? cls[i] : C_INVALID;
   }
-  uint32_t q0 = wave_off[2 * wid], q1 = wave_off[2 * wid + 1];
+  uint32_t q0 = wave_off[3 * wid], q1 = wave_off[3 * wid + 1], q2 = wave_off[3 * wid + 2];
   unsigned long long o_dev = 0, a_dev = ~0ull, o_addr = 0, a_addr = ~0ull, o_ks = 0, a_ks = ~0ull, o_ke = 0,
-                     a_ke = ~0ull, o_kd = 0, a_kd = ~0ull;
+                     a_ke = ~0ull, o_kd = 0, a_kd = ~0ull, o_ua = 0, a_ua = ~0ull, o_uc = 0, a_uc = ~0ull;
   const uint64_t lt = lanemask_lt();
 #pragma unroll 4
   for (int r = 0; r < kRounds; ++r) {
     const uint32_t i = wb + r * 64 + lane;
-    const bool is_ad = c[r] == C_ALLOCDEL, is_k = c[r] == C_KERNEL;
-    const uint64_t bad = __ballot(is_ad), bk = __ballot(is_k);
-    if (is_ad) {
+    const bool is_ad = c[r] == C_ALLOCDEL, is_k = c[r] == C_KERNEL, is_ut = c[r] == C_COPYIN;
+    const uint64_t bad = __ballot(is_ad), bk = __ballot(is_k), bu = __ballot(is_ut);
+    if (is_ut) {
+      const odp_event& e = ev[i];
+      const uint32_t q = q2 + (uint32_t)__popcll(bu & lt);
+      const uint64_t code = (uint64_t)(((e.src_dev + 1) << 4) | (e.dst_dev + 1)), sa = e.src_addr;
+      S.ut_idx[q] = i;
+      S.ut_w_addr[q] = sa;
+      S.ut_w_code[q] = code;
+      S.ut_ts[q] = e.t_start;
+      S.ut_vals[q] = q;
+      o_ua |= sa;
+      a_ua &= sa;
+      o_uc |= code;
+      a_uc &= code;
+    } else if (is_ad) {
       const odp_event& e = ev[i];
       const uint32_t q = q0 + (uint32_t)__popcll(bad & lt);
       const uint64_t dv = (uint64_t)(e.dst_dev + 1), ad = e.dst_addr;
@@ -463,6 +518,7 @@ __global__ __launch_bounds__(kT) void subset_scatter_kernel(const odp_event* __r
     }
     q0 += (uint32_t)__popcll(bad);
     q1 += (uint32_t)__popcll(bk);
+    q2 += (uint32_t)__popcll(bu);
   }
   // (identity values where a lane saw no such record)
   block_store<R_OR>(parts.at(S_AD_DEV_OR), o_dev);
@@ -475,6 +531,10 @@ __global__ __launch_bounds__(kT) void subset_scatter_kernel(const odp_event* __r
   block_store<R_AND>(parts.at(S_KE_AND), a_ke);
   block_store<R_OR>(parts.at(S_KD_OR), o_kd);
   block_store<R_AND>(parts.at(S_KD_AND), a_kd);
+  block_store<R_OR>(parts.at(S_UT_ADDR_OR), o_ua);
+  block_store<R_AND>(parts.at(S_UT_ADDR_AND), a_ua);
+  block_store<R_OR>(parts.at(S_UT_CODE_OR), o_uc);
+  block_store<R_AND>(parts.at(S_UT_CODE_AND), a_uc);
 }
 
 // One block per slot: reduces the blocks' partials of slots [first, first +
@@ -485,10 +545,12 @@ __global__ __launch_bounds__(kT) void reduce_parts_kernel(Parts parts, uint32_t 
   const unsigned long long* p = parts.p + (size_t)slot * parts.stride;
   int op = R_ADD;
   switch (slot) {
-    case S_DIG_OR: case S_AD_DEV_OR: case S_AD_ADDR_OR: case S_KS_OR: case S_KE_OR: case S_KD_OR: op = R_OR; break;
-    case S_DIG_AND: case S_AD_DEV_AND: case S_AD_ADDR_AND: case S_KS_AND: case S_KE_AND: case S_KD_AND: op = R_AND; break;
-    case S_FIRST_BAD: op = R_MIN; break;
-    case S_MAX_EP: op = R_MAX; break;
+    case S_DIG_OR: case S_AD_DEV_OR: case S_AD_ADDR_OR: case S_KS_OR: case S_KE_OR: case S_KD_OR:
+    case S_UT_ADDR_OR: case S_UT_CODE_OR: op = R_OR; break;
+    case S_DIG_AND: case S_AD_DEV_AND: case S_AD_ADDR_AND: case S_KS_AND: case S_KE_AND: case S_KD_AND:
+    case S_UT_ADDR_AND: case S_UT_CODE_AND: op = R_AND; break;
+    case S_FIRST_BAD: case S_TMIN: op = R_MIN; break;
+    case S_MAX_EP: case S_TMAX: op = R_MAX; break;
     default: break;
   }
   unsigned long long v = op == R_AND || op == R_MIN ? ~0ull : 0ull;
@@ -517,6 +579,13 @@ __global__ __launch_bounds__(kT) void reduce_parts_kernel(Parts parts, uint32_t 
     case S_DIG_AND: ctl->m_digest.vand = v; break;
     case S_FIRST_BAD: ctl->first_bad = (uint32_t)min(v, (unsigned long long)kNone); break;
     case S_MAX_EP: ctl->max_ep = (uint32_t)v; break;
+    case S_TMIN: ctl->t_min = v; break;
+    case S_TMAX: ctl->t_max = v; break;
+    case S_UT_ADDR_OR: ctl->m_ut_addr.vor = v; break;
+    case S_UT_ADDR_AND: ctl->m_ut_addr.vand = v; break;
+    case S_UT_CODE_OR: ctl->m_ut_code.vor = v; break;
+    case S_UT_CODE_AND: ctl->m_ut_code.vand = v; break;
+    case S_ELIM_TX: ctl->elim_tx = v; break;
     case S_AD_DEV_OR: ctl->m_ad_dev.vor = v; break;
     case S_AD_DEV_AND: ctl->m_ad_dev.vand = v; break;
     case S_AD_ADDR_OR: ctl->m_ad_addr.vor = v; break;
@@ -1500,7 +1569,7 @@ __device__ void ddrt_final_body(const DDArgs& A, uint32_t (*s_val)[kWaveElems], 
     carry = f63 ? x63 : S::fop(carry, x63);
   }
   BS<MODE> bcarry = get_b<MODE>(A.carry[wid].bs);
-  unsigned long long c_dd = 0, c_grp = 0, c_tx = 0, c_rx = 0, b_dd = 0, t_dd = 0, b_rx = 0, t_rx = 0;
+  unsigned long long c_dd = 0, c_grp = 0, c_tx = 0, c_rx = 0, b_dd = 0, t_dd = 0, b_rx = 0, t_rx = 0, t_el = 0;
 #pragma unroll 1
   for (int r = kRounds - 1; r >= 0; --r) {
     const uint32_t j = wb + r * 64 + lane;
@@ -1551,6 +1620,7 @@ __device__ void ddrt_final_body(const DDArgs& A, uint32_t (*s_val)[kWaveElems], 
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
+      t_el += ed[q];  // removable once, whether DD, RT_RX or both
       if (rs[q] & ODP_F_DD) {
         b_dd += eb[q];
         t_dd += ed[q];
@@ -1569,6 +1639,7 @@ __device__ void ddrt_final_body(const DDArgs& A, uint32_t (*s_val)[kWaveElems], 
   block_store<R_ADD>(A.parts.at(S_RT_RX), c_rx);
   block_store<R_ADD>(A.parts.at(S_RT_BYTES), b_rx);
   block_store<R_ADD>(A.parts.at(S_RT_TIME), t_rx);
+  block_store<R_ADD>(A.parts.at(S_ELIM_TX), t_el);
 }
 
 __global__ __launch_bounds__(kT) void ddrt_final_kernel(DDArgs A) {
@@ -1697,14 +1768,21 @@ __global__ __launch_bounds__(kT) void pair_scatter_kernel(PairArgs P) {
 // ---------------------------------------------------------------------------
 // 6. Kernel lists per device (sorted by device, then start / end).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kT) void kernel_ranges_kernel(const SortJob* ks, const uint64_t* k_w_dev, const uint32_t* n_k,
-                                                           AnaCtl* ctl) {
+// Also writes the two sorted orders out as plain arrays of starts and ends,
+// so the binary searches of the unused-mapping rules read one array each.
+__global__ __launch_bounds__(kT) void kernel_ranges_kernel(const SortJob* ks, const SortJob* ke, const uint64_t* k_w_dev,
+                                                           const uint64_t* k_w_start, const uint64_t* k_w_end,
+                                                           const uint32_t* n_k, uint64_t* starts_sorted,
+                                                           uint64_t* ends_sorted, AnaCtl* ctl) {
   const uint32_t n = *n_k;
   const uint32_t* v = ks->vals[ks->npasses & 1];
+  const uint32_t* ve = ke->vals[ke->npasses & 1];
   for (uint32_t j = blockIdx.x * kT + threadIdx.x; j < n; j += gridDim.x * kT) {
     const uint32_t d = (uint32_t)k_w_dev[v[j]];
     if (j == 0 || (uint32_t)k_w_dev[v[j - 1]] != d) ctl->dev_lo[d] = j;
     if (j + 1 == n || (uint32_t)k_w_dev[v[j + 1]] != d) ctl->dev_hi[d] = j + 1;
+    starts_sorted[j] = k_w_start[v[j]];
+    ends_sorted[j] = k_w_end[ve[j]];
   }
 }
 
@@ -1714,8 +1792,8 @@ __global__ __launch_bounds__(kT) void kernel_ranges_kernel(const SortJob* ks, co
 struct RaArgs {
   const odp_event* ev;
   const SortJob* pr_job;
-  const SortJob* ks_job;  // kernels by (device, start)
-  const SortJob* ke_job;  // kernels by (device, end)
+  const uint64_t* starts_sorted;  // kernel starts in (device, start) order
+  const uint64_t* ends_sorted;    // kernel ends in (device, end) order
   const uint32_t* n_pairs;
   const uint32_t* pr_alloc;
   const uint32_t* pr_del;
@@ -1723,9 +1801,7 @@ struct RaArgs {
   const uint64_t* pr_w_bytes;
   const uint64_t* pr_w_dev;
   const uint64_t* pr_w_haddr;
-  const uint64_t* k_w_start;
-  const uint64_t* k_w_end;
-  const AnaCtl* ctl;
+  AnaCtl* ctl;
   uint8_t* flags;
   odp_report* rep;
 };
@@ -1734,25 +1810,31 @@ __device__ __forceinline__ bool same_pair_key(const RaArgs& R, uint32_t a, uint3
   return R.pr_w_haddr[a] == R.pr_w_haddr[b] && R.pr_w_dev[a] == R.pr_w_dev[b] && R.pr_w_bytes[a] == R.pr_w_bytes[b];
 }
 
-// Number of entries of the sorted list (values into `w`) within [lo, hi) whose word is <= x (le) or < x.
-__device__ __forceinline__ uint32_t count_upto(const uint32_t* v, const uint64_t* w, uint32_t lo, uint32_t hi, uint64_t x,
-                                               bool le) {
+// Number of entries of the sorted array w within [lo, hi) that are <= x (le) or < x.
+__device__ __forceinline__ uint32_t count_upto(const uint64_t* w, uint32_t lo, uint32_t hi, uint64_t x, bool le) {
   uint32_t a = lo, b = hi;
   while (a < b) {
     const uint32_t m = (a + b) / 2;
-    const uint64_t y = w[v[m]];
+    const uint64_t y = w[m];
     if (le ? (y <= x) : (y < x)) a = m + 1; else b = m;
   }
   return a - lo;
+}
+
+// Kernels on device code `dev` whose closed interval meets [lo, hi] (lo <= hi):
+// those that start by hi, less those that end before lo (an interval that
+// ends before lo also starts before hi).
+__device__ __forceinline__ uint32_t kernels_meeting(const uint64_t* starts, const uint64_t* ends, const AnaCtl* ctl,
+                                                    uint32_t dev, uint64_t lo, uint64_t hi) {
+  const uint32_t a = ctl->dev_lo[dev], b = ctl->dev_hi[dev];
+  return count_upto(starts, a, b, hi, true) - count_upto(ends, a, b, lo, false);
 }
 
 __global__ __launch_bounds__(kT) void ra_ua_kernel(RaArgs R) {
   const uint32_t n = *R.n_pairs;
   const SortJob& s = *R.pr_job;
   const uint32_t* v = s.vals[s.npasses & 1];
-  const uint32_t* vs = R.ks_job->vals[R.ks_job->npasses & 1];
-  const uint32_t* ve = R.ke_job->vals[R.ke_job->npasses & 1];
-  unsigned long long c_ra = 0, c_grp = 0, b_ra = 0, t_ra = 0, c_ua = 0, b_ua = 0, t_ua = 0;
+  unsigned long long c_ra = 0, c_grp = 0, b_ra = 0, t_ra = 0, c_ua = 0, b_ua = 0, t_ua = 0, t_el = 0;
   for (uint32_t j = blockIdx.x * kT + threadIdx.x; j < n; j += gridDim.x * kT) {
     const uint32_t k = v[j];
     const bool head = j == 0 || !same_pair_key(R, k, v[j - 1]);
@@ -1770,15 +1852,13 @@ __global__ __launch_bounds__(kT) void ra_ua_kernel(RaArgs R) {
     }
     c_grp += group2;
     const uint32_t dev = (uint32_t)R.pr_w_dev[k];
-    const uint32_t lo = R.ctl->dev_lo[dev], hi = R.ctl->dev_hi[dev];
-    const uint32_t started = count_upto(vs, R.k_w_start, lo, hi, d.t_end, true);
-    const uint32_t ended = count_upto(ve, R.k_w_end, lo, hi, a.t_start, false);
-    if (started == ended) {
+    if (kernels_meeting(R.starts_sorted, R.ends_sorted, R.ctl, dev, a.t_start, d.t_end) == 0) {
       f |= ODP_F_UA;
       ++c_ua;
       b_ua += a.bytes;
       t_ua += dur;
     }
+    if (f & (ODP_F_RA | ODP_F_UA)) t_el += dur;  // the pair is removable once
     R.flags[ai] = f;
   }
   block_add(&R.rep->ra_events, c_ra);
@@ -1788,6 +1868,90 @@ __global__ __launch_bounds__(kT) void ra_ua_kernel(RaArgs R) {
   block_add(&R.rep->ua_events, c_ua);
   block_add(&R.rep->ua_bytes, b_ua);
   block_add(&R.rep->ua_time_ns, t_ua);
+  block_add(&R.ctl->elim_pairs, t_el);
+}
+
+// ---------------------------------------------------------------------------
+// 8. Unused transfers (Def. 4, transfer half; Alg. 5).
+//
+// A copy into device memory is unused when no kernel on that device can read
+// it before the next copy to the same place (same receiving device, sending
+// device and source address) begins, or ever when none follows: no kernel's
+// closed interval meets [copy.t_start, next.t_start]. Over the copy-ins sorted
+// stably by (endpoints, source address), the next copy of a record is the
+// element after it when that has the same key. Results go to a byte per
+// copy-in (its position in log order), merged into the flags after the join.
+// ---------------------------------------------------------------------------
+struct UtArgs {
+  const odp_event* ev;
+  const SortJob* ut_job;
+  const uint32_t* n_ut;
+  const uint32_t* ut_idx;
+  const uint64_t* ut_w_addr;
+  const uint64_t* ut_w_code;
+  const uint64_t* ut_ts;
+  const uint64_t* starts_sorted;
+  const uint64_t* ends_sorted;
+  uint8_t* ut_hit;
+  AnaCtl* ctl;
+  uint8_t* flags;
+  odp_report* rep;
+};
+
+__global__ __launch_bounds__(kT) void ut_kernel(UtArgs U) {
+  const uint32_t n = *U.n_ut;
+  const SortJob& s = *U.ut_job;
+  const uint32_t* v = s.vals[s.npasses & 1];
+  unsigned long long c_ut = 0, b_ut = 0, t_ut = 0;
+  for (uint32_t j = blockIdx.x * kT + threadIdx.x; j < n; j += gridDim.x * kT) {
+    const uint32_t q = v[j];
+    const uint64_t addr = U.ut_w_addr[q], code = U.ut_w_code[q];
+    uint64_t hi = ~0ull;
+    if (j + 1 < n) {
+      const uint32_t qn = v[j + 1];
+      if (U.ut_w_addr[qn] == addr && U.ut_w_code[qn] == code) hi = U.ut_ts[qn];
+    }
+    const uint32_t dev = (uint32_t)(code & 15);
+    const bool unused = kernels_meeting(U.starts_sorted, U.ends_sorted, U.ctl, dev, U.ut_ts[q], hi) == 0;
+    U.ut_hit[q] = unused;
+    if (unused) {
+      const odp_event& e = U.ev[U.ut_idx[q]];
+      ++c_ut;
+      b_ut += e.bytes;
+      t_ut += e.t_end - e.t_start;
+    }
+  }
+  block_add(&U.rep->ut_events, c_ut);
+  block_add(&U.rep->ut_bytes, b_ut);
+  block_add(&U.rep->ut_time_ns, t_ut);
+}
+
+// After the join: ORs F_UT into the flags (copy-ins in log order, so the
+// writes advance through the flag array) and adds the removable time of the
+// copies that no other flag already made removable.
+__global__ __launch_bounds__(kT) void ut_merge_kernel(UtArgs U) {
+  const uint32_t n = *U.n_ut;
+  unsigned long long t_el = 0;
+  for (uint32_t q = blockIdx.x * kT + threadIdx.x; q < n; q += gridDim.x * kT) {
+    if (!U.ut_hit[q]) continue;
+    const uint32_t i = U.ut_idx[q];
+    const uint8_t f = U.flags[i];
+    U.flags[i] = f | ODP_F_UT;
+    if (!(f & (ODP_F_DD | ODP_F_RT_RX))) {
+      const odp_event& e = U.ev[i];
+      t_el += e.t_end - e.t_start;
+    }
+  }
+  block_add(&U.ctl->elim_ut, t_el);
+}
+
+// The optimization-potential estimate (Sec. 7.6): the run's time is the span
+// of the valid records; removing the flagged mappings would save elim_ns.
+__device__ void write_estimate(odp_report* rep, bool any_valid, uint64_t t_min, uint64_t t_max, uint64_t elim) {
+  const uint64_t span = any_valid ? t_max - t_min : 0;
+  rep->span_ns = span;
+  rep->elim_ns = elim;
+  rep->predicted_speedup = span == 0 ? 1.0 : elim >= span ? (double)INFINITY : (double)span / (double)(span - elim);
 }
 
 __global__ void finalize_kernel(AnaCtl* ctl, odp_report* rep) {
@@ -1798,6 +1962,8 @@ __global__ void finalize_kernel(AnaCtl* ctl, odp_report* rep) {
   rep->ra_members = rep->ra_events + rep->ra_groups;
   rep->first_bad_event = ctl->first_bad;
   rep->status = ctl->first_bad != kNone ? 1 : 0;
+  write_estimate(rep, rep->n_events > rep->n_invalid, ctl->t_min, ctl->t_max,
+                 ctl->elim_tx + ctl->elim_pairs + ctl->elim_ut);
 }
 
 // ---------------------------------------------------------------------------
@@ -1805,10 +1971,12 @@ __global__ void finalize_kernel(AnaCtl* ctl, odp_report* rep) {
 // ---------------------------------------------------------------------------
 enum Buf {
   B_CTL, B_JOBS, B_CLS, B_AUX, B_BKEY0, B_BKEY1, B_BVAL0, B_BVAL1, B_TILECNT, B_AD, B_K, B_PR, B_HIST,
-  B_TOTALS, B_SEG, B_SKEY, B_PARTS
+  B_TOTALS, B_SEG, B_SKEY, B_PARTS, B_UT
 };
 
-constexpr int kJobBig = 0, kJobAd = 1, kJobKs = 2, kJobKe = 3, kJobPr = 4, kNumJobs = 5;
+// Jobs 1..4 (the subsets) are sorted together in the same launches.
+constexpr int kJobBig = 0, kJobAd = 1, kJobKs = 2, kJobKe = 3, kJobUt = 4, kJobPr = 5, kNumJobs = 6;
+constexpr int kSubsetJobs = 4;
 
 template <typename T>
 T* carve(char*& p, size_t count) {
@@ -1834,13 +2002,17 @@ struct Views {
   uint32_t* ad_vals1;
   uint32_t* k_vals_s1;
   uint32_t* k_vals_e1;
+  uint64_t* starts_sorted;
+  uint64_t* ends_sorted;
+  uint32_t* ut_vals1;
+  uint8_t* ut_hit;
   uint32_t *pr_alloc, *pr_del, *pr_vals, *pr_vals1;
   uint64_t *pr_w_bytes, *pr_w_dev, *pr_w_haddr;
   uint32_t* hist;
   uint32_t* totals;
   WaveAgg* agg;    // per wavefront of the digest job
   WaveAgg* carry;
-  unsigned long long* skey[8];  // key ping-pong of the four subset jobs
+  unsigned long long* skey[2 * (kNumJobs - 1)];  // key ping-pong of the subset and pair jobs
   Parts parts;                  // per-block partials of the grid-wide reductions
 };
 
@@ -1858,7 +2030,7 @@ Views views(Workspace* ws) {
   v.bv[0] = static_cast<uint32_t*>(b[B_BVAL0].ptr);
   v.bv[1] = static_cast<uint32_t*>(b[B_BVAL1].ptr);
   v.tile_cnt = static_cast<uint32_t*>(b[B_TILECNT].ptr);
-  v.wave_cnt = v.tile_cnt + 2 * (size_t)v.ntc;
+  v.wave_cnt = v.tile_cnt + 2 * (size_t)v.ntc;  // 3 counters per wavefront
   const size_t cap = v.cap;
   char* pa = static_cast<char*>(b[B_AD].ptr);
   v.S.ad_idx = carve<uint32_t>(pa, cap);
@@ -1877,6 +2049,16 @@ Views views(Workspace* ws) {
   v.k_vals_s1 = carve<uint32_t>(pk, cap);
   v.S.k_vals_e = carve<uint32_t>(pk, cap);
   v.k_vals_e1 = carve<uint32_t>(pk, cap);
+  v.starts_sorted = carve<uint64_t>(pk, cap);
+  v.ends_sorted = carve<uint64_t>(pk, cap);
+  char* pu = static_cast<char*>(b[B_UT].ptr);
+  v.S.ut_idx = carve<uint32_t>(pu, cap);
+  v.S.ut_w_addr = carve<uint64_t>(pu, cap);
+  v.S.ut_w_code = carve<uint64_t>(pu, cap);
+  v.S.ut_ts = carve<uint64_t>(pu, cap);
+  v.S.ut_vals = carve<uint32_t>(pu, cap);
+  v.ut_vals1 = carve<uint32_t>(pu, cap);
+  v.ut_hit = carve<uint8_t>(pu, cap);
   char* pp = static_cast<char*>(b[B_PR].ptr);
   v.pr_alloc = carve<uint32_t>(pp, cap);
   v.pr_del = carve<uint32_t>(pp, cap);
@@ -1891,7 +2073,7 @@ Views views(Workspace* ws) {
   v.agg = carve<WaveAgg>(ps, (size_t)v.ntc * (kT / 64));
   v.carry = carve<WaveAgg>(ps, (size_t)v.ntc * (kT / 64));
   char* pkey = static_cast<char*>(b[B_SKEY].ptr);
-  for (int i = 0; i < 8; ++i) v.skey[i] = carve<unsigned long long>(pkey, cap);
+  for (int i = 0; i < 2 * (kNumJobs - 1); ++i) v.skey[i] = carve<unsigned long long>(pkey, cap);
   v.parts.p = static_cast<unsigned long long*>(b[B_PARTS].ptr);
   v.parts.stride = v.ntc;
   return v;
@@ -1944,6 +2126,17 @@ void build_jobs(const Views& v, SortJob* hj) {
   hj[kJobKe].vals[1] = v.k_vals_e1;
   hj[kJobKe].words[0] = v.S.k_w_end;
   hj[kJobKe].masks[0] = &ctl->m_k_end;
+  // copy-ins by (endpoint code, source address): each group in log order
+  hj[kJobUt].n_ptr = &ctl->n_ut;
+  hj[kJobUt].vals[0] = v.S.ut_vals;
+  hj[kJobUt].vals[1] = v.ut_vals1;
+  hj[kJobUt].words[0] = v.S.ut_w_addr;
+  hj[kJobUt].masks[0] = &ctl->m_ut_addr;
+  hj[kJobUt].word_bytes[0] = 8;
+  hj[kJobUt].words[1] = v.S.ut_w_code;
+  hj[kJobUt].masks[1] = &ctl->m_ut_code;
+  hj[kJobUt].word_bytes[1] = 1;
+  hj[kJobUt].nwords = 2;
   // paired allocations by (host address, device, bytes)
   hj[kJobPr].n_ptr = &ctl->n_pairs;
   hj[kJobPr].vals[0] = v.pr_vals;
@@ -1980,14 +2173,15 @@ int analyze_reserve(Workspace* ws, size_t max_events) {
   if ((e = b[B_CTL].ensure(sizeof(AnaCtl))) || (e = b[B_JOBS].ensure(sizeof(SortJob) * kNumJobs)) ||
       (e = b[B_CLS].ensure(cap)) || (e = b[B_AUX].ensure(cap)) || (e = b[B_BKEY0].ensure(cap * 8)) ||
       (e = b[B_BKEY1].ensure(cap * 8)) || (e = b[B_BVAL0].ensure(cap * 4)) || (e = b[B_BVAL1].ensure(cap * 4)) ||
-      (e = b[B_TILECNT].ensure((size_t)nt * 8 * (1 + kT / 64))) ||
+      (e = b[B_TILECNT].ensure((size_t)nt * 4 * (2 + 3 * (kT / 64)))) ||
       (e = b[B_AD].ensure(cap * (4 + 8 + 8 + 4 + 4 + 4 + 1) + 64)) ||
-      (e = b[B_K].ensure(cap * (4 + 8 + 8 + 8 + 4 * 4) + 64)) ||
+      (e = b[B_K].ensure(cap * (4 + 8 + 8 + 8 + 4 * 4 + 8 + 8) + 64)) ||
+      (e = b[B_UT].ensure(cap * (4 + 8 + 8 + 8 + 4 + 4 + 1) + 64)) ||
       (e = b[B_PR].ensure(cap * (4 + 4 + 8 + 8 + 8 + 4 + 4) + 64)) ||
       (e = b[B_HIST].ensure((size_t)kNumJobs * 256 * nt * 4)) ||
       (e = b[B_TOTALS].ensure((size_t)kNumJobs * kMaxPasses * 256 * 4)) ||
       (e = b[B_SEG].ensure((size_t)nt * (kT / 64) * 2 * sizeof(WaveAgg) + 64)) ||
-      (e = b[B_SKEY].ensure(cap * 8 * 8 + 64)) || (e = b[B_PARTS].ensure((size_t)kSlots * nt * 8)))
+      (e = b[B_SKEY].ensure(cap * 8 * 2 * (kNumJobs - 1) + 64)) || (e = b[B_PARTS].ensure((size_t)kSlots * nt * 8)))
     return e;
   if (!ws->a_side) {
     ODP_HIP(hipStreamCreateWithFlags(&ws->a_side, hipStreamNonBlocking));
@@ -2032,13 +2226,21 @@ struct TinyLds {
   int8_t src[kTinyMax], dst[kTinyMax];
   uint8_t op[kTinyMax], cls[kTinyMax], paired[kTinyMax];
   uint32_t wcnt[kTinyMax / 64][3];
-  unsigned long long acc[kTinyMax / 64][24];
+  unsigned long long acc[kTinyMax / 64][32];
 };
 
 enum TinyAcc {
   TA_INV, TA_TX, TA_K, TA_PAIRS, TA_UNP_A, TA_UNP_D, TA_DD, TA_DD_GRP, TA_DD_B, TA_DD_T, TA_RT_TX, TA_RT_RX, TA_RT_B,
-  TA_RT_T, TA_RA, TA_RA_GRP, TA_RA_B, TA_RA_T, TA_UA, TA_UA_B, TA_UA_T, TA_BAD, TA_COUNT
+  TA_RT_T, TA_RA, TA_RA_GRP, TA_RA_B, TA_RA_T, TA_UA, TA_UA_B, TA_UA_T, TA_UT, TA_UT_B, TA_UT_T, TA_ELIM, TA_TMIN,
+  TA_TMAX, TA_BAD, TA_COUNT
 };
+static_assert(TA_COUNT <= 32, "tiny accumulators");
+
+// The workgroup reduction of each accumulator: the first rejected record and
+// the earliest start take the minimum, the latest end the maximum, the rest sum.
+__device__ __forceinline__ unsigned long long tiny_red(int k, unsigned long long a, unsigned long long b) {
+  return (k == TA_BAD || k == TA_TMIN) ? min(a, b) : k == TA_TMAX ? max(a, b) : a + b;
+}
 
 __global__ __launch_bounds__(kTinyMax) void analyze_tiny_kernel(const odp_event* __restrict__ ev, uint32_t n,
                                                                uint8_t* __restrict__ flags, odp_report* __restrict__ rep) {
@@ -2094,6 +2296,8 @@ __global__ __launch_bounds__(kTinyMax) void analyze_tiny_kernel(const odp_event*
 #pragma unroll
   for (int k = 0; k < TA_COUNT; ++k) a[k] = 0;
   a[TA_BAD] = in && c == C_INVALID ? i : kNone;
+  a[TA_TMIN] = in && c != C_INVALID ? L.ts[i] : ~0ull;
+  a[TA_TMAX] = in && c != C_INVALID ? L.te[i] : 0ull;
   a[TA_INV] = in && c == C_INVALID;
   a[TA_TX] = c == C_TRANSFER;
   a[TA_K] = c == C_KERNEL;
@@ -2136,6 +2340,36 @@ __global__ __launch_bounds__(kTinyMax) void analyze_tiny_kernel(const odp_event*
       a[TA_RT_B] = b;
       a[TA_RT_T] = d;
     }
+    // unused transfer: a copy into device memory that no kernel on the device
+    // meets between its start and the start of the next copy to the same
+    // (receiver, sender, source address)
+    if (L.op[i] != ODP_D2H && ds >= 0) {
+      const unsigned long long sa = L.saddr[i];
+      unsigned long long hi = ~0ull;
+      bool found = false;
+#pragma unroll 4
+      for (uint32_t q = 0; q < cnt[0]; ++q) {
+        const uint32_t j = L.list[0][q];
+        if (!found && j > i && L.op[j] != ODP_D2H && L.dst[j] == ds && L.src[j] == sr && L.saddr[j] == sa) {
+          hi = L.ts[j];
+          found = true;
+        }
+      }
+      const unsigned long long lo = L.ts[i];
+      bool read = false;
+#pragma unroll 4
+      for (uint32_t q = 0; q < cnt[2]; ++q) {
+        const uint32_t k = L.list[2][q];
+        read |= L.dst[k] == ds && L.ts[k] <= hi && L.te[k] >= lo;
+      }
+      if (!read) {
+        f |= ODP_F_UT;
+        a[TA_UT] = 1;
+        a[TA_UT_B] = b;
+        a[TA_UT_T] = d;
+      }
+    }
+    if (f & (ODP_F_DD | ODP_F_RT_RX | ODP_F_UT)) a[TA_ELIM] = d;
   }
   // pairing: a DELETE pairs with the record just before it in its (device,
   // device address) group when that record is an ALLOC
@@ -2202,6 +2436,7 @@ __global__ __launch_bounds__(kTinyMax) void analyze_tiny_kernel(const odp_event*
       a[TA_UA_B] = b;
       a[TA_UA_T] = d;
     }
+    if (ra || !used) a[TA_ELIM] = d;
   }
   if (in) flags[i] = f;
   // the report: sums (the first rejected record: minimum) over the workgroup
@@ -2209,17 +2444,14 @@ __global__ __launch_bounds__(kTinyMax) void analyze_tiny_kernel(const odp_event*
   for (int k = 0; k < TA_COUNT; ++k) {
     unsigned long long v = a[k];
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-      const unsigned long long y = __shfl_xor(v, o, 64);
-      v = k == TA_BAD ? min(v, y) : v + y;
-    }
+    for (int o = 32; o >= 1; o >>= 1) v = tiny_red(k, v, __shfl_xor(v, o, 64));
     if (lane == 0) L.acc[w][k] = v;
   }
   __syncthreads();
   if (i < TA_COUNT) {  // one thread per field folds the wavefronts' partials
-    unsigned long long v = i == TA_BAD ? (unsigned long long)kNone : 0ull;
+    unsigned long long v = L.acc[0][i];
 #pragma unroll
-    for (int x = 0; x < (int)(kTinyMax / 64); ++x) v = i == TA_BAD ? min(v, L.acc[x][i]) : v + L.acc[x][i];
+    for (int x = 1; x < (int)(kTinyMax / 64); ++x) v = tiny_red((int)i, v, L.acc[x][i]);
     L.acc[0][i] = v;
   }
   __syncthreads();
@@ -2249,6 +2481,10 @@ __global__ __launch_bounds__(kTinyMax) void analyze_tiny_kernel(const odp_event*
     rep->ua_events = t[TA_UA];
     rep->ua_bytes = t[TA_UA_B];
     rep->ua_time_ns = t[TA_UA_T];
+    rep->ut_events = t[TA_UT];
+    rep->ut_bytes = t[TA_UT_B];
+    rep->ut_time_ns = t[TA_UT_T];
+    write_estimate(rep, t[TA_INV] < n, t[TA_TMIN], t[TA_TMAX], t[TA_ELIM]);
     rep->first_bad_event = (uint32_t)t[TA_BAD];
     rep->status = t[TA_BAD] != kNone ? 1 : 0;
   }
@@ -2367,16 +2603,17 @@ extern "C" int odp_analyze_trace(const odp_event* events, size_t n, uint8_t* out
 
   // The allocation path on the side stream (enqueued after the digest path,
   // whose chain is the longer one, so that one starts first).
-  hipLaunchKernelGGL(scan_pairs_kernel, dim3(1), dim3(1024), 0, side, v.wave_cnt, nt * (kT / 64), &ctl->n_ad,
-                     &ctl->n_k);
+  hipLaunchKernelGGL(scan_counts_kernel<3>, dim3(1), dim3(1024), 0, side, v.wave_cnt, nt * (kT / 64), &ctl->n_ad,
+                     &ctl->n_k, &ctl->n_ut);
   hipLaunchKernelGGL(subset_scatter_kernel, dim3(nt), dim3(kT), 0, side, events, v.cls, nn, v.wave_cnt, v.S, v.parts);
   hipLaunchKernelGGL(reduce_parts_kernel, dim3(S_DD_EVENTS - S_AD_DEV_OR), dim3(kT), 0, side, v.parts, nt,
                      (uint32_t)S_AD_DEV_OR, ctl, out_report);
-  // ALLOC/DELETE by (device, address), kernels by (device, start) and (device, end)
-  // The subsets are usually far smaller than the log: a capped number of
-  // blocks per job loops over its tiles instead of a block per log tile.
+  // ALLOC/DELETE by (device, address), kernels by (device, start) and (device,
+  // end), copy-ins by (endpoints, source address). The subsets are usually
+  // far smaller than the log: a capped number of blocks per job loops over
+  // its tiles instead of a block per log tile.
   const uint32_t side_blocks = std::min<uint32_t>(nt, (uint32_t)cus * 2);
-  const JobSet Js{v.jobs + kJobAd, 3, side_blocks};
+  const JobSet Js{v.jobs + kJobAd, kSubsetJobs, side_blocks};
   hipLaunchKernelGGL(sort_plan_kernel, dim3(1), dim3(64), 0, side, Js, 0u);
   if (small) {
     hipLaunchKernelGGL(sort_small_kernel, dim3(Js.njobs), dim3(kQT), 0, side, Js);
@@ -2409,10 +2646,27 @@ extern "C" int odp_analyze_trace(const odp_event* events, size_t n, uint8_t* out
   P.rep = out_report;
   hipLaunchKernelGGL(pair_kernel, dim3(grid_map), dim3(kT), 0, side, P);
   hipLaunchKernelGGL(pair_count_kernel, dim3(nt), dim3(kT), 0, side, P);
-  hipLaunchKernelGGL(scan_pairs_kernel, dim3(1), dim3(1024), 0, side, v.tile_cnt, nt, &ctl->n_pairs, nullptr);
+  hipLaunchKernelGGL(scan_counts_kernel<2>, dim3(1), dim3(1024), 0, side, v.tile_cnt, nt, &ctl->n_pairs, nullptr,
+                     nullptr);
   hipLaunchKernelGGL(pair_scatter_kernel, dim3(nt), dim3(kT), 0, side, P);
-  hipLaunchKernelGGL(kernel_ranges_kernel, dim3(grid_map), dim3(kT), 0, side, v.jobs + kJobKs, v.S.k_w_dev,
-                     &ctl->n_k, ctl);
+  hipLaunchKernelGGL(kernel_ranges_kernel, dim3(grid_map), dim3(kT), 0, side, v.jobs + kJobKs, v.jobs + kJobKe,
+                     v.S.k_w_dev, v.S.k_w_start, v.S.k_w_end, &ctl->n_k, v.starts_sorted, v.ends_sorted, ctl);
+  // Unused transfers (their flags are merged after the join).
+  UtArgs U;
+  U.ev = events;
+  U.ut_job = v.jobs + kJobUt;
+  U.n_ut = &ctl->n_ut;
+  U.ut_idx = v.S.ut_idx;
+  U.ut_w_addr = v.S.ut_w_addr;
+  U.ut_w_code = v.S.ut_w_code;
+  U.ut_ts = v.S.ut_ts;
+  U.starts_sorted = v.starts_sorted;
+  U.ends_sorted = v.ends_sorted;
+  U.ut_hit = v.ut_hit;
+  U.ctl = ctl;
+  U.flags = out_flags;
+  U.rep = out_report;
+  hipLaunchKernelGGL(ut_kernel, dim3(grid_map), dim3(kT), 0, side, U);
 
   // Second sort: pairs by (host address, device, bytes).
   const JobSet J2{v.jobs + kJobPr, 1, side_blocks};
@@ -2430,8 +2684,8 @@ extern "C" int odp_analyze_trace(const odp_event* events, size_t n, uint8_t* out
   RaArgs R;
   R.ev = events;
   R.pr_job = v.jobs + kJobPr;
-  R.ks_job = v.jobs + kJobKs;
-  R.ke_job = v.jobs + kJobKe;
+  R.starts_sorted = v.starts_sorted;
+  R.ends_sorted = v.ends_sorted;
   R.n_pairs = &ctl->n_pairs;
   R.pr_alloc = v.pr_alloc;
   R.pr_del = v.pr_del;
@@ -2439,8 +2693,6 @@ extern "C" int odp_analyze_trace(const odp_event* events, size_t n, uint8_t* out
   R.pr_w_bytes = v.pr_w_bytes;
   R.pr_w_dev = v.pr_w_dev;
   R.pr_w_haddr = v.pr_w_haddr;
-  R.k_w_start = v.S.k_w_start;
-  R.k_w_end = v.S.k_w_end;
   R.ctl = ctl;
   R.flags = out_flags;
   R.rep = out_report;
@@ -2448,6 +2700,7 @@ extern "C" int odp_analyze_trace(const odp_event* events, size_t n, uint8_t* out
   ODP_HIP(hipEventRecord(ws->a_join, side));
 
   ODP_HIP(hipStreamWaitEvent(stream, ws->a_join, 0));
+  hipLaunchKernelGGL(ut_merge_kernel, dim3(grid_map), dim3(kT), 0, stream, U);
   hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(64), 0, stream, ctl, out_report);
   return check_hip(hipGetLastError(), "odp_analyze_trace launch");
 }

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libodp.so")
 
 ODP_OK, ODP_EINVAL, ODP_ERANGE, ODP_ENOMEM, ODP_EHIP, ODP_ECAPACITY = 0, -1, -2, -3, -4, -5
-F_DD, F_RT_TX, F_RT_RX, F_RA, F_UA, F_PAIRED, F_INVALID = 1, 2, 4, 8, 16, 32, 128
+F_DD, F_RT_TX, F_RT_RX, F_RA, F_UA, F_PAIRED, F_UT, F_INVALID = 1, 2, 4, 8, 16, 32, 64, 128
 
 REPORT_FIELDS = [
     "n_events", "n_invalid", "n_transfers", "n_kernels",
@@ -23,8 +23,10 @@ REPORT_FIELDS = [
     "rt_pairs", "rt_rx_events", "rt_bytes", "rt_time_ns",
     "ra_events", "ra_groups", "ra_members", "ra_bytes", "ra_time_ns",
     "ua_events", "ua_bytes", "ua_time_ns",
+    "ut_events", "ut_bytes", "ut_time_ns",
+    "span_ns", "elim_ns",
 ]
-REPORT_BYTES = 8 * len(REPORT_FIELDS) + 8
+REPORT_BYTES = 8 * len(REPORT_FIELDS) + 16  # + predicted_speedup (double), status, first_bad_event
 
 EXPORTS = [
     "odp_digest_buffers", "odp_digest_buffers_plain", "odp_analyze_trace", "odp_version",
@@ -156,8 +158,9 @@ def report_to_dict(buf):
     vals = raw[:8 * len(REPORT_FIELDS)].view(np.uint64)
     d = {f: int(v) for f, v in zip(REPORT_FIELDS, vals)}
     tail = raw[8 * len(REPORT_FIELDS):]
-    d["status"] = int(tail[:4].view(np.int32)[0])
-    d["first_bad_event"] = int(tail[4:8].view(np.uint32)[0])
+    d["predicted_speedup"] = float(tail[:8].view(np.float64)[0])
+    d["status"] = int(tail[8:12].view(np.int32)[0])
+    d["first_bad_event"] = int(tail[12:16].view(np.uint32)[0])
     return d
 
 
