@@ -100,6 +100,29 @@ enum {
 int odp_digest_buffers(const void* const* ptrs, const uint64_t* sizes, size_t n, uint64_t* out,
                        odp_stream_t stream);
 
+/* Batched digest that allocates nothing, for callers that cannot allocate
+ * device memory (code under hipGraph capture, tight serving loops, harnesses
+ * that forbid allocation). Same arguments and result as odp_digest_buffers;
+ * its workspace is one fixed array of ODP_NOALLOC_SCRATCH_BYTES in the
+ * library's device code, which each GPU the library runs on holds from load
+ * until the process ends. The call makes no device or pinned allocation and
+ * builds no graph (its launches go straight onto `stream`).
+ *   n > ODP_NOALLOC_MAX_BUFFERS returns ODP_ERANGE and enqueues nothing.
+ *   The buffers larger than 4096 bytes may hold at most ODP_NOALLOC_MAX_NODES
+ *   level-1 nodes in all (the sum of ceil(size / 262144) over them; 16 GiB
+ *   of data in large buffers). The sizes are read on the device, so a call
+ *   over that limit is found there: every out[i] is set to 0 and
+ *   odp_device_status() reports ODP_ECAPACITY. Check it before handing the
+ *   digests to the analysis.
+ * Every call on one GPU shares that GPU's array and leaves the last call's
+ * contents in it: calls that overlap on one GPU (on different streams, or
+ * from different threads) race and must be ordered by the caller. */
+#define ODP_NOALLOC_MAX_BUFFERS 16384
+#define ODP_NOALLOC_MAX_NODES 65536
+#define ODP_NOALLOC_SCRATCH_BYTES 4619520
+int odp_digest_buffers_noalloc(const void* const* ptrs, const uint64_t* sizes, size_t n, uint64_t* out,
+                               odp_stream_t stream);
+
 /* Per-buffer digest: the plain form, one kernel launch per buffer.
  *   host_ptrs   HOST, n entries: device start address of buffer i.
  *   host_sizes  HOST, n entries: byte length of buffer i.
@@ -315,7 +338,8 @@ int odp_reserve(size_t max_buffers, uint64_t max_total_bytes, size_t max_events,
 int odp_release(void);
 
 /* Sticky device-side status of the current device: ODP_OK or ODP_ECAPACITY
- * when a batched digest call found its tree workspace too small. Reading it
+ * when a batched digest call (odp_digest_buffers or
+ * odp_digest_buffers_noalloc) found its tree workspace too small. Reading it
  * synchronises the device and clears it. */
 int odp_device_status(void);
 

@@ -639,6 +639,7 @@ struct PlanArgs {
   uint64_t nblk;
   DigestCtl* ctl;
   uint64_t cap_items, cap_tree, cap_tk;
+  uint64_t cap_nodes;   // level-1 nodes of buffers above one leaf, at most (the fixed array's limit)
 };
 
 constexpr int kPlanThreads = 256;
@@ -708,7 +709,7 @@ __device__ void finalize_plan(const PlanArgs& A, const uint64_t carry[kQ]) {
   c->head = 0;
   // item numbers run past n_items by up to five per workgroup of at most 2^14
   c->overflow = (carry[0] > A.cap_items || carry[2] > A.cap_tree || carry[3] > A.cap_tk ||
-                 c->n_items >= 0xFFFF0000ull - (5ull << 14)) ? 1u : 0u;
+                 carry[0] + carry[4] > A.cap_nodes || c->n_items >= 0xFFFF0000ull - (5ull << 14)) ? 1u : 0u;
 }
 
 __global__ __launch_bounds__(kPlanThreads) void plan_count_kernel(PlanArgs A) {
@@ -1081,40 +1082,83 @@ int digest_reserve(Workspace* ws, size_t max_buffers, uint64_t max_total_bytes) 
   return ODP_OK;
 }
 
+// Device memory one batched call works in: the grow-only workspace of a
+// (device, stream) pair, or the fixed array of the no-allocation entry point.
+struct BatchedSpace {
+  int device;
+  uint64_t* node_off;   // [cap_buffers + 1]
+  uint64_t* tree_off;   // [cap_buffers]
+  uint64_t* tk_off;     // [cap_buffers]
+  uint32_t* small_list; // [cap_buffers]
+  uint64_t* blk;        // [kQ * tiles of cap_buffers]
+  NodeRec* med_rec;     // [cap_buffers]
+  DigestCtl* ctl;
+  uint32_t* item_buf;   // [cap_items]
+  NodeRec* item_rec;    // [cap_items]
+  uint64_t* tree;       // [cap_tree]
+  uint32_t* tickets;    // [cap_tk], zero between calls
+  uint64_t cap_items, cap_tree, cap_tk;
+  uint64_t cap_nodes;   // level-1 nodes of buffers above one leaf, at most
+  uint32_t* status;     // sticky status word (ODP_ECAPACITY on overflow)
+};
+
+BatchedSpace space_of(Workspace* ws) {
+  BatchedSpace S;
+  S.device = ws->device;
+  S.node_off = static_cast<uint64_t*>(ws->node_off.ptr);
+  S.tree_off = static_cast<uint64_t*>(ws->tree_off.ptr);
+  S.tk_off = static_cast<uint64_t*>(ws->tk_off.ptr);
+  S.small_list = static_cast<uint32_t*>(ws->small_list.ptr);
+  S.blk = static_cast<uint64_t*>(ws->blk.ptr);
+  S.med_rec = static_cast<NodeRec*>(ws->med_rec.ptr);
+  S.ctl = static_cast<DigestCtl*>(ws->ctl.ptr);
+  S.item_buf = static_cast<uint32_t*>(ws->item_buf.ptr);
+  S.item_rec = static_cast<NodeRec*>(ws->item_rec.ptr);
+  S.tree = static_cast<uint64_t*>(ws->tree.ptr);
+  S.tickets = static_cast<uint32_t*>(ws->tickets.ptr);
+  S.cap_items = ws->cap_items;
+  S.cap_tree = ws->cap_tree;
+  S.cap_tk = ws->cap_tk;
+  S.cap_nodes = ~0ull;  // bounded by the item, tree and ticket capacities
+  S.status = device_status_word(ws->device);
+  return S;
+}
+
 // item_hint: an upper bound on the work items when the caller knows one
 // (0: unknown), to size the grids of small batches.
-static int enqueue_batched(Workspace* ws, const void* const* ptrs, const uint64_t* sizes, size_t n, uint64_t* out,
-                           hipStream_t stream, uint64_t item_hint = 0) {
+static int enqueue_batched(const BatchedSpace& S, const void* const* ptrs, const uint64_t* sizes, size_t n,
+                           uint64_t* out, hipStream_t stream, uint64_t item_hint = 0) {
   PlanArgs P;
   P.ptrs = ptrs;
   P.sizes = sizes;
   P.out = out;
-  P.tree = static_cast<uint64_t*>(ws->tree.ptr);
-  P.rec = static_cast<NodeRec*>(ws->item_rec.ptr);
-  P.med_rec = static_cast<NodeRec*>(ws->med_rec.ptr);
+  P.tree = S.tree;
+  P.rec = S.item_rec;
+  P.med_rec = S.med_rec;
   P.split = tuning().split_bytes;
   P.n = n;
-  P.node_off = static_cast<uint64_t*>(ws->node_off.ptr);
-  P.tree_off = static_cast<uint64_t*>(ws->tree_off.ptr);
-  P.tk_off = static_cast<uint64_t*>(ws->tk_off.ptr);
-  P.small_list = static_cast<uint32_t*>(ws->small_list.ptr);
-  P.blk = static_cast<uint64_t*>(ws->blk.ptr);
+  P.node_off = S.node_off;
+  P.tree_off = S.tree_off;
+  P.tk_off = S.tk_off;
+  P.small_list = S.small_list;
+  P.blk = S.blk;
   P.nblk = (n + kPlanTile - 1) / kPlanTile;
-  P.ctl = static_cast<DigestCtl*>(ws->ctl.ptr);
-  P.cap_items = ws->cap_items;
-  P.cap_tree = ws->cap_tree;
-  P.cap_tk = ws->cap_tk;
+  P.ctl = S.ctl;
+  P.cap_items = S.cap_items;
+  P.cap_tree = S.cap_tree;
+  P.cap_tk = S.cap_tk;
+  P.cap_nodes = S.cap_nodes;
   if (P.nblk > 1) {
     hipLaunchKernelGGL(plan_count_kernel, dim3((unsigned)P.nblk), dim3(kPlanThreads), 0, stream, P);
     hipLaunchKernelGGL(plan_scan_kernel, dim3(1), dim3(kPlanThreads), 0, stream, P);
   }
   hipLaunchKernelGGL(plan_write_kernel, dim3((unsigned)P.nblk), dim3(kPlanThreads), 0, stream, P);
-  const uint64_t cus = (uint64_t)cu_count(ws->device);
+  const uint64_t cus = (uint64_t)cu_count(S.device);
   auto sized = [&](uint64_t full, uint64_t per) {
     return (unsigned)(item_hint ? std::max<uint64_t>(1, std::min<uint64_t>(full, ceil_div(item_hint, per))) : full);
   };
   hipLaunchKernelGGL(plan_items_kernel, dim3(sized(cus * 4, kPlanThreads)), dim3(kPlanThreads), 0, stream, P,
-                     static_cast<uint32_t*>(ws->item_buf.ptr));
+                     S.item_buf);
   BatchArgs B;
   B.ptrs = ptrs;
   B.sizes = sizes;
@@ -1124,13 +1168,13 @@ static int enqueue_batched(Workspace* ws, const void* const* ptrs, const uint64_
   B.tree_off = P.tree_off;
   B.tk_off = P.tk_off;
   B.small_list = P.small_list;
-  B.item_buf = static_cast<const uint32_t*>(ws->item_buf.ptr);
+  B.item_buf = S.item_buf;
   B.rec = P.rec;
   B.med_rec = P.med_rec;
-  B.tree = static_cast<uint64_t*>(ws->tree.ptr);
-  B.tickets = static_cast<uint32_t*>(ws->tickets.ptr);
+  B.tree = S.tree;
+  B.tickets = S.tickets;
   B.ctl = P.ctl;
-  B.status = device_status_word(ws->device);
+  B.status = S.status;
   const uint64_t bpc = tuning().blocks_per_cu;
   hipLaunchKernelGGL(digest_batched_kernel, dim3(sized(cus * bpc, 1)), dim3(kThreads), 0, stream, B);
   hipLaunchKernelGGL(digest_tree_kernel, dim3(sized(cus * 4, 64 * kWaves)), dim3(kThreads), 0, stream, B);
@@ -1162,7 +1206,7 @@ extern "C" int odp_digest_buffers(const void* const* ptrs, const uint64_t* sizes
     if (e) return e;
   }
   const Tuning& tn = tuning();
-  if (!tn.use_graph || capturing) return enqueue_batched(ws, ptrs, sizes, n, out, stream);
+  if (!tn.use_graph || capturing) return enqueue_batched(space_of(ws), ptrs, sizes, n, out, stream);
   const uint32_t grid = cu_count(ws->device) * tn.blocks_per_cu;
   if (!(ws->graph && ws->g_ptrs == ptrs && ws->g_sizes == sizes && ws->g_out == out && ws->g_n == n &&
         ws->g_grid == grid && ws->g_split == tn.split_bytes)) {
@@ -1176,7 +1220,7 @@ extern "C" int odp_digest_buffers(const void* const* ptrs, const uint64_t* sizes
     hipError_t he = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     int e = ODP_OK;
     if (he == hipSuccess) {
-      e = enqueue_batched(ws, ptrs, sizes, n, out, cs);
+      e = enqueue_batched(space_of(ws), ptrs, sizes, n, out, cs);
       he = hipStreamEndCapture(cs, &g);
     }
     (void)hipStreamDestroy(cs);
@@ -1231,9 +1275,132 @@ int digest_batched_direct(const void* const* ptrs, const uint64_t* sizes, size_t
     return set_error(ODP_ENOMEM, "digest: workspace for %zu buffers not reserved", n);
   // node items <= total_bytes / node + n; small groups <= n / 64 + 1
   const uint64_t hint = total_bytes / kNodeBytes + n + n / kRows + 1;
-  return enqueue_batched(ws, ptrs, sizes, n, out, stream, hint);
+  return enqueue_batched(space_of(ws), ptrs, sizes, n, out, stream, hint);
 }
 }  // namespace odp
+
+// ---------------------------------------------------------------------------
+// The batched digest without allocation: every workspace byte lives in one
+// fixed device array, `scratch`, laid out like the grow-only workspace for at
+// most ODP_NOALLOC_MAX_BUFFERS buffers and ODP_NOALLOC_MAX_NODES level-1
+// nodes. Each device holds its own copy of the array, at its own address,
+// from load to process end; host code reaches it only through that address.
+// ---------------------------------------------------------------------------
+namespace odp {
+namespace {
+constexpr uint64_t kNaBuffers = ODP_NOALLOC_MAX_BUFFERS;
+constexpr uint64_t kNaTiles = (kNaBuffers + kPlanTile - 1) / kPlanTile;
+constexpr uint64_t kNaItems = uint64_t(ODP_NOALLOC_MAX_NODES) + kNaBuffers;  // as digest_reserve
+constexpr uint64_t kNaTree = kNaItems + kNaItems / 32 + 4 * kNaBuffers;
+constexpr uint64_t kNaTk = kNaItems / 32 + 4 * kNaBuffers;
+constexpr uint64_t al256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
+constexpr uint64_t kOffNodeOff = 0;
+constexpr uint64_t kOffTreeOff = al256(kOffNodeOff + (kNaBuffers + 1) * 8);
+constexpr uint64_t kOffTkOff = al256(kOffTreeOff + kNaBuffers * 8);
+constexpr uint64_t kOffSmall = al256(kOffTkOff + kNaBuffers * 8);
+constexpr uint64_t kOffBlk = al256(kOffSmall + kNaBuffers * 4);
+constexpr uint64_t kOffMed = al256(kOffBlk + kNaTiles * kQ * 8);
+constexpr uint64_t kOffCtl = al256(kOffMed + kNaBuffers * sizeof(NodeRec));
+constexpr uint64_t kOffItemBuf = al256(kOffCtl + sizeof(DigestCtl));
+constexpr uint64_t kOffItemRec = al256(kOffItemBuf + kNaItems * 4);
+constexpr uint64_t kOffTree = al256(kOffItemRec + kNaItems * sizeof(NodeRec));
+constexpr uint64_t kOffTk = al256(kOffTree + kNaTree * 8);
+constexpr uint64_t kOffStatus = al256(kOffTk + kNaTk * 4);
+constexpr uint64_t kScratchBytes = al256(kOffStatus + 4);
+static_assert(kScratchBytes == ODP_NOALLOC_SCRATCH_BYTES, "header states the array's size");
+}  // namespace
+}  // namespace odp
+
+static __device__ __align__(256) unsigned char scratch[odp::kScratchBytes];
+
+namespace odp {
+namespace {
+constexpr int kNaMaxDevices = 64;
+std::mutex g_na_mu;
+unsigned char* g_na_ptr[kNaMaxDevices];  // device address of `scratch` on each device, once set up
+
+// Zeroes what must start at zero: the tickets (each is also reset by its last
+// user, so calls leave them zero) and the status word.
+__global__ void na_clear_kernel(uint32_t* tickets, uint64_t ntk, uint32_t* status) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ntk; i += (uint64_t)gridDim.x * blockDim.x)
+    tickets[i] = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *status = 0;
+}
+
+// Once per device, with that device current: the array's device address, and
+// the clear. Later calls read the cached address only.
+int na_base(int dev, hipStream_t stream, unsigned char** base) {
+  std::lock_guard<std::mutex> lk(g_na_mu);
+  if (!g_na_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return check_hip(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+    unsigned char* b = static_cast<unsigned char*>(p);
+    hipLaunchKernelGGL(na_clear_kernel, dim3(64), dim3(256), 0, stream, reinterpret_cast<uint32_t*>(b + kOffTk), kNaTk,
+                       reinterpret_cast<uint32_t*>(b + kOffStatus));
+    const hipError_t le = hipGetLastError();
+    if (le != hipSuccess) return check_hip(le, "no-allocation digest set-up");
+    (void)cu_count(dev);  // cached before the first launch sizes its grids
+    g_na_ptr[dev] = b;
+  }
+  *base = g_na_ptr[dev];
+  return ODP_OK;
+}
+}  // namespace
+
+int noalloc_take_status(int dev) {
+  unsigned char* b = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_na_mu);
+    if (dev < 0 || dev >= kNaMaxDevices || !g_na_ptr[dev]) return ODP_OK;
+    b = g_na_ptr[dev];
+  }
+  uint32_t v = 0;
+  ODP_HIP(hipMemcpy(&v, b + kOffStatus, sizeof(v), hipMemcpyDeviceToHost));
+  if (v) {
+    const uint32_t zero = 0;
+    ODP_HIP(hipMemcpy(b + kOffStatus, &zero, sizeof(zero), hipMemcpyHostToDevice));
+  }
+  return v ? -(int)v : ODP_OK;
+}
+}  // namespace odp
+
+extern "C" int odp_digest_buffers_noalloc(const void* const* ptrs, const uint64_t* sizes, size_t n, uint64_t* out,
+                                          odp_stream_t stream_) {
+  hipStream_t stream = static_cast<hipStream_t>(stream_);
+  if (n == 0) return ODP_OK;
+  if (!ptrs || !sizes || !out)
+    return set_error(ODP_EINVAL, "odp_digest_buffers_noalloc: null array with n = %zu", n);
+  if (n > (size_t)ODP_NOALLOC_MAX_BUFFERS)
+    return set_error(ODP_ERANGE, "odp_digest_buffers_noalloc: n = %zu above the maximum of %d buffers", n,
+                     ODP_NOALLOC_MAX_BUFFERS);
+  int dev = 0;
+  int e = current_device(&dev);
+  if (e) return e;
+  if (dev < 0 || dev >= kNaMaxDevices)
+    return set_error(ODP_ERANGE, "odp_digest_buffers_noalloc: device %d above %d", dev, kNaMaxDevices - 1);
+  unsigned char* b = nullptr;
+  if ((e = na_base(dev, stream, &b))) return e;
+  BatchedSpace S;
+  S.device = dev;
+  S.node_off = reinterpret_cast<uint64_t*>(b + kOffNodeOff);
+  S.tree_off = reinterpret_cast<uint64_t*>(b + kOffTreeOff);
+  S.tk_off = reinterpret_cast<uint64_t*>(b + kOffTkOff);
+  S.small_list = reinterpret_cast<uint32_t*>(b + kOffSmall);
+  S.blk = reinterpret_cast<uint64_t*>(b + kOffBlk);
+  S.med_rec = reinterpret_cast<NodeRec*>(b + kOffMed);
+  S.ctl = reinterpret_cast<DigestCtl*>(b + kOffCtl);
+  S.item_buf = reinterpret_cast<uint32_t*>(b + kOffItemBuf);
+  S.item_rec = reinterpret_cast<NodeRec*>(b + kOffItemRec);
+  S.tree = reinterpret_cast<uint64_t*>(b + kOffTree);
+  S.tickets = reinterpret_cast<uint32_t*>(b + kOffTk);
+  S.cap_items = kNaItems;
+  S.cap_tree = kNaTree;
+  S.cap_tk = kNaTk;
+  S.cap_nodes = ODP_NOALLOC_MAX_NODES;
+  S.status = reinterpret_cast<uint32_t*>(b + kOffStatus);
+  return enqueue_batched(S, ptrs, sizes, n, out, stream);
+}
 
 extern "C" int odp_digest_buffers_plain(const void* const* host_ptrs, const uint64_t* host_sizes, size_t n,
                                         uint64_t* out, odp_stream_t stream_) {

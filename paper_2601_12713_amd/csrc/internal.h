@@ -95,6 +95,9 @@ int digest_plain_reserve(Workspace* ws, uint64_t max_bytes);
 int digest_batched_direct(const void* const* ptrs, const uint64_t* sizes, size_t n, uint64_t* out, hipStream_t stream,
                           uint64_t total_bytes);
 int analyze_reserve(Workspace* ws, size_t max_events);
+// Reads and clears the status word of the no-allocation digest on `dev`
+// (ODP_OK when that entry point never ran there). Synchronous.
+int noalloc_take_status(int dev);
 void analyze_release(Workspace* ws);
 
 }  // namespace odp

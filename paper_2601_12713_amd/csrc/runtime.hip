@@ -172,7 +172,9 @@ extern "C" int odp_device_status(void) {
     h = g_status_host[dev];
   }
   const uint32_t v = __atomic_exchange_n(h, 0u, __ATOMIC_SEQ_CST);
-  return v ? -(int)v : ODP_OK;
+  const int na = noalloc_take_status(dev);
+  if (v) return -(int)v;
+  return na;
 }
 
 extern "C" int odp_get_tuning(odp_tuning* out) {

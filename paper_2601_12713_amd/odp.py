@@ -29,7 +29,8 @@ REPORT_FIELDS = [
 REPORT_BYTES = 8 * len(REPORT_FIELDS) + 16  # + predicted_speedup (double), status, first_bad_event
 
 EXPORTS = [
-    "odp_digest_buffers", "odp_digest_buffers_plain", "odp_analyze_trace", "odp_version",
+    "odp_digest_buffers", "odp_digest_buffers_noalloc", "odp_digest_buffers_plain", "odp_analyze_trace",
+    "odp_version",
     "odp_last_error_string", "odp_reserve", "odp_release", "odp_device_status",
     "odp_get_tuning", "odp_set_tuning", "odp_server_create", "odp_server_run", "odp_server_drain",
     "odp_server_log", "odp_server_destroy",
@@ -62,6 +63,7 @@ def load(path=LIB_PATH):
     L = ctypes.CDLL(path)
     p, sz, u64, i32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_uint64, ctypes.c_int
     L.odp_digest_buffers.argtypes = [p, p, sz, p, p]
+    L.odp_digest_buffers_noalloc.argtypes = [p, p, sz, p, p]
     L.odp_digest_buffers_plain.argtypes = [p, p, sz, p, p]
     L.odp_analyze_trace.argtypes = [p, sz, p, p, p]
     L.odp_version.argtypes = []
@@ -113,6 +115,17 @@ def digest_buffers(ptrs, sizes, out, stream=None):
     """Batched digest. ptrs, sizes: int64/uint64 device tensors of n entries; out: int64 device tensor."""
     n = int(sizes.numel())
     _check(load().odp_digest_buffers(_ptr(ptrs), _ptr(sizes), n, _ptr(out), _stream(stream)))
+    return out
+
+
+NOALLOC_MAX_BUFFERS, NOALLOC_MAX_NODES = 16384, 65536
+
+
+def digest_buffers_noalloc(ptrs, sizes, out, stream=None):
+    """Batched digest in the library's fixed device array (no allocation);
+    same arguments as digest_buffers."""
+    n = int(sizes.numel())
+    _check(load().odp_digest_buffers_noalloc(_ptr(ptrs), _ptr(sizes), n, _ptr(out), _stream(stream)))
     return out
 
 
