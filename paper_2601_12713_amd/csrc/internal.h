@@ -72,6 +72,9 @@ struct Workspace {
 };
 
 Workspace* workspace_for(hipStream_t stream, int* err);
+// Frees the workspace of (device, stream), if any, after the stream is idle
+// (for owners of a stream that is about to be destroyed).
+void workspace_drop(int device, hipStream_t stream);
 uint32_t* device_status_word(int device);  // device-visible sticky status (host-mapped)
 int current_device(int* dev);
 int cu_count(int device);

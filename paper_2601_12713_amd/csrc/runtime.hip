@@ -136,6 +136,35 @@ extern "C" int odp_reserve(size_t max_buffers, uint64_t max_total_bytes, size_t 
   return ODP_OK;
 }
 
+namespace odp {
+// Frees one workspace (its device must be current and idle for its stream).
+static void free_workspace(Workspace* ws) {
+  if (ws->graph) (void)hipGraphExecDestroy(ws->graph);
+  DevBuf* bufs[] = {&ws->node_off, &ws->tree_off, &ws->tk_off, &ws->small_list, &ws->blk, &ws->ctl,
+                    &ws->item_buf, &ws->item_rec, &ws->med_rec, &ws->tree, &ws->tickets, &ws->p_tree, &ws->p_tickets};
+  for (DevBuf* b : bufs) b->release();
+  analyze_release(ws);
+  delete ws;
+}
+
+void workspace_drop(int device, hipStream_t stream) {
+  Workspace* ws = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_ws.find(std::make_pair(device, stream));
+    if (it == g_ws.end()) return;
+    ws = it->second;
+    g_ws.erase(it);
+  }
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(device);
+  (void)hipStreamSynchronize(stream);
+  free_workspace(ws);
+  (void)hipSetDevice(cur);
+}
+}  // namespace odp
+
 extern "C" int odp_release(void) {
   std::vector<Workspace*> all;
   {
@@ -148,12 +177,7 @@ extern "C" int odp_release(void) {
   for (Workspace* ws : all) {
     (void)hipSetDevice(ws->device);
     (void)hipDeviceSynchronize();
-    if (ws->graph) (void)hipGraphExecDestroy(ws->graph);
-    DevBuf* bufs[] = {&ws->node_off, &ws->tree_off, &ws->tk_off, &ws->small_list, &ws->blk, &ws->ctl,
-                      &ws->item_buf, &ws->item_rec, &ws->med_rec, &ws->tree, &ws->tickets, &ws->p_tree, &ws->p_tickets};
-    for (DevBuf* b : bufs) b->release();
-    analyze_release(ws);
-    delete ws;
+    free_workspace(ws);
   }
   (void)hipSetDevice(cur);
   return ODP_OK;

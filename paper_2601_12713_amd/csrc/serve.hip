@@ -311,7 +311,11 @@ static int server_alloc(odp_server* s) {
 }
 
 static void server_free(odp_server* s) {
-  if (s->stream) (void)hipStreamSynchronize(s->stream);
+  if (s->stream) {
+    (void)hipStreamSynchronize(s->stream);
+    // the digest and analysis workspace the library keeps for this stream
+    workspace_drop(s->device, s->stream);
+  }
   (void)hipFree(s->log);
   (void)hipFree(s->imm);
   for (Table* T : {&s->t_dd, &s->t_rx, &s->t_ad}) (void)hipFree(T->slots);

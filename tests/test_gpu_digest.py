@@ -226,3 +226,26 @@ def test_batched_digest_replayed_from_a_graph(odp):
         torch.cuda.synchronize()
         assert out.cpu().numpy().view(np.uint64).tolist() == want
     assert odp.device_status() == 0
+
+
+def test_batched_capacity_overflow_sets_status(odp):
+    """A workspace reserved for 2,048 buffers and 1 MiB in all (room for
+    2,052 level-1 nodes), then 100 views of one 16 MiB buffer (6,400 nodes)
+    on the same stream: the plan does not fit, every digest of the call is 0
+    and odp_device_status reports ODP_ECAPACITY once (then clears). The next
+    call within the reserve is correct again."""
+    s = torch.cuda.Stream()  # a fresh workspace
+    rng = np.random.default_rng(41)
+    host = [rng.integers(0, 256, size=16 << 20, dtype=np.uint8)] * 100
+    t = [dev_bytes(host[0])] * 100
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        odp.reserve(max_buffers=2048, max_total_bytes=1 << 20, stream=s)
+        got = odp.digest_tensors(t, stream=s)
+    assert (got == 0).all()
+    assert odp.device_status() == odp.ODP_ECAPACITY
+    assert odp.device_status() == odp.ODP_OK
+    with torch.cuda.stream(s):
+        small = odp.digest_tensors(t[:1], stream=s)
+    assert small.tolist() == [oracle.d64(host[0])]
+    assert odp.device_status() == odp.ODP_OK

@@ -155,3 +155,26 @@ def test_serve_rejects_bad_requests(odp):
         odp.Server(max_events=8, budget_bytes=1 << 20, max_tick=2000)
     with pytest.raises(odp.OdpError):
         odp.Server(max_events=0, budget_bytes=1 << 20)
+
+
+def test_servers_release_their_memory(odp, arena):
+    """Creating, running, draining and destroying servers in a loop leaves the
+    device's free memory where it was after the first cycle: a server frees
+    its own buffers and the workspace the library kept for its stream."""
+    a, host = arena
+    sched = W.ServingSchedule(seed=26, n=20_000, rate=2e6, lo=4096, hi=64 << 10, arena=a)
+
+    def cycle():
+        srv = odp.Server(max_events=len(sched.events), budget_bytes=1 << 30)
+        srv.run(sched.events, sched.payload_ptrs(), sched.payload_bytes, sched.arrival_ns)
+        srv.drain()
+        srv.close()
+        torch.cuda.synchronize()
+        return torch.cuda.mem_get_info()[0]
+
+    first = cycle()
+    for _ in range(6):
+        last = cycle()
+    # one cycle's workspace alone is several MiB (the drain's analysis of
+    # 20,000 records and the digest reserve); a leak would accumulate six
+    assert abs(int(first) - int(last)) < (4 << 20), (first, last)
