@@ -9,12 +9,15 @@ written into the event log, and the log is analysed (duplicate, round-trip,
 repeated and unused mappings). Inputs are resident in HBM before timing.
 
 Workloads (--workload):
-  large-arrays  (default) 16 fp64 arrays of 2^25 elements, each sent 4 times
+  batch         (default) 100,000 buffers, log-uniform 64 B-16 MiB capped at
+                48e9 bytes in total, 25% copies; a step digests them with one
+                batched launch sequence (hipGraph replay, saved tuning), writes
+                the digests into the batch's 101,562-record transfer log and
+                analyses it. The per-buffer-launch form of the same buffers
+                and the large-arrays workload are timed beside it (extras).
+  large-arrays  16 fp64 arrays of 2^25 elements, each sent 4 times
                 (64 transfers of 256 MiB); one digest launch per transfer;
                 the metric is the digest rate in GB/s.
-  batch         100,000 buffers, log-uniform 64 B-16 MiB capped at 48 GB in
-                total, 25% copies; one batched launch (hipGraph replay) per
-                step, with the per-buffer-launch form timed beside it.
   trace         10^7 map records over 10^5 Zipf(1.1) slots plus kernel
                 records; the analysis alone; metric in events/s.
   plain-small   64 buffers of 4 KiB-256 KiB and a 1,000-record log, digests
@@ -44,14 +47,17 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="large-arrays",
+    ap.add_argument("--workload", default="batch",
                     choices=["large-arrays", "batch", "trace", "plain-small", "serve", "rate-vs-size"])
     ap.add_argument("--serve-seconds", type=float, default=4.0,
                     help="serve: schedule length per rate (at most 200,000 requests)")
     ap.add_argument("--plain-requests", type=int, default=20_000,
                     help="serve: requests of each schedule replayed through the plain server")
-    ap.add_argument("--cpu-seconds", type=float, default=10.0,
-                    help="approximate CPU time budget of the oracle baseline sample")
+    ap.add_argument("--cpu-seconds", type=float, default=6.0,
+                    help="wall time of the oracle baseline sample (split between its one-thread and "
+                         "all-thread legs)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="batch: skip the per-buffer form and the large-arrays extras")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--blocks-per-cu", type=int, default=None, help="batched digest tuning override")
     ap.add_argument("--split-bytes", type=int, default=None, help="batched digest tuning override")
@@ -126,11 +132,22 @@ class KernelTimer:
         e1.record(self.stream)
         self.pairs.append((e0, e1))
 
-    def mean_ms(self):
+    def durations_ms(self):
         self.torch.cuda.synchronize()
-        if not self.pairs:
+        return [a.elapsed_time(b) for a, b in self.pairs]
+
+    def mean_ms(self):
+        d = self.durations_ms()
+        return float(np.mean(d)) if d else None
+
+    def summary(self):
+        """Mean, median, p10 and p90 of the timed durations (ms)."""
+        d = self.durations_ms()
+        if not d:
             return None
-        return float(np.mean([a.elapsed_time(b) for a, b in self.pairs]))
+        return {"mean": round(float(np.mean(d)), 5), "median": round(float(np.median(d)), 5),
+                "p10": round(float(np.percentile(d, 10)), 5), "p90": round(float(np.percentile(d, 90)), 5),
+                "n": len(d)}
 
 
 def timed_steps(torch, step, steps, warmup):
@@ -206,27 +223,114 @@ def run_large_arrays(args, torch, odp, W):
                      "kernel": "digest_one_kernel (one launch per 256 MiB buffer; HIP events around the 64 "
                                "back-to-back launches of a step, divided by 64)",
                      "kernel_ms": round(kern_ms, 5)},
-        "extras": {"batched_GBps": round(total / (b_ms * 1e-3) / 1e9, 1),
+        "extras": {"step_kernels_ms": timer.summary(),
+                   "batched_GBps": round(total / (b_ms * 1e-3) / 1e9, 1),
                    "batched_frac_of_peak": round(total / (b_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                    "per_buffer_GBps": round(achieved, 1),
                    "dd_events": rep["dd_events"], "planted_dd": la.planted_dd},
     }
 
     def cpu_sample(budget_s):
-        import oracle
-        host = [la.snapshots[i].cpu().numpy().view(np.uint8) for i in range(min(4, n))]
-        done, t0 = 0, time.perf_counter()
-        k = 0
-        while True:
-            oracle.d64(host[k % len(host)])
-            done += nbytes
-            k += 1
-            if time.perf_counter() - t0 >= budget_s:
-                break
-        el = time.perf_counter() - t0
-        return done / el / 1e9, "%d digests of 256 MiB fp64 arrays by the serial oracle (%.1f s)" % (k, el)
+        host = [la.snapshots[i].cpu().numpy().view(np.uint8) for i in range(min(16, n))]
+        one, many, T = oracle_rates(host, budget_s)
+        return {"value": round(many, 3), "cores": T, "value_1_thread": round(one, 3),
+                "sample": "the oracle (g++ -O3 -march=native on this host) digesting %d of the 256 MiB fp64 "
+                          "arrays over and over: %.1f s on 1 thread, then %.1f s on %d threads over disjoint "
+                          "arrays" % (len(host), budget_s / 2, budget_s / 2, T)}
 
     return line, cpu_sample
+
+
+def oracle_threads():
+    """Threads of the oracle's parallel leg: the host's cores, at most 16 (a
+    one-GPU machine's share)."""
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def oracle_rates(host, budget_s):
+    """Digest rate of the serial oracle over a list of host byte arrays: one
+    thread for half the budget, then T threads over disjoint buffers (each
+    thread walks its own share in turn) for the other half. The oracle is
+    compiled for this host (-O3 -march=native) first, outside the timing."""
+    import tempfile
+    from concurrent.futures import ThreadPoolExecutor
+    import oracle
+    oracle.use_native_build(tempfile.mkdtemp(prefix="odp_oracle_"))
+    done, k, t0 = 0, 0, time.perf_counter()
+    while True:
+        h = host[k % len(host)]
+        oracle.d64(h)
+        done += h.size
+        k += 1
+        if time.perf_counter() - t0 >= budget_s / 2:
+            break
+    one = done / (time.perf_counter() - t0) / 1e9
+    T = oracle_threads()
+    deadline = time.perf_counter() + budget_s / 2
+
+    def worker(t):
+        mine = host[t::T] or host[:1]
+        got, j = 0, 0
+        while time.perf_counter() < deadline:
+            h = mine[j % len(mine)]
+            oracle.d64(h)  # releases the GIL
+            got += h.size
+            j += 1
+        return got
+
+    t1 = time.perf_counter()
+    with ThreadPoolExecutor(T) as ex:
+        total = sum(ex.map(worker, range(T)))
+    many = total / (time.perf_counter() - t1) / 1e9
+    return one, many, T
+
+
+def measure_large_arrays(torch, odp, W, steps):
+    """The large-arrays workload's digest rates: per-buffer launches (HIP events
+    around each step's 64 launches) and the batched form over the same buffers."""
+    la = W.LargeArrays(seed=2, device="cuda")
+    la.materialize()
+    n = len(la.snapshots)
+    nbytes = la.n_elem * 8
+    ptrs = [s.data_ptr() for s in la.snapshots]
+    sizes = [nbytes] * n
+    stream = torch.cuda.current_stream()
+    out = torch.zeros(n, dtype=torch.int64, device="cuda")
+    timer = KernelTimer(torch, stream)
+
+    def step(mode):
+        e0 = timer.start() if mode else None
+        odp.digest_buffers_plain(ptrs, sizes, out, stream)
+        if mode:
+            timer.stop(e0)
+
+    timed_steps(torch, step, steps, 2)
+    per = timer.summary()
+    dptr = torch.tensor(np.array(ptrs, dtype=np.uint64).view(np.int64), device="cuda")
+    dsz = torch.tensor(np.array(sizes, dtype=np.uint64).view(np.int64), device="cuda")
+    out_b = torch.zeros(n, dtype=torch.int64, device="cuda")
+    btimer = KernelTimer(torch, stream)
+
+    def bstep(mode):
+        e0 = btimer.start() if mode else None
+        odp.digest_buffers(dptr, dsz, out_b, stream)
+        if mode:
+            btimer.stop(e0)
+
+    timed_steps(torch, bstep, steps, 2)
+    assert torch.equal(out, out_b), "batched and per-buffer digests differ"
+    bsum = btimer.summary()
+    total = n * nbytes
+    res = {"buffers": n, "bytes": total,
+           "per_buffer_GBps": round(total / (per["mean"] * 1e-3) / 1e9, 1),
+           "per_buffer_kernel_us_mean": round(per["mean"] * 1e3 / n, 2),
+           "per_buffer_kernel_us_median": round(per["median"] * 1e3 / n, 2),
+           "per_buffer_frac_of_peak": round(total / (per["mean"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "batched_GBps": round(total / (bsum["mean"] * 1e-3) / 1e9, 1),
+           "batched_frac_of_peak": round(total / (bsum["mean"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    del la, out, out_b
+    torch.cuda.empty_cache()
+    return res
 
 
 def run_batch(args, torch, odp, W):
@@ -236,66 +340,107 @@ def run_batch(args, torch, odp, W):
     dptr = torch.tensor(bb.pointers().view(np.int64), device="cuda")
     dsz = torch.tensor(bb.sizes.view(np.int64), device="cuda")
     out = torch.zeros(n, dtype=torch.int64, device="cuda")
-    odp.reserve(max_buffers=n, max_total_bytes=int(bb.total_bytes), stream=stream)
-    timer = KernelTimer(torch, stream)
+    ev, tx = bb.transfer_log()
+    m = len(ev)
+    odp.reserve(max_buffers=n, max_total_bytes=int(bb.total_bytes), max_events=m, stream=stream)
+    d_ev = torch.from_numpy(ev.view(np.uint8).reshape(-1).copy()).to("cuda")
+    ev_u64 = d_ev.view(torch.int64).view(m, 8)
+    d_tx = torch.from_numpy(tx.astype(np.int64)).to("cuda")
+    d_flags = torch.zeros(m, dtype=torch.uint8, device="cuda")
+    d_rep = torch.zeros(odp.REPORT_BYTES, dtype=torch.uint8, device="cuda")
+    dtimer = KernelTimer(torch, stream)
+    atimer = KernelTimer(torch, stream)
 
     def step(mode):
-        e0 = timer.start() if mode else None
-        odp.digest_buffers(dptr, dsz, out, stream)
+        e0 = dtimer.start() if mode else None
+        odp.digest_buffers(dptr, dsz, out, stream)  # plan + persistent digest + tree kernels, one graph
         if mode:
-            timer.stop(e0)
+            dtimer.stop(e0)
+        ev_u64[:, 0].index_copy_(0, d_tx, out)  # digest field of each transfer record
+        e1 = atimer.start() if mode else None
+        odp.analyze_trace(d_ev, d_flags, d_rep, stream=stream, n=m)
+        if mode:
+            atimer.stop(e1)
 
     ms = timed_steps(torch, step, args.steps, args.warmup)
-    kern_ms = timer.mean_ms()
-    total = bb.total_bytes
-    hp, hs = bb.pointers().tolist(), bb.sizes.tolist()
-    out_p = torch.zeros(n, dtype=torch.int64, device="cuda")
-    ptimer = KernelTimer(torch, stream)
-
-    def pstep(mode):
-        e0 = ptimer.start() if mode else None
-        odp.digest_buffers_plain(hp, hs, out_p, stream)
-        if mode:
-            ptimer.stop(e0)
-
-    timed_steps(torch, pstep, 2, 1)
-    p_ms = ptimer.mean_ms()
-    assert torch.equal(out, out_p), "batched and per-buffer digests differ"
+    assert odp.device_status() == odp.ODP_OK
+    dsum, asum = dtimer.summary(), atimer.summary()
+    rep = odp.report_to_dict(d_rep.cpu().numpy())
+    copies = int((bb.copy_of >= 0).sum())
+    assert rep["dd_events"] == copies, (rep["dd_events"], copies)
     g = out.cpu().numpy()
     cp = bb.copy_of >= 0
     assert (g[cp] == g[bb.copy_of[cp]]).all(), "copies must digest like their sources"
+    total = bb.total_bytes
     value = total / (ms * 1e-3) / 1e9
-    achieved = total / (kern_ms * 1e-3) / 1e9
+    achieved = total / (dsum["mean"] * 1e-3) / 1e9
+    extras = {"tuning": odp.get_tuning(), "digest_ms": dsum, "analysis_ms": asum,
+              "analysis_events_per_s": round(m / (asum["mean"] * 1e-3), 0),
+              "digest_frac_of_peak_median": round(total / (dsum["median"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+              "dd_events": rep["dd_events"], "copies": copies, "ut_events": rep["ut_events"]}
+    if not args.no_extras:
+        hp, hs = bb.pointers().tolist(), bb.sizes.tolist()
+        out_p = torch.zeros(n, dtype=torch.int64, device="cuda")
+        ptimer = KernelTimer(torch, stream)
+
+        def pstep(mode):
+            e0 = ptimer.start() if mode else None
+            odp.digest_buffers_plain(hp, hs, out_p, stream)
+            if mode:
+                ptimer.stop(e0)
+
+        timed_steps(torch, pstep, 2, 1)
+        p_ms = ptimer.mean_ms()
+        assert torch.equal(out, out_p), "batched and per-buffer digests differ"
+        extras.update({"per_buffer_GBps": round(total / (p_ms * 1e-3) / 1e9, 2), "per_buffer_ms": round(p_ms, 2),
+                       "batched_vs_per_buffer": round(p_ms / dsum["mean"], 1)})
+        del out_p
     line = {
-        "metric": "batched digest GB/s (one hipGraph-replayed persistent launch)",
+        "metric": "batched digest GB/s, 100,000 buffers in one hipGraph-replayed launch (incl. trace analysis)",
         "value": round(value, 1),
         "unit": "GB/s",
         "ms_per_step": round(ms, 4),
         "config": {"workload": "batch: 100,000 buffers, log-uniform 64 B-16 MiB scaled to 48e9 bytes, "
-                               "uint8/fp32/fp64 contents, 25% copies",
-                   "buffers": int(n), "bytes_per_step": int(total)},
+                               "uint8/fp32/fp64 contents, 25%% copies; batched digest, then analysis of the "
+                               "%d-record transfer log" % m,
+                   "buffers": int(n), "bytes_per_step": int(total), "events": m},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "plan + digest_batched_kernel graph", "kernel_ms": round(kern_ms, 4)},
-        "extras": {"tuning": odp.get_tuning(),
-                   "per_buffer_GBps": round(total / (p_ms * 1e-3) / 1e9, 2), "per_buffer_ms": round(p_ms, 2),
-                   "speedup_vs_per_buffer": round(p_ms / kern_ms, 1)},
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic_from_profile("digest_batched_kernel.batch", DIGEST_SOURCES),
+                     "kernel": "batched digest: one graph replay per step (plan kernels, digest_batched_kernel, "
+                               "digest_tree_kernel); HIP events around the replay on the launch stream; "
+                               "algorithmic bytes = the 48e9 bytes of the buffers",
+                     "kernel_ms": dsum["mean"]},
+        "extras": extras,
     }
 
-    def cpu_sample(budget_s):
-        import oracle
+    # the oracle baseline's sample: random whole buffers (~2 GB) copied to the host
+    # now, outside any timing, so the device arena can be freed for the extras
+    sample = None
+    if not args.no_cpu_baseline:
         rng = np.random.default_rng(0)
-        order = rng.permutation(n)
-        done, k, t0 = 0, 0, time.perf_counter()
-        while time.perf_counter() - t0 < budget_s and k < n:
-            i = int(order[k])
-            oracle.d64(bb.buffer(i).cpu().numpy())
-            done += int(bb.sizes[i])
-            k += 1
-        el = time.perf_counter() - t0
-        return done / el / 1e9, "%d random buffers (%.2f GB) by the serial oracle, copy time included" % (k, done / 1e9)
+        pick, tot = [], 0
+        for i in rng.permutation(n):
+            pick.append(int(i))
+            tot += int(bb.sizes[i])
+            if tot >= 2e9:
+                break
+        sample = ([bb.buffer(i).cpu().numpy() for i in pick], tot)
 
-    return line, cpu_sample
+    def cpu_sample(budget_s):
+        host, tot = sample
+        one, many, T = oracle_rates(host, budget_s)
+        return {"value": round(many, 3), "cores": T, "value_1_thread": round(one, 3),
+                "sample": "the oracle (g++ -O3 -march=native on this host) digesting %d random buffers of the batch "
+                          "(%.2f GB, host copies made before timing) over and over: %.1f s on 1 thread, then "
+                          "%.1f s on %d threads over disjoint buffers" % (len(host), tot / 1e9, budget_s / 2,
+                                                                          budget_s / 2, T)}
+
+    if not args.no_extras:
+        del bb, dptr, dsz, d_ev, ev_u64
+        torch.cuda.empty_cache()
+        extras["large_arrays"] = measure_large_arrays(torch, odp, W, max(5, args.steps))
+    return line, (cpu_sample if sample else None)
 
 
 def run_rate_vs_size(args, torch, odp, W):
@@ -421,7 +566,9 @@ def run_trace(args, torch, odp, W):
         line["extras"]["measured_GBps"] = round(line["roofline"]["traffic"] / (kern_ms * 1e-3) / 1e9, 1)
 
     def cpu_sample(budget_s):
+        import tempfile
         import oracle
+        oracle.use_native_build(tempfile.mkdtemp(prefix="odp_oracle_"))
         m = 1
         while True:
             sub = tr.events[:m]
@@ -429,7 +576,9 @@ def run_trace(args, torch, odp, W):
             oracle.analyze(sub)
             el = time.perf_counter() - t0
             if el * 4 >= budget_s or m >= n:
-                return m / el, "oracle on the first %d records (%.1f s)" % (m, el)
+                return {"value": round(m / el, 0), "cores": 1,
+                        "sample": "the oracle (g++ -O3 -march=native on this host, one thread: its rules are "
+                                  "chronological passes) on the first %d records (%.1f s)" % (m, el)}
             m = min(n, m * 4)
 
     return line, cpu_sample
@@ -558,10 +707,11 @@ def main():
            "data": "synthetic (seeded; shapes of the paper's workloads)", "config": line["config"],
            "roofline": line["roofline"]}
     if cpu_sample is not None and not args.no_cpu_baseline:
-        v, desc = cpu_sample(args.cpu_seconds)
+        cb = cpu_sample(args.cpu_seconds)
         cores, model = host_info()
-        out["cpu_baseline"] = {"value": round(v, 3), "unit": line["unit"], "cores": 1, "kind": "oracle",
-                               "sample": desc, "host_cores": cores, "host_cpu": model}
+        out["cpu_baseline"] = {"value": cb.pop("value"), "unit": line["unit"], "cores": cb.pop("cores"),
+                               "kind": "oracle", "sample": cb.pop("sample"), **cb,
+                               "host_cores": cores, "host_cpu": model}
     out["extras"] = line.get("extras")
     print(json.dumps(out), flush=True)
 

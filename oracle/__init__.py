@@ -50,10 +50,19 @@ class _Report(ctypes.Structure):
 _lib = None
 
 
-def lib():
+def use_native_build(directory):
+    """Loads a copy compiled with -march=native for this host (built into
+    `directory`) in place of the portable build; used to time the oracle as a
+    CPU baseline. Same source, same results."""
+    global _lib
+    _lib = None
+    return lib(_build.build_native(directory))
+
+
+def lib(path=None):
     global _lib
     if _lib is None:
-        path = _build.build(force=False)
+        path = path or _build.build(force=False)
         L = ctypes.CDLL(path)
         u64, p = ctypes.c_uint64, ctypes.c_void_p
         L.orc_xxh64.restype = u64

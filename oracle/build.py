@@ -11,6 +11,15 @@ SRC = os.path.join(HERE, "odp_oracle.cpp")
 LIB = os.path.join(HERE, "liboracle.so")
 
 
+def build_native(directory: str) -> str:
+    """A copy of the oracle compiled for the CPU it runs on (-O3 -march=native),
+    for timing it as a CPU baseline; built where it will run, never shipped."""
+    path = os.path.join(directory, "liboracle_native.so")
+    cmd = ["g++", "-O3", "-march=native", "-std=c++17", "-shared", "-fPIC", "-o", path, SRC]
+    subprocess.run(cmd, check=True)
+    return path
+
+
 def build(force: bool = True) -> str:
     if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
         return LIB

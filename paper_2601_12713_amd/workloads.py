@@ -386,19 +386,30 @@ class BatchBuffers:
         gen.manual_seed(seed)
         arena = torch.empty(total, dtype=torch.uint8, device=device)
         # Fill the whole arena with random bytes, then overwrite float regions
-        # with normal values, in chunks so no temporary exceeds ~1 GiB.
+        # with normal values, in chunks so no temporary exceeds ~1 GiB: the
+        # normals of consecutive buffers of one dtype are drawn together in
+        # float64 (rounded to float32 for float32 buffers) and sliced out.
         chunk = 1 << 30
         for off in range(0, total, chunk):
             m = min(chunk, total - off)
             arena[off:off + m].copy_(torch.randint(0, 256, (m,), dtype=torch.uint8, device=device, generator=gen))
         for kind, dt, es in ((1, torch.float32, 4), (2, torch.float64, 8)):
-            idx = np.nonzero((kinds == kind) & (copy_of < 0))[0]
-            for i in idx:
-                cnt = int(sizes[i]) // es
-                if cnt == 0:
-                    continue
-                o = int(offsets[i])
-                arena[o:o + cnt * es].view(dt).copy_(torch.randn(cnt, dtype=dt, device=device, generator=gen))
+            idx = [int(i) for i in np.nonzero((kinds == kind) & (copy_of < 0))[0] if int(sizes[i]) >= es]
+            start = 0
+            while start < len(idx):
+                stop, cnt = start, 0
+                while stop < len(idx) and (stop == start or cnt + int(sizes[idx[stop]]) // es <= (1 << 27)):
+                    cnt += int(sizes[idx[stop]]) // es
+                    stop += 1
+                vals = torch.randn(cnt, dtype=torch.float64, device=device, generator=gen).to(dt)
+                p = 0
+                for i in idx[start:stop]:
+                    c = int(sizes[i]) // es
+                    o = int(offsets[i])
+                    arena[o:o + c * es].view(dt).copy_(vals[p:p + c])
+                    p += c
+                del vals
+                start = stop
         for i in np.nonzero(copy_of >= 0)[0]:
             j = int(copy_of[i])
             o, oj, s = int(offsets[i]), int(offsets[j]), int(sizes[i])
@@ -408,6 +419,29 @@ class BatchBuffers:
     def buffer(self, i):
         o, s = int(self.offsets[i]), int(self.sizes[i])
         return self.arena[o:o + s]
+
+    def transfer_log(self, kernel_every=64):
+        """The batch as a chronological log: one host-to-device record per
+        buffer (host and device addresses from its offset, digest field 0 until
+        the digests are written in), and a KERNEL record on device 0 after every
+        ``kernel_every`` transfers. Returns (events, index of each buffer's
+        record). Copies re-send their source's bytes to the same device, so the
+        duplicate count is exactly the number of copies."""
+        n = self.sizes.size
+        per = kernel_every + 1
+        total = n + n // kernel_every
+        ev = empty_events(total)
+        pos = np.arange(total)
+        is_k = (pos % per) == kernel_every
+        tx = np.nonzero(~is_k)[0][:n]
+        ev["op"] = np.where(is_k, KERNEL, H2D)
+        ev["src_dev"], ev["dst_dev"] = HOST, 0
+        ev["src_addr"][tx] = np.uint64(HOST_BASE) + self.offsets
+        ev["dst_addr"][tx] = np.uint64(DEV_BASE) + self.offsets
+        ev["bytes"][tx] = self.sizes
+        ev["t_start"] = pos.astype(np.uint64) * np.uint64(1000)
+        ev["t_end"] = ev["t_start"] + np.uint64(500)
+        return ev, tx
 
     def pointers(self):
         base = self.arena.data_ptr()
