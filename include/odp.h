@@ -249,14 +249,24 @@ int odp_analyze_trace(const odp_event* events, size_t n, uint8_t* out_flags, odp
  *
  * A request is one odp_event plus, for a transfer, the device-resident bytes it
  * moved (the digest field is then filled from those bytes). Requests are
- * admitted into ticks as slots and the in-flight byte budget allow; a tick is
- * one batched digest of its payloads and one classification against
- * device-resident per-key state, appended to a device-resident log.
- * Flags known at arrival (DD, RT_RX, PAIRED) are exact per tick; flags that
- * depend on later records (RT_TX, RA, UA, UT) are resolved when the server is
- * drained, by the analysis of the whole log in arrival order (the rules of
- * Sec. 4, Defs. 1-4, and Sec. 5; the paper analyses post mortem, serving is an
- * extension).
+ * admitted into ticks as slots and the memory budget allow; a tick is one
+ * batched digest of its payloads (on the server's digest stream) and one
+ * classification against device-resident per-key state (on its classification
+ * stream, after that digest), appended to a device-resident log; the digest of
+ * the next tick overlaps the classification of the current one.
+ * Every flag is set in the server's "known" flags as soon as the records that
+ * decide it have arrived (the rules of Sec. 4, Defs. 1-4, and Sec. 5; the
+ * paper analyses post mortem, serving is an extension):
+ *   DD, RT_RX, PAIRED, INVALID  at the record's arrival;
+ *   RT_TX  when a later transfer carries the digest back;
+ *   RA     when the ALLOC is paired (or when an earlier ALLOC of its key is);
+ *   UA     once a record starting after the DELETE's end has arrived;
+ *   UT     once a record starting after the next copy's start has arrived.
+ * UA and UT are set early only while no record has been rejected: they rest on
+ * the log being chronological, and a record rejected later can let a later
+ * record start earlier than one already logged. A transfer never sent back and
+ * a copy never overwritten are decided by the drain, which runs the full
+ * analysis of the whole log in arrival order.
  * Errors: every call returns an ODP_* code; on failure the message is in
  * odp_last_error_string(). A server belongs to one host thread.
  * ------------------------------------------------------------------------ */
@@ -269,7 +279,9 @@ enum {
 
 typedef struct odp_server_config {
   uint64_t max_events;   /* records over the server's life (log capacity), 1 .. 2^32 - 1 */
-  uint64_t budget_bytes; /* in-flight payload bytes admitted at most */
+  uint64_t budget_bytes; /* device memory budget: the server's state and digest workspace
+                            (odp_server_stats.state_bytes, fixed at creation) plus the payload
+                            bytes of the requests in flight */
   uint32_t max_inflight; /* in-flight requests admitted at most (slots) */
   uint32_t max_tick;     /* records per tick, 1 .. 1024 */
   uint32_t mode;         /* ODP_SERVER_BATCHED or ODP_SERVER_PLAIN */
@@ -282,18 +294,22 @@ typedef struct odp_server_stats {
   uint64_t max_tick;     /* largest tick */
   uint64_t bytes;        /* payload bytes digested */
   uint64_t budget_waits; /* requests whose admission waited for the byte budget */
+  uint64_t state_bytes;  /* device bytes of the server's state and digest workspace */
 } odp_server_stats;
 
-/* Creates a server on the current device with its own stream; allocates the
- * log (64 B per record), three state tables (32 B x 2 x max_events each,
- * rounded up to a power of two) and the digest workspace for budget_bytes.
- * *out is owned by the caller until odp_server_destroy. */
+/* Creates a server on the current device with its own two streams; allocates
+ * the log (64 B per record), the per-record flags and links (9 B), the
+ * per-device kernel lists (176 B per record), the waiting windows (64 B per
+ * record), six state tables (40 B x 2 x max_events each, rounded up to a
+ * power of two) and the digest workspace for payload batches up to
+ * budget_bytes. ODP_EINVAL when budget_bytes does not exceed what that
+ * takes. *out is owned by the caller until odp_server_destroy. */
 int odp_server_create(const odp_server_config* cfg, odp_server** out);
 
 /* Runs an open-loop schedule to completion. All arrays are HOST arrays of n:
  *   events         the records (arrival order)
  *   payload_ptrs   device address of the bytes each record moved, or 0
- *   payload_bytes  their length (a request above budget_bytes is rejected)
+ *   payload_bytes  their length (a request above budget_bytes - state_bytes is rejected)
  *   arrival_ns     scheduled arrival, ns after the call starts, non-decreasing
  *   complete_ns    out: when the request's tick was seen complete, ns after start
  * Blocks until every request is complete. Requests keep arrival order in the
@@ -302,10 +318,10 @@ int odp_server_run(odp_server* s, const odp_event* events, const uint64_t* paylo
                    const uint64_t* arrival_ns, size_t n, uint64_t* complete_ns, odp_server_stats* stats);
 
 /* Waits for the server, then (each optional, DEVICE arrays of the logged count):
- * out_imm gets the flags known at arrival; out_flags/out_report get the
- * analysis of the whole log (both or neither). ODP_ECAPACITY if a state table
- * ran full. */
-int odp_server_drain(odp_server* s, uint8_t* out_imm, uint8_t* out_flags, odp_report* out_report);
+ * out_known gets the flags decided so far (see above); out_flags/out_report
+ * get the analysis of the whole log (both or neither). ODP_ECAPACITY if a
+ * state table ran full. */
+int odp_server_drain(odp_server* s, uint8_t* out_known, uint8_t* out_flags, odp_report* out_report);
 
 /* Copies the logged records (digests filled in) to DEVICE out_events (may be
  * NULL) and their count to *n. */

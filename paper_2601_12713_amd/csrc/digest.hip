@@ -1044,6 +1044,15 @@ __global__ __launch_bounds__(kThreads) void digest_tree_kernel(BatchArgs A) {
 // ---------------------------------------------------------------------------
 // Host side.
 // ---------------------------------------------------------------------------
+uint64_t digest_workspace_bytes(size_t max_buffers, uint64_t max_total_bytes) {
+  const uint64_t nb = max_buffers < 1024 ? 1024 : max_buffers;
+  const uint64_t nblk = (nb + kPlanTile - 1) / kPlanTile;
+  const uint64_t items = max_total_bytes / kNodeBytes + nb;
+  const uint64_t tree = items + items / 32 + 4 * nb, tk = items / 32 + 4 * nb;
+  return (nb + 1) * 8 + 2 * nb * 8 + nb * 4 + nblk * kQ * 8 + nb * sizeof(NodeRec) + sizeof(DigestCtl) +
+         items * (4 + sizeof(NodeRec)) + tree * 8 + tk * 4;
+}
+
 int digest_reserve(Workspace* ws, size_t max_buffers, uint64_t max_total_bytes) {
   // A captured graph holds workspace addresses: drop it before anything moves.
   if (ws->graph) {
@@ -1257,6 +1266,12 @@ int plain_reserve_slots(Workspace* ws, uint64_t need_tree, uint64_t need_tk) {
   ws->p_cap_tree = tr;
   ws->p_cap_tk = tk;
   return ODP_OK;
+}
+
+uint64_t digest_plain_workspace_bytes(uint64_t max_bytes) {
+  uint64_t tr = 0, tk = 0;
+  if (max_bytes > kLeaf) tree_need(ceil_div(ceil_div(max_bytes, kLeaf), kFanIn), tr, tk);
+  return std::max<uint64_t>(tr, 1024) * 8 + std::max<uint64_t>(tk, 256) * 4;
 }
 
 int digest_plain_reserve(Workspace* ws, uint64_t max_bytes) {

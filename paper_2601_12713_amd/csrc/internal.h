@@ -91,6 +91,9 @@ struct Tuning {
 Tuning& tuning();
 
 int digest_reserve(Workspace* ws, size_t max_buffers, uint64_t max_total_bytes);
+// Device bytes that digest_reserve / digest_plain_reserve allocate for these sizes.
+uint64_t digest_workspace_bytes(size_t max_buffers, uint64_t max_total_bytes);
+uint64_t digest_plain_workspace_bytes(uint64_t max_bytes);
 // Workspace of the per-buffer form for buffers of up to max_bytes (grow-only).
 int digest_plain_reserve(Workspace* ws, uint64_t max_bytes);
 // Batched digest enqueued with direct launches (workspace reserved

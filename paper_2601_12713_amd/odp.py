@@ -225,7 +225,7 @@ SERVER_BATCHED, SERVER_PLAIN = 0, 1
 
 class _ServerStats(ctypes.Structure):
     _fields_ = [("seconds", ctypes.c_double), ("ticks", ctypes.c_uint64), ("max_tick", ctypes.c_uint64),
-                ("bytes", ctypes.c_uint64), ("budget_waits", ctypes.c_uint64)]
+                ("bytes", ctypes.c_uint64), ("budget_waits", ctypes.c_uint64), ("state_bytes", ctypes.c_uint64)]
 
 
 def _load_server():
@@ -271,7 +271,7 @@ class Server:
         return done[:n], {f: getattr(st, f) for f, _ in _ServerStats._fields_}
 
     def drain(self):
-        """Returns (flags known at arrival, final flags, final report dict) as host arrays."""
+        """Returns (flags decided before the drain, final flags, final report dict) as host arrays."""
         import torch
         L = _load_server()
         n = self._n

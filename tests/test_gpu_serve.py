@@ -1,7 +1,8 @@
 """Serving through the C ABI (odp_server_*): every request's digest is the same
-in the mix as alone and as the oracle's, the flags known at arrival agree with
-the final ones, and the final flags after draining equal the oracle's analysis
-of the arrival-ordered log. All bit-exact."""
+in the mix as alone and as the oracle's; the flags the server decided before
+the drain equal the oracle's for every record whose deciding records had
+arrived, and are unset for the others; the final flags after draining equal the
+oracle's analysis of the arrival-ordered log. All bit-exact."""
 import numpy as np
 import pytest
 
@@ -13,7 +14,39 @@ from gpu_helpers import compare
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
-IMMEDIATE = 1 | 4 | 32 | 128  # DD, RT_RX, PAIRED, INVALID
+F_DD, F_RT_TX, F_RT_RX, F_RA, F_UA, F_PAIRED, F_UT, F_INVALID = 1, 2, 4, 8, 16, 32, 64, 128
+# decided once the whole log has arrived: at a record's arrival, or when a
+# later record (a transfer back, a pairing) arrives
+EXACT = F_DD | F_RT_TX | F_RT_RX | F_RA | F_PAIRED | F_INVALID
+
+
+def decided_windows(ev, valid):
+    """Which records' UA and UT bits the server has decided by the end of the
+    log: a paired ALLOC whose DELETE ends before the last record starts; a copy
+    into a device (H2D or D2D) whose next copy of the same (receiver, sender,
+    source address) starts before the last record starts. Without a rejected
+    record only (otherwise they wait for the drain)."""
+    n = len(ev)
+    ua = np.zeros(n, dtype=bool)
+    ut = np.zeros(n, dtype=bool)
+    if n == 0 or not valid.all():
+        return ua, ut
+    last = int(ev["t_start"][-1])
+    open_ad = {}
+    nxt = {}
+    for i in range(n):
+        op = int(ev["op"][i])
+        if op in (1, 5):
+            k = (int(ev["dst_dev"][i]), int(ev["dst_addr"][i]))
+            if op == 5 and k in open_ad and int(ev["op"][open_ad[k]]) == 1 and int(ev["t_end"][i]) < last:
+                ua[open_ad[k]] = True
+            open_ad[k] = i
+        elif op in (2, 4) and int(ev["dst_dev"][i]) >= 0:
+            k = (int(ev["dst_dev"][i]), int(ev["src_dev"][i]), int(ev["src_addr"][i]))
+            if k in nxt and int(ev["t_start"][i]) < last:
+                ut[nxt[k]] = True
+            nxt[k] = i
+    return ua, ut
 
 
 @pytest.fixture(scope="module")
@@ -54,11 +87,22 @@ def check_served(odp, sched, ev_o, log, imm, fl, rep):
         assert (log[f] == sched.events[f]).all(), f
     fo, ro = oracle.analyze(ev_o)
     compare(fl, rep, fo, ro)
-    bad = np.nonzero((imm & IMMEDIATE) != (fo & IMMEDIATE))[0]
-    assert bad.size == 0, "arrival flags differ at %s: %s vs %s" % (
-        bad[:10].tolist(), imm[bad[:10]].tolist(), fo[bad[:10]].tolist())
-    assert not (imm & np.uint8(0xFF ^ IMMEDIATE)).any(), "only DD, RT_RX, PAIRED and INVALID are known at arrival"
+    check_known(imm, fo, ev_o)
     return fo, ro
+
+
+def check_known(known, fo, ev):
+    bad = np.nonzero((known & EXACT) != (fo & EXACT))[0]
+    assert bad.size == 0, "flags decided before the drain differ at %s: %s vs %s" % (
+        bad[:10].tolist(), known[bad[:10]].tolist(), fo[bad[:10]].tolist())
+    valid = (fo & F_INVALID) == 0
+    ua, ut = decided_windows(ev, valid)
+    for bit, dec in ((F_UA, ua), (F_UT, ut)):
+        if valid.all():
+            want = np.where(dec, fo & bit, 0)
+            diff = np.nonzero((known & bit) != want)[0]
+            assert diff.size == 0, "bit %d before the drain differs at %s" % (bit, diff[:10].tolist())
+    return ua, ut
 
 
 @pytest.mark.parametrize("max_tick", [1, 7, 1024])
@@ -178,3 +222,21 @@ def test_servers_release_their_memory(odp, arena):
     # one cycle's workspace alone is several MiB (the drain's analysis of
     # 20,000 records and the digest reserve); a leak would accumulate six
     assert abs(int(first) - int(last)) < (4 << 20), (first, last)
+
+
+@pytest.mark.parametrize("max_tick", [1, 5, 1024])
+def test_flags_decided_before_the_drain(odp, arena, max_tick):
+    """Round trips sent back several ticks later, repeated and unused
+    allocations, copies overwritten before any kernel: every bit a record can
+    have is set before the drain once its deciding records have arrived, equal
+    to the oracle's, in ticks of one record, of a few and of many."""
+    a, host = arena
+    sched = W.ServingSchedule(seed=27, n=4000, rate=100_000.0, lo=4096, hi=256 << 10, arena=a)
+    ev_o = oracle_events(sched, host)
+    log, imm, fl, rep, done, stats = served(odp, sched, budget_bytes=512 << 20, max_tick=max_tick)
+    fo, ro = check_served(odp, sched, ev_o, log, imm, fl, rep)
+    ua, ut = decided_windows(ev_o, (fo & F_INVALID) == 0)
+    for bit, name in ((F_RT_TX, "rt_pairs"), (F_RA, "ra_events")):
+        assert int(((imm & bit) != 0).sum()) == ro[name] > 0
+    assert ((imm & F_UA) != 0).sum() > 0 and ((imm & F_UT) != 0).sum() > 0
+    assert ua.sum() > 0.9 * ((fo & F_PAIRED) != 0).sum() / 2  # nearly every window closed by the end
