@@ -49,6 +49,10 @@ constexpr int kMaxWords = 3;
 constexpr int kMaxPasses = 24;
 constexpr int kEp = 11;                 // endpoints: host (0) and devices 0..9 (1..10)
 constexpr uint8_t kNotTransfer = 0xFF;
+// Counters per wavefront of the classification, scanned into the subset
+// offsets: ALLOC/DELETE, KERNEL and copy-in records, then KERNEL records per
+// device code (device + 1).
+constexpr int kWaveCnt = 3 + kEp;
 // Logs of fewer than 2^24 records carry each record's endpoint code in the
 // top byte of its digest-sort value (the record index in the low 24 bits), so
 // the scans over the sorted order need no gather of the code by index.
@@ -81,6 +85,9 @@ struct AnaCtl {
       m_ut_code;
   uint32_t dev_lo[kEp], dev_hi[kEp];  // per-device ranges in the sorted kernel order
   uint64_t t_min, t_max;              // earliest start and latest end of the valid records
+  uint32_t kd_base[kEp], kd_total[kEp];  // KERNEL records per device code: list offsets and counts
+  uint32_t ut_need_sort;              // 1: some copy-in is decided by the sorted path
+  uint32_t kern_sort;                 // 1: the kernel lists are sorted (the count form's binary searches)
   // removable time (Sec. 7.6), in three parts written by different stages:
   // transfers flagged DD or RT_RX; pairs flagged RA or UA; transfers flagged
   // UT only
@@ -115,6 +122,8 @@ struct SortJob {
   // (no record rejected), so its passes are skipped then; kNoWord if none.
   const uint32_t* first_bad;
   uint32_t mono_word;
+  // When set and *run_flag is 0 the job runs no pass (its order is not needed).
+  const uint32_t* run_flag;
 };
 constexpr uint32_t kNoWord = 0xFFFFFFFFu;
 
@@ -273,6 +282,8 @@ __global__ void init_kernel(AnaCtl* ctl, odp_report* rep, uint32_t* totals, uint
     ctl->t_min = ~0ull;
     ctl->t_max = 0;
     ctl->elim_tx = ctl->elim_pairs = ctl->elim_ut = 0;
+    ctl->ut_need_sort = 0;
+    ctl->kern_sort = 0;
     WordMask* m = &ctl->m_digest;
     for (int i = 0; i < kNumMasks; ++i) {
       m[i].vor = 0;
@@ -297,10 +308,18 @@ __device__ __forceinline__ bool dev_ok(int d) { return d >= -1 && d <= ODP_MAX_D
 __global__ __launch_bounds__(kT) void classify_kernel(const odp_event* __restrict__ ev, uint32_t n, uint8_t* __restrict__ flags,
                                                       uint8_t* __restrict__ cls, uint8_t* __restrict__ aux,
                                                       unsigned long long* __restrict__ keys, uint32_t* __restrict__ vals,
-                                                      uint32_t* __restrict__ wave_cnt, Parts parts) {
+                                                      uint32_t* __restrict__ wave_cnt, uint64_t* __restrict__ wave_kmax,
+                                                      Parts parts) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const uint32_t wid = blockIdx.x * (kT / 64) + w;
   const uint32_t wb = wid * kWaveElems;
+  __shared__ uint32_t s_kdev[kT / 64][kEp];
+  __shared__ unsigned long long s_kmax[kT / 64][kEp];
+  if (lane < kEp) {
+    s_kdev[w][lane] = 0;
+    s_kmax[w][lane] = 0;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
   unsigned long long n_inv = 0, n_tx = 0, n_k = 0, kor = 0, kand = ~0ull, tmin = ~0ull, tmax = 0;
   uint32_t bad = kNone, mep = 0, c_ad = 0, c_k = 0, c_ut = 0;
   // records of the next round are loaded while this round is classified; the
@@ -339,6 +358,8 @@ __global__ __launch_bounds__(kT) void classify_kernel(const odp_event* __restric
           c = C_KERNEL;
           ++n_k;
           ++c_k;
+          atomicAdd(&s_kdev[w][e.dst_dev + 1], 1u);
+          atomicMax(&s_kmax[w][e.dst_dev + 1], (unsigned long long)e.t_end);
         } else {
           c = C_ALLOCDEL;
           ++c_ad;
@@ -365,9 +386,14 @@ __global__ __launch_bounds__(kT) void classify_kernel(const odp_event* __restric
     c_ut += __shfl_xor(c_ut, o, 64);
   }
   if (lane == 0) {
-    wave_cnt[3 * wid] = c_ad;
-    wave_cnt[3 * wid + 1] = c_k;
-    wave_cnt[3 * wid + 2] = c_ut;
+    wave_cnt[kWaveCnt * wid] = c_ad;
+    wave_cnt[kWaveCnt * wid + 1] = c_k;
+    wave_cnt[kWaveCnt * wid + 2] = c_ut;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  if (lane < kEp) {
+    wave_cnt[kWaveCnt * wid + 3 + lane] = s_kdev[w][lane];
+    wave_kmax[kEp * wid + lane] = s_kmax[w][lane];
   }
   block_store<R_ADD>(parts.at(S_N_INVALID), n_inv);
   block_store<R_ADD>(parts.at(S_N_TRANSFERS), n_tx);
@@ -384,45 +410,146 @@ __global__ __launch_bounds__(kT) void classify_kernel(const odp_event* __restric
 // 2. Ordered compaction of the ALLOC/DELETE and KERNEL subsets.
 // ---------------------------------------------------------------------------
 // Exclusive scan of K interleaved u32 counters (cnt[K*t + c]) over `ntiles`
-// entries (one block); the totals go to tot[c] where that is not null.
+// entries (one block, for short arrays); the totals of the first two go to
+// tot0 / tot1 where not null.
 template <int K>
 __global__ __launch_bounds__(1024) void scan_counts_kernel(uint32_t* cnt, uint32_t ntiles, uint32_t* tot0,
-                                                           uint32_t* tot1, uint32_t* tot2) {
-  __shared__ uint32_t sh[K][1024];
+                                                           uint32_t* tot1) {
+  __shared__ uint32_t wsum[K][16];
   __shared__ uint32_t carry[K];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   if (threadIdx.x < K) carry[threadIdx.x] = 0;
   __syncthreads();
   for (uint32_t base = 0; base < ntiles; base += 1024) {
     const uint32_t t = base + threadIdx.x;
-    uint32_t own[K];
+    uint32_t own[K], x[K];
 #pragma unroll
     for (int c = 0; c < K; ++c) {
       own[c] = t < ntiles ? cnt[K * t + c] : 0;
-      sh[c][threadIdx.x] = own[c];
+      x[c] = own[c];
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x[c], o, 64);
+        if (lane >= o) x[c] += y;
+      }
+      if (lane == 63) wsum[c][w] = x[c];
     }
     __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-      uint32_t x[K];
 #pragma unroll
-      for (int c = 0; c < K; ++c) x[c] = threadIdx.x >= (uint32_t)o ? sh[c][threadIdx.x - o] : 0;
-      __syncthreads();
-#pragma unroll
-      for (int c = 0; c < K; ++c) sh[c][threadIdx.x] += x[c];
-      __syncthreads();
-    }
-    if (t < ntiles) {
-#pragma unroll
-      for (int c = 0; c < K; ++c) cnt[K * t + c] = carry[c] + sh[c][threadIdx.x] - own[c];
+    for (int c = 0; c < K; ++c) {
+      uint32_t before = carry[c] + x[c] - own[c];
+      for (int q = 0; q < w; ++q) before += wsum[c][q];
+      if (t < ntiles) cnt[K * t + c] = before;
     }
     __syncthreads();
-    if (threadIdx.x < K) carry[threadIdx.x] += sh[threadIdx.x][1023];
+    if (threadIdx.x < K) {
+      uint32_t s = 0;
+      for (int q = 0; q < 16; ++q) s += wsum[threadIdx.x][q];
+      carry[threadIdx.x] += s;
+    }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    uint32_t* tot[3] = {tot0, tot1, tot2};
-#pragma unroll
-    for (int c = 0; c < K; ++c)
-      if (tot[c]) *tot[c] = carry[c];
+    if (tot0) *tot0 = carry[0];
+    if (K > 1 && tot1) *tot1 = carry[K > 1 ? 1 : 0];
+  }
+}
+
+// The classification's per-wavefront counters (kWaveCnt sums) and per-device
+// latest kernel ends (kEp maxima), scanned into exclusive prefixes in two
+// steps: each block of 1,024 wavefronts scans its chunk in place and stores
+// the chunk's totals; one block then scans the chunk totals (the consumer adds
+// its chunk's prefix). Rounds of 1,024 entries, one thread each, so every
+// load is coalesced.
+struct WaveScan {
+  uint32_t* cnt;   // [nw][kWaveCnt]
+  uint64_t* kmax;  // [nw][kEp]
+  uint32_t* ccnt;  // [nchunk][kWaveCnt]: chunk totals, then their exclusive prefixes
+  uint64_t* cmax;  // [nchunk][kEp]
+  uint32_t nw;
+};
+constexpr uint32_t kScanChunk = 1024;
+
+template <typename T, bool MAX>
+__device__ __forceinline__ T block_excl(T v, T* wtot, T& total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  T x = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    const T y = __shfl_up(x, o, 64);
+    if (lane >= o) x = MAX ? (x > y ? x : y) : x + y;
+  }
+  if (lane == 63) wtot[w] = x;
+  __syncthreads();
+  T before = __shfl_up(x, 1, 64);
+  if (lane == 0) before = 0;
+  T all = 0;
+  for (int q = 0; q < 16; ++q) {
+    if (q < w) before = MAX ? (before > wtot[q] ? before : wtot[q]) : before + wtot[q];
+    all = MAX ? (all > wtot[q] ? all : wtot[q]) : all + wtot[q];
+  }
+  __syncthreads();
+  total = all;
+  return before;
+}
+
+__global__ __launch_bounds__(1024) void wave_scan_local_kernel(WaveScan S) {
+  __shared__ uint32_t wc[16];
+  __shared__ unsigned long long wm[16];
+  const uint32_t i = blockIdx.x * kScanChunk + threadIdx.x;
+  const bool in = i < S.nw;
+  for (int c = 0; c < kWaveCnt; ++c) {
+    uint32_t tot;
+    const uint32_t ex = block_excl<uint32_t, false>(in ? S.cnt[(size_t)kWaveCnt * i + c] : 0u, wc, tot);
+    if (in) S.cnt[(size_t)kWaveCnt * i + c] = ex;
+    if (threadIdx.x == 0) S.ccnt[(size_t)kWaveCnt * blockIdx.x + c] = tot;
+  }
+  for (int d = 0; d < kEp; ++d) {
+    unsigned long long tot;
+    const unsigned long long ex =
+        block_excl<unsigned long long, true>(in ? (unsigned long long)S.kmax[(size_t)kEp * i + d] : 0ull, wm, tot);
+    if (in) S.kmax[(size_t)kEp * i + d] = ex;
+    if (threadIdx.x == 0) S.cmax[(size_t)kEp * blockIdx.x + d] = tot;
+  }
+}
+
+__global__ __launch_bounds__(1024) void wave_scan_chunks_kernel(WaveScan S, uint32_t nchunk, uint32_t* tot_ad,
+                                                                uint32_t* tot_k, uint32_t* tot_ut, AnaCtl* ctl) {
+  __shared__ uint32_t wc[16];
+  __shared__ unsigned long long wm[16];
+  __shared__ uint32_t carry_c[kWaveCnt];
+  __shared__ unsigned long long carry_m[kEp];
+  if (threadIdx.x < kWaveCnt) carry_c[threadIdx.x] = 0;
+  if (threadIdx.x < kEp) carry_m[threadIdx.x] = 0;
+  __syncthreads();
+  for (uint32_t base = 0; base < nchunk; base += 1024) {
+    const uint32_t i = base + threadIdx.x;
+    const bool in = i < nchunk;
+    for (int c = 0; c < kWaveCnt; ++c) {
+      uint32_t tot;
+      const uint32_t ex = block_excl<uint32_t, false>(in ? S.ccnt[(size_t)kWaveCnt * i + c] : 0u, wc, tot);
+      if (in) S.ccnt[(size_t)kWaveCnt * i + c] = carry_c[c] + ex;
+      __syncthreads();
+      if (threadIdx.x == 0) carry_c[c] += tot;
+    }
+    for (int d = 0; d < kEp; ++d) {
+      unsigned long long tot;
+      const unsigned long long ex =
+          block_excl<unsigned long long, true>(in ? (unsigned long long)S.cmax[(size_t)kEp * i + d] : 0ull, wm, tot);
+      if (in) S.cmax[(size_t)kEp * i + d] = max(carry_m[d], ex);
+      __syncthreads();
+      if (threadIdx.x == 0) carry_m[d] = max(carry_m[d], tot);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    *tot_ad = carry_c[0];
+    *tot_k = carry_c[1];
+    *tot_ut = carry_c[2];
+    uint32_t base = 0;
+    for (int d = 0; d < kEp; ++d) {
+      ctl->kd_base[d] = base;
+      ctl->kd_total[d] = carry_c[3 + d];
+      base += carry_c[3 + d];
+    }
   }
 }
 
@@ -432,6 +559,13 @@ struct SubsetOut {
   uint64_t* ut_w_code;  // endpoint code (src_dev + 1) << 4 | (dst_dev + 1)
   uint64_t* ut_ts;      // t_start
   uint32_t* ut_vals;
+  uint32_t* ut_kc;      // KERNEL records on the receiving device logged before the copy
+  uint64_t* ut_km;      // the latest end among those (0 when there is none)
+  uint32_t* ad_kc;      // ALLOC/DELETE: KERNEL records on its device logged before it
+  uint64_t* ad_km;      // ... and the latest end among them
+  uint64_t* kd_ts;      // KERNEL records per device code in log order (from kd_base[code]): start
+  uint32_t* kd_idx;     // ... and record index
+  const AnaCtl* ctl;
   uint32_t* ad_idx;
   uint8_t* ad_op;
   uint64_t* ad_w_dev;
@@ -450,10 +584,11 @@ struct SubsetOut {
 // takes its 1,024 records in 16 coalesced rounds of 64 (lane l: record
 // wb + 64r + l); a ballot per round gives each matching lane its rank, so the
 // entries land in record order at the wavefront's scanned offsets, and the
-// records of a round are read together.
+// records of a round are read together. Each copy-in also gets the number of
+// KERNEL records on its receiving device logged before it: the device's count
+// before the wavefront (scanned) plus the kernels of earlier rounds and lanes.
 __global__ __launch_bounds__(kT) void subset_scatter_kernel(const odp_event* __restrict__ ev, const uint8_t* __restrict__ cls,
-                                                            uint32_t n, const uint32_t* __restrict__ wave_off, SubsetOut S,
-                                                            Parts parts) {
+                                                            uint32_t n, WaveScan W, SubsetOut S, Parts parts) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const uint32_t wid = blockIdx.x * (kT / 64) + w;
   const uint32_t wb = wid * kWaveElems;
@@ -463,7 +598,18 @@ __global__ __launch_bounds__(kT) void subset_scatter_kernel(const odp_event* __r
     const uint32_t i = wb + r * 64 + lane;
     c[r] = i < n ? cls[i] : C_INVALID;
   }
-  uint32_t q0 = wave_off[3 * wid], q1 = wave_off[3 * wid + 1], q2 = wave_off[3 * wid + 2];
+  // offsets: the wavefront's prefix within its chunk plus the chunk's prefix
+  const uint32_t* wo = W.cnt + (size_t)kWaveCnt * wid;
+  const uint32_t* co = W.ccnt + (size_t)kWaveCnt * (wid / kScanChunk);
+  uint32_t q0 = wo[0] + co[0], q1 = wo[1] + co[1], q2 = wo[2] + co[2];
+  __shared__ uint32_t s_kc[kT / 64][kEp];            // kernels per device code before the current round
+  __shared__ unsigned long long s_km[kT / 64][kEp];  // the latest end among them
+  if (lane < kEp) {
+    s_kc[w][lane] = wo[3 + lane] + co[3 + lane];
+    s_km[w][lane] = max((unsigned long long)W.kmax[(size_t)kEp * wid + lane],
+                        (unsigned long long)W.cmax[(size_t)kEp * (wid / kScanChunk) + lane]);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
   unsigned long long o_dev = 0, a_dev = ~0ull, o_addr = 0, a_addr = ~0ull, o_ks = 0, a_ks = ~0ull, o_ke = 0,
                      a_ke = ~0ull, o_kd = 0, a_kd = ~0ull, o_ua = 0, a_ua = ~0ull, o_uc = 0, a_uc = ~0ull;
   const uint64_t lt = lanemask_lt();
@@ -472,6 +618,39 @@ __global__ __launch_bounds__(kT) void subset_scatter_kernel(const odp_event* __r
     const uint32_t i = wb + r * 64 + lane;
     const bool is_ad = c[r] == C_ALLOCDEL, is_k = c[r] == C_KERNEL, is_ut = c[r] == C_COPYIN;
     const uint64_t bad = __ballot(is_ad), bk = __ballot(is_k), bu = __ballot(is_ut);
+    // the device code of kernels and copy-ins (both in dst_dev)
+    const uint32_t dc = (is_k || is_ut || is_ad) ? (uint32_t)(ev[i].dst_dev + 1) : 0u;
+    const unsigned long long kend = is_k ? (unsigned long long)ev[i].t_end : 0ull;
+    uint32_t kc = (is_ut || is_k || is_ad) ? s_kc[w][dc] : 0u;
+    unsigned long long km = (is_ut || is_ad) ? s_km[w][dc] : 0ull;
+    if (bk) {
+      uint32_t devs = is_k ? 1u << dc : 0u;
+      for (int o = 32; o >= 1; o >>= 1) devs |= __shfl_xor(devs, o, 64);
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      while (devs) {
+        const uint32_t d = (uint32_t)__builtin_ctz(devs);
+        devs &= devs - 1;
+        const uint64_t kd = __ballot(is_k && dc == d);
+        // latest end among this device's kernels in lower lanes (exclusive max scan)
+        unsigned long long x = (is_k && dc == d) ? kend : 0ull;
+        for (int o = 1; o < 64; o <<= 1) {
+          const unsigned long long y = __shfl_up(x, o, 64);
+          if (lane >= o) x = max(x, y);
+        }
+        unsigned long long ex = __shfl_up(x, 1, 64);
+        if (lane == 0) ex = 0;
+        const unsigned long long all = __shfl(x, 63, 64);
+        if ((is_ut || is_k || is_ad) && dc == d) {
+          kc += (uint32_t)__popcll(kd & lt);
+          km = max(km, ex);
+        }
+        if (lane == 0) {
+          s_kc[w][d] += (uint32_t)__popcll(kd);
+          s_km[w][d] = max(s_km[w][d], all);
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    }
     if (is_ut) {
       const odp_event& e = ev[i];
       const uint32_t q = q2 + (uint32_t)__popcll(bu & lt);
@@ -481,6 +660,8 @@ __global__ __launch_bounds__(kT) void subset_scatter_kernel(const odp_event* __r
       S.ut_w_code[q] = code;
       S.ut_ts[q] = e.t_start;
       S.ut_vals[q] = q;
+      S.ut_kc[q] = kc;
+      S.ut_km[q] = km;
       o_ua |= sa;
       a_ua &= sa;
       o_uc |= code;
@@ -495,6 +676,8 @@ __global__ __launch_bounds__(kT) void subset_scatter_kernel(const odp_event* __r
       S.ad_w_addr[q] = ad;
       S.ad_vals[q] = q;
       S.ad_alloc_partner[q] = kNone;
+      S.ad_kc[q] = kc;
+      S.ad_km[q] = km;
       o_dev |= dv;
       a_dev &= dv;
       o_addr |= ad;
@@ -505,6 +688,10 @@ __global__ __launch_bounds__(kT) void subset_scatter_kernel(const odp_event* __r
       const uint64_t dv = (uint64_t)(e.dst_dev + 1);
       S.k_idx[q] = i;
       S.k_w_start[q] = e.t_start;
+      // this kernel's place among its device's kernels in log order
+      const uint32_t kp = S.ctl->kd_base[dc] + kc;
+      S.kd_ts[kp] = e.t_start;
+      S.kd_idx[kp] = i;
       S.k_w_end[q] = e.t_end;
       S.k_w_dev[q] = dv;
       S.k_vals_s[q] = q;
@@ -619,7 +806,8 @@ __global__ void sort_plan_kernel(JobSet J, uint32_t first_passes) {
   SortJob& s = J.jobs[j];
   uint32_t np = 0;
   const uint32_t skip = (s.first_bad && *s.first_bad == kNone) ? s.mono_word : kNoWord;
-  for (uint32_t w = 0; w < s.nwords; ++w) {
+  const uint32_t nwords = (s.run_flag && *s.run_flag == 0) ? 0u : s.nwords;
+  for (uint32_t w = 0; w < nwords; ++w) {
     if (w == skip) continue;
     // bits that are 1 in some key and 0 in another (0 when there are no keys)
     const unsigned long long var = s.masks[w]->vor & ~s.masks[w]->vand;
@@ -1774,6 +1962,7 @@ __global__ __launch_bounds__(kT) void kernel_ranges_kernel(const SortJob* ks, co
                                                            const uint64_t* k_w_start, const uint64_t* k_w_end,
                                                            const uint32_t* n_k, uint64_t* starts_sorted,
                                                            uint64_t* ends_sorted, AnaCtl* ctl) {
+  if (!ctl->kern_sort) return;  // the chronological path reads the per-device lists instead
   const uint32_t n = *n_k;
   const uint32_t* v = ks->vals[ks->npasses & 1];
   const uint32_t* ve = ke->vals[ke->npasses & 1];
@@ -1801,6 +1990,9 @@ struct RaArgs {
   const uint64_t* pr_w_bytes;
   const uint64_t* pr_w_dev;
   const uint64_t* pr_w_haddr;
+  const uint32_t* ad_kc;
+  const uint64_t* ad_km;
+  const uint64_t* kd_ts;
   AnaCtl* ctl;
   uint8_t* flags;
   odp_report* rep;
@@ -1830,7 +2022,13 @@ __device__ __forceinline__ uint32_t kernels_meeting(const uint64_t* starts, cons
   return count_upto(starts, a, b, hi, true) - count_upto(ends, a, b, lo, false);
 }
 
+// UA in a chronological log, with K and M as for unused transfers: the pair is
+// used when M(ALLOC) reaches the ALLOC's start, or a kernel is logged between
+// the ALLOC and the DELETE (K(DELETE) > K(ALLOC)), or the first kernel logged
+// after the DELETE starts by the DELETE's end. Otherwise the count form's two
+// binary searches decide.
 __global__ __launch_bounds__(kT) void ra_ua_kernel(RaArgs R) {
+  const bool chrono = !R.ctl->kern_sort;
   const uint32_t n = *R.n_pairs;
   const SortJob& s = *R.pr_job;
   const uint32_t* v = s.vals[s.npasses & 1];
@@ -1852,7 +2050,16 @@ __global__ __launch_bounds__(kT) void ra_ua_kernel(RaArgs R) {
     }
     c_grp += group2;
     const uint32_t dev = (uint32_t)R.pr_w_dev[k];
-    if (kernels_meeting(R.starts_sorted, R.ends_sorted, R.ctl, dev, a.t_start, d.t_end) == 0) {
+    bool used;
+    if (chrono) {
+      const uint32_t pa = R.pr_alloc[k], pd = R.pr_del[k];
+      const uint32_t ka = R.ad_kc[pa], kd = R.ad_kc[pd], total = R.ctl->kd_total[dev];
+      used = (ka > 0 && R.ad_km[pa] >= a.t_start) || kd != ka ||
+             (kd < total && R.kd_ts[R.ctl->kd_base[dev] + kd] <= d.t_end);
+    } else {
+      used = kernels_meeting(R.starts_sorted, R.ends_sorted, R.ctl, dev, a.t_start, d.t_end) != 0;
+    }
+    if (!used) {
       f |= ODP_F_UA;
       ++c_ua;
       b_ua += a.bytes;
@@ -1890,58 +2097,189 @@ struct UtArgs {
   const uint64_t* ut_w_addr;
   const uint64_t* ut_w_code;
   const uint64_t* ut_ts;
+  const uint32_t* ut_kc;
+  const uint64_t* ut_km;
   const uint64_t* starts_sorted;
   const uint64_t* ends_sorted;
-  uint8_t* ut_hit;
+  uint32_t* next_q;  // per copy-in (log order): the next copy of its place, or kNone
+  uint8_t* ut_hit;   // per copy-in (log order): 1 unused, 0 used, 2 left to the sorted path
+  const uint64_t* kd_ts;   // KERNEL records per device code in log order: start
+  const uint32_t* kd_idx;  // ... and record index
   AnaCtl* ctl;
   uint8_t* flags;
   odp_report* rep;
 };
 
-__global__ __launch_bounds__(kT) void ut_kernel(UtArgs U) {
+// In a chronological log (no record rejected), with K(c) the number of
+// kernels on c's device logged before copy c, M(c) the latest end among them
+// and k the first kernel on the device logged after c, whether a kernel meets
+// [c.t_start, n.t_start] (n the next copy of c's place) is decided by:
+//   M(c) >= c.t_start (K(c) > 0)   a kernel is still running: used
+//   no k (K(c) counts them all)    nothing can read c later: unused
+//   otherwise the next copy of c's place, searched forward among the copies
+//   logged before k: if it starts before k does, c is overwritten unread
+//   (unused); if it starts when k does, or there is none before k, k can
+//   read c (used).
+// The forward search stops after kUtWindow copies; a copy still undecided
+// then, or any copy of a log with a rejected record, is left to the sorted
+// path below, which the device then switches on.
+constexpr uint32_t kUtWindow = 64;
+
+__global__ __launch_bounds__(kT) void ut_scan_kernel(UtArgs U) {
+  const uint32_t n = *U.n_ut;
+  const bool chrono = U.ctl->first_bad == kNone;
+  if (!chrono) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      U.ctl->kern_sort = 1;
+      if (n) U.ctl->ut_need_sort = 1;
+    }
+    return;
+  }
+  bool undecided = false;
+  for (uint32_t q = blockIdx.x * kT + threadIdx.x; q < n; q += gridDim.x * kT) {
+    const uint64_t code = U.ut_w_code[q];
+    const uint32_t d = (uint32_t)(code & 15);
+    const uint64_t ts = U.ut_ts[q];
+    const uint32_t k = U.ut_kc[q], total = U.ctl->kd_total[d];
+    uint8_t hit;
+    if (k > 0 && U.ut_km[q] >= ts) {
+      hit = 0;
+    } else if (k == total) {
+      hit = 1;
+    } else {
+      const uint32_t kp = U.ctl->kd_base[d] + k;
+      const uint64_t sk = U.kd_ts[kp];
+      const uint32_t kidx = U.kd_idx[kp];
+      const uint64_t addr = U.ut_w_addr[q];
+      hit = 0;
+      // eight candidates' loads in flight at a time
+      bool done = false;
+      for (uint32_t r0 = q + 1; !done; r0 += 8) {
+        uint32_t ix[8];
+        uint64_t ad[8], co[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const uint32_t r = r0 + u;
+          const bool ok = r < n;
+          ix[u] = ok ? U.ut_idx[r] : kNone;
+          ad[u] = ok ? U.ut_w_addr[r] : 0ull;
+          co[u] = ok ? U.ut_w_code[r] : 0ull;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          if (done) continue;
+          const uint32_t r = r0 + u;
+          if (r >= n || ix[u] > kidx) {
+            done = true;  // no next copy before k (past k, the next copy, if any, comes after it)
+          } else if (r - (q + 1) == kUtWindow) {
+            hit = 2;
+            done = true;
+          } else if (ad[u] == addr && co[u] == code) {
+            hit = U.ut_ts[r] < sk ? 1 : 0;
+            done = true;
+          }
+        }
+      }
+      undecided |= hit == 2;
+    }
+    U.ut_hit[q] = hit;
+  }
+  if (__syncthreads_or(undecided) && threadIdx.x == 0) {
+    U.ctl->ut_need_sort = 1;
+    U.ctl->kern_sort = 1;
+  }
+}
+
+// The sorted path (only when switched on). Over the copy-ins sorted stably by
+// (endpoints, source address): the next copy of a copy's place is the element
+// after it when that has the same key.
+// A wavefront takes 64 consecutive sorted elements, so each lane gets its
+// neighbour's key by a lane move and only the last lane loads one more.
+__global__ __launch_bounds__(kT) void ut_next_kernel(UtArgs U) {
+  if (!U.ctl->ut_need_sort) return;
   const uint32_t n = *U.n_ut;
   const SortJob& s = *U.ut_job;
   const uint32_t* v = s.vals[s.npasses & 1];
-  unsigned long long c_ut = 0, b_ut = 0, t_ut = 0;
-  for (uint32_t j = blockIdx.x * kT + threadIdx.x; j < n; j += gridDim.x * kT) {
-    const uint32_t q = v[j];
-    const uint64_t addr = U.ut_w_addr[q], code = U.ut_w_code[q];
-    uint64_t hi = ~0ull;
-    if (j + 1 < n) {
-      const uint32_t qn = v[j + 1];
-      if (U.ut_w_addr[qn] == addr && U.ut_w_code[qn] == code) hi = U.ut_ts[qn];
+  const int lane = threadIdx.x & 63;
+  for (uint32_t j0 = blockIdx.x * kT + (threadIdx.x & ~63u); j0 < n; j0 += gridDim.x * kT) {
+    const uint32_t j = j0 + lane;
+    const bool in = j < n;
+    const uint32_t q = in ? v[j] : 0u;
+    const uint64_t a = in ? U.ut_w_addr[q] : 0ull, c = in ? U.ut_w_code[q] : 0ull;
+    uint64_t an = __shfl_down(a, 1, 64), cn = __shfl_down(c, 1, 64);
+    uint32_t qn = (uint32_t)__shfl_down((int)q, 1, 64);
+    if (lane == 63 && j + 1 < n) {
+      qn = v[j + 1];
+      an = U.ut_w_addr[qn];
+      cn = U.ut_w_code[qn];
     }
-    const uint32_t dev = (uint32_t)(code & 15);
-    const bool unused = kernels_meeting(U.starts_sorted, U.ends_sorted, U.ctl, dev, U.ut_ts[q], hi) == 0;
-    U.ut_hit[q] = unused;
-    if (unused) {
-      const odp_event& e = U.ev[U.ut_idx[q]];
-      ++c_ut;
-      b_ut += e.bytes;
-      t_ut += e.t_end - e.t_start;
+    if (in) U.next_q[q] = (j + 1 < n && an == a && cn == c) ? qn : kNone;
+  }
+}
+
+// Over the copy-ins in log order: whether a kernel on the receiving device
+// meets [copy start, next copy start] (no upper end without a next copy). In a chronological log (no record rejected) a device's kernels
+// in start order are in log order, and with K(q) the number of them logged
+// before copy q and M(q) the latest end among those, a kernel meets the window
+// of copy c with next copy n exactly when: M(c) reaches c's start (K(c) > 0),
+// or a kernel is logged between c and n (K(n) > K(c)), or the first kernel
+// logged after n starts at n's start (a tie). Without a next copy: M(c)
+// reaches c's start, or any kernel is logged after c. Otherwise the two binary
+// searches of the count form decide. The result goes to ut_hit (merged into
+// the flags after the join); only copies the forward search left open are
+// decided here in a chronological log.
+__global__ __launch_bounds__(kT) void ut_eval_kernel(UtArgs U) {
+  if (!U.ctl->ut_need_sort) return;
+  const uint32_t n = *U.n_ut;
+  const bool chrono = U.ctl->first_bad == kNone;
+  for (uint32_t q = blockIdx.x * kT + threadIdx.x; q < n; q += gridDim.x * kT) {
+    if (chrono && U.ut_hit[q] != 2) continue;
+    const uint32_t dev = (uint32_t)(U.ut_w_code[q] & 15);
+    const uint64_t ts = U.ut_ts[q];
+    const uint32_t nq = U.next_q[q];
+    bool read;
+    if (chrono) {
+      const uint32_t lo_d = U.ctl->dev_lo[dev], cnt = U.ctl->dev_hi[dev] - lo_d;
+      const uint32_t k = U.ut_kc[q];
+      read = k > 0 && U.ut_km[q] >= ts;
+      if (!read) {
+        if (nq != kNone) {
+          const uint32_t kn = U.ut_kc[nq];
+          read = kn != k || (kn < cnt && U.starts_sorted[lo_d + kn] == U.ut_ts[nq]);
+        } else {
+          read = k != cnt;
+        }
+      }
+    } else {
+      const uint64_t hi = nq != kNone ? U.ut_ts[nq] : ~0ull;
+      read = kernels_meeting(U.starts_sorted, U.ends_sorted, U.ctl, dev, ts, hi) != 0;
     }
+    U.ut_hit[q] = !read;
+  }
+}
+
+// After the join: ORs F_UT into the flags (copy-ins in log order, so the
+// writes advance through the flag array), sums the unused copies' bytes and
+// time, and adds the removable time of those no other flag already made
+// removable.
+__global__ __launch_bounds__(kT) void ut_merge_kernel(UtArgs U) {
+  const uint32_t n = *U.n_ut;
+  unsigned long long c_ut = 0, b_ut = 0, t_ut = 0, t_el = 0;
+  for (uint32_t q = blockIdx.x * kT + threadIdx.x; q < n; q += gridDim.x * kT) {
+    if (U.ut_hit[q] != 1) continue;
+    const uint32_t i = U.ut_idx[q];
+    const uint8_t f = U.flags[i];
+    U.flags[i] = f | ODP_F_UT;
+    const odp_event& e = U.ev[i];
+    const uint64_t d = e.t_end - e.t_start;
+    ++c_ut;
+    b_ut += e.bytes;
+    t_ut += d;
+    if (!(f & (ODP_F_DD | ODP_F_RT_RX))) t_el += d;
   }
   block_add(&U.rep->ut_events, c_ut);
   block_add(&U.rep->ut_bytes, b_ut);
   block_add(&U.rep->ut_time_ns, t_ut);
-}
-
-// After the join: ORs F_UT into the flags (copy-ins in log order, so the
-// writes advance through the flag array) and adds the removable time of the
-// copies that no other flag already made removable.
-__global__ __launch_bounds__(kT) void ut_merge_kernel(UtArgs U) {
-  const uint32_t n = *U.n_ut;
-  unsigned long long t_el = 0;
-  for (uint32_t q = blockIdx.x * kT + threadIdx.x; q < n; q += gridDim.x * kT) {
-    if (!U.ut_hit[q]) continue;
-    const uint32_t i = U.ut_idx[q];
-    const uint8_t f = U.flags[i];
-    U.flags[i] = f | ODP_F_UT;
-    if (!(f & (ODP_F_DD | ODP_F_RT_RX))) {
-      const odp_event& e = U.ev[i];
-      t_el += e.t_end - e.t_start;
-    }
-  }
   block_add(&U.ctl->elim_ut, t_el);
 }
 
@@ -1971,7 +2309,7 @@ __global__ void finalize_kernel(AnaCtl* ctl, odp_report* rep) {
 // ---------------------------------------------------------------------------
 enum Buf {
   B_CTL, B_JOBS, B_CLS, B_AUX, B_BKEY0, B_BKEY1, B_BVAL0, B_BVAL1, B_TILECNT, B_AD, B_K, B_PR, B_HIST,
-  B_TOTALS, B_SEG, B_SKEY, B_PARTS, B_UT
+  B_TOTALS, B_SEG, B_SKEY, B_PARTS, B_UT, B_WSCAN
 };
 
 // Jobs 1..4 (the subsets) are sorted together in the same launches.
@@ -2005,7 +2343,9 @@ struct Views {
   uint64_t* starts_sorted;
   uint64_t* ends_sorted;
   uint32_t* ut_vals1;
+  uint32_t* next_q;
   uint8_t* ut_hit;
+  WaveScan wscan;
   uint32_t *pr_alloc, *pr_del, *pr_vals, *pr_vals1;
   uint64_t *pr_w_bytes, *pr_w_dev, *pr_w_haddr;
   uint32_t* hist;
@@ -2030,7 +2370,7 @@ Views views(Workspace* ws) {
   v.bv[0] = static_cast<uint32_t*>(b[B_BVAL0].ptr);
   v.bv[1] = static_cast<uint32_t*>(b[B_BVAL1].ptr);
   v.tile_cnt = static_cast<uint32_t*>(b[B_TILECNT].ptr);
-  v.wave_cnt = v.tile_cnt + 2 * (size_t)v.ntc;  // 3 counters per wavefront
+  v.wave_cnt = v.tile_cnt + 2 * (size_t)v.ntc;  // kWaveCnt counters per wavefront
   const size_t cap = v.cap;
   char* pa = static_cast<char*>(b[B_AD].ptr);
   v.S.ad_idx = carve<uint32_t>(pa, cap);
@@ -2039,6 +2379,8 @@ Views views(Workspace* ws) {
   v.S.ad_vals = carve<uint32_t>(pa, cap);
   v.ad_vals1 = carve<uint32_t>(pa, cap);
   v.S.ad_alloc_partner = carve<uint32_t>(pa, cap);
+  v.S.ad_kc = carve<uint32_t>(pa, cap);
+  v.S.ad_km = carve<uint64_t>(pa, cap);
   v.S.ad_op = carve<uint8_t>(pa, cap);
   char* pk = static_cast<char*>(b[B_K].ptr);
   v.S.k_idx = carve<uint32_t>(pk, cap);
@@ -2051,14 +2393,27 @@ Views views(Workspace* ws) {
   v.k_vals_e1 = carve<uint32_t>(pk, cap);
   v.starts_sorted = carve<uint64_t>(pk, cap);
   v.ends_sorted = carve<uint64_t>(pk, cap);
+  v.S.kd_ts = carve<uint64_t>(pk, cap);
+  v.S.kd_idx = carve<uint32_t>(pk, cap);
+  v.S.ctl = v.ctl;
   char* pu = static_cast<char*>(b[B_UT].ptr);
   v.S.ut_idx = carve<uint32_t>(pu, cap);
   v.S.ut_w_addr = carve<uint64_t>(pu, cap);
   v.S.ut_w_code = carve<uint64_t>(pu, cap);
   v.S.ut_ts = carve<uint64_t>(pu, cap);
   v.S.ut_vals = carve<uint32_t>(pu, cap);
+  v.S.ut_kc = carve<uint32_t>(pu, cap);
+  v.S.ut_km = carve<uint64_t>(pu, cap);
   v.ut_vals1 = carve<uint32_t>(pu, cap);
+  v.next_q = carve<uint32_t>(pu, cap);
   v.ut_hit = carve<uint8_t>(pu, cap);
+  char* pw = static_cast<char*>(b[B_WSCAN].ptr);
+  const uint32_t nw = v.ntc * (kT / 64), nchunk = ceil_div32(nw, kScanChunk);
+  v.wscan.cnt = v.wave_cnt;
+  v.wscan.kmax = carve<uint64_t>(pw, (size_t)nw * kEp);
+  v.wscan.ccnt = carve<uint32_t>(pw, (size_t)nchunk * kWaveCnt);
+  v.wscan.cmax = carve<uint64_t>(pw, (size_t)nchunk * kEp);
+  v.wscan.nw = nw;
   char* pp = static_cast<char*>(b[B_PR].ptr);
   v.pr_alloc = carve<uint32_t>(pp, cap);
   v.pr_del = carve<uint32_t>(pp, cap);
@@ -2122,6 +2477,8 @@ void build_jobs(const Views& v, SortJob* hj) {
   // then need no sorting: a stable sort by device keeps them in order.
   hj[kJobKs].first_bad = &ctl->first_bad;
   hj[kJobKs].mono_word = 0;
+  hj[kJobKs].run_flag = &ctl->kern_sort;
+  hj[kJobKe].run_flag = &ctl->kern_sort;
   hj[kJobKe].vals[0] = v.S.k_vals_e;
   hj[kJobKe].vals[1] = v.k_vals_e1;
   hj[kJobKe].words[0] = v.S.k_w_end;
@@ -2137,6 +2494,7 @@ void build_jobs(const Views& v, SortJob* hj) {
   hj[kJobUt].masks[1] = &ctl->m_ut_code;
   hj[kJobUt].word_bytes[1] = 1;
   hj[kJobUt].nwords = 2;
+  hj[kJobUt].run_flag = &ctl->ut_need_sort;
   // paired allocations by (host address, device, bytes)
   hj[kJobPr].n_ptr = &ctl->n_pairs;
   hj[kJobPr].vals[0] = v.pr_vals;
@@ -2164,19 +2522,33 @@ void build_jobs(const Views& v, SortJob* hj) {
 
 }  // namespace
 
+// A captured graph holds workspace addresses: dropped before anything moves.
+static void analyze_drop_graph(Workspace* ws) {
+  if (ws->a_graph) {
+    (void)hipDeviceSynchronize();
+    (void)hipGraphExecDestroy(ws->a_graph);
+    ws->a_graph = nullptr;
+  }
+  ws->ag_ev = nullptr;
+  ws->ag_n = 0;
+}
+
 int analyze_reserve(Workspace* ws, size_t max_events) {
   size_t cap = max_events < 4096 ? 4096 : max_events;
   if (cap <= ws->a_cap_events) return ODP_OK;
+  analyze_drop_graph(ws);
   const uint32_t nt = ceil_div32(cap, kTile);
   DevBuf* b = ws->a_bufs;
   int e;
   if ((e = b[B_CTL].ensure(sizeof(AnaCtl))) || (e = b[B_JOBS].ensure(sizeof(SortJob) * kNumJobs)) ||
       (e = b[B_CLS].ensure(cap)) || (e = b[B_AUX].ensure(cap)) || (e = b[B_BKEY0].ensure(cap * 8)) ||
       (e = b[B_BKEY1].ensure(cap * 8)) || (e = b[B_BVAL0].ensure(cap * 4)) || (e = b[B_BVAL1].ensure(cap * 4)) ||
-      (e = b[B_TILECNT].ensure((size_t)nt * 4 * (2 + 3 * (kT / 64)))) ||
-      (e = b[B_AD].ensure(cap * (4 + 8 + 8 + 4 + 4 + 4 + 1) + 64)) ||
-      (e = b[B_K].ensure(cap * (4 + 8 + 8 + 8 + 4 * 4 + 8 + 8) + 64)) ||
-      (e = b[B_UT].ensure(cap * (4 + 8 + 8 + 8 + 4 + 4 + 1) + 64)) ||
+      (e = b[B_TILECNT].ensure((size_t)nt * 4 * (2 + kWaveCnt * (kT / 64)))) ||
+      (e = b[B_AD].ensure(cap * (4 + 8 + 8 + 4 + 4 + 4 + 4 + 8 + 1) + 64)) ||
+      (e = b[B_K].ensure(cap * (4 + 8 + 8 + 8 + 4 * 4 + 8 + 8 + 8 + 4) + 64)) ||
+      (e = b[B_UT].ensure(cap * (4 + 8 + 8 + 8 + 4 + 4 + 8 + 4 + 4 + 1) + 64)) ||
+      (e = b[B_WSCAN].ensure((size_t)nt * (kT / 64) * kEp * 8 +
+                             (size_t)ceil_div32((size_t)nt * (kT / 64), kScanChunk) * (kWaveCnt * 4 + kEp * 8) + 64)) ||
       (e = b[B_PR].ensure(cap * (4 + 4 + 8 + 8 + 8 + 4 + 4) + 64)) ||
       (e = b[B_HIST].ensure((size_t)kNumJobs * 256 * nt * 4)) ||
       (e = b[B_TOTALS].ensure((size_t)kNumJobs * kMaxPasses * 256 * 4)) ||
@@ -2196,6 +2568,7 @@ int analyze_reserve(Workspace* ws, size_t max_events) {
 }
 
 void analyze_release(Workspace* ws) {
+  analyze_drop_graph(ws);
   for (DevBuf& b : ws->a_bufs) b.release();
   ws->a_cap_events = 0;
   if (ws->a_side) {
@@ -2518,29 +2891,10 @@ uint32_t first_digest_passes(size_t n) {
 
 using namespace odp;
 
-extern "C" int odp_analyze_trace(const odp_event* events, size_t n, uint8_t* out_flags, odp_report* out_report,
-                                 odp_stream_t stream_) {
-  hipStream_t stream = static_cast<hipStream_t>(stream_);
-  if (n > 0xFFFFFFFFull) return set_error(ODP_ERANGE, "odp_analyze_trace: n = %zu above 2^32 - 1", n);
-  if (!out_report) return set_error(ODP_EINVAL, "odp_analyze_trace: null report");
-  if (n > 0 && (!events || !out_flags)) return set_error(ODP_EINVAL, "odp_analyze_trace: null array with n = %zu", n);
-  if (n <= kTinyMax) {
-    // one workgroup, no workspace
-    hipLaunchKernelGGL(analyze_tiny_kernel, dim3(1), dim3(kTinyMax), 0, stream, events, (uint32_t)n, out_flags,
-                       out_report);
-    return check_hip(hipGetLastError(), "odp_analyze_trace launch");
-  }
-  int err = 0;
-  Workspace* ws = workspace_for(stream, &err);
-  if (!ws) return err;
-  hipStreamCaptureStatus capst = hipStreamCaptureStatusNone;
-  ODP_HIP(hipStreamIsCapturing(stream, &capst));
-  if (n > ws->a_cap_events || !ws->a_cap_events) {
-    if (capst != hipStreamCaptureStatusNone)
-      return set_error(ODP_ENOMEM, "odp_analyze_trace: workspace for %zu records not reserved before capture", n);
-    int e = analyze_reserve(ws, n);
-    if (e) return e;
-  }
+// The launch sequence of one analysis of more than kTinyMax records, in the
+// workspace `ws` (reserved for n), enqueued on `stream`.
+static int enqueue_analysis(Workspace* ws, const odp_event* events, size_t n, uint8_t* out_flags,
+                            odp_report* out_report, hipStream_t stream) {
   const Views v = views(ws);
   const uint32_t nn = (uint32_t)n;
   const uint32_t nt = n ? ceil_div32(n, kTile) : 1;  // tiles of this call
@@ -2555,7 +2909,7 @@ extern "C" int odp_analyze_trace(const odp_event* events, size_t n, uint8_t* out
     return check_hip(hipGetLastError(), "odp_analyze_trace launch");
   }
   hipLaunchKernelGGL(classify_kernel, dim3(nt), dim3(kT), 0, stream, events, nn, out_flags, v.cls, v.aux, v.bk[0],
-                     v.bv[0], v.wave_cnt, v.parts);
+                     v.bv[0], v.wave_cnt, v.wscan.kmax, v.parts);
   // the classification's counts, digest masks, first rejected record and endpoint range
   hipLaunchKernelGGL(reduce_parts_kernel, dim3(S_AD_DEV_OR), dim3(kT), 0, stream, v.parts, nt, 0u, ctl, out_report);
 
@@ -2566,46 +2920,38 @@ extern "C" int odp_analyze_trace(const odp_event* events, size_t n, uint8_t* out
   ODP_HIP(hipEventRecord(ws->a_fork, stream));
   ODP_HIP(hipStreamWaitEvent(side, ws->a_fork, 0));
 
-  // Records by digest (up to 8 passes), then duplicates and round trips.
-  const JobSet Jb{v.jobs + kJobBig, 1, nt};
   const bool small = n <= kSmallMax;  // every job then has at most kSmallMax elements
-  const uint32_t kfirst = small ? 0u : first_digest_passes(n);
-  // the digest histograms take two tiles per block on long logs (measured a
-  // little faster than one: the per-block start-up is amortised)
-  const JobSet Jh{v.jobs + kJobBig, 1, nt > 4u * (uint32_t)cus ? (nt + 1) / 2 : nt};
-  hipLaunchKernelGGL(sort_plan_kernel, dim3(1), dim3(64), 0, stream, Jb, kfirst);
-  if (small) {
-    hipLaunchKernelGGL(sort_small_kernel, dim3(Jb.njobs), dim3(kQT), 0, stream, Jb);
-  } else {
-    for (uint32_t p = 0; p < 8; ++p) {
-      if (kfirst && p >= kfirst) hipLaunchKernelGGL(sort_collide_kernel, dim3(nt), dim3(kT), 0, stream, v.jobs + kJobBig, p);
-      hipLaunchKernelGGL(sort_hist_kernel, dim3(Jh.stride), dim3(kT), 0, stream, Jh, p);
-      hipLaunchKernelGGL(sort_scan_kernel, dim3(256), dim3(kT), 0, stream, Jb, p);
-      hipLaunchKernelGGL(sort_scatter_kernel, dim3(nt), dim3(kST), 0, stream, Jb, p);
-    }
-  }
-  DDArgs D;
-  D.ev = events;
-  D.n = nn;
-  D.aux = v.aux;
-  D.job = v.jobs + kJobBig;
-  D.ctl = ctl;
-  D.agg = v.agg;
-  D.carry = v.carry;
-  D.flags = out_flags;
-  D.rep = out_report;
-  D.parts = v.parts;
-  hipLaunchKernelGGL(ddrt_agg_kernel, dim3(nt), dim3(kT), 0, stream, D);
-  hipLaunchKernelGGL(ddrt_carry_kernel, dim3(1), dim3(kCT), 0, stream, D, nt * (kT / 64));
-  hipLaunchKernelGGL(ddrt_final_kernel, dim3(nt), dim3(kT), 0, stream, D);
-  hipLaunchKernelGGL(reduce_parts_kernel, dim3(kSlots - S_DD_EVENTS), dim3(kT), 0, stream, v.parts, nt,
-                     (uint32_t)S_DD_EVENTS, ctl, out_report);
-
-  // The allocation path on the side stream (enqueued after the digest path,
-  // whose chain is the longer one, so that one starts first).
-  hipLaunchKernelGGL(scan_counts_kernel<3>, dim3(1), dim3(1024), 0, side, v.wave_cnt, nt * (kT / 64), &ctl->n_ad,
-                     &ctl->n_k, &ctl->n_ut);
-  hipLaunchKernelGGL(subset_scatter_kernel, dim3(nt), dim3(kT), 0, side, events, v.cls, nn, v.wave_cnt, v.S, v.parts);
+  // The allocation path on the side stream, enqueued first: the runtime
+  // issues launches (and a graph's nodes) in this order, and this path waits
+  // only for the classification.
+  WaveScan WS = v.wscan;
+  WS.nw = nt * (kT / 64);
+  const uint32_t nchunk = ceil_div32(WS.nw, kScanChunk);
+  hipLaunchKernelGGL(wave_scan_local_kernel, dim3(nchunk), dim3(1024), 0, side, WS);
+  hipLaunchKernelGGL(wave_scan_chunks_kernel, dim3(1), dim3(1024), 0, side, WS, nchunk, &ctl->n_ad, &ctl->n_k,
+                     &ctl->n_ut, ctl);
+  hipLaunchKernelGGL(subset_scatter_kernel, dim3(nt), dim3(kT), 0, side, events, v.cls, nn, WS, v.S, v.parts);
+  // Unused transfers (their flags are merged after the join).
+  UtArgs U;
+  U.ev = events;
+  U.ut_job = v.jobs + kJobUt;
+  U.n_ut = &ctl->n_ut;
+  U.ut_idx = v.S.ut_idx;
+  U.ut_w_addr = v.S.ut_w_addr;
+  U.ut_w_code = v.S.ut_w_code;
+  U.ut_ts = v.S.ut_ts;
+  U.ut_kc = v.S.ut_kc;
+  U.ut_km = v.S.ut_km;
+  U.starts_sorted = v.starts_sorted;
+  U.ends_sorted = v.ends_sorted;
+  U.next_q = v.next_q;
+  U.ut_hit = v.ut_hit;
+  U.kd_ts = v.S.kd_ts;
+  U.kd_idx = v.S.kd_idx;
+  U.ctl = ctl;
+  U.flags = out_flags;
+  U.rep = out_report;
+  hipLaunchKernelGGL(ut_scan_kernel, dim3(grid_map), dim3(kT), 0, side, U);
   hipLaunchKernelGGL(reduce_parts_kernel, dim3(S_DD_EVENTS - S_AD_DEV_OR), dim3(kT), 0, side, v.parts, nt,
                      (uint32_t)S_AD_DEV_OR, ctl, out_report);
   // ALLOC/DELETE by (device, address), kernels by (device, start) and (device,
@@ -2646,27 +2992,12 @@ extern "C" int odp_analyze_trace(const odp_event* events, size_t n, uint8_t* out
   P.rep = out_report;
   hipLaunchKernelGGL(pair_kernel, dim3(grid_map), dim3(kT), 0, side, P);
   hipLaunchKernelGGL(pair_count_kernel, dim3(nt), dim3(kT), 0, side, P);
-  hipLaunchKernelGGL(scan_counts_kernel<2>, dim3(1), dim3(1024), 0, side, v.tile_cnt, nt, &ctl->n_pairs, nullptr,
-                     nullptr);
+  hipLaunchKernelGGL(scan_counts_kernel<2>, dim3(1), dim3(1024), 0, side, v.tile_cnt, nt, &ctl->n_pairs, nullptr);
   hipLaunchKernelGGL(pair_scatter_kernel, dim3(nt), dim3(kT), 0, side, P);
   hipLaunchKernelGGL(kernel_ranges_kernel, dim3(grid_map), dim3(kT), 0, side, v.jobs + kJobKs, v.jobs + kJobKe,
                      v.S.k_w_dev, v.S.k_w_start, v.S.k_w_end, &ctl->n_k, v.starts_sorted, v.ends_sorted, ctl);
-  // Unused transfers (their flags are merged after the join).
-  UtArgs U;
-  U.ev = events;
-  U.ut_job = v.jobs + kJobUt;
-  U.n_ut = &ctl->n_ut;
-  U.ut_idx = v.S.ut_idx;
-  U.ut_w_addr = v.S.ut_w_addr;
-  U.ut_w_code = v.S.ut_w_code;
-  U.ut_ts = v.S.ut_ts;
-  U.starts_sorted = v.starts_sorted;
-  U.ends_sorted = v.ends_sorted;
-  U.ut_hit = v.ut_hit;
-  U.ctl = ctl;
-  U.flags = out_flags;
-  U.rep = out_report;
-  hipLaunchKernelGGL(ut_kernel, dim3(grid_map), dim3(kT), 0, side, U);
+  hipLaunchKernelGGL(ut_next_kernel, dim3(grid_map), dim3(kT), 0, side, U);
+  hipLaunchKernelGGL(ut_eval_kernel, dim3(grid_map), dim3(kT), 0, side, U);
 
   // Second sort: pairs by (host address, device, bytes).
   const JobSet J2{v.jobs + kJobPr, 1, side_blocks};
@@ -2693,14 +3024,119 @@ extern "C" int odp_analyze_trace(const odp_event* events, size_t n, uint8_t* out
   R.pr_w_bytes = v.pr_w_bytes;
   R.pr_w_dev = v.pr_w_dev;
   R.pr_w_haddr = v.pr_w_haddr;
+  R.ad_kc = v.S.ad_kc;
+  R.ad_km = v.S.ad_km;
+  R.kd_ts = v.S.kd_ts;
   R.ctl = ctl;
   R.flags = out_flags;
   R.rep = out_report;
   hipLaunchKernelGGL(ra_ua_kernel, dim3(grid_map), dim3(kT), 0, side, R);
+  // Records by digest (up to 8 passes), then duplicates and round trips, on
+  // the caller's stream.
+  const JobSet Jb{v.jobs + kJobBig, 1, nt};
+  const uint32_t kfirst = small ? 0u : first_digest_passes(n);
+  // the digest histograms take two tiles per block on long logs (measured a
+  // little faster than one: the per-block start-up is amortised)
+  const JobSet Jh{v.jobs + kJobBig, 1, nt > 4u * (uint32_t)cus ? (nt + 1) / 2 : nt};
+  hipLaunchKernelGGL(sort_plan_kernel, dim3(1), dim3(64), 0, stream, Jb, kfirst);
+  if (small) {
+    hipLaunchKernelGGL(sort_small_kernel, dim3(Jb.njobs), dim3(kQT), 0, stream, Jb);
+  } else {
+    for (uint32_t p = 0; p < 8; ++p) {
+      if (kfirst && p >= kfirst) hipLaunchKernelGGL(sort_collide_kernel, dim3(nt), dim3(kT), 0, stream, v.jobs + kJobBig, p);
+      hipLaunchKernelGGL(sort_hist_kernel, dim3(Jh.stride), dim3(kT), 0, stream, Jh, p);
+      hipLaunchKernelGGL(sort_scan_kernel, dim3(256), dim3(kT), 0, stream, Jb, p);
+      hipLaunchKernelGGL(sort_scatter_kernel, dim3(nt), dim3(kST), 0, stream, Jb, p);
+    }
+  }
+  DDArgs D;
+  D.ev = events;
+  D.n = nn;
+  D.aux = v.aux;
+  D.job = v.jobs + kJobBig;
+  D.ctl = ctl;
+  D.agg = v.agg;
+  D.carry = v.carry;
+  D.flags = out_flags;
+  D.rep = out_report;
+  D.parts = v.parts;
+  hipLaunchKernelGGL(ddrt_agg_kernel, dim3(nt), dim3(kT), 0, stream, D);
+  hipLaunchKernelGGL(ddrt_carry_kernel, dim3(1), dim3(kCT), 0, stream, D, nt * (kT / 64));
+  hipLaunchKernelGGL(ddrt_final_kernel, dim3(nt), dim3(kT), 0, stream, D);
+  hipLaunchKernelGGL(reduce_parts_kernel, dim3(kSlots - S_DD_EVENTS), dim3(kT), 0, stream, v.parts, nt,
+                     (uint32_t)S_DD_EVENTS, ctl, out_report);
+
   ODP_HIP(hipEventRecord(ws->a_join, side));
 
   ODP_HIP(hipStreamWaitEvent(stream, ws->a_join, 0));
   hipLaunchKernelGGL(ut_merge_kernel, dim3(grid_map), dim3(kT), 0, stream, U);
   hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(64), 0, stream, ctl, out_report);
   return check_hip(hipGetLastError(), "odp_analyze_trace launch");
+}
+
+extern "C" int odp_analyze_trace(const odp_event* events, size_t n, uint8_t* out_flags, odp_report* out_report,
+                                 odp_stream_t stream_) {
+  hipStream_t stream = static_cast<hipStream_t>(stream_);
+  if (n > 0xFFFFFFFFull) return set_error(ODP_ERANGE, "odp_analyze_trace: n = %zu above 2^32 - 1", n);
+  if (!out_report) return set_error(ODP_EINVAL, "odp_analyze_trace: null report");
+  if (n > 0 && (!events || !out_flags)) return set_error(ODP_EINVAL, "odp_analyze_trace: null array with n = %zu", n);
+  if (n <= kTinyMax) {
+    // one workgroup, no workspace
+    hipLaunchKernelGGL(analyze_tiny_kernel, dim3(1), dim3(kTinyMax), 0, stream, events, (uint32_t)n, out_flags,
+                       out_report);
+    return check_hip(hipGetLastError(), "odp_analyze_trace launch");
+  }
+  int err = 0;
+  Workspace* ws = workspace_for(stream, &err);
+  if (!ws) return err;
+  hipStreamCaptureStatus capst = hipStreamCaptureStatusNone;
+  ODP_HIP(hipStreamIsCapturing(stream, &capst));
+  const bool capturing = capst != hipStreamCaptureStatusNone;
+  if (n > ws->a_cap_events || !ws->a_cap_events) {
+    if (capturing)
+      return set_error(ODP_ENOMEM, "odp_analyze_trace: workspace for %zu records not reserved before capture", n);
+    int e = analyze_reserve(ws, n);
+    if (e) return e;
+  }
+  if (capturing) return enqueue_analysis(ws, events, n, out_flags, out_report, stream);
+  // The sequence is some fifty launches on two streams; a call repeated with
+  // the same arguments replays it as one graph instead (the first repeat
+  // captures it), so the host's launch cost leaves the device's time.
+  const bool same = ws->ag_ev == events && ws->ag_n == n && ws->ag_flags == out_flags && ws->ag_rep == out_report;
+  if (!same) {
+    if (ws->a_graph) {
+      ODP_HIP(hipGraphExecDestroy(ws->a_graph));
+      ws->a_graph = nullptr;
+    }
+    ws->ag_ev = events;
+    ws->ag_n = n;
+    ws->ag_flags = out_flags;
+    ws->ag_rep = out_report;
+    return enqueue_analysis(ws, events, n, out_flags, out_report, stream);
+  }
+  if (!ws->a_graph) {
+    hipStream_t cs;
+    ODP_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    hipError_t he = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    int e = ODP_OK;
+    if (he == hipSuccess) {
+      e = enqueue_analysis(ws, events, n, out_flags, out_report, cs);
+      he = hipStreamEndCapture(cs, &g);
+    }
+    (void)hipStreamDestroy(cs);
+    if (he != hipSuccess) return check_hip(he, "analysis graph capture");
+    if (e) {
+      if (g) (void)hipGraphDestroy(g);
+      return e;
+    }
+    he = hipGraphInstantiate(&ws->a_graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (he != hipSuccess) {
+      ws->a_graph = nullptr;
+      return check_hip(he, "analysis graph instantiate");
+    }
+  }
+  ODP_HIP(hipGraphLaunch(ws->a_graph, stream));
+  return ODP_OK;
 }

@@ -61,6 +61,12 @@ struct Workspace {
   size_t a_cap_events = 0;
   hipStream_t a_side = nullptr;
   hipEvent_t a_fork = nullptr, a_join = nullptr;
+  // graph of the analysis launches for repeated calls with the same arguments
+  hipGraphExec_t a_graph = nullptr;
+  const void* ag_ev = nullptr;  // arguments of the graph (a_graph set) or of the last direct call
+  size_t ag_n = 0;
+  void* ag_flags = nullptr;
+  void* ag_rep = nullptr;
   // graph cache of the batched digest
   hipGraphExec_t graph = nullptr;
   const void* g_ptrs = nullptr;

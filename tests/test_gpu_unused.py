@@ -161,3 +161,25 @@ def test_copies_from_every_endpoint(odp):
     ev["bytes"] = 64
     fg, rg = check(odp, ev)
     assert rg["ut_events"] > 1000
+
+
+@pytest.mark.parametrize("every", [40, 500])
+def test_long_kernel_epochs(odp, every):
+    """Chronological logs whose kernels are far apart: a copy's next copy is
+    searched forward among the copies before the next kernel; past 64 copies
+    the sorted path decides (switched on by the device). Ties of a copy's start
+    with the next kernel's start occur on purpose."""
+    rng = np.random.default_rng(every)
+    m = 30_000
+    ev = W.empty_events(m)
+    is_k = (np.arange(m) % every) == every - 1
+    ev["op"] = np.where(is_k, W.KERNEL, rng.choice([W.H2D, W.D2H], size=m, p=[0.8, 0.2]))
+    ev["src_dev"] = np.where(ev["op"] == W.D2H, 0, -1)
+    ev["dst_dev"] = np.where(ev["op"] == W.D2H, -1, rng.integers(0, 2, size=m))
+    ev["src_addr"] = W.HOST_BASE + 4096 * rng.integers(0, 5, size=m).astype(np.uint64)
+    ev["digest"] = rng.integers(0, 100, size=m).astype(np.uint64)
+    ev["t_start"] = np.cumsum(rng.integers(0, 2, size=m)).astype(np.uint64)
+    ev["t_end"] = ev["t_start"] + rng.integers(0, 3, size=m).astype(np.uint64)
+    ev["bytes"] = 64
+    fg, rg = check(odp, ev)
+    assert 0 < rg["ut_events"] < rg["n_transfers"]
