@@ -113,8 +113,8 @@ struct SortJob {
   uint32_t npasses;                // device-computed: the passes that run
   // The digest job may sort on its least significant varying bytes first
   // (np_first passes) and run each further pass (up to np_full) only when a
-  // check finds two different keys that agree on the bytes sorted so far;
-  // other jobs: all equal.
+  // check finds a long run of equal sorted bytes holding two different keys
+  // (short ones are sorted in place); other jobs: all equal.
   uint32_t np_first, np_full;
   uint8_t pw[kMaxPasses], ps[kMaxPasses];
   uint8_t pg[kMaxPasses];          // 1: this pass reads its key word from words[pw] by value
@@ -826,40 +826,145 @@ __global__ void sort_plan_kernel(JobSet J, uint32_t first_passes) {
   s.npasses = s.np_first;
 }
 
-// Before deferred pass p (p >= np_first): the keys, sorted on the bytes of
-// passes 0..p-1, are grouped by those bytes only. Adjacent keys that agree on
-// them but differ elsewhere mean two digests share them (their groups may then
-// interleave), and pass p is switched on; the check before pass p+1 then looks
-// again. Otherwise equal sorted bytes already imply equal keys, so each group
-// of equal keys is contiguous and in input order, which is all the duplicate
-// and round-trip scans use, and the remaining passes stay off. Runs only while
-// every pass before p ran (npasses == p).
-__global__ __launch_bounds__(kT) void sort_collide_kernel(SortJob* job, uint32_t p) {
+// Local fix of the digest job, launched before each deferred pass p (p >=
+// np_first) and once after the last. After the passes 0..q-1 that ran, the
+// keys, sorted stably on those bytes, fall into runs of equal sorted bytes.
+// The duplicate and round-trip scans need each digest's elements together and
+// in input order only, so a run that holds one digest is done, and a run that
+// holds several (which may interleave) is done once sorted stably by the whole
+// key. Runs longer than kFixMax that hold several digests switch pass q on
+// instead; shorter ones are sorted in place.
+//
+// Check (npasses == p): a "collision" is an element whose key differs from its
+// predecessor's in the same run. Each block stages a tile of kFixTile keys with
+// kFixHalo more on each side in LDS, which holds every key a walk of at most
+// kFixMax steps reaches. The first collision of each run walks to the run's
+// ends and records the run (start << 32 | length) in the buffers pass p would
+// write: tile t keeps its count in vals[(p+1)&1][t] and its runs at
+// keys[(p+1)&1][t * kFixTile/2 ...]; a tile holds at most kFixTile/2 first
+// collisions, since each has its run's previous element before it. No key
+// moves in the check, so every walk sees the same array.
+// Sort (npasses == p-1, so pass p-1 did not run): a block per tile of the
+// check before p-1, a thread per recorded run, each an insertion sort; the
+// runs are disjoint.
+constexpr uint32_t kFixMax = 128;
+constexpr uint32_t kFixTile = 4 * kT;
+constexpr uint32_t kFixHalo = kFixMax + 1;
+constexpr uint32_t kWalkIdle = 0, kWalking = 1, kWalkEnd = 2, kWalkLong = 3;
+
+__global__ __launch_bounds__(kT) void sort_fix_kernel(SortJob* job, uint32_t p) {
   SortJob& s = *job;
-  if (s.npasses != p || p >= s.np_full) return;
+  const uint32_t np = s.npasses;
   const uint32_t n = *s.n_ptr;
+  const uint32_t nft = (n + kFixTile - 1) / kFixTile;
+  if (p >= 1 && np == p - 1 && p - 1 < s.np_full) {
+    const unsigned long long* runs = s.keys[p & 1];
+    const uint32_t* cnt = s.vals[p & 1];
+    unsigned long long* k = s.keys[(p - 1) & 1];
+    uint32_t* v = s.vals[(p - 1) & 1];
+    for (uint32_t t = blockIdx.x; t < nft; t += gridDim.x) {
+      const uint32_t c = cnt[t];
+      for (uint32_t r = threadIdx.x; r < c; r += kT) {
+        const unsigned long long run = runs[(size_t)t * (kFixTile / 2) + r];
+        const uint32_t j = (uint32_t)(run >> 32), e = j + (uint32_t)run;
+        for (uint32_t a = j + 1; a < e; ++a) {  // stable: equal keys keep their order
+          const unsigned long long ka = k[a];
+          const uint32_t va = v[a];
+          uint32_t b = a;
+          while (b > j && k[b - 1] > ka) {
+            k[b] = k[b - 1];
+            v[b] = v[b - 1];
+            --b;
+          }
+          k[b] = ka;
+          v[b] = va;
+        }
+      }
+    }
+    return;
+  }
+  if (np != p || p >= s.np_full) return;
   unsigned long long mask = 0;
   for (uint32_t q = 0; q < p; ++q) mask |= 0xFFull << s.ps[q];
   const unsigned long long* k = s.keys[p & 1];
-  const int lane = threadIdx.x & 63;
-  const uint32_t wb = (blockIdx.x * (kT / 64) + (threadIdx.x >> 6)) * kWaveElems;
-  unsigned long long key[kRounds];
-#pragma unroll
-  for (int r = 0; r < kRounds; ++r) {
-    const uint32_t j = wb + r * 64 + lane;
-    key[r] = j < n ? k[j] : 0ull;
+  unsigned long long* runs = s.keys[(p + 1) & 1];
+  uint32_t* cnt = s.vals[(p + 1) & 1];
+  __shared__ unsigned long long s_k[kFixTile + 2 * kFixHalo];
+  __shared__ uint32_t s_w[kT / 64];
+  const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  bool long_mixed = false;
+  for (uint32_t t = blockIdx.x; t < nft; t += gridDim.x) {
+    // s_k[i] holds key lo + i (where 0 <= lo + i < n)
+    const long long lo = (long long)t * kFixTile - kFixHalo;
+    for (uint32_t i = threadIdx.x; i < kFixTile + 2 * kFixHalo; i += kT) {
+      const long long g = lo + i;
+      if (g >= 0 && g < (long long)n) s_k[i] = k[g];
+    }
+    __syncthreads();
+    uint32_t recorded = 0;
+    for (uint32_t r = 0; r < kFixTile / kT; ++r) {
+      const uint32_t j = t * kFixTile + r * kT + threadIdx.x;
+      // Both walks loop while any lane of the wavefront still walks, so all
+      // lanes leave them together and their outcome is a plain integer
+      // (hipcc has lost per-lane booleans set in a loop that lanes leave at
+      // different trips).
+      uint32_t st = 0, e = 0, back = kWalkIdle, fwd = kWalkIdle;
+      unsigned long long kj = 0, kp = 0;
+      if (j > 0 && j < n) {
+        kj = s_k[j - lo];
+        kp = s_k[j - 1 - lo];
+        if (kj != kp && ((kj ^ kp) & mask) == 0) {
+          st = j - 1;
+          back = kWalking;
+        }
+      }
+      // back to the run's start st (every key in [st, j) equals kp), or to
+      // an earlier collision
+      while (__ballot(back == kWalking)) {
+        if (back == kWalking) {
+          if (j - st >= kFixMax) {
+            back = kWalkLong;
+          } else if (st == 0) {
+            back = kWalkEnd;
+          } else {
+            const unsigned long long c = s_k[st - 1 - lo];
+            if (((c ^ kj) & mask) != 0) back = kWalkEnd;
+            else if (c != kp) back = kWalkIdle;  // not the run's first collision
+            else --st;
+          }
+        }
+      }
+      // forward to the run's end e (exclusive)
+      if (back == kWalkEnd) {
+        e = j + 1;
+        fwd = kWalking;
+      }
+      while (__ballot(fwd == kWalking)) {
+        if (fwd == kWalking) {
+          if (e - st > kFixMax) fwd = kWalkLong;
+          else if (e >= n || ((s_k[e - lo] ^ kj) & mask) != 0) fwd = kWalkEnd;
+          else ++e;
+        }
+      }
+      long_mixed |= back == kWalkLong || fwd == kWalkLong;
+      const bool rec = fwd == kWalkEnd;
+      const uint64_t m = __ballot(rec);
+      if (lane == 0) s_w[w] = (uint32_t)__popcll(m);
+      __syncthreads();
+      uint32_t off = recorded, tot = 0;
+      for (uint32_t q = 0; q < kT / 64; ++q) {
+        off += q < w ? s_w[q] : 0u;
+        tot += s_w[q];
+      }
+      if (rec)
+        runs[(size_t)t * (kFixTile / 2) + off + (uint32_t)__popcll(m & lanemask_lt())] =
+            ((unsigned long long)st << 32) | (e - st);
+      recorded += tot;
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) cnt[t] = recorded;
   }
-  const unsigned long long before = (lane == 0 && wb > 0 && wb < n) ? k[wb - 1] : key[0];
-  bool hit = false;
-#pragma unroll
-  for (int r = 0; r < kRounds; ++r) {
-    const uint32_t j = wb + r * 64 + lane;
-    unsigned long long prev = __shfl_up(key[r], 1, 64);
-    const unsigned long long last = __shfl(key[r > 0 ? r - 1 : 0], 63, 64);
-    if (lane == 0) prev = r > 0 ? last : before;
-    if (j < n && j > 0) hit |= (((key[r] ^ prev) & mask) == 0) && key[r] != prev;
-  }
-  if (__syncthreads_or(hit) && threadIdx.x == 0) s.npasses = p + 1;
+  if (__syncthreads_or(long_mixed) && threadIdx.x == 0) s.npasses = p + 1;
 }
 
 // Locates this block's job and first tile; returns false when the block has
@@ -2863,28 +2968,14 @@ __global__ __launch_bounds__(kTinyMax) void analyze_tiny_kernel(const odp_event*
   }
 }
 
-// Digest passes to run before the first collision check, for n records (at
-// most n distinct digests, uniformly distributed): the k in 4..8 with the least
-// expected cost in passes, where a check costs a fifth of a pass, pass j (j >=
-// k) runs only when two distinct digests agree on their low j bytes, with
-// probability at most P(j) = n^2 / 2^(8j+1), and is preceded by a check.
-// 8 means no check.
+// Digest passes to run before the first local fix, for n records (at most n
+// distinct digests): the least k with 2^(8k) >= 16 n, so that a run of equal
+// low bytes holds on average at most 1/16 of a digest besides its own and the
+// local sorts (a few, short) replace the remaining passes.
 uint32_t first_digest_passes(size_t n) {
-  const double nn = (double)n * (double)n;
-  constexpr double kCheck = 0.2;
-  // tail[j]: expected cost from just after pass j-1 on, checks included
-  double tail[9];
-  tail[8] = 0.0;
-  for (int j = 7; j >= 4; --j)
-    tail[j] = kCheck + std::min(1.0, std::ldexp(nn, -(8 * j + 1))) * (1.0 + tail[j + 1]);
-  uint32_t best = 8;
-  double best_cost = 8.0;
-  for (uint32_t k = 4; k < 8; ++k)
-    if (k + tail[k] < best_cost) {
-      best_cost = k + tail[k];
-      best = k;
-    }
-  return best;
+  uint32_t k = 1;
+  while (k < 8 && std::ldexp(1.0, 8 * (int)k) < 16.0 * (double)n) ++k;
+  return k;
 }
 
 }  // namespace odp
@@ -3035,6 +3126,7 @@ static int enqueue_analysis(Workspace* ws, const odp_event* events, size_t n, ui
   // the caller's stream.
   const JobSet Jb{v.jobs + kJobBig, 1, nt};
   const uint32_t kfirst = small ? 0u : first_digest_passes(n);
+  const uint32_t nft = (uint32_t)((n + kFixTile - 1) / kFixTile);  // tiles of the local fix
   // the digest histograms take two tiles per block on long logs (measured a
   // little faster than one: the per-block start-up is amortised)
   const JobSet Jh{v.jobs + kJobBig, 1, nt > 4u * (uint32_t)cus ? (nt + 1) / 2 : nt};
@@ -3043,11 +3135,12 @@ static int enqueue_analysis(Workspace* ws, const odp_event* events, size_t n, ui
     hipLaunchKernelGGL(sort_small_kernel, dim3(Jb.njobs), dim3(kQT), 0, stream, Jb);
   } else {
     for (uint32_t p = 0; p < 8; ++p) {
-      if (kfirst && p >= kfirst) hipLaunchKernelGGL(sort_collide_kernel, dim3(nt), dim3(kT), 0, stream, v.jobs + kJobBig, p);
+      if (kfirst && p >= kfirst) hipLaunchKernelGGL(sort_fix_kernel, dim3(nft), dim3(kT), 0, stream, v.jobs + kJobBig, p);
       hipLaunchKernelGGL(sort_hist_kernel, dim3(Jh.stride), dim3(kT), 0, stream, Jh, p);
       hipLaunchKernelGGL(sort_scan_kernel, dim3(256), dim3(kT), 0, stream, Jb, p);
       hipLaunchKernelGGL(sort_scatter_kernel, dim3(nt), dim3(kST), 0, stream, Jb, p);
     }
+    if (kfirst) hipLaunchKernelGGL(sort_fix_kernel, dim3(nft), dim3(kT), 0, stream, v.jobs + kJobBig, 8u);
   }
   DDArgs D;
   D.ev = events;

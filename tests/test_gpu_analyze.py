@@ -206,14 +206,14 @@ def test_one_workgroup_sort_threshold(odp, n):
 
 @pytest.mark.parametrize("m,seed", [(30_000, 1), (1_000_000, 2)])
 def test_digests_sharing_low_bytes(odp, m, seed):
-    """The digest sort first orders by the low bytes only (4 of them at 30,000
-    records, 5 at a million); before each further pass a check switches that
-    pass on only when two different digests still agree on every byte sorted
-    so far. Planted digests that differ from another only in byte 6 or 7,
-    interleaved in time with it, need every pass (else their groups interleave
-    and the flags go wrong); planted ones that differ only in byte 4 need the
-    passes up to byte 4 and no more; unrelated random digests take whatever
-    the checks find. Every case must give the oracle's result."""
+    """The digest sort first orders by the low bytes only (3 of them at 30,000
+    records and at a million, 4 at ten million); runs of equal low bytes that hold several digests
+    are then sorted in place by the whole digest when they are short, and
+    switch the next pass on when they are long. Planted digests that differ
+    from another only in byte 6 or 7, or only in byte 4, interleaved in time
+    with it, land in short mixed runs (else their groups interleave and the
+    flags go wrong); unrelated random digests take whatever the checks find.
+    Every case must give the oracle's result."""
     rng = np.random.default_rng(seed)
     ev = W.empty_events(m)
     ev["op"] = rng.choice([W.H2D, W.D2H, W.D2D], size=m)
@@ -235,6 +235,32 @@ def test_digests_sharing_low_bytes(odp, m, seed):
     ev["digest"] = high
     fg, rg = check(odp, ev)
     assert rg["dd_events"] > m // 4 and rg["rt_pairs"] > 0
+
+
+@pytest.mark.parametrize("m,byte", [(30_000, 7), (30_000, 3), (1_000_000, 5)])
+def test_long_runs_of_shared_low_bytes(odp, m, byte):
+    """Two groups of 400 records each whose digests differ only in one high
+    byte, interleaved in time, form one run of equal low bytes longer than any
+    run sorted in place: the passes up to that byte must run, and the other
+    records (random digests, some in short mixed runs) still come out right."""
+    rng = np.random.default_rng(m + byte)
+    ev = W.empty_events(m)
+    ev["op"] = rng.choice([W.H2D, W.D2H, W.D2D], size=m)
+    ev["src_dev"] = rng.integers(-1, 3, size=m)
+    ev["dst_dev"] = rng.integers(-1, 3, size=m)
+    ev["t_start"] = np.arange(m, dtype=np.uint64) * 3
+    ev["t_end"] = ev["t_start"] + 2
+    top = np.uint64(0xFFFFFFFFFFFFFFFE)
+    base = rng.integers(0, top, size=m // 8, dtype=np.uint64, endpoint=True)
+    dig = rng.choice(base, size=m)
+    dig = np.where(rng.random(m) < 0.1, dig ^ np.uint64(1 << 60), dig)
+    a = np.uint64(0x0123456789ABCDEF)
+    pos = rng.choice(m, size=800, replace=False)
+    dig[pos[:400]] = a
+    dig[pos[400:]] = a ^ np.uint64(0x80 << (8 * byte))
+    ev["digest"] = dig
+    fg, rg = check(odp, ev)
+    assert rg["dd_events"] >= 792
 
 
 def big_subset_log(rng, m, kind):
