@@ -61,6 +61,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--blocks-per-cu", type=int, default=None, help="batched digest tuning override")
     ap.add_argument("--split-bytes", type=int, default=None, help="batched digest tuning override")
+    ap.add_argument("--chunk-nodes", type=int, default=None, help="batched digest tuning override")
     ap.add_argument("--tuning", default=None, metavar="JSON",
                     help="apply a tuning file written by paper_2601_12713_amd/autotune.py")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -694,8 +695,8 @@ def main():
     if args.tuning:
         from paper_2601_12713_amd import autotune
         autotune.apply(args.tuning)
-    if args.blocks_per_cu is not None or args.split_bytes is not None:
-        odp.set_tuning(blocks_per_cu=args.blocks_per_cu, split_bytes=args.split_bytes)
+    if args.blocks_per_cu is not None or args.split_bytes is not None or args.chunk_nodes is not None:
+        odp.set_tuning(blocks_per_cu=args.blocks_per_cu, split_bytes=args.split_bytes, chunk_nodes=args.chunk_nodes)
     if args.copy_probe:
         src = torch.randint(0, 1 << 30, (args.copy_probe // 4,), dtype=torch.int32, device="cuda")
         dst = torch.empty_like(src)

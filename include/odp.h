@@ -366,7 +366,10 @@ typedef struct odp_tuning {
   uint32_t split_bytes;     /* level-1 nodes of at most this many bytes (0 or 4096..65536) are
                                hashed and combined by one wavefront, four per work item;
                                larger nodes take a whole workgroup */
-  uint32_t reserved[5];
+  uint32_t chunk_nodes;     /* work items a workgroup claims at once from the queue, 1..16
+                               (0 reads as 1): consecutive items, so a chunk of node items is
+                               64 * chunk_nodes consecutive leaves (256 KiB each node) */
+  uint32_t reserved[4];
 } odp_tuning;
 
 int odp_get_tuning(odp_tuning* out);

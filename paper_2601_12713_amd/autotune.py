@@ -1,12 +1,12 @@
 """Autotuner of the batched digest's launch parameters.
 
 Searches workgroups per compute unit x the one-wavefront split (the size of a
-level-1 node below which one wavefront, not a whole workgroup, hashes it) on a
-held-out batch (seed 101, the batch workload's size distribution at a smaller
+level-1 node below which one wavefront, not a whole workgroup, hashes it) x the
+chunk (work items a workgroup claims at once: 1-8 level-1 nodes, 64-512
+consecutive leaves) on a held-out batch (seed 101, the batch workload's size distribution at a smaller
 total), times each point with HIP events on the launch stream, checks that
 every point returns the same digests, and writes a per-device JSON. The leaf
-(4096 B) and fan-in (64) belong to the digest definition and are not tuned;
-the work item of a workgroup is one level-1 node (256 KiB).
+(4096 B) and fan-in (64) belong to the digest definition and are not tuned.
 
     python -m paper_2601_12713_amd.autotune [--out PATH] [--total-bytes B] [--buffers N]
 
@@ -21,8 +21,9 @@ import time
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-BLOCKS_PER_CU = (2, 4, 8)
+BLOCKS_PER_CU = (1, 2, 4, 8)
 SPLITS = (0, 16384, 32768, 65536)
+CHUNKS = (1, 2, 4, 8)
 
 
 def default_path(arch):
@@ -33,7 +34,8 @@ def apply(path):
     from . import odp
     with open(path) as f:
         best = json.load(f)["best"]
-    odp.set_tuning(blocks_per_cu=int(best["blocks_per_cu"]), split_bytes=int(best["split_bytes"]), use_graph=1)
+    odp.set_tuning(blocks_per_cu=int(best["blocks_per_cu"]), split_bytes=int(best["split_bytes"]),
+                   chunk_nodes=int(best.get("chunk_nodes", 1)), use_graph=1)
     return best
 
 
@@ -54,28 +56,27 @@ def tune(total_bytes=8_000_000_000, n=20_000, reps=5, warmup=2, log=print):
     saved = odp.get_tuning()
     points, ref = [], None
     try:
-        for bpc in BLOCKS_PER_CU:
-            for split in SPLITS:
-                odp.set_tuning(blocks_per_cu=bpc, split_bytes=split, use_graph=1)
-                for _ in range(warmup):
-                    odp.digest_buffers(dptr, dsz, out, stream)
-                e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
-                e0.record(stream)
-                for _ in range(reps):
-                    odp.digest_buffers(dptr, dsz, out, stream)
-                e1.record(stream)
-                torch.cuda.synchronize()
-                ms = e0.elapsed_time(e1) / reps
-                got = out.cpu().numpy()
-                if ref is None:
-                    ref = got.copy()
-                if not np.array_equal(got, ref):
-                    raise RuntimeError("tuning point %s gave different digests" % ((bpc, split),))
-                gbps = bb.total_bytes / (ms * 1e-3) / 1e9
-                points.append({"blocks_per_cu": bpc, "split_bytes": split, "ms": round(ms, 4),
-                               "GBps": round(gbps, 1)})
-                log("blocks_per_cu=%d split_bytes=%6d  %.3f ms  %.1f GB/s" % (bpc, split, ms, gbps))
+        for bpc, split, chunk in [(b, s, c) for b in BLOCKS_PER_CU for s in SPLITS for c in CHUNKS]:
+            odp.set_tuning(blocks_per_cu=bpc, split_bytes=split, chunk_nodes=chunk, use_graph=1)
+            for _ in range(warmup):
+                odp.digest_buffers(dptr, dsz, out, stream)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                odp.digest_buffers(dptr, dsz, out, stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            got = out.cpu().numpy()
+            if ref is None:
+                ref = got.copy()
+            if not np.array_equal(got, ref):
+                raise RuntimeError("tuning point %s gave different digests" % ((bpc, split, chunk),))
+            gbps = bb.total_bytes / (ms * 1e-3) / 1e9
+            points.append({"blocks_per_cu": bpc, "split_bytes": split, "chunk_nodes": chunk, "ms": round(ms, 4),
+                           "GBps": round(gbps, 1)})
+            log("blocks_per_cu=%d split_bytes=%6d chunk_nodes=%d  %.3f ms  %.1f GB/s" % (bpc, split, chunk, ms, gbps))
     finally:
         odp.set_tuning(**saved)
     best = max(points, key=lambda p: p["GBps"])
@@ -85,7 +86,8 @@ def tune(total_bytes=8_000_000_000, n=20_000, reps=5, warmup=2, log=print):
             n, int(bb.total_bytes)),
         "reps": reps, "timed_with": "HIP events on the launch stream around %d graph replays" % reps,
         "created": time.strftime("%Y-%m-%d %H:%M:%S"), "points": points,
-        "best": {"blocks_per_cu": best["blocks_per_cu"], "split_bytes": best["split_bytes"], "use_graph": 1},
+        "best": {"blocks_per_cu": best["blocks_per_cu"], "split_bytes": best["split_bytes"],
+                 "chunk_nodes": best["chunk_nodes"], "use_graph": 1},
     }
 
 

@@ -707,9 +707,10 @@ __device__ void finalize_plan(const PlanArgs& A, const uint64_t carry[kQ]) {
   c->tree_total = carry[2];
   c->tk_total = carry[3];
   c->head = 0;
-  // item numbers run past n_items by up to five per workgroup of at most 2^14
+  // item numbers run past n_items by up to (3 * workgroups + 2) * chunk, at
+  // most 2^20 for 2^14 workgroups and chunks of 16
   c->overflow = (carry[0] > A.cap_items || carry[2] > A.cap_tree || carry[3] > A.cap_tk ||
-                 carry[0] + carry[4] > A.cap_nodes || c->n_items >= 0xFFFF0000ull - (5ull << 14)) ? 1u : 0u;
+                 carry[0] + carry[4] > A.cap_nodes || c->n_items >= 0xFFFF0000ull - (1ull << 20)) ? 1u : 0u;
 }
 
 __global__ __launch_bounds__(kPlanThreads) void plan_count_kernel(PlanArgs A) {
@@ -842,6 +843,7 @@ struct BatchArgs {
   uint32_t* tickets;
   DigestCtl* ctl;
   uint32_t* status;  // host-mapped sticky status word
+  uint32_t chunk;    // items per claim
 };
 
 __device__ __forceinline__ bool aligned16(const uint8_t* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
@@ -864,10 +866,13 @@ __device__ __forceinline__ const uint8_t* fast_rows(const uint8_t* base, uint32_
   return aligned16(base) && end <= len ? base + (uint32_t)w * kRowsPerWave * kLeaf : nullptr;
 }
 
-// Persistent batched digest. Each workgroup claims items from the queue two
-// ahead of the one it hashes, so the claim and the item's record arrive while
-// the current item streams; each wavefront carries its load pipeline from one
-// node item into the next. Per item there is one barrier: after it, one
+// Persistent batched digest. Workgroups take the items in chunks of
+// A.chunk consecutive ones: workgroup b starts with chunks b and b + grid,
+// then claims chunks from the queue (numbered from 2 * grid on). The item two
+// ahead of the one being hashed is settled during it (a claim when it opens a
+// chunk), so the claim and the item's record arrive while the current item
+// streams; each wavefront carries its load pipeline from one node item into
+// the next. Per item there is one barrier: after it, one
 // wavefront (rotating) folds the 64 leaf digests into the level-1 digest and
 // stores it without waiting (out[i] for one-node buffers, else the tree slot
 // that the tree kernel climbs from).
@@ -886,16 +891,23 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
   // items blockIdx.x and blockIdx.x + gridDim.x are this workgroup's; later
   // ones come from the queue, numbered from 2 * gridDim.x on. A workgroup
   // with nothing to do leaves without touching the queue.
-  const uint32_t first_queued = 2u * gridDim.x;
-  uint32_t cur = blockIdx.x, nxt = blockIdx.x + gridDim.x;
+  const uint32_t C = A.chunk, first_queued = 2u * gridDim.x;
+  // item i of this workgroup's sequence, for the two preassigned chunks (i < 2C)
+  auto pre_item = [&](uint32_t i) { return i < C ? blockIdx.x * C + i : (blockIdx.x + gridDim.x) * C + (i - C); };
+  uint32_t cur = pre_item(0), nxt = pre_item(1);
   NodeRec rc = load_rec(A, cur, n_node), rn = load_rec(A, nxt, n_node);
   constexpr int NL = kSlabBatch / 64;
   u32x4 RA[NL], RB[NL];
   bool pre = false;
   RowDesc* rows = sm.rows + w * kRowsPerWave;
   for (uint32_t k = 0; cur < n_items; ++k) {
+    // the item two ahead: the next of nxt's chunk, or the first of a new one
     uint32_t claim = 0;
-    if (t == 0) claim = first_queued + atomicAdd(&A.ctl->head, 1u);
+    if (t == 0) {
+      if (k + 2 < 2 * C) claim = pre_item(k + 2);
+      else if ((k + 2) % C == 0) claim = (first_queued + atomicAdd(&A.ctl->head, 1u)) * C;
+      else claim = nxt + 1;
+    }
     const bool is_node = cur < n_node;
     const bool is_med = !is_node && cur < med_end;
     const uint8_t* base = uniform_ptr(rc.base);
@@ -1184,6 +1196,7 @@ static int enqueue_batched(const BatchedSpace& S, const void* const* ptrs, const
   B.tickets = S.tickets;
   B.ctl = P.ctl;
   B.status = S.status;
+  B.chunk = std::max<uint32_t>(1, tuning().chunk_nodes);
   const uint64_t bpc = tuning().blocks_per_cu;
   hipLaunchKernelGGL(digest_batched_kernel, dim3(sized(cus * bpc, 1)), dim3(kThreads), 0, stream, B);
   hipLaunchKernelGGL(digest_tree_kernel, dim3(sized(cus * 4, 64 * kWaves)), dim3(kThreads), 0, stream, B);
@@ -1218,7 +1231,7 @@ extern "C" int odp_digest_buffers(const void* const* ptrs, const uint64_t* sizes
   if (!tn.use_graph || capturing) return enqueue_batched(space_of(ws), ptrs, sizes, n, out, stream);
   const uint32_t grid = cu_count(ws->device) * tn.blocks_per_cu;
   if (!(ws->graph && ws->g_ptrs == ptrs && ws->g_sizes == sizes && ws->g_out == out && ws->g_n == n &&
-        ws->g_grid == grid && ws->g_split == tn.split_bytes)) {
+        ws->g_grid == grid && ws->g_split == tn.split_bytes && ws->g_chunk == tn.chunk_nodes)) {
     if (ws->graph) {
       ODP_HIP(hipGraphExecDestroy(ws->graph));
       ws->graph = nullptr;
@@ -1250,6 +1263,7 @@ extern "C" int odp_digest_buffers(const void* const* ptrs, const uint64_t* sizes
     ws->g_n = n;
     ws->g_grid = grid;
     ws->g_split = tn.split_bytes;
+    ws->g_chunk = tn.chunk_nodes;
   }
   ODP_HIP(hipGraphLaunch(ws->graph, stream));
   return ODP_OK;

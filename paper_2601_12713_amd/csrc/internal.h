@@ -75,6 +75,7 @@ struct Workspace {
   size_t g_n = 0;
   uint32_t g_grid = 0;
   uint32_t g_split = 0;
+  uint32_t g_chunk = 0;
 };
 
 Workspace* workspace_for(hipStream_t stream, int* err);
@@ -93,6 +94,7 @@ struct Tuning {
   uint32_t blocks_per_cu = 4;
   uint32_t use_graph = 1;
   uint32_t split_bytes = 0;
+  uint32_t chunk_nodes = 1;
 };
 Tuning& tuning();
 

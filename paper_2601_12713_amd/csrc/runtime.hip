@@ -207,6 +207,7 @@ extern "C" int odp_get_tuning(odp_tuning* out) {
   out->blocks_per_cu = g_tuning.blocks_per_cu;
   out->use_graph = g_tuning.use_graph;
   out->split_bytes = g_tuning.split_bytes;
+  out->chunk_nodes = g_tuning.chunk_nodes;
   return ODP_OK;
 }
 
@@ -217,8 +218,11 @@ extern "C" int odp_set_tuning(const odp_tuning* in) {
   if (in->use_graph > 1) return set_error(ODP_EINVAL, "odp_set_tuning: use_graph must be 0 or 1");
   if (in->split_bytes != 0 && (in->split_bytes < 4096 || in->split_bytes > 65536))
     return set_error(ODP_EINVAL, "odp_set_tuning: split_bytes %u not 0 or in 4096..65536", in->split_bytes);
+  if (in->chunk_nodes > 16)
+    return set_error(ODP_EINVAL, "odp_set_tuning: chunk_nodes %u outside 1..16", in->chunk_nodes);
   g_tuning.blocks_per_cu = in->blocks_per_cu;
   g_tuning.use_graph = in->use_graph;
   g_tuning.split_bytes = in->split_bytes;
+  g_tuning.chunk_nodes = in->chunk_nodes ? in->chunk_nodes : 1u;
   return ODP_OK;
 }

@@ -45,7 +45,7 @@ class OdpError(RuntimeError):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("blocks_per_cu", ctypes.c_uint32), ("use_graph", ctypes.c_uint32),
-                ("split_bytes", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 5)]
+                ("split_bytes", ctypes.c_uint32), ("chunk_nodes", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 4)]
 
 
 _lib = None
@@ -192,10 +192,11 @@ def device_status():
 def get_tuning():
     t = Tuning()
     _check(load().odp_get_tuning(ctypes.byref(t)))
-    return {"blocks_per_cu": int(t.blocks_per_cu), "use_graph": int(t.use_graph), "split_bytes": int(t.split_bytes)}
+    return {"blocks_per_cu": int(t.blocks_per_cu), "use_graph": int(t.use_graph), "split_bytes": int(t.split_bytes),
+            "chunk_nodes": int(t.chunk_nodes)}
 
 
-def set_tuning(blocks_per_cu=None, use_graph=None, split_bytes=None):
+def set_tuning(blocks_per_cu=None, use_graph=None, split_bytes=None, chunk_nodes=None):
     t = Tuning()
     _check(load().odp_get_tuning(ctypes.byref(t)))
     if blocks_per_cu is not None:
@@ -204,6 +205,8 @@ def set_tuning(blocks_per_cu=None, use_graph=None, split_bytes=None):
         t.use_graph = int(use_graph)
     if split_bytes is not None:
         t.split_bytes = int(split_bytes)
+    if chunk_nodes is not None:
+        t.chunk_nodes = int(chunk_nodes)
     _check(load().odp_set_tuning(ctypes.byref(t)))
 
 

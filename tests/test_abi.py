@@ -83,6 +83,8 @@ def test_invalid_arguments_before_any_device_call():
     assert L.odp_set_tuning(bad) == -1
     bad = (ctypes.c_uint32 * 8)(4, 1, 100, 0, 0, 0, 0, 0)            # split below one leaf
     assert L.odp_set_tuning(bad) == -1
+    bad = (ctypes.c_uint32 * 8)(4, 1, 0, 17, 0, 0, 0, 0)             # 17 items per claim
+    assert L.odp_set_tuning(bad) == -1
     L.odp_server_create.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
     h = ctypes.c_void_p()
     cfg = (ctypes.c_uint64 * 2)(0, 1 << 20)

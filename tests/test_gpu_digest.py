@@ -133,8 +133,9 @@ SPLIT_SIZES = [4097, 16 * 4096, 16 * 4096 + 1, 32 * 4096, 262144 + 4096, 262144 
 
 
 def test_tuning_points_same_digests(odp):
-    """Six launch configurations (workgroups per CU, graph or direct, split
-    between one-wavefront and one-workgroup nodes) give the oracle's digests."""
+    """Nine launch configurations (workgroups per CU, graph or direct, split
+    between one-wavefront and one-workgroup nodes, items claimed at once)
+    give the oracle's digests."""
     rng = np.random.default_rng(18)
     host = [rng.integers(0, 256, size=int(s), dtype=np.uint8) for s in SPLIT_SIZES]
     host += [rng.integers(0, 256, size=int(s), dtype=np.uint8) for s in rng.integers(1, 300_000, size=300)]
@@ -142,13 +143,16 @@ def test_tuning_points_same_digests(odp):
     t = [dev_bytes(h) for h in host]
     saved = odp.get_tuning()
     try:
-        for bpc, graph, split in [(8, 1, 65536), (1, 1, 0), (2, 0, 4096), (4, 1, 16384), (8, 0, 32768),
-                                  (3, 1, 65536)]:
-            odp.set_tuning(blocks_per_cu=bpc, use_graph=graph, split_bytes=split)
+        for bpc, graph, split, chunk in [(8, 1, 65536, 1), (1, 1, 0, 1), (2, 0, 4096, 2), (4, 1, 16384, 4),
+                                         (8, 0, 32768, 8), (3, 1, 65536, 3), (1, 1, 0, 16), (4, 0, 0, 5),
+                                         (2, 1, 32768, 16)]:
+            odp.set_tuning(blocks_per_cu=bpc, use_graph=graph, split_bytes=split, chunk_nodes=chunk)
             for _ in range(2):
-                assert odp.digest_tensors(t).tolist() == want, (bpc, graph, split)
+                assert odp.digest_tensors(t).tolist() == want, (bpc, graph, split, chunk)
         with pytest.raises(odp.OdpError):
             odp.set_tuning(split_bytes=100)
+        with pytest.raises(odp.OdpError):
+            odp.set_tuning(chunk_nodes=17)
     finally:
         odp.set_tuning(**saved)
     assert odp.digest_tensors(t, plain=True).tolist() == want
