@@ -244,6 +244,25 @@ typedef struct odp_report {
 int odp_analyze_trace(const odp_event* events, size_t n, uint8_t* out_flags, odp_report* out_report,
                       odp_stream_t stream);
 
+/* Comparison mode for logs with three or more endpoints (Sec. 5, Alg. 2;
+ * Sec. 7.8): the analysis above (same flags and report) plus the <tx, rx>
+ * pairs that Algorithm 2 records when followed literally. For each digest h
+ * and endpoint d the algorithm keeps the list R(h, d) of all valid transfers
+ * of h into d, over the whole log in log order, and a count c(h, d); walking
+ * the valid transfers (H2D, D2H, D2D; self-transfers included) in log order,
+ * it records a transfer tx of h out of s, with rx = R(h, s)[c(h, s)], when
+ * c(h, s) < |R(h, s)|, and then adds one to c(h, dst(tx)). On two endpoints
+ * these pairs are the round trips of the rule above; on more, rx can precede
+ * tx or come from a third endpoint, which the definitional rule never pairs.
+ *   out_rx      device, n uint32: for a recorded tx, the record index of its rx;
+ *               0xFFFFFFFF for every other record (written for all n)
+ *   out_npairs  device, one uint64: the number of recorded pairs
+ * Always runs on the workspace (any n, also n <= 512); never replayed from
+ * the analysis graph cache. Errors as odp_analyze_trace, and ODP_EINVAL for a
+ * null out_npairs, or a null out_rx with n > 0. */
+int odp_analyze_trace_alg2(const odp_event* events, size_t n, uint8_t* out_flags, odp_report* out_report,
+                           uint32_t* out_rx, uint64_t* out_npairs, odp_stream_t stream);
+
 /* ---------------------------------------------------------------------------
  * Serving: mapping-event requests classified as they arrive.
  *

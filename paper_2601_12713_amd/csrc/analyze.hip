@@ -2410,6 +2410,183 @@ __global__ void finalize_kernel(AnaCtl* ctl, odp_report* rep) {
 }
 
 // ---------------------------------------------------------------------------
+// 9. Literal Algorithm 2 (comparison mode for three or more endpoints).
+// ---------------------------------------------------------------------------
+// Algorithm 2 keeps, for each digest h and endpoint d, the list R(h, d) of
+// every valid transfer of h into d (over the whole log, in log order) and a
+// count c(h, d); walking the transfers in log order, it records a transfer tx
+// of h out of s with rx = R(h, s)[c(h, s)] when c(h, s) < |R(h, s)|, and then
+// adds one to c(h, dst(tx)). So c(h, d) counts the recorded transfers into d
+// so far, and rx can precede tx or come from a third endpoint.
+// Within one digest's transfers in log order this is, equivalently: a transfer
+// k out of s is recorded unless it is late for s (every transfer into s comes
+// before k) and every transfer into s was recorded; the late ones decide in
+// log order through one bit per endpoint, F(d) = some transfer into d is
+// unrecorded, which only grows. A recorded k pairs with the m-th transfer into
+// s, m = the recorded transfers into s before k.
+// One wavefront per 64 sorted positions handles the digest groups that start
+// there: groups of one transfer at once (recorded, with rx = itself, exactly
+// when it is a self-transfer), longer ones one after another in three
+// sweeps: counts per endpoint, then the decisions and each group's transfers
+// listed by destination endpoint (in `lists`), then rx.
+struct Alg2Args {
+  const SortJob* job;        // the digest job (keys/vals in buffer npasses & 1)
+  const uint8_t* aux;
+  uint32_t n;
+  uint32_t* rx;              // [n] partner record, or kNone
+  unsigned long long* npairs;
+};
+
+__global__ __launch_bounds__(kT) void alg2_fill_kernel(uint32_t* rx, uint32_t n, unsigned long long* npairs) {
+  const uint32_t i = blockIdx.x * kT + threadIdx.x;
+  if (i < n) rx[i] = kNone;
+  if (i == 0) *npairs = 0;
+}
+
+// per-lane pick of arr[idx] (idx < kEp) from a wave-replicated array
+__device__ __forceinline__ uint32_t pick(const uint32_t (&arr)[kEp], uint32_t idx) {
+  uint32_t r = 0;
+#pragma unroll
+  for (int e = 0; e < kEp; ++e) r = (uint32_t)e == idx ? arr[e] : r;
+  return r;
+}
+__device__ __forceinline__ uint64_t pick64(const uint64_t (&arr)[kEp], uint32_t idx) {
+  uint64_t r = 0;
+#pragma unroll
+  for (int e = 0; e < kEp; ++e) r = (uint32_t)e == idx ? arr[e] : r;
+  return r;
+}
+
+// endpoint codes (0 host, 1 + device) of sorted position j; a transfer when x
+__device__ __forceinline__ void alg2_load(const Alg2Args& A, const uint32_t* v, uint32_t j, bool& x, uint32_t& src,
+                                          uint32_t& dst, uint32_t& rec) {
+  const uint32_t w = v[j];
+  const uint8_t a = A.n < kPackLimit ? (uint8_t)(w >> 24) : A.aux[w];
+  rec = A.n < kPackLimit ? (w & kIdxMask) : w;
+  x = a != kNotTransfer;
+  src = x ? (uint32_t)(a >> 4) : 0u;
+  dst = x ? (uint32_t)(a & 15) : 0u;
+}
+
+__global__ __launch_bounds__(kT) void alg2_kernel(Alg2Args A) {
+  const SortJob& s = *A.job;
+  const unsigned long long* k = s.keys[s.npasses & 1];
+  const uint32_t* v = s.vals[s.npasses & 1];
+  uint32_t* lists = s.vals[(s.npasses + 1) & 1];
+  const uint32_t n = A.n, lane = threadIdx.x & 63;
+  const uint64_t lt = lanemask_lt();
+  const uint32_t c0 = (blockIdx.x * kT + threadIdx.x) / 64 * 64;
+  if (c0 >= n) return;
+  const uint32_t j = c0 + lane;
+  const bool in = j < n;
+  const unsigned long long key = in ? k[j] : 0ull;
+  const bool head = in && (j == 0 || k[j - 1] != key);
+  const bool tail = in && (j + 1 == n || k[j + 1] != key);
+  uint64_t pairs = 0;
+  {  // groups of one record
+    bool x = false;
+    uint32_t src = 0, dst = 0, rec = 0;
+    if (head && tail) alg2_load(A, v, j, x, src, dst, rec);
+    if (x && src == dst) A.rx[rec] = rec;
+    pairs += (uint64_t)__popcll(__ballot(x && src == dst));
+  }
+  uint64_t heads = __ballot(head && !tail);
+  while (heads) {
+    const uint32_t g0 = c0 + (uint32_t)__builtin_ctzll(heads);
+    heads &= heads - 1;
+    const unsigned long long gkey = k[g0];
+    // sweep 1: transfers into each endpoint, and the group's end g1
+    uint32_t cnt[kEp];
+#pragma unroll
+    for (int e = 0; e < kEp; ++e) cnt[e] = 0;
+    uint32_t g1 = g0;
+    for (uint32_t b = g0;; b += 64) {
+      const uint32_t jj = b + lane;
+      const bool inr = jj < n && k[jj] == gkey;
+      bool x = false;
+      uint32_t src = 0, dst = 0, rec = 0;
+      if (inr) alg2_load(A, v, jj, x, src, dst, rec);
+#pragma unroll
+      for (int e = 0; e < kEp; ++e) cnt[e] += (uint32_t)__popcll(__ballot(x && dst == (uint32_t)e));
+      const uint32_t m = (uint32_t)__popcll(__ballot(inr));
+      g1 = b + m;
+      if (m < 64) break;
+    }
+    uint32_t base[kEp];
+    {
+      uint32_t acc = g0;
+#pragma unroll
+      for (int e = 0; e < kEp; ++e) {
+        base[e] = acc;
+        acc += cnt[e];
+      }
+    }
+    // sweep 2: decisions, each transfer's place in the list of its
+    // destination, and the rank in R(h, src) of each recorded one (kept in
+    // rx until sweep 3)
+    uint32_t seen[kEp], unrec[kEp];
+#pragma unroll
+    for (int e = 0; e < kEp; ++e) seen[e] = unrec[e] = 0;
+    uint32_t F = 0;
+    for (uint32_t b = g0; b < g1; b += 64) {
+      const uint32_t jj = b + lane;
+      bool x = false;
+      uint32_t src = 0, dst = 0, rec = 0;
+      if (jj < g1) alg2_load(A, v, jj, x, src, dst, rec);
+      uint64_t into[kEp];
+#pragma unroll
+      for (int e = 0; e < kEp; ++e) into[e] = __ballot(x && dst == (uint32_t)e);
+      const uint32_t before_src = pick(seen, src) + (uint32_t)__popcll(pick64(into, src) & lt);
+      const bool late = x && before_src == pick(cnt, src);
+      uint64_t rest = __ballot(late), um = 0;
+      while (rest) {
+        const uint64_t c = __ballot(((rest >> lane) & 1) && !((F >> src) & 1));
+        if (!c) break;
+        const int k0 = __builtin_ctzll(c);
+        um |= 1ull << k0;
+        F |= 1u << __shfl((int)dst, k0, 64);
+        rest &= k0 == 63 ? 0ull : ~0ull << (k0 + 1);
+      }
+      const bool u = (um >> lane) & 1;
+      uint64_t uinto[kEp];
+#pragma unroll
+      for (int e = 0; e < kEp; ++e) uinto[e] = __ballot(u && dst == (uint32_t)e);
+      if (x) {
+        const uint32_t my_rank = pick(seen, dst) + (uint32_t)__popcll(pick64(into, dst) & lt);
+        __hip_atomic_store(lists + pick(base, dst) + my_rank, rec, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t m = before_src - pick(unrec, src) - (uint32_t)__popcll(pick64(uinto, src) & lt);
+        __hip_atomic_store(A.rx + rec, u ? kNone : m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+#pragma unroll
+      for (int e = 0; e < kEp; ++e) {
+        seen[e] += (uint32_t)__popcll(into[e]);
+        unrec[e] += (uint32_t)__popcll(uinto[e]);
+      }
+    }
+    // the stores above reach the L2 before sweep 3 reads them past the L1
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    // sweep 3: rank -> record
+    for (uint32_t b = g0; b < g1; b += 64) {
+      const uint32_t jj = b + lane;
+      bool x = false;
+      uint32_t src = 0, dst = 0, rec = 0;
+      if (jj < g1) alg2_load(A, v, jj, x, src, dst, rec);
+      bool paired = false;
+      if (x) {
+        const uint32_t m = __hip_atomic_load(A.rx + rec, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (m != kNone) {
+          paired = true;
+          A.rx[rec] = __hip_atomic_load(lists + pick(base, src) + m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
+      pairs += (uint64_t)__popcll(__ballot(paired));
+    }
+  }
+  if (lane == 0 && pairs) atomicAdd(A.npairs, (unsigned long long)pairs);
+}
+
+// ---------------------------------------------------------------------------
 // Workspace layout.
 // ---------------------------------------------------------------------------
 enum Buf {
@@ -2982,10 +3159,12 @@ uint32_t first_digest_passes(size_t n) {
 
 using namespace odp;
 
-// The launch sequence of one analysis of more than kTinyMax records, in the
-// workspace `ws` (reserved for n), enqueued on `stream`.
+// The launch sequence of one analysis (of more than kTinyMax records unless
+// the literal Algorithm 2 pairs are asked for too, in alg2_rx / alg2_np), in
+// the workspace `ws` (reserved for n), enqueued on `stream`.
 static int enqueue_analysis(Workspace* ws, const odp_event* events, size_t n, uint8_t* out_flags,
-                            odp_report* out_report, hipStream_t stream) {
+                            odp_report* out_report, hipStream_t stream, uint32_t* alg2_rx = nullptr,
+                            unsigned long long* alg2_np = nullptr) {
   const Views v = views(ws);
   const uint32_t nn = (uint32_t)n;
   const uint32_t nt = n ? ceil_div32(n, kTile) : 1;  // tiles of this call
@@ -2995,6 +3174,8 @@ static int enqueue_analysis(Workspace* ws, const odp_event* events, size_t n, ui
 
   hipLaunchKernelGGL(init_kernel, dim3(64), dim3(kT), 0, stream, ctl, out_report, v.totals,
                      (uint32_t)(kNumJobs * kMaxPasses * 256), nn);
+  if (alg2_rx)
+    hipLaunchKernelGGL(alg2_fill_kernel, dim3(n ? ceil_div32(n, kT) : 1), dim3(kT), 0, stream, alg2_rx, nn, alg2_np);
   if (n == 0) {
     hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(64), 0, stream, ctl, out_report);
     return check_hip(hipGetLastError(), "odp_analyze_trace launch");
@@ -3158,6 +3339,15 @@ static int enqueue_analysis(Workspace* ws, const odp_event* events, size_t n, ui
   hipLaunchKernelGGL(ddrt_final_kernel, dim3(nt), dim3(kT), 0, stream, D);
   hipLaunchKernelGGL(reduce_parts_kernel, dim3(kSlots - S_DD_EVENTS), dim3(kT), 0, stream, v.parts, nt,
                      (uint32_t)S_DD_EVENTS, ctl, out_report);
+  if (alg2_rx) {
+    Alg2Args G;
+    G.job = v.jobs + kJobBig;
+    G.aux = v.aux;
+    G.n = nn;
+    G.rx = alg2_rx;
+    G.npairs = alg2_np;
+    hipLaunchKernelGGL(alg2_kernel, dim3(ceil_div32(n, kT)), dim3(kT), 0, stream, G);
+  }
 
   ODP_HIP(hipEventRecord(ws->a_join, side));
 
@@ -3232,4 +3422,26 @@ extern "C" int odp_analyze_trace(const odp_event* events, size_t n, uint8_t* out
   }
   ODP_HIP(hipGraphLaunch(ws->a_graph, stream));
   return ODP_OK;
+}
+
+extern "C" int odp_analyze_trace_alg2(const odp_event* events, size_t n, uint8_t* out_flags, odp_report* out_report,
+                                      uint32_t* out_rx, uint64_t* out_npairs, odp_stream_t stream_) {
+  hipStream_t stream = static_cast<hipStream_t>(stream_);
+  if (n > 0xFFFFFFFFull) return set_error(ODP_ERANGE, "odp_analyze_trace_alg2: n = %zu above 2^32 - 1", n);
+  if (!out_report || !out_npairs) return set_error(ODP_EINVAL, "odp_analyze_trace_alg2: null report or pair count");
+  if (n > 0 && (!events || !out_flags || !out_rx))
+    return set_error(ODP_EINVAL, "odp_analyze_trace_alg2: null array with n = %zu", n);
+  int err = 0;
+  Workspace* ws = workspace_for(stream, &err);
+  if (!ws) return err;
+  hipStreamCaptureStatus capst = hipStreamCaptureStatusNone;
+  ODP_HIP(hipStreamIsCapturing(stream, &capst));
+  if (n > ws->a_cap_events || !ws->a_cap_events) {
+    if (capst != hipStreamCaptureStatusNone)
+      return set_error(ODP_ENOMEM, "odp_analyze_trace_alg2: workspace for %zu records not reserved before capture", n);
+    int e = analyze_reserve(ws, n);
+    if (e) return e;
+  }
+  return enqueue_analysis(ws, events, n, out_flags, out_report, stream, out_rx,
+                          reinterpret_cast<unsigned long long*>(out_npairs));
 }

@@ -30,7 +30,7 @@ REPORT_BYTES = 8 * len(REPORT_FIELDS) + 16  # + predicted_speedup (double), stat
 
 EXPORTS = [
     "odp_digest_buffers", "odp_digest_buffers_noalloc", "odp_digest_buffers_plain", "odp_analyze_trace",
-    "odp_version",
+    "odp_analyze_trace_alg2", "odp_version",
     "odp_last_error_string", "odp_reserve", "odp_release", "odp_device_status",
     "odp_get_tuning", "odp_set_tuning", "odp_server_create", "odp_server_run", "odp_server_drain",
     "odp_server_log", "odp_server_destroy",
@@ -66,6 +66,7 @@ def load(path=LIB_PATH):
     L.odp_digest_buffers_noalloc.argtypes = [p, p, sz, p, p]
     L.odp_digest_buffers_plain.argtypes = [p, p, sz, p, p]
     L.odp_analyze_trace.argtypes = [p, sz, p, p, p]
+    L.odp_analyze_trace_alg2.argtypes = [p, sz, p, p, p, p, p]
     L.odp_version.argtypes = []
     L.odp_last_error_string.argtypes = []
     L.odp_last_error_string.restype = ctypes.c_char_p
@@ -163,6 +164,16 @@ def analyze_trace(events, out_flags, out_report, stream=None, n=None):
     if n is None:
         n = events.numel() * events.element_size() // 64
     _check(load().odp_analyze_trace(_ptr(events), n, _ptr(out_flags), _ptr(out_report), _stream(stream)))
+
+
+def analyze_trace_alg2(events, out_flags, out_report, out_rx, out_npairs, stream=None, n=None):
+    """analyze_trace plus the pairs the literal Algorithm 2 records: out_rx (int32/uint32 device
+    tensor, n) gets the rx record of each recorded tx, else 0xFFFFFFFF; out_npairs (one 64-bit
+    device word) their number."""
+    if n is None:
+        n = events.numel() * events.element_size() // 64
+    _check(load().odp_analyze_trace_alg2(_ptr(events), n, _ptr(out_flags), _ptr(out_report), _ptr(out_rx),
+                                         _ptr(out_npairs), _stream(stream)))
 
 
 def report_to_dict(buf):

@@ -60,6 +60,8 @@ def test_range_errors_before_any_device_call():
     assert b"2^32" in L.odp_last_error_string()
     L.odp_analyze_trace.argtypes = [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     assert L.odp_analyze_trace(fake, big, fake, fake, None) == -2
+    L.odp_analyze_trace_alg2.argtypes = [ctypes.c_void_p, ctypes.c_size_t] + [ctypes.c_void_p] * 5
+    assert L.odp_analyze_trace_alg2(fake, big, fake, fake, fake, fake, None) == -2
     for f in (L.odp_digest_buffers, L.odp_digest_buffers_plain):
         f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p]
         assert f(fake, fake, big, fake, None) == -2
@@ -74,6 +76,9 @@ def test_invalid_arguments_before_any_device_call():
     L.odp_analyze_trace.argtypes = [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     assert L.odp_analyze_trace(None, 5, fake, fake, None) == -1      # null events with n > 0
     assert L.odp_analyze_trace(fake, 5, fake, None, None) == -1      # null report
+    L.odp_analyze_trace_alg2.argtypes = [ctypes.c_void_p, ctypes.c_size_t] + [ctypes.c_void_p] * 5
+    assert L.odp_analyze_trace_alg2(fake, 5, fake, fake, fake, None, None) == -1   # null pair count
+    assert L.odp_analyze_trace_alg2(fake, 5, fake, fake, None, fake, None) == -1   # null rx with n > 0
     for f in (L.odp_digest_buffers, L.odp_digest_buffers_noalloc, L.odp_digest_buffers_plain):
         f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p]
         assert f(None, fake, 3, fake, None) == -1
