@@ -272,7 +272,8 @@ int odp_analyze_trace_alg2(const odp_event* events, size_t n, uint8_t* out_flags
  * batched digest of its payloads (on the server's digest stream) and one
  * classification against device-resident per-key state (on its classification
  * stream, after that digest), appended to a device-resident log; the digest of
- * the next tick overlaps the classification of the current one.
+ * the next tick overlaps the classification of the current one (a tick
+ * submitted while none is in flight is classified on the digest stream).
  * Every flag is set in the server's "known" flags as soon as the records that
  * decide it have arrived (the rules of Sec. 4, Defs. 1-4, and Sec. 5; the
  * paper analyses post mortem, serving is an extension):

@@ -7,7 +7,8 @@
 // kernel (on its classification stream, ordered after the digest by an event)
 // that works against device-resident per-key state and appends the records to
 // a device-resident log. With two ticks in flight, the digest of tick k+1 runs
-// while tick k is classified.
+// while tick k is classified; a tick submitted while none is in flight is
+// classified on the digest stream, right after its digest.
 //
 // Every flag of a record is set as soon as the records that decide it have
 // arrived (Sec. 4, Defs. 1-4; the paper analyses post mortem, so this is an
@@ -696,9 +697,14 @@ StageView stage_view(uint8_t* base, uint32_t m) {
 // Enqueues one tick: the staging copy and the digest of the payloads (one
 // persistent batched launch, or per-buffer launches in the plain mode) on the
 // digest stream; the classification on the server stream, after the digest.
-// The digest of the next tick then runs during this classification.
-static int launch_tick(odp_server* s, int b, uint32_t m, uint64_t bytes) {
+// The digest of the next tick then runs during this classification. A tick
+// submitted while none is in flight (`idle`) has nothing to overlap: its
+// classification follows the digest on the digest stream itself, without the
+// hop between streams. A later tick's classification stays ordered after it:
+// its digest, which it waits for, follows it on the digest stream.
+static int launch_tick(odp_server* s, int b, uint32_t m, uint64_t bytes, bool idle) {
   hipStream_t ds = s->dstream;
+  hipStream_t cs = idle ? ds : s->stream;
   ODP_HIP(hipMemcpyAsync(s->d_stage[b], s->h_stage[b], m * kStageBytes, hipMemcpyHostToDevice, ds));
   const StageView hv = stage_view(s->h_stage[b], m), dv = stage_view(s->d_stage[b], m);
   // Tick sizes change every tick: direct launches rather than a captured
@@ -708,8 +714,10 @@ static int launch_tick(odp_server* s, int b, uint32_t m, uint64_t bytes) {
               ? odp_digest_buffers_plain(reinterpret_cast<const void* const*>(hv.ptr), hv.size, m, s->d_dig[b], ds)
               : digest_batched_direct(reinterpret_cast<const void* const*>(dv.ptr), dv.size, m, s->d_dig[b], ds, bytes);
   if (e) return e;
-  ODP_HIP(hipEventRecord(s->digested[b], ds));
-  ODP_HIP(hipStreamWaitEvent(s->stream, s->digested[b], 0));
+  if (!idle) {
+    ODP_HIP(hipEventRecord(s->digested[b], ds));
+    ODP_HIP(hipStreamWaitEvent(s->stream, s->digested[b], 0));
+  }
   TickArgs A;
   A.tick_ev = dv.ev;
   A.tick_dig = s->d_dig[b];
@@ -734,9 +742,9 @@ static int launch_tick(odp_server* s, int b, uint32_t m, uint64_t bytes) {
   A.t_ra = s->t_ra;
   A.t_ut = s->t_ut;
   A.st = s->st;
-  hipLaunchKernelGGL(serve_tick_kernel, dim3(1), dim3(kTickMax), 0, s->stream, A);
+  hipLaunchKernelGGL(serve_tick_kernel, dim3(1), dim3(kTickMax), 0, cs, A);
   ODP_HIP(hipGetLastError());
-  ODP_HIP(hipEventRecord(s->done[b], s->stream));
+  ODP_HIP(hipEventRecord(s->done[b], cs));
   s->n_logged += m;
   s->n_ticks++;
   return ODP_OK;
@@ -820,7 +828,7 @@ extern "C" int odp_server_run(odp_server* s, const odp_event* events, const uint
         std::memmove(w.has, v.has, m);
       }
       if (m) {
-        int e = launch_tick(s, b, m, bytes);
+        int e = launch_tick(s, b, m, bytes, inflight.empty());
         if (e) return e;
         inflight.push_back({b, first, m, bytes});
         inflight_bytes += bytes;
@@ -840,6 +848,7 @@ extern "C" int odp_server_run(odp_server* s, const odp_event* events, const uint
 
 extern "C" int odp_server_drain(odp_server* s, uint8_t* out_known, uint8_t* out_flags, odp_report* out_report) {
   if (!s) return set_error(ODP_EINVAL, "odp_server_drain: null server");
+  ODP_HIP(hipStreamSynchronize(s->dstream));
   ODP_HIP(hipStreamSynchronize(s->stream));
   ServeState hs;
   ODP_HIP(hipMemcpy(&hs, s->st, sizeof(hs), hipMemcpyDeviceToHost));
@@ -851,12 +860,14 @@ extern "C" int odp_server_drain(odp_server* s, uint8_t* out_known, uint8_t* out_
     int e = odp_analyze_trace(s->log, n, out_flags, out_report, s->stream);
     if (e) return e;
   }
+  ODP_HIP(hipStreamSynchronize(s->dstream));
   ODP_HIP(hipStreamSynchronize(s->stream));
   return ODP_OK;
 }
 
 extern "C" int odp_server_log(odp_server* s, odp_event* out_events, size_t* n) {
   if (!s || !n) return set_error(ODP_EINVAL, "odp_server_log: null argument");
+  ODP_HIP(hipStreamSynchronize(s->dstream));
   ODP_HIP(hipStreamSynchronize(s->stream));
   *n = s->n_logged;
   if (out_events && s->n_logged)
