@@ -1960,7 +1960,6 @@ struct PairArgs {
   uint64_t* pr_w_bytes;
   uint64_t* pr_w_dev;
   uint64_t* pr_w_haddr;
-  uint32_t* pr_vals;
   uint8_t* flags;
   AnaCtl* ctl;
   odp_report* rep;
@@ -2034,7 +2033,6 @@ __global__ __launch_bounds__(kT) void pair_scatter_kernel(PairArgs P) {
       P.pr_w_bytes[k] = e.bytes;
       P.pr_w_dev[k] = dv;
       P.pr_w_haddr[k] = e.src_addr;
-      P.pr_vals[k] = k;
       P.flags[P.ad_idx[partner]] = ODP_F_PAIRED;  // the DELETE of the pair
       o_b |= e.bytes;
       a_b &= e.bytes;
@@ -2083,9 +2081,110 @@ __global__ __launch_bounds__(kT) void kernel_ranges_kernel(const SortJob* ks, co
 // ---------------------------------------------------------------------------
 // 7. Repeated and unused allocations, flags of paired allocations.
 // ---------------------------------------------------------------------------
+// Groups of paired allocations by (host address, device, bytes) (Def. 3,
+// Alg. 3's key) in an open-addressing table instead of a sort: RA needs, per
+// pair, only whether an earlier pair of its key exists, and the rule's groups.
+// Each pair probes linearly from the hash of its key and either claims an
+// empty slot (its owner word, by compare-and-swap) or joins the slot whose
+// owner has the same key, comparing the three key words of the owner, which
+// the pair list already holds, so no thread waits for another. A slot keeps
+// the smallest pair index of its key (pairs are numbered in ALLOC log order,
+// so that is the first ALLOC) and whether a second pair joined it. Keys of
+// many pairs are the common case (one hot buffer re-mapped again and again),
+// so the owner and the smallest index are read first and written atomically
+// only when that can change them, and "joined" is a plain store of 1. The
+// table has a power of two >= 2 x (pairs) slots, so a probe always ends.
+struct PairTable {
+  uint32_t* owner;  // 0 empty, else 1 + the pair that claimed the slot
+  uint32_t* first;  // smallest pair index of the slot's key
+  uint32_t* multi;  // 1 when two or more pairs have the slot's key
+  uint32_t* slot;   // per pair: the slot of its key
+};
+
+__host__ __device__ __forceinline__ uint32_t pair_table_mask(uint32_t n_pairs) {
+  uint64_t c = 1024;
+  while (c < 2ull * n_pairs) c <<= 1;
+  return (uint32_t)(c - 1);
+}
+
+__device__ __forceinline__ uint32_t pair_hash(uint64_t haddr, uint64_t dev, uint64_t bytes) {
+  uint64_t h = haddr * 0x9E3779B97F4A7C15ull ^ (bytes + 0x632BE59BD9B4E019ull) ^ (dev << 57);
+  h ^= h >> 31;
+  h *= 0xBF58476D1CE4E5B9ull;
+  h ^= h >> 29;
+  return (uint32_t)h;
+}
+
+__device__ __forceinline__ bool same_pair_key(const uint64_t* haddr, const uint64_t* dev, const uint64_t* bytes,
+                                              uint32_t a, uint32_t b) {
+  return haddr[a] == haddr[b] && dev[a] == dev[b] && bytes[a] == bytes[b];
+}
+
+__global__ __launch_bounds__(kT) void pair_table_clear_kernel(PairTable T, const uint32_t* n_pairs) {
+  const uint32_t size = pair_table_mask(*n_pairs) + 1;
+  for (uint32_t i = blockIdx.x * kT + threadIdx.x; i < size; i += gridDim.x * kT) {
+    T.owner[i] = 0;
+    T.first[i] = kNone;
+    T.multi[i] = 0;
+  }
+}
+
+__global__ __launch_bounds__(kT) void pair_table_insert_kernel(PairTable T, const uint32_t* n_pairs,
+                                                              const uint64_t* haddr, const uint64_t* dev,
+                                                              const uint64_t* bytes) {
+  const uint32_t n = *n_pairs;
+  const uint32_t tmask = pair_table_mask(n);
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t waves = gridDim.x * (kT / 64);
+  for (uint32_t base = (blockIdx.x * (kT / 64) + (threadIdx.x >> 6)) * 64; base < n; base += waves * 64) {
+    const uint32_t k = base + lane;
+    const bool in = k < n;
+    const uint64_t ha = in ? haddr[k] : 0, dv = in ? dev[k] : 0, by = in ? bytes[k] : 0;
+    const uint32_t t0 = in ? pair_hash(ha, dv, by) & tmask : 0u;
+    // Lanes of one key inside the wavefront: the lowest (the smallest pair
+    // index) inserts for all of them. One round per distinct key, lane moves
+    // only; every lane knows its leader afterwards.
+    uint64_t pending = __ballot(in);
+    uint32_t leader = lane;
+    uint64_t group = 0;
+    while (pending) {
+      const int l = __builtin_ctzll(pending);
+      const uint32_t lt0 = (uint32_t)__shfl((int)t0, l, 64);
+      const uint64_t lha = __shfl(ha, l, 64), ldv = __shfl(dv, l, 64), lby = __shfl(by, l, 64);
+      const bool same = ((pending >> lane) & 1) && t0 == lt0 && ha == lha && dv == ldv && by == lby;
+      const uint64_t m = __ballot(same);
+      pending &= ~m;
+      if (same) leader = (uint32_t)l;
+      if ((uint32_t)l == lane) group = m;
+    }
+    uint32_t t = t0;
+    if (in && leader == lane) {
+      // the probe loop's lanes leave at different trips: what they decide is
+      // stored inside it, only the slot index leaves it
+      const bool several = __popcll(group) > 1;
+      for (uint32_t probe = 0; probe <= tmask; ++probe, t = (t + 1) & tmask) {
+        // an owner once set never changes: a stale 0 only costs the CAS
+        uint32_t o = T.owner[t];
+        if (o == 0) o = atomicCAS(T.owner + t, 0u, k + 1);
+        if (o == 0) {  // claimed
+          if (several) T.multi[t] = 1;
+          break;
+        }
+        if (same_pair_key(haddr, dev, bytes, o - 1, k)) {  // joined
+          if (T.multi[t] == 0) T.multi[t] = 1;
+          break;
+        }
+      }
+      if (k < T.first[t]) atomicMin(T.first + t, k);
+    }
+    t = (uint32_t)__shfl((int)t, (int)leader, 64);
+    if (in) T.slot[k] = t;
+  }
+}
+
 struct RaArgs {
   const odp_event* ev;
-  const SortJob* pr_job;
+  PairTable T;
   const uint64_t* starts_sorted;  // kernel starts in (device, start) order
   const uint64_t* ends_sorted;    // kernel ends in (device, end) order
   const uint32_t* n_pairs;
@@ -2103,9 +2202,6 @@ struct RaArgs {
   odp_report* rep;
 };
 
-__device__ __forceinline__ bool same_pair_key(const RaArgs& R, uint32_t a, uint32_t b) {
-  return R.pr_w_haddr[a] == R.pr_w_haddr[b] && R.pr_w_dev[a] == R.pr_w_dev[b] && R.pr_w_bytes[a] == R.pr_w_bytes[b];
-}
 
 // Number of entries of the sorted array w within [lo, hi) that are <= x (le) or < x.
 __device__ __forceinline__ uint32_t count_upto(const uint64_t* w, uint32_t lo, uint32_t hi, uint64_t x, bool le) {
@@ -2135,13 +2231,12 @@ __device__ __forceinline__ uint32_t kernels_meeting(const uint64_t* starts, cons
 __global__ __launch_bounds__(kT) void ra_ua_kernel(RaArgs R) {
   const bool chrono = !R.ctl->kern_sort;
   const uint32_t n = *R.n_pairs;
-  const SortJob& s = *R.pr_job;
-  const uint32_t* v = s.vals[s.npasses & 1];
   unsigned long long c_ra = 0, c_grp = 0, b_ra = 0, t_ra = 0, c_ua = 0, b_ua = 0, t_ua = 0, t_el = 0;
-  for (uint32_t j = blockIdx.x * kT + threadIdx.x; j < n; j += gridDim.x * kT) {
-    const uint32_t k = v[j];
-    const bool head = j == 0 || !same_pair_key(R, k, v[j - 1]);
-    const bool group2 = head && j + 1 < n && same_pair_key(R, k, v[j + 1]);
+  for (uint32_t k = blockIdx.x * kT + threadIdx.x; k < n; k += gridDim.x * kT) {
+    // the slot of k's key: its first pair (the earliest ALLOC), and whether it has more
+    const uint32_t t = R.T.slot[k];
+    const bool head = R.T.first[t] == k;
+    const bool group2 = head && R.T.multi[t] != 0;
     const uint32_t ai = R.ad_idx[R.pr_alloc[k]], di = R.ad_idx[R.pr_del[k]];
     const odp_event& a = R.ev[ai];
     const odp_event& d = R.ev[di];
@@ -2628,7 +2723,8 @@ struct Views {
   uint32_t* next_q;
   uint8_t* ut_hit;
   WaveScan wscan;
-  uint32_t *pr_alloc, *pr_del, *pr_vals, *pr_vals1;
+  uint32_t *pr_alloc, *pr_del;
+  PairTable pt;
   uint64_t *pr_w_bytes, *pr_w_dev, *pr_w_haddr;
   uint32_t* hist;
   uint32_t* totals;
@@ -2702,8 +2798,11 @@ Views views(Workspace* ws) {
   v.pr_w_bytes = carve<uint64_t>(pp, cap);
   v.pr_w_dev = carve<uint64_t>(pp, cap);
   v.pr_w_haddr = carve<uint64_t>(pp, cap);
-  v.pr_vals = carve<uint32_t>(pp, cap);
-  v.pr_vals1 = carve<uint32_t>(pp, cap);
+  const size_t tcap = (size_t)pair_table_mask((uint32_t)std::min<size_t>(cap / 2, 0x7FFFFFFFu)) + 1;
+  v.pt.owner = carve<uint32_t>(pp, tcap);
+  v.pt.first = carve<uint32_t>(pp, tcap);
+  v.pt.multi = carve<uint32_t>(pp, tcap);
+  v.pt.slot = carve<uint32_t>(pp, cap);
   v.hist = static_cast<uint32_t*>(b[B_HIST].ptr);
   v.totals = static_cast<uint32_t*>(b[B_TOTALS].ptr);
   char* ps = static_cast<char*>(b[B_SEG].ptr);
@@ -2778,19 +2877,6 @@ void build_jobs(const Views& v, SortJob* hj) {
   hj[kJobUt].nwords = 2;
   hj[kJobUt].run_flag = &ctl->ut_need_sort;
   // paired allocations by (host address, device, bytes)
-  hj[kJobPr].n_ptr = &ctl->n_pairs;
-  hj[kJobPr].vals[0] = v.pr_vals;
-  hj[kJobPr].vals[1] = v.pr_vals1;
-  hj[kJobPr].words[0] = v.pr_w_bytes;
-  hj[kJobPr].masks[0] = &ctl->m_p_bytes;
-  hj[kJobPr].word_bytes[0] = 8;
-  hj[kJobPr].words[1] = v.pr_w_dev;
-  hj[kJobPr].masks[1] = &ctl->m_p_dev;
-  hj[kJobPr].word_bytes[1] = 1;
-  hj[kJobPr].words[2] = v.pr_w_haddr;
-  hj[kJobPr].masks[2] = &ctl->m_p_haddr;
-  hj[kJobPr].word_bytes[2] = 8;
-  hj[kJobPr].nwords = 3;
   for (int j = 1; j < kNumJobs; ++j) {
     hj[j].keys[0] = v.skey[2 * (j - 1)];
     hj[j].keys[1] = v.skey[2 * (j - 1) + 1];
@@ -2831,7 +2917,8 @@ int analyze_reserve(Workspace* ws, size_t max_events) {
       (e = b[B_UT].ensure(cap * (4 + 8 + 8 + 8 + 4 + 4 + 8 + 4 + 4 + 1) + 64)) ||
       (e = b[B_WSCAN].ensure((size_t)nt * (kT / 64) * kEp * 8 +
                              (size_t)ceil_div32((size_t)nt * (kT / 64), kScanChunk) * (kWaveCnt * 4 + kEp * 8) + 64)) ||
-      (e = b[B_PR].ensure(cap * (4 + 4 + 8 + 8 + 8 + 4 + 4) + 64)) ||
+      (e = b[B_PR].ensure(cap * (4 + 4 + 8 + 8 + 8 + 4) +
+                          ((size_t)pair_table_mask((uint32_t)std::min<size_t>(cap / 2, 0x7FFFFFFFu)) + 1) * 12 + 64)) ||
       (e = b[B_HIST].ensure((size_t)kNumJobs * 256 * nt * 4)) ||
       (e = b[B_TOTALS].ensure((size_t)kNumJobs * kMaxPasses * 256 * 4)) ||
       (e = b[B_SEG].ensure((size_t)nt * (kT / 64) * 2 * sizeof(WaveAgg) + 64)) ||
@@ -3258,7 +3345,6 @@ static int enqueue_analysis(Workspace* ws, const odp_event* events, size_t n, ui
   P.pr_w_bytes = v.pr_w_bytes;
   P.pr_w_dev = v.pr_w_dev;
   P.pr_w_haddr = v.pr_w_haddr;
-  P.pr_vals = v.pr_vals;
   P.flags = out_flags;
   P.ctl = ctl;
   P.rep = out_report;
@@ -3271,22 +3357,14 @@ static int enqueue_analysis(Workspace* ws, const odp_event* events, size_t n, ui
   hipLaunchKernelGGL(ut_next_kernel, dim3(grid_map), dim3(kT), 0, side, U);
   hipLaunchKernelGGL(ut_eval_kernel, dim3(grid_map), dim3(kT), 0, side, U);
 
-  // Second sort: pairs by (host address, device, bytes).
-  const JobSet J2{v.jobs + kJobPr, 1, side_blocks};
-  hipLaunchKernelGGL(sort_plan_kernel, dim3(1), dim3(64), 0, side, J2, 0u);
-  if (small) {
-    hipLaunchKernelGGL(sort_small_kernel, dim3(J2.njobs), dim3(kQT), 0, side, J2);
-  } else {
-    for (uint32_t p = 0; p < 17; ++p) {
-      hipLaunchKernelGGL(sort_hist_kernel, dim3(side_blocks), dim3(kT), 0, side, J2, p);
-      hipLaunchKernelGGL(sort_scan_kernel, dim3(256), dim3(kT), 0, side, J2, p);
-      hipLaunchKernelGGL(sort_scatter_kernel, dim3(side_blocks), dim3(kST), 0, side, J2, p);
-    }
-  }
+  // Pairs grouped by (host address, device, bytes) in a table.
+  hipLaunchKernelGGL(pair_table_clear_kernel, dim3(grid_map), dim3(kT), 0, side, v.pt, &ctl->n_pairs);
+  hipLaunchKernelGGL(pair_table_insert_kernel, dim3(grid_map), dim3(kT), 0, side, v.pt, &ctl->n_pairs,
+                     v.pr_w_haddr, v.pr_w_dev, v.pr_w_bytes);
 
   RaArgs R;
   R.ev = events;
-  R.pr_job = v.jobs + kJobPr;
+  R.T = v.pt;
   R.starts_sorted = v.starts_sorted;
   R.ends_sorted = v.ends_sorted;
   R.n_pairs = &ctl->n_pairs;

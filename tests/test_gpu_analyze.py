@@ -333,3 +333,30 @@ def test_log_above_packed_index_limit(odp):
     ev["bytes"] = np.where(op == W.KERNEL, 0, 4096).astype(np.uint64)
     fg, rg = check(odp, ev)
     assert rg["n_events"] == m and rg["dd_events"] > 1_000_000 and rg["rt_pairs"] > 1000
+
+
+@pytest.mark.parametrize("pairs,keys,hot", [(1000, 500, 0.0), (150_000, 100_000, 0.5), (40_000, 3, 0.0)])
+def test_allocation_groups_of_every_size(odp, pairs, keys, hot):
+    """Paired allocations grouped by (host address, device, bytes) for RA: a
+    table barely larger than the keys (many probes run into each other), one
+    key holding half of 150,000 pairs (many lanes of a wavefront share it),
+    and three keys for 40,000 pairs; each against the oracle."""
+    rng = np.random.default_rng(pairs + keys)
+    m = 2 * pairs
+    ev = W.empty_events(m)
+    ev["op"] = np.tile([W.ALLOC, W.DELETE], pairs)
+    key = rng.integers(0, keys, size=pairs)
+    key = np.where(rng.random(pairs) < hot, 0, key)
+    dev = (key % 3).astype(np.int8)
+    ev["dst_dev"] = np.repeat(dev, 2)
+    ev["src_dev"] = -1
+    ev["src_addr"] = np.repeat(np.uint64(W.HOST_BASE) + (key // 3).astype(np.uint64) * np.uint64(4096), 2)
+    ev["bytes"] = np.repeat(np.uint64(64) << (key % 5).astype(np.uint64), 2)
+    ev["dst_addr"] = np.repeat(np.uint64(W.DEV_BASE) + np.arange(pairs, dtype=np.uint64) * np.uint64(64), 2)
+    ev["t_start"] = np.arange(m, dtype=np.uint64) * 2
+    ev["t_end"] = ev["t_start"] + 1
+    kern = rng.random(m) < 0.02
+    ev["op"] = np.where(kern, W.KERNEL, ev["op"])
+    ev["bytes"] = np.where(kern, 0, ev["bytes"])
+    fg, rg = check(odp, ev)
+    assert rg["ra_events"] > 0
