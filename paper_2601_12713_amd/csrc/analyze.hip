@@ -34,6 +34,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <functional>
+#include <vector>
 
 #include "internal.h"
 
@@ -2325,6 +2327,13 @@ struct UtArgs {
 // path below, which the device then switches on.
 constexpr uint32_t kUtWindow = 64;
 
+// A block takes kT consecutive copy-ins (one per thread) and stages the
+// fields of the copies its searches can reach (the next kT + kUtWindow) in
+// LDS, so that each search reads LDS instead of re-reading the arrays. What
+// a search decides is stored inside its loop (its lanes leave it at
+// different trips).
+constexpr uint32_t kUtStage = kT + kUtWindow;
+
 __global__ __launch_bounds__(kT) void ut_scan_kernel(UtArgs U) {
   const uint32_t n = *U.n_ut;
   const bool chrono = U.ctl->first_bad == kNone;
@@ -2335,58 +2344,54 @@ __global__ __launch_bounds__(kT) void ut_scan_kernel(UtArgs U) {
     }
     return;
   }
-  bool undecided = false;
-  for (uint32_t q = blockIdx.x * kT + threadIdx.x; q < n; q += gridDim.x * kT) {
-    const uint64_t code = U.ut_w_code[q];
-    const uint32_t d = (uint32_t)(code & 15);
-    const uint64_t ts = U.ut_ts[q];
-    const uint32_t k = U.ut_kc[q], total = U.ctl->kd_total[d];
-    uint8_t hit;
-    if (k > 0 && U.ut_km[q] >= ts) {
-      hit = 0;
-    } else if (k == total) {
-      hit = 1;
-    } else {
-      const uint32_t kp = U.ctl->kd_base[d] + k;
-      const uint64_t sk = U.kd_ts[kp];
-      const uint32_t kidx = U.kd_idx[kp];
-      const uint64_t addr = U.ut_w_addr[q];
-      hit = 0;
-      // eight candidates' loads in flight at a time
-      bool done = false;
-      for (uint32_t r0 = q + 1; !done; r0 += 8) {
-        uint32_t ix[8];
-        uint64_t ad[8], co[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const uint32_t r = r0 + u;
-          const bool ok = r < n;
-          ix[u] = ok ? U.ut_idx[r] : kNone;
-          ad[u] = ok ? U.ut_w_addr[r] : 0ull;
-          co[u] = ok ? U.ut_w_code[r] : 0ull;
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          if (done) continue;
-          const uint32_t r = r0 + u;
-          if (r >= n || ix[u] > kidx) {
-            done = true;  // no next copy before k (past k, the next copy, if any, comes after it)
-          } else if (r - (q + 1) == kUtWindow) {
-            hit = 2;
-            done = true;
-          } else if (ad[u] == addr && co[u] == code) {
-            hit = U.ut_ts[r] < sk ? 1 : 0;
-            done = true;
+  __shared__ uint32_t s_ix[kUtStage];
+  __shared__ unsigned long long s_ad[kUtStage], s_co[kUtStage], s_ts[kUtStage];
+  for (uint32_t b0 = blockIdx.x * kT; b0 < n; b0 += gridDim.x * kT) {
+    // s_*[x] holds copy-in b0 + 1 + x (index kNone past the last)
+    for (uint32_t x = threadIdx.x; x < kUtStage; x += kT) {
+      const uint32_t r = b0 + 1 + x;
+      const bool ok = r < n;
+      s_ix[x] = ok ? U.ut_idx[r] : kNone;
+      s_ad[x] = ok ? U.ut_w_addr[r] : 0ull;
+      s_co[x] = ok ? U.ut_w_code[r] : 0ull;
+      s_ts[x] = ok ? U.ut_ts[r] : 0ull;
+    }
+    __syncthreads();
+    const uint32_t q = b0 + threadIdx.x;
+    if (q < n) {
+      const uint64_t code = U.ut_w_code[q];
+      const uint32_t d = (uint32_t)(code & 15);
+      const uint64_t ts = U.ut_ts[q];
+      const uint32_t k = U.ut_kc[q], total = U.ctl->kd_total[d];
+      if (k > 0 && U.ut_km[q] >= ts) {
+        U.ut_hit[q] = 0;  // a kernel is still running
+      } else if (k == total) {
+        U.ut_hit[q] = 1;  // no kernel follows
+      } else {
+        const uint32_t kp = U.ctl->kd_base[d] + k;
+        const uint64_t sk = U.kd_ts[kp];
+        const uint32_t kidx = U.kd_idx[kp];
+        const uint64_t addr = U.ut_w_addr[q];
+        // the copies after q, up to kUtWindow of them, before kernel kp
+        for (uint32_t x = threadIdx.x, m = 0;; ++x, ++m) {
+          if (s_ix[x] > kidx) {  // none before the kernel (past the last copy too)
+            U.ut_hit[q] = 0;
+            break;
+          }
+          if (m == kUtWindow) {  // undecided: the sorted path takes it
+            U.ut_hit[q] = 2;
+            U.ctl->ut_need_sort = 1;
+            U.ctl->kern_sort = 1;
+            break;
+          }
+          if (s_ad[x] == addr && s_co[x] == code) {  // the next copy of the place
+            U.ut_hit[q] = s_ts[x] < sk ? 1 : 0;
+            break;
           }
         }
       }
-      undecided |= hit == 2;
     }
-    U.ut_hit[q] = hit;
-  }
-  if (__syncthreads_or(undecided) && threadIdx.x == 0) {
-    U.ctl->ut_need_sort = 1;
-    U.ctl->kern_sort = 1;
+    __syncthreads();
   }
 }
 
@@ -3257,6 +3262,11 @@ static int enqueue_analysis(Workspace* ws, const odp_event* events, size_t n, ui
   const uint32_t nt = n ? ceil_div32(n, kTile) : 1;  // tiles of this call
   const int cus = cu_count(ws->device);
   const uint32_t grid_map = std::min<uint32_t>(nt * 4, (uint32_t)cus * 8);
+  // one thread per element of a subset of at most n (copy-ins) or n / 2
+  // (pairs) elements, for the per-element kernels that wait on chains of
+  // dependent loads and add nothing up per block: they overlap those waits
+  // across many more waves than a grid-stride loop over grid_map blocks does
+  const uint32_t grid_rec = n ? ceil_div32(n, kT) : 1, grid_pair = ceil_div32(n / 2 + 1, kT);
   AnaCtl* ctl = v.ctl;
 
   hipLaunchKernelGGL(init_kernel, dim3(64), dim3(kT), 0, stream, ctl, out_report, v.totals,
@@ -3280,16 +3290,18 @@ static int enqueue_analysis(Workspace* ws, const odp_event* events, size_t n, ui
   ODP_HIP(hipStreamWaitEvent(side, ws->a_fork, 0));
 
   const bool small = n <= kSmallMax;  // every job then has at most kSmallMax elements
-  // The allocation path on the side stream, enqueued first: the runtime
-  // issues launches (and a graph's nodes) in this order, and this path waits
-  // only for the classification.
+  // The launches of the two paths are collected, then issued alternately:
+  // the runtime issues launches (and a graph's nodes) in the order they were
+  // made, and a path whose launches all came after the other's started late
+  // (measured: the digest path waited for most of the allocation path).
+  std::vector<std::function<void()>> SQ, MQ;  // side stream, caller's stream
   WaveScan WS = v.wscan;
   WS.nw = nt * (kT / 64);
   const uint32_t nchunk = ceil_div32(WS.nw, kScanChunk);
-  hipLaunchKernelGGL(wave_scan_local_kernel, dim3(nchunk), dim3(1024), 0, side, WS);
-  hipLaunchKernelGGL(wave_scan_chunks_kernel, dim3(1), dim3(1024), 0, side, WS, nchunk, &ctl->n_ad, &ctl->n_k,
-                     &ctl->n_ut, ctl);
-  hipLaunchKernelGGL(subset_scatter_kernel, dim3(nt), dim3(kT), 0, side, events, v.cls, nn, WS, v.S, v.parts);
+  SQ.push_back([=] { hipLaunchKernelGGL(wave_scan_local_kernel, dim3(nchunk), dim3(1024), 0, side, WS); });
+  SQ.push_back([=] { hipLaunchKernelGGL(wave_scan_chunks_kernel, dim3(1), dim3(1024), 0, side, WS, nchunk, &ctl->n_ad, &ctl->n_k,
+                     &ctl->n_ut, ctl); });
+  SQ.push_back([=] { hipLaunchKernelGGL(subset_scatter_kernel, dim3(nt), dim3(kT), 0, side, events, v.cls, nn, WS, v.S, v.parts); });
   // Unused transfers (their flags are merged after the join).
   UtArgs U;
   U.ev = events;
@@ -3310,23 +3322,23 @@ static int enqueue_analysis(Workspace* ws, const odp_event* events, size_t n, ui
   U.ctl = ctl;
   U.flags = out_flags;
   U.rep = out_report;
-  hipLaunchKernelGGL(ut_scan_kernel, dim3(grid_map), dim3(kT), 0, side, U);
-  hipLaunchKernelGGL(reduce_parts_kernel, dim3(S_DD_EVENTS - S_AD_DEV_OR), dim3(kT), 0, side, v.parts, nt,
-                     (uint32_t)S_AD_DEV_OR, ctl, out_report);
+  SQ.push_back([=] { hipLaunchKernelGGL(ut_scan_kernel, dim3(grid_rec), dim3(kT), 0, side, U); });
+  SQ.push_back([=] { hipLaunchKernelGGL(reduce_parts_kernel, dim3(S_DD_EVENTS - S_AD_DEV_OR), dim3(kT), 0, side, v.parts, nt,
+                     (uint32_t)S_AD_DEV_OR, ctl, out_report); });
   // ALLOC/DELETE by (device, address), kernels by (device, start) and (device,
   // end), copy-ins by (endpoints, source address). The subsets are usually
   // far smaller than the log: a capped number of blocks per job loops over
   // its tiles instead of a block per log tile.
   const uint32_t side_blocks = std::min<uint32_t>(nt, (uint32_t)cus * 2);
   const JobSet Js{v.jobs + kJobAd, kSubsetJobs, side_blocks};
-  hipLaunchKernelGGL(sort_plan_kernel, dim3(1), dim3(64), 0, side, Js, 0u);
+  SQ.push_back([=] { hipLaunchKernelGGL(sort_plan_kernel, dim3(1), dim3(64), 0, side, Js, 0u); });
   if (small) {
-    hipLaunchKernelGGL(sort_small_kernel, dim3(Js.njobs), dim3(kQT), 0, side, Js);
+    SQ.push_back([=] { hipLaunchKernelGGL(sort_small_kernel, dim3(Js.njobs), dim3(kQT), 0, side, Js); });
   } else {
     for (uint32_t p = 0; p < 9; ++p) {
-      hipLaunchKernelGGL(sort_hist_kernel, dim3(Js.njobs * side_blocks), dim3(kT), 0, side, Js, p);
-      hipLaunchKernelGGL(sort_scan_kernel, dim3(256 * Js.njobs), dim3(kT), 0, side, Js, p);
-      hipLaunchKernelGGL(sort_scatter_kernel, dim3(Js.njobs * side_blocks), dim3(kST), 0, side, Js, p);
+      SQ.push_back([=] { hipLaunchKernelGGL(sort_hist_kernel, dim3(Js.njobs * side_blocks), dim3(kT), 0, side, Js, p); });
+      SQ.push_back([=] { hipLaunchKernelGGL(sort_scan_kernel, dim3(256 * Js.njobs), dim3(kT), 0, side, Js, p); });
+      SQ.push_back([=] { hipLaunchKernelGGL(sort_scatter_kernel, dim3(Js.njobs * side_blocks), dim3(kST), 0, side, Js, p); });
     }
   }
   // Pairing and the pair list.
@@ -3348,19 +3360,19 @@ static int enqueue_analysis(Workspace* ws, const odp_event* events, size_t n, ui
   P.flags = out_flags;
   P.ctl = ctl;
   P.rep = out_report;
-  hipLaunchKernelGGL(pair_kernel, dim3(grid_map), dim3(kT), 0, side, P);
-  hipLaunchKernelGGL(pair_count_kernel, dim3(nt), dim3(kT), 0, side, P);
-  hipLaunchKernelGGL(scan_counts_kernel<2>, dim3(1), dim3(1024), 0, side, v.tile_cnt, nt, &ctl->n_pairs, nullptr);
-  hipLaunchKernelGGL(pair_scatter_kernel, dim3(nt), dim3(kT), 0, side, P);
-  hipLaunchKernelGGL(kernel_ranges_kernel, dim3(grid_map), dim3(kT), 0, side, v.jobs + kJobKs, v.jobs + kJobKe,
-                     v.S.k_w_dev, v.S.k_w_start, v.S.k_w_end, &ctl->n_k, v.starts_sorted, v.ends_sorted, ctl);
-  hipLaunchKernelGGL(ut_next_kernel, dim3(grid_map), dim3(kT), 0, side, U);
-  hipLaunchKernelGGL(ut_eval_kernel, dim3(grid_map), dim3(kT), 0, side, U);
+  SQ.push_back([=] { hipLaunchKernelGGL(pair_kernel, dim3(grid_map), dim3(kT), 0, side, P); });
+  SQ.push_back([=] { hipLaunchKernelGGL(pair_count_kernel, dim3(nt), dim3(kT), 0, side, P); });
+  SQ.push_back([=] { hipLaunchKernelGGL(scan_counts_kernel<2>, dim3(1), dim3(1024), 0, side, v.tile_cnt, nt, &ctl->n_pairs, nullptr); });
+  SQ.push_back([=] { hipLaunchKernelGGL(pair_scatter_kernel, dim3(nt), dim3(kT), 0, side, P); });
+  SQ.push_back([=] { hipLaunchKernelGGL(kernel_ranges_kernel, dim3(grid_map), dim3(kT), 0, side, v.jobs + kJobKs, v.jobs + kJobKe,
+                     v.S.k_w_dev, v.S.k_w_start, v.S.k_w_end, &ctl->n_k, v.starts_sorted, v.ends_sorted, ctl); });
+  SQ.push_back([=] { hipLaunchKernelGGL(ut_next_kernel, dim3(grid_map), dim3(kT), 0, side, U); });
+  SQ.push_back([=] { hipLaunchKernelGGL(ut_eval_kernel, dim3(grid_map), dim3(kT), 0, side, U); });
 
   // Pairs grouped by (host address, device, bytes) in a table.
-  hipLaunchKernelGGL(pair_table_clear_kernel, dim3(grid_map), dim3(kT), 0, side, v.pt, &ctl->n_pairs);
-  hipLaunchKernelGGL(pair_table_insert_kernel, dim3(grid_map), dim3(kT), 0, side, v.pt, &ctl->n_pairs,
-                     v.pr_w_haddr, v.pr_w_dev, v.pr_w_bytes);
+  SQ.push_back([=] { hipLaunchKernelGGL(pair_table_clear_kernel, dim3(grid_map), dim3(kT), 0, side, v.pt, &ctl->n_pairs); });
+  SQ.push_back([=] { hipLaunchKernelGGL(pair_table_insert_kernel, dim3(grid_pair), dim3(kT), 0, side, v.pt, &ctl->n_pairs,
+                     v.pr_w_haddr, v.pr_w_dev, v.pr_w_bytes); });
 
   RaArgs R;
   R.ev = events;
@@ -3380,7 +3392,7 @@ static int enqueue_analysis(Workspace* ws, const odp_event* events, size_t n, ui
   R.ctl = ctl;
   R.flags = out_flags;
   R.rep = out_report;
-  hipLaunchKernelGGL(ra_ua_kernel, dim3(grid_map), dim3(kT), 0, side, R);
+  SQ.push_back([=] { hipLaunchKernelGGL(ra_ua_kernel, dim3(grid_map), dim3(kT), 0, side, R); });
   // Records by digest (up to 8 passes), then duplicates and round trips, on
   // the caller's stream.
   const JobSet Jb{v.jobs + kJobBig, 1, nt};
@@ -3389,17 +3401,17 @@ static int enqueue_analysis(Workspace* ws, const odp_event* events, size_t n, ui
   // the digest histograms take two tiles per block on long logs (measured a
   // little faster than one: the per-block start-up is amortised)
   const JobSet Jh{v.jobs + kJobBig, 1, nt > 4u * (uint32_t)cus ? (nt + 1) / 2 : nt};
-  hipLaunchKernelGGL(sort_plan_kernel, dim3(1), dim3(64), 0, stream, Jb, kfirst);
+  MQ.push_back([=] { hipLaunchKernelGGL(sort_plan_kernel, dim3(1), dim3(64), 0, stream, Jb, kfirst); });
   if (small) {
-    hipLaunchKernelGGL(sort_small_kernel, dim3(Jb.njobs), dim3(kQT), 0, stream, Jb);
+    MQ.push_back([=] { hipLaunchKernelGGL(sort_small_kernel, dim3(Jb.njobs), dim3(kQT), 0, stream, Jb); });
   } else {
     for (uint32_t p = 0; p < 8; ++p) {
-      if (kfirst && p >= kfirst) hipLaunchKernelGGL(sort_fix_kernel, dim3(nft), dim3(kT), 0, stream, v.jobs + kJobBig, p);
-      hipLaunchKernelGGL(sort_hist_kernel, dim3(Jh.stride), dim3(kT), 0, stream, Jh, p);
-      hipLaunchKernelGGL(sort_scan_kernel, dim3(256), dim3(kT), 0, stream, Jb, p);
-      hipLaunchKernelGGL(sort_scatter_kernel, dim3(nt), dim3(kST), 0, stream, Jb, p);
+      if (kfirst && p >= kfirst) MQ.push_back([=] { hipLaunchKernelGGL(sort_fix_kernel, dim3(nft), dim3(kT), 0, stream, v.jobs + kJobBig, p); });
+      MQ.push_back([=] { hipLaunchKernelGGL(sort_hist_kernel, dim3(Jh.stride), dim3(kT), 0, stream, Jh, p); });
+      MQ.push_back([=] { hipLaunchKernelGGL(sort_scan_kernel, dim3(256), dim3(kT), 0, stream, Jb, p); });
+      MQ.push_back([=] { hipLaunchKernelGGL(sort_scatter_kernel, dim3(nt), dim3(kST), 0, stream, Jb, p); });
     }
-    if (kfirst) hipLaunchKernelGGL(sort_fix_kernel, dim3(nft), dim3(kT), 0, stream, v.jobs + kJobBig, 8u);
+    if (kfirst) MQ.push_back([=] { hipLaunchKernelGGL(sort_fix_kernel, dim3(nft), dim3(kT), 0, stream, v.jobs + kJobBig, 8u); });
   }
   DDArgs D;
   D.ev = events;
@@ -3412,11 +3424,11 @@ static int enqueue_analysis(Workspace* ws, const odp_event* events, size_t n, ui
   D.flags = out_flags;
   D.rep = out_report;
   D.parts = v.parts;
-  hipLaunchKernelGGL(ddrt_agg_kernel, dim3(nt), dim3(kT), 0, stream, D);
-  hipLaunchKernelGGL(ddrt_carry_kernel, dim3(1), dim3(kCT), 0, stream, D, nt * (kT / 64));
-  hipLaunchKernelGGL(ddrt_final_kernel, dim3(nt), dim3(kT), 0, stream, D);
-  hipLaunchKernelGGL(reduce_parts_kernel, dim3(kSlots - S_DD_EVENTS), dim3(kT), 0, stream, v.parts, nt,
-                     (uint32_t)S_DD_EVENTS, ctl, out_report);
+  MQ.push_back([=] { hipLaunchKernelGGL(ddrt_agg_kernel, dim3(nt), dim3(kT), 0, stream, D); });
+  MQ.push_back([=] { hipLaunchKernelGGL(ddrt_carry_kernel, dim3(1), dim3(kCT), 0, stream, D, nt * (kT / 64)); });
+  MQ.push_back([=] { hipLaunchKernelGGL(ddrt_final_kernel, dim3(nt), dim3(kT), 0, stream, D); });
+  MQ.push_back([=] { hipLaunchKernelGGL(reduce_parts_kernel, dim3(kSlots - S_DD_EVENTS), dim3(kT), 0, stream, v.parts, nt,
+                     (uint32_t)S_DD_EVENTS, ctl, out_report); });
   if (alg2_rx) {
     Alg2Args G;
     G.job = v.jobs + kJobBig;
@@ -3424,9 +3436,13 @@ static int enqueue_analysis(Workspace* ws, const odp_event* events, size_t n, ui
     G.n = nn;
     G.rx = alg2_rx;
     G.npairs = alg2_np;
-    hipLaunchKernelGGL(alg2_kernel, dim3(ceil_div32(n, kT)), dim3(kT), 0, stream, G);
+    MQ.push_back([=] { hipLaunchKernelGGL(alg2_kernel, dim3(ceil_div32(n, kT)), dim3(kT), 0, stream, G); });
   }
 
+  for (size_t q = 0; q < std::max(SQ.size(), MQ.size()); ++q) {
+    if (q < SQ.size()) SQ[q]();
+    if (q < MQ.size()) MQ[q]();
+  }
   ODP_HIP(hipEventRecord(ws->a_join, side));
 
   ODP_HIP(hipStreamWaitEvent(stream, ws->a_join, 0));
