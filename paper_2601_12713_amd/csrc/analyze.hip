@@ -34,8 +34,6 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
-#include <functional>
-#include <vector>
 
 #include "internal.h"
 
@@ -620,9 +618,12 @@ __global__ __launch_bounds__(kT) void subset_scatter_kernel(const odp_event* __r
     const uint32_t i = wb + r * 64 + lane;
     const bool is_ad = c[r] == C_ALLOCDEL, is_k = c[r] == C_KERNEL, is_ut = c[r] == C_COPYIN;
     const uint64_t bad = __ballot(is_ad), bk = __ballot(is_k), bu = __ballot(is_ut);
+    // the whole record, once, for the records this kernel lists
+    odp_event e{};
+    if (is_k || is_ut || is_ad) e = ev[i];
     // the device code of kernels and copy-ins (both in dst_dev)
-    const uint32_t dc = (is_k || is_ut || is_ad) ? (uint32_t)(ev[i].dst_dev + 1) : 0u;
-    const unsigned long long kend = is_k ? (unsigned long long)ev[i].t_end : 0ull;
+    const uint32_t dc = (is_k || is_ut || is_ad) ? (uint32_t)(e.dst_dev + 1) : 0u;
+    const unsigned long long kend = is_k ? (unsigned long long)e.t_end : 0ull;
     uint32_t kc = (is_ut || is_k || is_ad) ? s_kc[w][dc] : 0u;
     unsigned long long km = (is_ut || is_ad) ? s_km[w][dc] : 0ull;
     if (bk) {
@@ -654,7 +655,6 @@ __global__ __launch_bounds__(kT) void subset_scatter_kernel(const odp_event* __r
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     }
     if (is_ut) {
-      const odp_event& e = ev[i];
       const uint32_t q = q2 + (uint32_t)__popcll(bu & lt);
       const uint64_t code = (uint64_t)(((e.src_dev + 1) << 4) | (e.dst_dev + 1)), sa = e.src_addr;
       S.ut_idx[q] = i;
@@ -669,7 +669,6 @@ __global__ __launch_bounds__(kT) void subset_scatter_kernel(const odp_event* __r
       o_uc |= code;
       a_uc &= code;
     } else if (is_ad) {
-      const odp_event& e = ev[i];
       const uint32_t q = q0 + (uint32_t)__popcll(bad & lt);
       const uint64_t dv = (uint64_t)(e.dst_dev + 1), ad = e.dst_addr;
       S.ad_idx[q] = i;
@@ -685,7 +684,6 @@ __global__ __launch_bounds__(kT) void subset_scatter_kernel(const odp_event* __r
       o_addr |= ad;
       a_addr &= ad;
     } else if (is_k) {
-      const odp_event& e = ev[i];
       const uint32_t q = q1 + (uint32_t)__popcll(bk & lt);
       const uint64_t dv = (uint64_t)(e.dst_dev + 1);
       S.k_idx[q] = i;
@@ -2467,20 +2465,45 @@ __global__ __launch_bounds__(kT) void ut_eval_kernel(UtArgs U) {
 // writes advance through the flag array), sums the unused copies' bytes and
 // time, and adds the removable time of those no other flag already made
 // removable.
+// Sets ODP_F_UT and adds up the unused transfers, after the join (the
+// transfers' other flags are final then; a record flagged DD or RT_RX too
+// has its time counted as eliminable there already). Four copy-ins per
+// thread and step, their loads issued together: each is a chain of dependent
+// loads (result, record index, then flag and record).
 __global__ __launch_bounds__(kT) void ut_merge_kernel(UtArgs U) {
+  constexpr uint32_t kU = 4;
   const uint32_t n = *U.n_ut;
+  const uint32_t stride = gridDim.x * kT;
   unsigned long long c_ut = 0, b_ut = 0, t_ut = 0, t_el = 0;
-  for (uint32_t q = blockIdx.x * kT + threadIdx.x; q < n; q += gridDim.x * kT) {
-    if (U.ut_hit[q] != 1) continue;
-    const uint32_t i = U.ut_idx[q];
-    const uint8_t f = U.flags[i];
-    U.flags[i] = f | ODP_F_UT;
-    const odp_event& e = U.ev[i];
-    const uint64_t d = e.t_end - e.t_start;
-    ++c_ut;
-    b_ut += e.bytes;
-    t_ut += d;
-    if (!(f & (ODP_F_DD | ODP_F_RT_RX))) t_el += d;
+  for (uint32_t q0 = blockIdx.x * kT + threadIdx.x; q0 < n; q0 += kU * stride) {
+    bool hit[kU];
+    uint32_t idx[kU];
+#pragma unroll
+    for (uint32_t u = 0; u < kU; ++u) {
+      const uint32_t q = q0 + u * stride;
+      hit[u] = q < n && U.ut_hit[q] == 1;
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < kU; ++u) idx[u] = hit[u] ? U.ut_idx[q0 + u * stride] : 0u;
+    uint8_t f[kU];
+    uint64_t ts[kU], te[kU], by[kU];
+#pragma unroll
+    for (uint32_t u = 0; u < kU; ++u) {
+      f[u] = hit[u] ? U.flags[idx[u]] : 0;
+      ts[u] = hit[u] ? U.ev[idx[u]].t_start : 0;
+      te[u] = hit[u] ? U.ev[idx[u]].t_end : 0;
+      by[u] = hit[u] ? U.ev[idx[u]].bytes : 0;
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < kU; ++u) {
+      if (!hit[u]) continue;
+      U.flags[idx[u]] = f[u] | ODP_F_UT;
+      const uint64_t d = te[u] - ts[u];
+      ++c_ut;
+      b_ut += by[u];
+      t_ut += d;
+      if (!(f[u] & (ODP_F_DD | ODP_F_RT_RX))) t_el += d;
+    }
   }
   block_add(&U.rep->ut_events, c_ut);
   block_add(&U.rep->ut_bytes, b_ut);
@@ -3290,18 +3313,15 @@ static int enqueue_analysis(Workspace* ws, const odp_event* events, size_t n, ui
   ODP_HIP(hipStreamWaitEvent(side, ws->a_fork, 0));
 
   const bool small = n <= kSmallMax;  // every job then has at most kSmallMax elements
-  // The launches of the two paths are collected, then issued alternately:
-  // the runtime issues launches (and a graph's nodes) in the order they were
-  // made, and a path whose launches all came after the other's started late
-  // (measured: the digest path waited for most of the allocation path).
-  std::vector<std::function<void()>> SQ, MQ;  // side stream, caller's stream
+  // The allocation path on the side stream, enqueued first (it waits only
+  // for the classification), then the digest path on the caller's stream.
   WaveScan WS = v.wscan;
   WS.nw = nt * (kT / 64);
   const uint32_t nchunk = ceil_div32(WS.nw, kScanChunk);
-  SQ.push_back([=] { hipLaunchKernelGGL(wave_scan_local_kernel, dim3(nchunk), dim3(1024), 0, side, WS); });
-  SQ.push_back([=] { hipLaunchKernelGGL(wave_scan_chunks_kernel, dim3(1), dim3(1024), 0, side, WS, nchunk, &ctl->n_ad, &ctl->n_k,
-                     &ctl->n_ut, ctl); });
-  SQ.push_back([=] { hipLaunchKernelGGL(subset_scatter_kernel, dim3(nt), dim3(kT), 0, side, events, v.cls, nn, WS, v.S, v.parts); });
+  hipLaunchKernelGGL(wave_scan_local_kernel, dim3(nchunk), dim3(1024), 0, side, WS);
+  hipLaunchKernelGGL(wave_scan_chunks_kernel, dim3(1), dim3(1024), 0, side, WS, nchunk, &ctl->n_ad, &ctl->n_k,
+                     &ctl->n_ut, ctl);
+  hipLaunchKernelGGL(subset_scatter_kernel, dim3(nt), dim3(kT), 0, side, events, v.cls, nn, WS, v.S, v.parts);
   // Unused transfers (their flags are merged after the join).
   UtArgs U;
   U.ev = events;
@@ -3322,23 +3342,23 @@ static int enqueue_analysis(Workspace* ws, const odp_event* events, size_t n, ui
   U.ctl = ctl;
   U.flags = out_flags;
   U.rep = out_report;
-  SQ.push_back([=] { hipLaunchKernelGGL(ut_scan_kernel, dim3(grid_rec), dim3(kT), 0, side, U); });
-  SQ.push_back([=] { hipLaunchKernelGGL(reduce_parts_kernel, dim3(S_DD_EVENTS - S_AD_DEV_OR), dim3(kT), 0, side, v.parts, nt,
-                     (uint32_t)S_AD_DEV_OR, ctl, out_report); });
+  hipLaunchKernelGGL(ut_scan_kernel, dim3(grid_rec), dim3(kT), 0, side, U);
+  hipLaunchKernelGGL(reduce_parts_kernel, dim3(S_DD_EVENTS - S_AD_DEV_OR), dim3(kT), 0, side, v.parts, nt,
+                     (uint32_t)S_AD_DEV_OR, ctl, out_report);
   // ALLOC/DELETE by (device, address), kernels by (device, start) and (device,
   // end), copy-ins by (endpoints, source address). The subsets are usually
   // far smaller than the log: a capped number of blocks per job loops over
   // its tiles instead of a block per log tile.
   const uint32_t side_blocks = std::min<uint32_t>(nt, (uint32_t)cus * 2);
   const JobSet Js{v.jobs + kJobAd, kSubsetJobs, side_blocks};
-  SQ.push_back([=] { hipLaunchKernelGGL(sort_plan_kernel, dim3(1), dim3(64), 0, side, Js, 0u); });
+  hipLaunchKernelGGL(sort_plan_kernel, dim3(1), dim3(64), 0, side, Js, 0u);
   if (small) {
-    SQ.push_back([=] { hipLaunchKernelGGL(sort_small_kernel, dim3(Js.njobs), dim3(kQT), 0, side, Js); });
+    hipLaunchKernelGGL(sort_small_kernel, dim3(Js.njobs), dim3(kQT), 0, side, Js);
   } else {
     for (uint32_t p = 0; p < 9; ++p) {
-      SQ.push_back([=] { hipLaunchKernelGGL(sort_hist_kernel, dim3(Js.njobs * side_blocks), dim3(kT), 0, side, Js, p); });
-      SQ.push_back([=] { hipLaunchKernelGGL(sort_scan_kernel, dim3(256 * Js.njobs), dim3(kT), 0, side, Js, p); });
-      SQ.push_back([=] { hipLaunchKernelGGL(sort_scatter_kernel, dim3(Js.njobs * side_blocks), dim3(kST), 0, side, Js, p); });
+      hipLaunchKernelGGL(sort_hist_kernel, dim3(Js.njobs * side_blocks), dim3(kT), 0, side, Js, p);
+      hipLaunchKernelGGL(sort_scan_kernel, dim3(256 * Js.njobs), dim3(kT), 0, side, Js, p);
+      hipLaunchKernelGGL(sort_scatter_kernel, dim3(Js.njobs * side_blocks), dim3(kST), 0, side, Js, p);
     }
   }
   // Pairing and the pair list.
@@ -3360,19 +3380,19 @@ static int enqueue_analysis(Workspace* ws, const odp_event* events, size_t n, ui
   P.flags = out_flags;
   P.ctl = ctl;
   P.rep = out_report;
-  SQ.push_back([=] { hipLaunchKernelGGL(pair_kernel, dim3(grid_map), dim3(kT), 0, side, P); });
-  SQ.push_back([=] { hipLaunchKernelGGL(pair_count_kernel, dim3(nt), dim3(kT), 0, side, P); });
-  SQ.push_back([=] { hipLaunchKernelGGL(scan_counts_kernel<2>, dim3(1), dim3(1024), 0, side, v.tile_cnt, nt, &ctl->n_pairs, nullptr); });
-  SQ.push_back([=] { hipLaunchKernelGGL(pair_scatter_kernel, dim3(nt), dim3(kT), 0, side, P); });
-  SQ.push_back([=] { hipLaunchKernelGGL(kernel_ranges_kernel, dim3(grid_map), dim3(kT), 0, side, v.jobs + kJobKs, v.jobs + kJobKe,
-                     v.S.k_w_dev, v.S.k_w_start, v.S.k_w_end, &ctl->n_k, v.starts_sorted, v.ends_sorted, ctl); });
-  SQ.push_back([=] { hipLaunchKernelGGL(ut_next_kernel, dim3(grid_map), dim3(kT), 0, side, U); });
-  SQ.push_back([=] { hipLaunchKernelGGL(ut_eval_kernel, dim3(grid_map), dim3(kT), 0, side, U); });
+  hipLaunchKernelGGL(pair_kernel, dim3(grid_map), dim3(kT), 0, side, P);
+  hipLaunchKernelGGL(pair_count_kernel, dim3(nt), dim3(kT), 0, side, P);
+  hipLaunchKernelGGL(scan_counts_kernel<2>, dim3(1), dim3(1024), 0, side, v.tile_cnt, nt, &ctl->n_pairs, nullptr);
+  hipLaunchKernelGGL(pair_scatter_kernel, dim3(nt), dim3(kT), 0, side, P);
+  hipLaunchKernelGGL(kernel_ranges_kernel, dim3(grid_map), dim3(kT), 0, side, v.jobs + kJobKs, v.jobs + kJobKe,
+                     v.S.k_w_dev, v.S.k_w_start, v.S.k_w_end, &ctl->n_k, v.starts_sorted, v.ends_sorted, ctl);
+  hipLaunchKernelGGL(ut_next_kernel, dim3(grid_map), dim3(kT), 0, side, U);
+  hipLaunchKernelGGL(ut_eval_kernel, dim3(grid_map), dim3(kT), 0, side, U);
 
   // Pairs grouped by (host address, device, bytes) in a table.
-  SQ.push_back([=] { hipLaunchKernelGGL(pair_table_clear_kernel, dim3(grid_map), dim3(kT), 0, side, v.pt, &ctl->n_pairs); });
-  SQ.push_back([=] { hipLaunchKernelGGL(pair_table_insert_kernel, dim3(grid_pair), dim3(kT), 0, side, v.pt, &ctl->n_pairs,
-                     v.pr_w_haddr, v.pr_w_dev, v.pr_w_bytes); });
+  hipLaunchKernelGGL(pair_table_clear_kernel, dim3(grid_map), dim3(kT), 0, side, v.pt, &ctl->n_pairs);
+  hipLaunchKernelGGL(pair_table_insert_kernel, dim3(grid_pair), dim3(kT), 0, side, v.pt, &ctl->n_pairs,
+                     v.pr_w_haddr, v.pr_w_dev, v.pr_w_bytes);
 
   RaArgs R;
   R.ev = events;
@@ -3392,7 +3412,7 @@ static int enqueue_analysis(Workspace* ws, const odp_event* events, size_t n, ui
   R.ctl = ctl;
   R.flags = out_flags;
   R.rep = out_report;
-  SQ.push_back([=] { hipLaunchKernelGGL(ra_ua_kernel, dim3(grid_map), dim3(kT), 0, side, R); });
+  hipLaunchKernelGGL(ra_ua_kernel, dim3(grid_map), dim3(kT), 0, side, R);
   // Records by digest (up to 8 passes), then duplicates and round trips, on
   // the caller's stream.
   const JobSet Jb{v.jobs + kJobBig, 1, nt};
@@ -3401,17 +3421,17 @@ static int enqueue_analysis(Workspace* ws, const odp_event* events, size_t n, ui
   // the digest histograms take two tiles per block on long logs (measured a
   // little faster than one: the per-block start-up is amortised)
   const JobSet Jh{v.jobs + kJobBig, 1, nt > 4u * (uint32_t)cus ? (nt + 1) / 2 : nt};
-  MQ.push_back([=] { hipLaunchKernelGGL(sort_plan_kernel, dim3(1), dim3(64), 0, stream, Jb, kfirst); });
+  hipLaunchKernelGGL(sort_plan_kernel, dim3(1), dim3(64), 0, stream, Jb, kfirst);
   if (small) {
-    MQ.push_back([=] { hipLaunchKernelGGL(sort_small_kernel, dim3(Jb.njobs), dim3(kQT), 0, stream, Jb); });
+    hipLaunchKernelGGL(sort_small_kernel, dim3(Jb.njobs), dim3(kQT), 0, stream, Jb);
   } else {
     for (uint32_t p = 0; p < 8; ++p) {
-      if (kfirst && p >= kfirst) MQ.push_back([=] { hipLaunchKernelGGL(sort_fix_kernel, dim3(nft), dim3(kT), 0, stream, v.jobs + kJobBig, p); });
-      MQ.push_back([=] { hipLaunchKernelGGL(sort_hist_kernel, dim3(Jh.stride), dim3(kT), 0, stream, Jh, p); });
-      MQ.push_back([=] { hipLaunchKernelGGL(sort_scan_kernel, dim3(256), dim3(kT), 0, stream, Jb, p); });
-      MQ.push_back([=] { hipLaunchKernelGGL(sort_scatter_kernel, dim3(nt), dim3(kST), 0, stream, Jb, p); });
+      if (kfirst && p >= kfirst) hipLaunchKernelGGL(sort_fix_kernel, dim3(nft), dim3(kT), 0, stream, v.jobs + kJobBig, p);
+      hipLaunchKernelGGL(sort_hist_kernel, dim3(Jh.stride), dim3(kT), 0, stream, Jh, p);
+      hipLaunchKernelGGL(sort_scan_kernel, dim3(256), dim3(kT), 0, stream, Jb, p);
+      hipLaunchKernelGGL(sort_scatter_kernel, dim3(nt), dim3(kST), 0, stream, Jb, p);
     }
-    if (kfirst) MQ.push_back([=] { hipLaunchKernelGGL(sort_fix_kernel, dim3(nft), dim3(kT), 0, stream, v.jobs + kJobBig, 8u); });
+    if (kfirst) hipLaunchKernelGGL(sort_fix_kernel, dim3(nft), dim3(kT), 0, stream, v.jobs + kJobBig, 8u);
   }
   DDArgs D;
   D.ev = events;
@@ -3424,11 +3444,11 @@ static int enqueue_analysis(Workspace* ws, const odp_event* events, size_t n, ui
   D.flags = out_flags;
   D.rep = out_report;
   D.parts = v.parts;
-  MQ.push_back([=] { hipLaunchKernelGGL(ddrt_agg_kernel, dim3(nt), dim3(kT), 0, stream, D); });
-  MQ.push_back([=] { hipLaunchKernelGGL(ddrt_carry_kernel, dim3(1), dim3(kCT), 0, stream, D, nt * (kT / 64)); });
-  MQ.push_back([=] { hipLaunchKernelGGL(ddrt_final_kernel, dim3(nt), dim3(kT), 0, stream, D); });
-  MQ.push_back([=] { hipLaunchKernelGGL(reduce_parts_kernel, dim3(kSlots - S_DD_EVENTS), dim3(kT), 0, stream, v.parts, nt,
-                     (uint32_t)S_DD_EVENTS, ctl, out_report); });
+  hipLaunchKernelGGL(ddrt_agg_kernel, dim3(nt), dim3(kT), 0, stream, D);
+  hipLaunchKernelGGL(ddrt_carry_kernel, dim3(1), dim3(kCT), 0, stream, D, nt * (kT / 64));
+  hipLaunchKernelGGL(ddrt_final_kernel, dim3(nt), dim3(kT), 0, stream, D);
+  hipLaunchKernelGGL(reduce_parts_kernel, dim3(kSlots - S_DD_EVENTS), dim3(kT), 0, stream, v.parts, nt,
+                     (uint32_t)S_DD_EVENTS, ctl, out_report);
   if (alg2_rx) {
     Alg2Args G;
     G.job = v.jobs + kJobBig;
@@ -3436,13 +3456,9 @@ static int enqueue_analysis(Workspace* ws, const odp_event* events, size_t n, ui
     G.n = nn;
     G.rx = alg2_rx;
     G.npairs = alg2_np;
-    MQ.push_back([=] { hipLaunchKernelGGL(alg2_kernel, dim3(ceil_div32(n, kT)), dim3(kT), 0, stream, G); });
+    hipLaunchKernelGGL(alg2_kernel, dim3(ceil_div32(n, kT)), dim3(kT), 0, stream, G);
   }
 
-  for (size_t q = 0; q < std::max(SQ.size(), MQ.size()); ++q) {
-    if (q < SQ.size()) SQ[q]();
-    if (q < MQ.size()) MQ[q]();
-  }
   ODP_HIP(hipEventRecord(ws->a_join, side));
 
   ODP_HIP(hipStreamWaitEvent(stream, ws->a_join, 0));
