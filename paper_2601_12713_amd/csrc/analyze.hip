@@ -854,7 +854,13 @@ constexpr uint32_t kWalkIdle = 0, kWalking = 1, kWalkEnd = 2, kWalkLong = 3;
 
 __global__ __launch_bounds__(kT) void sort_fix_kernel(SortJob* job, uint32_t p) {
   SortJob& s = *job;
-  const uint32_t np = s.npasses;
+  // One read per block: a check that finds a long run raises npasses while
+  // other blocks of the same launch start, and every wavefront of a block
+  // must take the same branch (the check's barriers).
+  __shared__ uint32_t s_np;
+  if (threadIdx.x == 0) s_np = __hip_atomic_load(&s.npasses, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  const uint32_t np = s_np;
   const uint32_t n = *s.n_ptr;
   const uint32_t nft = (n + kFixTile - 1) / kFixTile;
   if (p >= 1 && np == p - 1 && p - 1 < s.np_full) {
