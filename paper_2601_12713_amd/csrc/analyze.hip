@@ -86,6 +86,7 @@ struct AnaCtl {
   uint32_t dev_lo[kEp], dev_hi[kEp];  // per-device ranges in the sorted kernel order
   uint64_t t_min, t_max;              // earliest start and latest end of the valid records
   uint32_t kd_base[kEp], kd_total[kEp];  // KERNEL records per device code: list offsets and counts
+  uint32_t scan_ticket;               // blocks of the wave scan done (the last one resets it)
   uint32_t ut_need_sort;              // 1: some copy-in is decided by the sorted path
   uint32_t kern_sort;                 // 1: the kernel lists are sorted (the count form's binary searches)
   // removable time (Sec. 7.6), in three parts written by different stages:
@@ -284,6 +285,7 @@ __global__ void init_kernel(AnaCtl* ctl, odp_report* rep, uint32_t* totals, uint
     ctl->elim_tx = ctl->elim_pairs = ctl->elim_ut = 0;
     ctl->ut_need_sort = 0;
     ctl->kern_sort = 0;
+    ctl->scan_ticket = 0;
     WordMask* m = &ctl->m_digest;
     for (int i = 0; i < kNumMasks; ++i) {
       m[i].vor = 0;
@@ -469,86 +471,155 @@ struct WaveScan {
 };
 constexpr uint32_t kScanChunk = 1024;
 
-template <typename T, bool MAX>
-__device__ __forceinline__ T block_excl(T v, T* wtot, T& total) {
+// Exclusive scans of the per-wavefront counts (kWaveCnt) and maxima (kEp)
+// in one launch: a block of 1024 threads scans a chunk of kScanChunk
+// wavefronts, all quantities at once (their lane-move chains interleave, one
+// barrier in all); the block that finishes last, by a ticket, scans the chunk
+// totals and writes the subset sizes and per-device kernel list offsets.
+constexpr int kScanQ = kWaveCnt + kEp;
+
+__device__ __forceinline__ void scan_all(uint32_t (&c)[kWaveCnt], unsigned long long (&m)[kEp],
+                                         uint32_t (&wc)[16][kWaveCnt], unsigned long long (&wm)[16][kEp],
+                                         uint32_t (&tc)[kWaveCnt], unsigned long long (&tm)[kEp]) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  T x = v;
+  uint32_t xc[kWaveCnt];
+  unsigned long long xm[kEp];
+#pragma unroll
+  for (int q = 0; q < kWaveCnt; ++q) xc[q] = c[q];
+#pragma unroll
+  for (int q = 0; q < kEp; ++q) xm[q] = m[q];
+#pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
-    const T y = __shfl_up(x, o, 64);
-    if (lane >= o) x = MAX ? (x > y ? x : y) : x + y;
+#pragma unroll
+    for (int q = 0; q < kWaveCnt; ++q) {
+      const uint32_t y = __shfl_up(xc[q], o, 64);
+      if (lane >= o) xc[q] += y;
+    }
+#pragma unroll
+    for (int q = 0; q < kEp; ++q) {
+      const unsigned long long y = __shfl_up(xm[q], o, 64);
+      if (lane >= o) xm[q] = max(xm[q], y);
+    }
   }
-  if (lane == 63) wtot[w] = x;
-  __syncthreads();
-  T before = __shfl_up(x, 1, 64);
-  if (lane == 0) before = 0;
-  T all = 0;
-  for (int q = 0; q < 16; ++q) {
-    if (q < w) before = MAX ? (before > wtot[q] ? before : wtot[q]) : before + wtot[q];
-    all = MAX ? (all > wtot[q] ? all : wtot[q]) : all + wtot[q];
+  if (lane == 63) {
+#pragma unroll
+    for (int q = 0; q < kWaveCnt; ++q) wc[w][q] = xc[q];
+#pragma unroll
+    for (int q = 0; q < kEp; ++q) wm[w][q] = xm[q];
   }
   __syncthreads();
-  total = all;
-  return before;
+  const int nwv = (int)(blockDim.x / 64);
+#pragma unroll
+  for (int q = 0; q < kWaveCnt; ++q) {
+    uint32_t before = __shfl_up(xc[q], 1, 64), all = 0;
+    if (lane == 0) before = 0;
+    for (int v = 0; v < nwv; ++v) {
+      if (v < w) before += wc[v][q];
+      all += wc[v][q];
+    }
+    c[q] = before;
+    tc[q] = all;
+  }
+#pragma unroll
+  for (int q = 0; q < kEp; ++q) {
+    unsigned long long before = __shfl_up(xm[q], 1, 64), all = 0;
+    if (lane == 0) before = 0;
+    for (int v = 0; v < nwv; ++v) {
+      if (v < w) before = max(before, wm[v][q]);
+      all = max(all, wm[v][q]);
+    }
+    m[q] = before;
+    tm[q] = all;
+  }
+  __syncthreads();
 }
 
-__global__ __launch_bounds__(1024) void wave_scan_local_kernel(WaveScan S) {
-  __shared__ uint32_t wc[16];
-  __shared__ unsigned long long wm[16];
-  const uint32_t i = blockIdx.x * kScanChunk + threadIdx.x;
-  const bool in = i < S.nw;
-  for (int c = 0; c < kWaveCnt; ++c) {
-    uint32_t tot;
-    const uint32_t ex = block_excl<uint32_t, false>(in ? S.cnt[(size_t)kWaveCnt * i + c] : 0u, wc, tot);
-    if (in) S.cnt[(size_t)kWaveCnt * i + c] = ex;
-    if (threadIdx.x == 0) S.ccnt[(size_t)kWaveCnt * blockIdx.x + c] = tot;
-  }
-  for (int d = 0; d < kEp; ++d) {
-    unsigned long long tot;
-    const unsigned long long ex =
-        block_excl<unsigned long long, true>(in ? (unsigned long long)S.kmax[(size_t)kEp * i + d] : 0ull, wm, tot);
-    if (in) S.kmax[(size_t)kEp * i + d] = ex;
-    if (threadIdx.x == 0) S.cmax[(size_t)kEp * blockIdx.x + d] = tot;
-  }
-}
-
-__global__ __launch_bounds__(1024) void wave_scan_chunks_kernel(WaveScan S, uint32_t nchunk, uint32_t* tot_ad,
-                                                                uint32_t* tot_k, uint32_t* tot_ut, AnaCtl* ctl) {
-  __shared__ uint32_t wc[16];
-  __shared__ unsigned long long wm[16];
+__global__ __launch_bounds__(1024) void wave_scan_kernel(WaveScan S, uint32_t nchunk, AnaCtl* ctl) {
+  __shared__ uint32_t wc[16][kWaveCnt];
+  __shared__ unsigned long long wm[16][kEp];
   __shared__ uint32_t carry_c[kWaveCnt];
   __shared__ unsigned long long carry_m[kEp];
+  __shared__ uint32_t last;
+  __shared__ uint32_t s_tc[kWaveCnt];         // block totals (register arrays are
+  __shared__ unsigned long long s_tm[kEp];    // not indexed by thread)
+  uint32_t c[kWaveCnt], tc[kWaveCnt];
+  unsigned long long m[kEp], tm[kEp];
+  {
+    const uint32_t i = blockIdx.x * kScanChunk + threadIdx.x;
+    const bool in = i < S.nw;
+#pragma unroll
+    for (int q = 0; q < kWaveCnt; ++q) c[q] = in ? S.cnt[(size_t)kWaveCnt * i + q] : 0u;
+#pragma unroll
+    for (int q = 0; q < kEp; ++q) m[q] = in ? (unsigned long long)S.kmax[(size_t)kEp * i + q] : 0ull;
+    scan_all(c, m, wc, wm, tc, tm);
+    if (in) {
+#pragma unroll
+      for (int q = 0; q < kWaveCnt; ++q) S.cnt[(size_t)kWaveCnt * i + q] = c[q];
+#pragma unroll
+      for (int q = 0; q < kEp; ++q) S.kmax[(size_t)kEp * i + q] = m[q];
+    }
+    // The chunk totals (stored by wavefront 0) reach the device-coherent
+    // level before its ticket: agent-scope stores and a wait for their
+    // completion, not a fence (an agent-scope fence writes back the L2).
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int q = 0; q < kWaveCnt; ++q) s_tc[q] = tc[q];
+#pragma unroll
+      for (int q = 0; q < kEp; ++q) s_tm[q] = tm[q];
+    }
+    __syncthreads();
+    if (threadIdx.x < kWaveCnt)
+      __hip_atomic_store(S.ccnt + (size_t)kWaveCnt * blockIdx.x + threadIdx.x, s_tc[threadIdx.x], __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x < kEp)
+      __hip_atomic_store(S.cmax + (size_t)kEp * blockIdx.x + threadIdx.x, (uint64_t)s_tm[threadIdx.x],
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  if (threadIdx.x < 64) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  if (threadIdx.x == 0)
+    last = __hip_atomic_fetch_add(&ctl->scan_ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == nchunk - 1 ? 1u
+                                                                                                           : 0u;
+  __syncthreads();
+  if (!last) return;
   if (threadIdx.x < kWaveCnt) carry_c[threadIdx.x] = 0;
   if (threadIdx.x < kEp) carry_m[threadIdx.x] = 0;
   __syncthreads();
-  for (uint32_t base = 0; base < nchunk; base += 1024) {
+  for (uint32_t base = 0; base < nchunk; base += blockDim.x) {
     const uint32_t i = base + threadIdx.x;
     const bool in = i < nchunk;
-    for (int c = 0; c < kWaveCnt; ++c) {
-      uint32_t tot;
-      const uint32_t ex = block_excl<uint32_t, false>(in ? S.ccnt[(size_t)kWaveCnt * i + c] : 0u, wc, tot);
-      if (in) S.ccnt[(size_t)kWaveCnt * i + c] = carry_c[c] + ex;
-      __syncthreads();
-      if (threadIdx.x == 0) carry_c[c] += tot;
+#pragma unroll
+    for (int q = 0; q < kWaveCnt; ++q)
+      c[q] = in ? __hip_atomic_load(S.ccnt + (size_t)kWaveCnt * i + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
+#pragma unroll
+    for (int q = 0; q < kEp; ++q)
+      m[q] = in ? (unsigned long long)__hip_atomic_load(S.cmax + (size_t)kEp * i + q, __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT) : 0ull;
+    scan_all(c, m, wc, wm, tc, tm);
+    if (in) {
+#pragma unroll
+      for (int q = 0; q < kWaveCnt; ++q) S.ccnt[(size_t)kWaveCnt * i + q] = carry_c[q] + c[q];
+#pragma unroll
+      for (int q = 0; q < kEp; ++q) S.cmax[(size_t)kEp * i + q] = max(carry_m[q], m[q]);
     }
-    for (int d = 0; d < kEp; ++d) {
-      unsigned long long tot;
-      const unsigned long long ex =
-          block_excl<unsigned long long, true>(in ? (unsigned long long)S.cmax[(size_t)kEp * i + d] : 0ull, wm, tot);
-      if (in) S.cmax[(size_t)kEp * i + d] = max(carry_m[d], ex);
-      __syncthreads();
-      if (threadIdx.x == 0) carry_m[d] = max(carry_m[d], tot);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int q = 0; q < kWaveCnt; ++q) carry_c[q] += tc[q];
+#pragma unroll
+      for (int q = 0; q < kEp; ++q) carry_m[q] = max(carry_m[q], tm[q]);
     }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    *tot_ad = carry_c[0];
-    *tot_k = carry_c[1];
-    *tot_ut = carry_c[2];
-    uint32_t base = 0;
+    ctl->scan_ticket = 0;
+    ctl->n_ad = carry_c[0];
+    ctl->n_k = carry_c[1];
+    ctl->n_ut = carry_c[2];
+    uint32_t b = 0;
     for (int d = 0; d < kEp; ++d) {
-      ctl->kd_base[d] = base;
+      ctl->kd_base[d] = b;
       ctl->kd_total[d] = carry_c[3 + d];
-      base += carry_c[3 + d];
+      b += carry_c[3 + d];
     }
   }
 }
@@ -3324,9 +3395,7 @@ static int enqueue_analysis(Workspace* ws, const odp_event* events, size_t n, ui
   WaveScan WS = v.wscan;
   WS.nw = nt * (kT / 64);
   const uint32_t nchunk = ceil_div32(WS.nw, kScanChunk);
-  hipLaunchKernelGGL(wave_scan_local_kernel, dim3(nchunk), dim3(1024), 0, side, WS);
-  hipLaunchKernelGGL(wave_scan_chunks_kernel, dim3(1), dim3(1024), 0, side, WS, nchunk, &ctl->n_ad, &ctl->n_k,
-                     &ctl->n_ut, ctl);
+  hipLaunchKernelGGL(wave_scan_kernel, dim3(nchunk), dim3(1024), 0, side, WS, nchunk, ctl);
   hipLaunchKernelGGL(subset_scatter_kernel, dim3(nt), dim3(kT), 0, side, events, v.cls, nn, WS, v.S, v.parts);
   // Unused transfers (their flags are merged after the join).
   UtArgs U;
