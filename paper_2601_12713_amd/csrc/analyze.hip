@@ -6,27 +6,31 @@
 // (Alg. 2), <host address, device, bytes> for repeated allocations (Alg. 3),
 // a two-pointer sweep per device for unused allocations (Alg. 4) and a
 // per-device kernel pointer with candidate copies for unused transfers
-// (Alg. 5). Here the grouping is a stable LSD radix sort and the per-group
-// logic is a pass over the sorted order:
+// (Alg. 5). Here the grouping is a stable LSD radix sort (or, for Alg. 3's
+// key, a device hash table) and the per-group logic is a pass over the
+// sorted order:
 //
 //   classify   one read of the 64-byte records: validity, per-record flags,
 //              the digest sort keys, and a 1-byte class / endpoint code
 //   subsets    ordered compaction of ALLOC/DELETE, KERNEL and copy-in (H2D or
-//              D2D into a device) records
-//   sort #1    (all in the same launches) records by digest; ALLOC/DELETE by
-//              (device, device address); KERNELs by (device, start) and by
-//              (device, end); copy-ins by (endpoints, source address)
+//              D2D into a device) records, each with its device's kernel
+//              count and latest kernel end so far
+//   sorts      records by digest (low bytes first, then short runs of equal
+//              low bytes sorted in place); ALLOC/DELETE by (device, device
+//              address); when needed, KERNELs by (device, start) and by
+//              (device, end) and copy-ins by (endpoints, source address)
 //   DD/RT      forward and backward segmented scans over each digest group
 //   pairing    a DELETE pairs with its predecessor in its (device, address)
 //              group when that is an ALLOC; paired ALLOCs compacted in order
-//   sort #2    pairs by (bytes, device, host address)
-//   RA/UA      RA = not first of its key group; UA by two binary searches in
-//              the device's sorted kernel starts and ends
-//   UT         a copy-in and the next one of its group (the copy that
-//              overwrites it) bound the window a kernel must meet; the same
-//              two binary searches
+//   RA table   pairs grouped by (host address, device, bytes) in an
+//              open-addressing table: RA = not the first pair of its key
+//   UA, UT     the window [ALLOC start, DELETE end] or [copy start, next
+//              copy of the place's start] against the device's kernels: from
+//              the kernel counts in a chronological log, else by two binary
+//              searches in the sorted kernel starts and ends
 //   estimate   removable time per record over the union of its flags, the
 //              log's span, the predicted speedup
+//   Alg. 2     on request, the pairs the literal algorithm records
 //
 // Sort keys are 64-bit words; a job lists its words least significant first,
 // and digit passes whose byte is the same in every key are skipped on the
@@ -81,8 +85,7 @@ struct AnaCtl {
   uint32_t n_ut;        // copy-in records
   uint32_t first_bad;
   uint32_t max_ep;      // largest endpoint code among valid transfers
-  WordMask m_digest, m_ad_dev, m_ad_addr, m_k_start, m_k_end, m_k_dev, m_p_bytes, m_p_dev, m_p_haddr, m_ut_addr,
-      m_ut_code;
+  WordMask m_digest, m_ad_dev, m_ad_addr, m_k_start, m_k_end, m_k_dev, m_ut_addr, m_ut_code;
   uint32_t dev_lo[kEp], dev_hi[kEp];  // per-device ranges in the sorted kernel order
   uint64_t t_min, t_max;              // earliest start and latest end of the valid records
   uint32_t kd_base[kEp], kd_total[kEp];  // KERNEL records per device code: list offsets and counts
@@ -94,7 +97,7 @@ struct AnaCtl {
   // UT only
   uint64_t elim_tx, elim_pairs, elim_ut;
 };
-constexpr int kNumMasks = 11;
+constexpr int kNumMasks = 8;
 
 // One radix sort job. 64-bit keys move with the values; a job lists its key
 // words least significant first. A word with words[w] != null is gathered by
@@ -183,12 +186,6 @@ __device__ void block_add(uint64_t* dst64, unsigned long long v) {
   __syncthreads();
 }
 
-__device__ __forceinline__ void mask_update(WordMask* m, unsigned long long vor, unsigned long long vand) {
-  // vor/vand are block-reduced by the caller when it can; here per thread.
-  atomicOr(&m->vor, vor);
-  atomicAnd(&m->vand, vand);
-}
-
 // Per-block partials of the grid-wide reductions of the big launches
 // (classification, subset compaction, DD/RT): every block stores its own
 // slot entry and one small kernel reduces each slot afterwards, so no two
@@ -231,34 +228,6 @@ __device__ void block_store(unsigned long long* dst, unsigned long long v) {
     unsigned long long r = sh[0];
     for (int w = 1; w < kT / 64; ++w) r = red2<OP>(r, sh[w]);
     *dst = r;
-  }
-  __syncthreads();
-}
-
-__device__ void block_mask(WordMask* m, unsigned long long vor, unsigned long long vand, bool any) {
-  __shared__ unsigned long long so[kT / 64], sa[kT / 64];
-  __shared__ int sany[kT / 64];
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) {
-    vor |= __shfl_xor(vor, o, 64);
-    vand &= __shfl_xor(vand, o, 64);
-  }
-  const int anyw = __any(any);
-  if ((threadIdx.x & 63) == 0) {
-    so[threadIdx.x >> 6] = vor;
-    sa[threadIdx.x >> 6] = vand;
-    sany[threadIdx.x >> 6] = anyw;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned long long o = 0, a = ~0ull;
-    int an = 0;
-    for (int w = 0; w < kT / 64; ++w) {
-      o |= so[w];
-      a &= sa[w];
-      an |= sany[w];
-    }
-    if (an) mask_update(m, o, a);
   }
   __syncthreads();
 }
@@ -870,7 +839,7 @@ __global__ __launch_bounds__(kT) void reduce_parts_kernel(Parts parts, uint32_t 
 // 3. LSD radix sort, 8-bit digits, several independent jobs per launch.
 // ---------------------------------------------------------------------------
 // first_passes: when nonzero, the passes after that many are deferred to the
-// collision check (digest job only).
+// local fix (digest job only).
 __global__ void sort_plan_kernel(JobSet J, uint32_t first_passes) {
   const uint32_t j = threadIdx.x;
   if (j >= J.njobs) return;
@@ -2088,9 +2057,7 @@ __global__ __launch_bounds__(kT) void pair_scatter_kernel(PairArgs P) {
   if (threadIdx.x == 0) run = P.tile_cnt[2 * blockIdx.x];
   __syncthreads();
   const int w = threadIdx.x >> 6;
-  unsigned long long o_b = 0, a_b = ~0ull, o_d = 0, a_d = ~0ull, o_h = 0, a_h = ~0ull;
-  unsigned long long unp_a = 0, unp_d = 0;
-  bool any = false;
+  unsigned long long unp_a = 0;
   for (uint32_t r = 0; r < (uint32_t)kItems; ++r) {
     const uint32_t p = b + r * kT + threadIdx.x;
     const bool in = p < n;
@@ -2111,13 +2078,6 @@ __global__ __launch_bounds__(kT) void pair_scatter_kernel(PairArgs P) {
       P.pr_w_dev[k] = dv;
       P.pr_w_haddr[k] = e.src_addr;
       P.flags[P.ad_idx[partner]] = ODP_F_PAIRED;  // the DELETE of the pair
-      o_b |= e.bytes;
-      a_b &= e.bytes;
-      o_d |= dv;
-      a_d &= dv;
-      o_h |= e.src_addr;
-      a_h &= e.src_addr;
-      any = true;
     } else if (in && P.ad_op[p] == ODP_ALLOC) {
       ++unp_a;
     }
@@ -2126,11 +2086,7 @@ __global__ __launch_bounds__(kT) void pair_scatter_kernel(PairArgs P) {
       for (int x = 0; x < kT / 64; ++x) run += wc[x];
     __syncthreads();
   }
-  (void)unp_d;
   block_add(&P.rep->n_unpaired_alloc, unp_a);
-  block_mask(&P.ctl->m_p_bytes, o_b, a_b, any);
-  block_mask(&P.ctl->m_p_dev, o_d, a_d, any);
-  block_mask(&P.ctl->m_p_haddr, o_h, a_h, any);
 }
 
 // ---------------------------------------------------------------------------
@@ -2795,7 +2751,7 @@ enum Buf {
 };
 
 // Jobs 1..4 (the subsets) are sorted together in the same launches.
-constexpr int kJobBig = 0, kJobAd = 1, kJobKs = 2, kJobKe = 3, kJobUt = 4, kJobPr = 5, kNumJobs = 6;
+constexpr int kJobBig = 0, kJobAd = 1, kJobKs = 2, kJobKe = 3, kJobUt = 4, kNumJobs = 5;
 constexpr int kSubsetJobs = 4;
 
 template <typename T>
@@ -2835,7 +2791,7 @@ struct Views {
   uint32_t* totals;
   WaveAgg* agg;    // per wavefront of the digest job
   WaveAgg* carry;
-  unsigned long long* skey[2 * (kNumJobs - 1)];  // key ping-pong of the subset and pair jobs
+  unsigned long long* skey[2 * (kNumJobs - 1)];  // key ping-pong of the subset jobs
   Parts parts;                  // per-block partials of the grid-wide reductions
 };
 
@@ -2981,7 +2937,6 @@ void build_jobs(const Views& v, SortJob* hj) {
   hj[kJobUt].word_bytes[1] = 1;
   hj[kJobUt].nwords = 2;
   hj[kJobUt].run_flag = &ctl->ut_need_sort;
-  // paired allocations by (host address, device, bytes)
   for (int j = 1; j < kNumJobs; ++j) {
     hj[j].keys[0] = v.skey[2 * (j - 1)];
     hj[j].keys[1] = v.skey[2 * (j - 1) + 1];
