@@ -46,6 +46,7 @@ namespace odp {
 namespace {
 
 constexpr int kTickMax = 1024;     // records per tick (one workgroup)
+constexpr uint32_t kPerBufferTick = 3;  // ticks of at most this many requests digest per buffer
 // staged bytes per request: the record, the payload pointer and size, a flag
 constexpr size_t kStageBytes = sizeof(odp_event) + 8 + 8 + 1;
 constexpr uint32_t kEmpty = 0;
@@ -708,9 +709,10 @@ static int launch_tick(odp_server* s, int b, uint32_t m, uint64_t bytes, bool id
   ODP_HIP(hipMemcpyAsync(s->d_stage[b], s->h_stage[b], m * kStageBytes, hipMemcpyHostToDevice, ds));
   const StageView hv = stage_view(s->h_stage[b], m), dv = stage_view(s->d_stage[b], m);
   // Tick sizes change every tick: direct launches rather than a captured
-  // graph. A tick of one request takes the per-buffer launch (one kernel
-  // instead of the plan, the persistent digest and the tree kernels).
-  int e = s->cfg.mode == ODP_SERVER_PLAIN || m == 1
+  // graph. A tick of up to kPerBufferTick requests takes per-buffer launches
+  // (one kernel each instead of the plan, the persistent digest and the tree
+  // kernels: fewer launches and a shorter chain on the device).
+  int e = s->cfg.mode == ODP_SERVER_PLAIN || m <= kPerBufferTick
               ? odp_digest_buffers_plain(reinterpret_cast<const void* const*>(hv.ptr), hv.size, m, s->d_dig[b], ds)
               : digest_batched_direct(reinterpret_cast<const void* const*>(dv.ptr), dv.size, m, s->d_dig[b], ds, bytes);
   if (e) return e;
