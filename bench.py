@@ -13,8 +13,10 @@ Workloads (--workload):
                 48e9 bytes in total, 25% copies; a step digests them with one
                 batched launch sequence (hipGraph replay, saved tuning), writes
                 the digests into the batch's 101,562-record transfer log and
-                analyses it. The per-buffer-launch form of the same buffers
-                and the large-arrays workload are timed beside it (extras).
+                analyses it. The per-buffer-launch form of the same buffers,
+                the large-arrays workload, the trace analysis and a short
+                serving run (50k and 200k req/s) are measured beside it
+                (extras), so the line carries every figure of the metric.
   large-arrays  16 fp64 arrays of 2^25 elements, each sent 4 times
                 (64 transfers of 256 MiB); one digest launch per transfer;
                 the metric is the digest rate in GB/s.
@@ -441,6 +443,13 @@ def run_batch(args, torch, odp, W):
         del bb, dptr, dsz, d_ev, ev_u64
         torch.cuda.empty_cache()
         extras["large_arrays"] = measure_large_arrays(torch, odp, W, max(5, args.steps))
+        # the other two figures of the headline metric, so that this line carries them
+        # too: the trace analysis (--workload trace) and serving latency (--workload
+        # serve, here two rates over half a second each)
+        extras["trace"] = measure_trace(torch, odp, W, max(5, args.steps))
+        torch.cuda.empty_cache()
+        rates, sb, _ = measure_serve(torch, odp, W, (50_000, 200_000), 0.5, steps=1, warmup=1)
+        extras["serve"] = dict(rates, server_state_bytes=sb)
     return line, (cpu_sample if sample else None)
 
 
@@ -524,6 +533,32 @@ def run_rate_vs_size(args, torch, odp, W):
         "extras": rows,
     }
     return line, None
+
+
+def measure_trace(torch, odp, W, steps):
+    """The trace workload's analysis timed with HIP events (planted counts checked)."""
+    tr = W.TraceAtScale(seed=4)
+    n = len(tr.events)
+    stream = torch.cuda.current_stream()
+    d_ev = torch.from_numpy(tr.events.view(np.uint8).reshape(-1).copy()).to("cuda")
+    d_flags = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    d_rep = torch.zeros(odp.REPORT_BYTES, dtype=torch.uint8, device="cuda")
+    odp.reserve(max_events=n, stream=stream)
+    timer = KernelTimer(torch, stream)
+
+    def step(mode):
+        e0 = timer.start() if mode else None
+        odp.analyze_trace(d_ev, d_flags, d_rep, stream=stream, n=n)
+        if mode:
+            timer.stop(e0)
+
+    timed_steps(torch, step, steps, 2)
+    rep = odp.report_to_dict(d_rep.cpu().numpy())
+    for k, v in tr.planted.items():
+        assert rep[k] == v, (k, rep[k], v)
+    t = timer.summary()
+    return {"events": n, "ms": t, "events_per_s": round(n / (t["median"] * 1e-3), 0),
+            "frac_of_peak_65B_per_record": round(65.0 * n / (t["median"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
 def run_trace(args, torch, odp, W):
@@ -620,7 +655,9 @@ def run_plain_small(args, torch, odp, W):
     return line, None
 
 
-def run_serve(args, torch, odp, W):
+def measure_serve(torch, odp, W, rate_list, seconds, steps, warmup, plain_requests=0, burst=False):
+    """Serving schedules at the given rates (batched server; the plain one too when
+    plain_requests > 0; the 64 MiB burst when burst): p50/p99 latency and GB/s per rate."""
     gib = 1 << 30
     arena = torch.empty(16 * gib, dtype=torch.uint8, device="cuda")
     gen = torch.Generator(device="cuda")
@@ -645,23 +682,34 @@ def run_serve(args, torch, odp, W):
 
     state_bytes = [0]
     warm = W.ServingSchedule(seed=100, n=2000, rate=50_000.0, arena=arena)
-    for _ in range(max(args.warmup, 1)):
+    for _ in range(max(warmup, 1)):
         serve(warm, odp.SERVER_BATCHED, 2000)
-        serve(warm, odp.SERVER_PLAIN, 500)
+        if plain_requests:
+            serve(warm, odp.SERVER_PLAIN, 500)
     rates = {}
     t0 = time.perf_counter()
-    for rate in (10_000, 50_000, 200_000):
-        n = int(min(200_000, rate * args.serve_seconds))
+    for rate in rate_list:
+        n = int(min(200_000, rate * seconds))
         sched = W.ServingSchedule(seed=6, n=n, rate=float(rate), arena=arena)
-        runs = [serve(sched, odp.SERVER_BATCHED, n) for _ in range(args.steps)]
+        runs = [serve(sched, odp.SERVER_BATCHED, n) for _ in range(steps)]
         r = max(runs, key=lambda x: x["p99_us"])  # the worst of the repeats
-        r["plain"] = serve(sched, odp.SERVER_PLAIN, min(n, args.plain_requests))
+        if plain_requests:
+            r["plain"] = serve(sched, odp.SERVER_PLAIN, min(n, plain_requests))
         rates["%dk_per_s" % (rate // 1000)] = r
-    ms = (time.perf_counter() - t0) * 1e3 / (3 * args.steps)
-    # burst: 1000 requests of 64 MiB at t = 0 against the same budget
-    burst = W.ServingSchedule(seed=7, n=1000, rate=1e9, lo=64 << 20, hi=64 << 20, arena=arena)
-    burst.arrival_ns[:] = 0
-    rates["burst_1000x64MiB"] = serve(burst, odp.SERVER_BATCHED, 1000)
+    ms = (time.perf_counter() - t0) * 1e3 / (len(rate_list) * steps)
+    if burst:
+        # 1000 requests of 64 MiB at t = 0 against the same budget
+        b = W.ServingSchedule(seed=7, n=1000, rate=1e9, lo=64 << 20, hi=64 << 20, arena=arena)
+        b.arrival_ns[:] = 0
+        rates["burst_1000x64MiB"] = serve(b, odp.SERVER_BATCHED, 1000)
+    del arena
+    torch.cuda.empty_cache()
+    return rates, state_bytes[0], ms
+
+
+def run_serve(args, torch, odp, W):
+    rates, state_bytes, ms = measure_serve(torch, odp, W, (10_000, 50_000, 200_000), args.serve_seconds, args.steps,
+                                           args.warmup, plain_requests=args.plain_requests, burst=True)
     top = rates["200k_per_s"]
     line = {
         "metric": "serving GB/s at 200k req/s (p50/p99 latency in extras)",
@@ -671,7 +719,7 @@ def run_serve(args, torch, odp, W):
         "config": {"workload": "serve: Poisson 10k/50k/200k req/s, payloads log-uniform 4 KiB-64 MiB of a 16 GiB "
                                "arena, 20% repeats, planted round trips; 32e9-byte device memory budget (the "
                                "server's state and workspace plus the payloads in flight)",
-                   "server_state_bytes": state_bytes[0],
+                   "server_state_bytes": state_bytes,
                    "requests_per_rate": [v["requests"] for k, v in rates.items() if k.endswith("_per_s")]},
         "roofline": None,
         "extras": rates,
