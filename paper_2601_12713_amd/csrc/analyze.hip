@@ -128,6 +128,9 @@ struct SortJob {
   uint32_t mono_word;
   // When set and *run_flag is 0 the job runs no pass (its order is not needed).
   const uint32_t* run_flag;
+  // 1: the classification writes the per-tile counts of the keys' least
+  // significant byte, so a first pass on that byte needs no histogram launch
+  uint32_t hist0_pre;
 };
 constexpr uint32_t kNoWord = 0xFFFFFFFFu;
 
@@ -187,7 +190,7 @@ __device__ void block_add(uint64_t* dst64, unsigned long long v) {
 }
 
 // Per-block partials of the grid-wide reductions of the big launches
-// (classification, subset compaction, DD/RT): every block stores its own
+// (classification, subset compaction, DD/RT, RA/UA, UT): every block stores its own
 // slot entry and one small kernel reduces each slot afterwards, so no two
 // blocks touch the same word (same-address atomics from thousands of blocks
 // serialise at one L2 channel).
@@ -196,6 +199,8 @@ enum Slot : uint32_t {
   S_AD_DEV_OR, S_AD_DEV_AND, S_AD_ADDR_OR, S_AD_ADDR_AND, S_KS_OR, S_KS_AND, S_KE_OR, S_KE_AND, S_KD_OR, S_KD_AND,
   S_UT_ADDR_OR, S_UT_ADDR_AND, S_UT_CODE_OR, S_UT_CODE_AND,
   S_DD_EVENTS, S_DD_GROUPS, S_DD_BYTES, S_DD_TIME, S_RT_PAIRS, S_RT_RX, S_RT_BYTES, S_RT_TIME, S_ELIM_TX,
+  S_RA_EVENTS, S_RA_GROUPS, S_RA_BYTES, S_RA_TIME, S_UA_EVENTS, S_UA_BYTES, S_UA_TIME, S_ELIM_PAIRS,
+  S_UT_EVENTS, S_UT_BYTES, S_UT_TIME, S_ELIM_UT,
   kSlots
 };
 
@@ -275,22 +280,27 @@ __device__ __forceinline__ bool dev_ok(int d) { return d >= -1 && d <= ODP_MAX_D
 // One block per tile of kTile records; wavefront w takes the 1,024
 // consecutive records [tile*kTile + w*1024, ...) in 16 rounds of 64 and also
 // counts the ALLOC/DELETE, KERNEL and copy-in records it sees (for the
-// compaction).
+// compaction). The block also counts its tile's digest sort keys by least
+// significant byte (hist0, row length ntc): the digest sort's first pass when
+// that byte varies.
 __global__ __launch_bounds__(kT) void classify_kernel(const odp_event* __restrict__ ev, uint32_t n, uint8_t* __restrict__ flags,
                                                       uint8_t* __restrict__ cls, uint8_t* __restrict__ aux,
                                                       unsigned long long* __restrict__ keys, uint32_t* __restrict__ vals,
                                                       uint32_t* __restrict__ wave_cnt, uint64_t* __restrict__ wave_kmax,
-                                                      Parts parts) {
+                                                      uint32_t* __restrict__ hist0, uint32_t ntc, Parts parts) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const uint32_t wid = blockIdx.x * (kT / 64) + w;
   const uint32_t wb = wid * kWaveElems;
   __shared__ uint32_t s_kdev[kT / 64][kEp];
   __shared__ unsigned long long s_kmax[kT / 64][kEp];
+  __shared__ uint32_t s_h0[256];
+  static_assert(kT == 256, "one histogram bin per thread");
+  s_h0[threadIdx.x] = 0;
   if (lane < kEp) {
     s_kdev[w][lane] = 0;
     s_kmax[w][lane] = 0;
   }
-  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __syncthreads();
   unsigned long long n_inv = 0, n_tx = 0, n_k = 0, kor = 0, kand = ~0ull, tmin = ~0ull, tmax = 0;
   uint32_t bad = kNone, mep = 0, c_ad = 0, c_k = 0, c_ut = 0;
   // records of the next round are loaded while this round is classified; the
@@ -343,6 +353,7 @@ __global__ __launch_bounds__(kT) void classify_kernel(const odp_event* __restric
       cls[i] = c;
       aux[i] = a;
       keys[i] = key;
+      atomicAdd(&s_h0[key & 0xFF], 1u);
       vals[i] = n < kPackLimit ? i | ((uint32_t)a << 24) : i;
       kor |= key;
       kand &= key;
@@ -361,7 +372,8 @@ __global__ __launch_bounds__(kT) void classify_kernel(const odp_event* __restric
     wave_cnt[kWaveCnt * wid + 1] = c_k;
     wave_cnt[kWaveCnt * wid + 2] = c_ut;
   }
-  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __syncthreads();
+  hist0[(size_t)threadIdx.x * ntc + blockIdx.x] = s_h0[threadIdx.x];
   if (lane < kEp) {
     wave_cnt[kWaveCnt * wid + 3 + lane] = s_kdev[w][lane];
     wave_kmax[kEp * wid + lane] = s_kmax[w][lane];
@@ -442,14 +454,19 @@ constexpr uint32_t kScanChunk = 1024;
 
 // Exclusive scans of the per-wavefront counts (kWaveCnt) and maxima (kEp)
 // in one launch: a block of 1024 threads scans a chunk of kScanChunk
-// wavefronts, all quantities at once (their lane-move chains interleave, one
-// barrier in all); the block that finishes last, by a ticket, scans the chunk
-// totals and writes the subset sizes and per-device kernel list offsets.
-constexpr int kScanQ = kWaveCnt + kEp;
+// wavefronts, all quantities at once (their lane-move chains interleave); the
+// block that finishes last, by a ticket, scans the chunk totals and writes
+// the subset sizes and per-device kernel list offsets.
+constexpr int kScanW = 1024 / 64;  // wavefronts of a scan block
 
+// Each quantity is scanned inside every wavefront; the wavefront totals go to
+// LDS, where one thread per quantity turns them into exclusive prefixes (and
+// the block total, row kScanW), so each thread reads one prefix per quantity.
+// On return c and m hold the exclusive prefixes within the block and
+// wc[kScanW] / wm[kScanW] the block totals.
 __device__ __forceinline__ void scan_all(uint32_t (&c)[kWaveCnt], unsigned long long (&m)[kEp],
-                                         uint32_t (&wc)[16][kWaveCnt], unsigned long long (&wm)[16][kEp],
-                                         uint32_t (&tc)[kWaveCnt], unsigned long long (&tm)[kEp]) {
+                                         uint32_t (&wc)[kScanW + 1][kWaveCnt],
+                                         unsigned long long (&wm)[kScanW + 1][kEp]) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   uint32_t xc[kWaveCnt];
   unsigned long long xm[kEp];
@@ -477,42 +494,48 @@ __device__ __forceinline__ void scan_all(uint32_t (&c)[kWaveCnt], unsigned long 
     for (int q = 0; q < kEp; ++q) wm[w][q] = xm[q];
   }
   __syncthreads();
-  const int nwv = (int)(blockDim.x / 64);
+  if (threadIdx.x < kWaveCnt) {
+    const int q = threadIdx.x;
+    uint32_t run = 0;
+    for (int v = 0; v < kScanW; ++v) {
+      const uint32_t t = wc[v][q];
+      wc[v][q] = run;
+      run += t;
+    }
+    wc[kScanW][q] = run;
+  } else if (threadIdx.x >= 64 && threadIdx.x < 64 + kEp) {
+    const int q = threadIdx.x - 64;
+    unsigned long long run = 0;
+    for (int v = 0; v < kScanW; ++v) {
+      const unsigned long long t = wm[v][q];
+      wm[v][q] = run;
+      run = max(run, t);
+    }
+    wm[kScanW][q] = run;
+  }
+  __syncthreads();
 #pragma unroll
   for (int q = 0; q < kWaveCnt; ++q) {
-    uint32_t before = __shfl_up(xc[q], 1, 64), all = 0;
+    uint32_t before = __shfl_up(xc[q], 1, 64);
     if (lane == 0) before = 0;
-    for (int v = 0; v < nwv; ++v) {
-      if (v < w) before += wc[v][q];
-      all += wc[v][q];
-    }
-    c[q] = before;
-    tc[q] = all;
+    c[q] = before + wc[w][q];
   }
 #pragma unroll
   for (int q = 0; q < kEp; ++q) {
-    unsigned long long before = __shfl_up(xm[q], 1, 64), all = 0;
+    unsigned long long before = __shfl_up(xm[q], 1, 64);
     if (lane == 0) before = 0;
-    for (int v = 0; v < nwv; ++v) {
-      if (v < w) before = max(before, wm[v][q]);
-      all = max(all, wm[v][q]);
-    }
-    m[q] = before;
-    tm[q] = all;
+    m[q] = max(before, wm[w][q]);
   }
-  __syncthreads();
 }
 
 __global__ __launch_bounds__(1024) void wave_scan_kernel(WaveScan S, uint32_t nchunk, AnaCtl* ctl) {
-  __shared__ uint32_t wc[16][kWaveCnt];
-  __shared__ unsigned long long wm[16][kEp];
+  __shared__ uint32_t wc[kScanW + 1][kWaveCnt];
+  __shared__ unsigned long long wm[kScanW + 1][kEp];
   __shared__ uint32_t carry_c[kWaveCnt];
   __shared__ unsigned long long carry_m[kEp];
   __shared__ uint32_t last;
-  __shared__ uint32_t s_tc[kWaveCnt];         // block totals (register arrays are
-  __shared__ unsigned long long s_tm[kEp];    // not indexed by thread)
-  uint32_t c[kWaveCnt], tc[kWaveCnt];
-  unsigned long long m[kEp], tm[kEp];
+  uint32_t c[kWaveCnt];
+  unsigned long long m[kEp];
   {
     const uint32_t i = blockIdx.x * kScanChunk + threadIdx.x;
     const bool in = i < S.nw;
@@ -520,28 +543,21 @@ __global__ __launch_bounds__(1024) void wave_scan_kernel(WaveScan S, uint32_t nc
     for (int q = 0; q < kWaveCnt; ++q) c[q] = in ? S.cnt[(size_t)kWaveCnt * i + q] : 0u;
 #pragma unroll
     for (int q = 0; q < kEp; ++q) m[q] = in ? (unsigned long long)S.kmax[(size_t)kEp * i + q] : 0ull;
-    scan_all(c, m, wc, wm, tc, tm);
+    scan_all(c, m, wc, wm);
     if (in) {
 #pragma unroll
       for (int q = 0; q < kWaveCnt; ++q) S.cnt[(size_t)kWaveCnt * i + q] = c[q];
 #pragma unroll
       for (int q = 0; q < kEp; ++q) S.kmax[(size_t)kEp * i + q] = m[q];
     }
-    // The chunk totals (stored by wavefront 0) reach the device-coherent
-    // level before its ticket: agent-scope stores and a wait for their
-    // completion, not a fence (an agent-scope fence writes back the L2).
-    if (threadIdx.x == 0) {
-#pragma unroll
-      for (int q = 0; q < kWaveCnt; ++q) s_tc[q] = tc[q];
-#pragma unroll
-      for (int q = 0; q < kEp; ++q) s_tm[q] = tm[q];
-    }
-    __syncthreads();
+    // The chunk totals reach the device-coherent level before its ticket:
+    // agent-scope stores and a wait for their completion, not a fence (an
+    // agent-scope fence writes back the L2).
     if (threadIdx.x < kWaveCnt)
-      __hip_atomic_store(S.ccnt + (size_t)kWaveCnt * blockIdx.x + threadIdx.x, s_tc[threadIdx.x], __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(S.ccnt + (size_t)kWaveCnt * blockIdx.x + threadIdx.x, wc[kScanW][threadIdx.x],
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (threadIdx.x < kEp)
-      __hip_atomic_store(S.cmax + (size_t)kEp * blockIdx.x + threadIdx.x, (uint64_t)s_tm[threadIdx.x],
+      __hip_atomic_store(S.cmax + (size_t)kEp * blockIdx.x + threadIdx.x, (uint64_t)wm[kScanW][threadIdx.x],
                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   if (threadIdx.x < 64) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
@@ -563,7 +579,7 @@ __global__ __launch_bounds__(1024) void wave_scan_kernel(WaveScan S, uint32_t nc
     for (int q = 0; q < kEp; ++q)
       m[q] = in ? (unsigned long long)__hip_atomic_load(S.cmax + (size_t)kEp * i + q, __ATOMIC_RELAXED,
                                                         __HIP_MEMORY_SCOPE_AGENT) : 0ull;
-    scan_all(c, m, wc, wm, tc, tm);
+    scan_all(c, m, wc, wm);
     if (in) {
 #pragma unroll
       for (int q = 0; q < kWaveCnt; ++q) S.ccnt[(size_t)kWaveCnt * i + q] = carry_c[q] + c[q];
@@ -571,12 +587,8 @@ __global__ __launch_bounds__(1024) void wave_scan_kernel(WaveScan S, uint32_t nc
       for (int q = 0; q < kEp; ++q) S.cmax[(size_t)kEp * i + q] = max(carry_m[q], m[q]);
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-#pragma unroll
-      for (int q = 0; q < kWaveCnt; ++q) carry_c[q] += tc[q];
-#pragma unroll
-      for (int q = 0; q < kEp; ++q) carry_m[q] = max(carry_m[q], tm[q]);
-    }
+    if (threadIdx.x < kWaveCnt) carry_c[threadIdx.x] += wc[kScanW][threadIdx.x];
+    if (threadIdx.x < kEp) carry_m[threadIdx.x] = max(carry_m[threadIdx.x], wm[kScanW][threadIdx.x]);
     __syncthreads();
   }
   if (threadIdx.x == 0) {
@@ -831,6 +843,18 @@ __global__ __launch_bounds__(kT) void reduce_parts_kernel(Parts parts, uint32_t 
     case S_RT_RX: rep->rt_rx_events = v; break;
     case S_RT_BYTES: rep->rt_bytes = v; break;
     case S_RT_TIME: rep->rt_time_ns = v; break;
+    case S_RA_EVENTS: rep->ra_events = v; break;
+    case S_RA_GROUPS: rep->ra_groups = v; break;
+    case S_RA_BYTES: rep->ra_bytes = v; break;
+    case S_RA_TIME: rep->ra_time_ns = v; break;
+    case S_UA_EVENTS: rep->ua_events = v; break;
+    case S_UA_BYTES: rep->ua_bytes = v; break;
+    case S_UA_TIME: rep->ua_time_ns = v; break;
+    case S_ELIM_PAIRS: ctl->elim_pairs = v; break;
+    case S_UT_EVENTS: rep->ut_events = v; break;
+    case S_UT_BYTES: rep->ut_bytes = v; break;
+    case S_UT_TIME: rep->ut_time_ns = v; break;
+    case S_ELIM_UT: ctl->elim_ut = v; break;
     default: break;
   }
 }
@@ -1042,6 +1066,7 @@ __global__ __launch_bounds__(kT) void sort_hist_kernel(JobSet J, uint32_t p) {
   const SortJob* s;
   uint32_t tile, n;
   if (!job_tile(J, p, s, tile, n)) return;
+  if (p == 0 && s->hist0_pre && s->ps[0] == 0) return;  // counted by the classification
   __shared__ uint32_t h[256];
   do {
   h[threadIdx.x] = 0;
@@ -2232,7 +2257,7 @@ struct RaArgs {
   const uint64_t* kd_ts;
   AnaCtl* ctl;
   uint8_t* flags;
-  odp_report* rep;
+  Parts parts;  // one partial per block of each RA/UA sum
 };
 
 
@@ -2301,14 +2326,14 @@ __global__ __launch_bounds__(kT) void ra_ua_kernel(RaArgs R) {
     if (f & (ODP_F_RA | ODP_F_UA)) t_el += dur;  // the pair is removable once
     R.flags[ai] = f;
   }
-  block_add(&R.rep->ra_events, c_ra);
-  block_add(&R.rep->ra_groups, c_grp);
-  block_add(&R.rep->ra_bytes, b_ra);
-  block_add(&R.rep->ra_time_ns, t_ra);
-  block_add(&R.rep->ua_events, c_ua);
-  block_add(&R.rep->ua_bytes, b_ua);
-  block_add(&R.rep->ua_time_ns, t_ua);
-  block_add(&R.ctl->elim_pairs, t_el);
+  block_store<R_ADD>(R.parts.at(S_RA_EVENTS), c_ra);
+  block_store<R_ADD>(R.parts.at(S_RA_GROUPS), c_grp);
+  block_store<R_ADD>(R.parts.at(S_RA_BYTES), b_ra);
+  block_store<R_ADD>(R.parts.at(S_RA_TIME), t_ra);
+  block_store<R_ADD>(R.parts.at(S_UA_EVENTS), c_ua);
+  block_store<R_ADD>(R.parts.at(S_UA_BYTES), b_ua);
+  block_store<R_ADD>(R.parts.at(S_UA_TIME), t_ua);
+  block_store<R_ADD>(R.parts.at(S_ELIM_PAIRS), t_el);
 }
 
 // ---------------------------------------------------------------------------
@@ -2340,7 +2365,7 @@ struct UtArgs {
   const uint32_t* kd_idx;  // ... and record index
   AnaCtl* ctl;
   uint8_t* flags;
-  odp_report* rep;
+  Parts parts;  // one partial per block of each UT sum
 };
 
 // In a chronological log (no record rejected), with K(c) the number of
@@ -2538,10 +2563,10 @@ __global__ __launch_bounds__(kT) void ut_merge_kernel(UtArgs U) {
       if (!(f[u] & (ODP_F_DD | ODP_F_RT_RX))) t_el += d;
     }
   }
-  block_add(&U.rep->ut_events, c_ut);
-  block_add(&U.rep->ut_bytes, b_ut);
-  block_add(&U.rep->ut_time_ns, t_ut);
-  block_add(&U.ctl->elim_ut, t_el);
+  block_store<R_ADD>(U.parts.at(S_UT_EVENTS), c_ut);
+  block_store<R_ADD>(U.parts.at(S_UT_BYTES), b_ut);
+  block_store<R_ADD>(U.parts.at(S_UT_TIME), t_ut);
+  block_store<R_ADD>(U.parts.at(S_ELIM_UT), t_el);
 }
 
 // The optimization-potential estimate (Sec. 7.6): the run's time is the span
@@ -2891,6 +2916,7 @@ void build_jobs(const Views& v, SortJob* hj) {
   hj[kJobBig].masks[0] = &ctl->m_digest;
   hj[kJobBig].word_bytes[0] = 8;
   hj[kJobBig].nwords = 1;
+  hj[kJobBig].hist0_pre = 1;
   // ALLOC/DELETE by (device, device address); words least significant first
   hj[kJobAd].n_ptr = &ctl->n_ad;
   hj[kJobAd].vals[0] = v.S.ad_vals;
@@ -3317,6 +3343,9 @@ static int enqueue_analysis(Workspace* ws, const odp_event* events, size_t n, ui
   const uint32_t nt = n ? ceil_div32(n, kTile) : 1;  // tiles of this call
   const int cus = cu_count(ws->device);
   const uint32_t grid_map = std::min<uint32_t>(nt * 4, (uint32_t)cus * 8);
+  // grid-stride launches whose blocks store one partial per sum (at most one
+  // per tile: the partials' row length)
+  const uint32_t grid_sum = std::min<uint32_t>(nt, (uint32_t)cus * 8);
   // one thread per element of a subset of at most n (copy-ins) or n / 2
   // (pairs) elements, for the per-element kernels that wait on chains of
   // dependent loads and add nothing up per block: they overlap those waits
@@ -3333,7 +3362,7 @@ static int enqueue_analysis(Workspace* ws, const odp_event* events, size_t n, ui
     return check_hip(hipGetLastError(), "odp_analyze_trace launch");
   }
   hipLaunchKernelGGL(classify_kernel, dim3(nt), dim3(kT), 0, stream, events, nn, out_flags, v.cls, v.aux, v.bk[0],
-                     v.bv[0], v.wave_cnt, v.wscan.kmax, v.parts);
+                     v.bv[0], v.wave_cnt, v.wscan.kmax, v.hist + (size_t)kJobBig * 256 * v.ntc, v.ntc, v.parts);
   // the classification's counts, digest masks, first rejected record and endpoint range
   hipLaunchKernelGGL(reduce_parts_kernel, dim3(S_AD_DEV_OR), dim3(kT), 0, stream, v.parts, nt, 0u, ctl, out_report);
 
@@ -3371,7 +3400,7 @@ static int enqueue_analysis(Workspace* ws, const odp_event* events, size_t n, ui
   U.kd_idx = v.S.kd_idx;
   U.ctl = ctl;
   U.flags = out_flags;
-  U.rep = out_report;
+  U.parts = v.parts;
   hipLaunchKernelGGL(ut_scan_kernel, dim3(grid_rec), dim3(kT), 0, side, U);
   hipLaunchKernelGGL(reduce_parts_kernel, dim3(S_DD_EVENTS - S_AD_DEV_OR), dim3(kT), 0, side, v.parts, nt,
                      (uint32_t)S_AD_DEV_OR, ctl, out_report);
@@ -3441,8 +3470,10 @@ static int enqueue_analysis(Workspace* ws, const odp_event* events, size_t n, ui
   R.kd_ts = v.S.kd_ts;
   R.ctl = ctl;
   R.flags = out_flags;
-  R.rep = out_report;
-  hipLaunchKernelGGL(ra_ua_kernel, dim3(grid_map), dim3(kT), 0, side, R);
+  R.parts = v.parts;
+  hipLaunchKernelGGL(ra_ua_kernel, dim3(grid_sum), dim3(kT), 0, side, R);
+  hipLaunchKernelGGL(reduce_parts_kernel, dim3(S_ELIM_PAIRS + 1 - S_RA_EVENTS), dim3(kT), 0, side, v.parts, grid_sum,
+                     (uint32_t)S_RA_EVENTS, ctl, out_report);
   // Records by digest (up to 8 passes), then duplicates and round trips, on
   // the caller's stream.
   const JobSet Jb{v.jobs + kJobBig, 1, nt};
@@ -3477,7 +3508,7 @@ static int enqueue_analysis(Workspace* ws, const odp_event* events, size_t n, ui
   hipLaunchKernelGGL(ddrt_agg_kernel, dim3(nt), dim3(kT), 0, stream, D);
   hipLaunchKernelGGL(ddrt_carry_kernel, dim3(1), dim3(kCT), 0, stream, D, nt * (kT / 64));
   hipLaunchKernelGGL(ddrt_final_kernel, dim3(nt), dim3(kT), 0, stream, D);
-  hipLaunchKernelGGL(reduce_parts_kernel, dim3(kSlots - S_DD_EVENTS), dim3(kT), 0, stream, v.parts, nt,
+  hipLaunchKernelGGL(reduce_parts_kernel, dim3(S_ELIM_TX + 1 - S_DD_EVENTS), dim3(kT), 0, stream, v.parts, nt,
                      (uint32_t)S_DD_EVENTS, ctl, out_report);
   if (alg2_rx) {
     Alg2Args G;
@@ -3492,7 +3523,9 @@ static int enqueue_analysis(Workspace* ws, const odp_event* events, size_t n, ui
   ODP_HIP(hipEventRecord(ws->a_join, side));
 
   ODP_HIP(hipStreamWaitEvent(stream, ws->a_join, 0));
-  hipLaunchKernelGGL(ut_merge_kernel, dim3(grid_map), dim3(kT), 0, stream, U);
+  hipLaunchKernelGGL(ut_merge_kernel, dim3(grid_sum), dim3(kT), 0, stream, U);
+  hipLaunchKernelGGL(reduce_parts_kernel, dim3(S_ELIM_UT + 1 - S_UT_EVENTS), dim3(kT), 0, stream, v.parts, grid_sum,
+                     (uint32_t)S_UT_EVENTS, ctl, out_report);
   hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(64), 0, stream, ctl, out_report);
   return check_hip(hipGetLastError(), "odp_analyze_trace launch");
 }
