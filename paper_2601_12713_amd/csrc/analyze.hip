@@ -1825,11 +1825,17 @@ __device__ __forceinline__ BwdEl<MODE> bcomb(const BwdEl<MODE>& a, const BwdEl<M
 // wavefront scans: a first sweep gives each wavefront's forward and backward
 // totals, LDS carries them across wavefronts, and a second sweep writes every
 // element's exclusive forward prefix and backward suffix.
+// Each sweep loads the aggregates of its next round while it scans the
+// current one (agg_raw), so its rounds wait on one load each in turn.
+__device__ __forceinline__ WaveAgg agg_raw(const DDArgs& A, uint32_t e, uint32_t end) {
+  WaveAgg g{};
+  if (e < end) g = A.agg[e];
+  return g;
+}
 template <int MODE>
-__device__ __forceinline__ void load_agg(const DDArgs& A, uint32_t e, uint32_t end, FwdEl<MODE>& x, BwdEl<MODE>& y) {
+__device__ __forceinline__ void load_agg(const WaveAgg& g, uint32_t e, uint32_t end, FwdEl<MODE>& x, BwdEl<MODE>& y) {
   using S = St<MODE>;
   if (e < end) {
-    const WaveAgg& g = A.agg[e];
     x = FwdEl<MODE>{g.ff, get_f<MODE>(g.fs)};
     y = BwdEl<MODE>{g.bf, get_b<MODE>(g.bs)};
   } else {
@@ -1850,10 +1856,13 @@ __device__ void ddrt_carry_body(const DDArgs& A, uint32_t nw) {
   // sweep 1: this wavefront's totals
   FwdEl<MODE> tf{0, S::fid()};
   BwdEl<MODE> tb{0, S::bid()};
+  WaveAgg g = agg_raw(A, c0 + lane, c1), gn{};
   for (uint32_t r = 0; r < rounds; ++r) {
+    if (r + 1 < rounds) gn = agg_raw(A, c0 + (r + 1) * 64 + lane, c1);
     FwdEl<MODE> x;
     BwdEl<MODE> y;
-    load_agg<MODE>(A, c0 + r * 64 + lane, c1, x, y);
+    load_agg<MODE>(g, c0 + r * 64 + lane, c1, x, y);
+    g = gn;
     wave_fscan<MODE>(x.f, x.v);
     wave_bscan<MODE>(y.f, y.v);
     tf = fcomb<MODE>(tf, FwdEl<MODE>{lane32(x.f, 63), S::lane(x.v, 63)});
@@ -1869,22 +1878,28 @@ __device__ void ddrt_carry_body(const DDArgs& A, uint32_t nw) {
   BwdEl<MODE> runb{0, S::bid()};
   for (int q = kW - 1; q > w; --q) runb = bcomb<MODE>(wbk[q], runb);
   // sweep 2: exclusive prefixes (forward, in order) and suffixes (backward)
+  g = agg_raw(A, c0 + lane, c1);
   for (uint32_t r = 0; r < rounds; ++r) {
     const uint32_t e = c0 + r * 64 + lane;
+    if (r + 1 < rounds) gn = agg_raw(A, e + 64, c1);
     FwdEl<MODE> x;
     BwdEl<MODE> y;
-    load_agg<MODE>(A, e, c1, x, y);
+    load_agg<MODE>(g, e, c1, x, y);
+    g = gn;
     wave_fscan<MODE>(x.f, x.v);
     const FwdEl<MODE> xp{dpp32<kDppWaveShr1>(0u, x.f), S::template dpp<kDppWaveShr1>(S::fid(), x.v)};
     const FwdEl<MODE> ex = lane == 0 ? run : fcomb<MODE>(run, xp);
     if (e < c1) put_f<MODE>(A.carry[e].fs, ex.v);
     run = fcomb<MODE>(run, FwdEl<MODE>{lane32(x.f, 63), S::lane(x.v, 63)});
   }
+  if (rounds) g = agg_raw(A, c0 + (rounds - 1) * 64 + lane, c1);
   for (uint32_t r = rounds; r-- > 0;) {
     const uint32_t e = c0 + r * 64 + lane;
+    if (r > 0) gn = agg_raw(A, e - 64, c1);
     FwdEl<MODE> x;
     BwdEl<MODE> y;
-    load_agg<MODE>(A, e, c1, x, y);
+    load_agg<MODE>(g, e, c1, x, y);
+    g = gn;
     wave_bscan<MODE>(y.f, y.v);
     const BwdEl<MODE> yn{dpp32<kDppWaveShl1>(0u, y.f), S::template dpp<kDppWaveShl1>(S::bid(), y.v)};
     const BwdEl<MODE> ex = lane == 63 ? runb : bcomb<MODE>(yn, runb);
