@@ -89,7 +89,11 @@ struct AnaCtl {
   uint32_t dev_lo[kEp], dev_hi[kEp];  // per-device ranges in the sorted kernel order
   uint64_t t_min, t_max;              // earliest start and latest end of the valid records
   uint32_t kd_base[kEp], kd_total[kEp];  // KERNEL records per device code: list offsets and counts
-  uint32_t scan_ticket;               // blocks of the wave scan done (the last one resets it)
+  // wave scan tickets: blocks done per quantity, then quantities done (the
+  // last user of each resets it), and each quantity's total
+  uint32_t scan_tq[kWaveCnt + kEp];
+  uint32_t scan_ticket;
+  uint64_t scan_tot[kWaveCnt + kEp];
   uint32_t ut_need_sort;              // 1: some copy-in is decided by the sorted path
   uint32_t kern_sort;                 // 1: the kernel lists are sorted (the count form's binary searches)
   // removable time (Sec. 7.6), in three parts written by different stages:
@@ -260,6 +264,7 @@ __global__ void init_kernel(AnaCtl* ctl, odp_report* rep, uint32_t* totals, uint
     ctl->ut_need_sort = 0;
     ctl->kern_sort = 0;
     ctl->scan_ticket = 0;
+    for (int q = 0; q < kWaveCnt + kEp; ++q) ctl->scan_tq[q] = 0;
     WordMask* m = &ctl->m_digest;
     for (int i = 0; i < kNumMasks; ++i) {
       m[i].vor = 0;
@@ -452,156 +457,109 @@ struct WaveScan {
 };
 constexpr uint32_t kScanChunk = 1024;
 
-// Exclusive scans of the per-wavefront counts (kWaveCnt) and maxima (kEp)
-// in one launch: a block of 1024 threads scans a chunk of kScanChunk
-// wavefronts, all quantities at once (their lane-move chains interleave); the
-// block that finishes last, by a ticket, scans the chunk totals and writes
-// the subset sizes and per-device kernel list offsets.
-constexpr int kScanW = 1024 / 64;  // wavefronts of a scan block
+// Exclusive scans of the per-wavefront counts (kWaveCnt, sums) and maxima
+// (kEp) in one launch: block (q, c) scans quantity q over chunk c of
+// kScanChunk wavefronts; the last block of a quantity, by a ticket, scans the
+// quantity's chunk totals, and the last quantity to finish writes the subset
+// sizes and per-device kernel list offsets. One quantity per block keeps the
+// kernel's code short: it runs once per call, from cold instruction caches,
+// where a block holding every quantity at once (unrolled) took 30 us.
+constexpr int kScanQ = kWaveCnt + kEp;
 
-// Each quantity is scanned inside every wavefront; the wavefront totals go to
-// LDS, where one thread per quantity turns them into exclusive prefixes (and
-// the block total, row kScanW), so each thread reads one prefix per quantity.
-// On return c and m hold the exclusive prefixes within the block and
-// wc[kScanW] / wm[kScanW] the block totals.
-__device__ __forceinline__ void scan_all(uint32_t (&c)[kWaveCnt], unsigned long long (&m)[kEp],
-                                         uint32_t (&wc)[kScanW + 1][kWaveCnt],
-                                         unsigned long long (&wm)[kScanW + 1][kEp]) {
+// Exclusive scan of x over the 1024 threads of the block (sum, or max when
+// MAX); returns the prefix and sets total. wt: 16 words of LDS.
+template <typename T, bool MAX>
+__device__ __forceinline__ T block_xscan(T x, T* wt, T& total) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  uint32_t xc[kWaveCnt];
-  unsigned long long xm[kEp];
-#pragma unroll
-  for (int q = 0; q < kWaveCnt; ++q) xc[q] = c[q];
-#pragma unroll
-  for (int q = 0; q < kEp; ++q) xm[q] = m[q];
-#pragma unroll
+  T v = x;
   for (int o = 1; o < 64; o <<= 1) {
-#pragma unroll
-    for (int q = 0; q < kWaveCnt; ++q) {
-      const uint32_t y = __shfl_up(xc[q], o, 64);
-      if (lane >= o) xc[q] += y;
-    }
-#pragma unroll
-    for (int q = 0; q < kEp; ++q) {
-      const unsigned long long y = __shfl_up(xm[q], o, 64);
-      if (lane >= o) xm[q] = max(xm[q], y);
-    }
+    const T y = __shfl_up(v, o, 64);
+    if (lane >= o) v = MAX ? max(v, y) : v + y;
   }
-  if (lane == 63) {
-#pragma unroll
-    for (int q = 0; q < kWaveCnt; ++q) wc[w][q] = xc[q];
-#pragma unroll
-    for (int q = 0; q < kEp; ++q) wm[w][q] = xm[q];
+  if (lane == 63) wt[w] = v;
+  __syncthreads();
+  if (w == 0) {
+    T u = lane < 16 ? wt[lane] : (T)0;
+    for (int o = 1; o < 16; o <<= 1) {
+      const T y = __shfl_up(u, o, 64);
+      if (lane >= o) u = MAX ? max(u, y) : u + y;
+    }
+    if (lane < 16) wt[lane] = u;  // inclusive over wavefronts
   }
   __syncthreads();
-  if (threadIdx.x < kWaveCnt) {
-    const int q = threadIdx.x;
-    uint32_t run = 0;
-    for (int v = 0; v < kScanW; ++v) {
-      const uint32_t t = wc[v][q];
-      wc[v][q] = run;
-      run += t;
-    }
-    wc[kScanW][q] = run;
-  } else if (threadIdx.x >= 64 && threadIdx.x < 64 + kEp) {
-    const int q = threadIdx.x - 64;
-    unsigned long long run = 0;
-    for (int v = 0; v < kScanW; ++v) {
-      const unsigned long long t = wm[v][q];
-      wm[v][q] = run;
-      run = max(run, t);
-    }
-    wm[kScanW][q] = run;
+  T before = __shfl_up(v, 1, 64);
+  if (lane == 0) before = 0;
+  const T wb = w > 0 ? wt[w - 1] : (T)0;
+  total = wt[15];
+  __syncthreads();  // wt is reused by the next scan
+  return MAX ? max(wb, before) : wb + before;
+}
+
+// Scans quantity q (element i at base[stride * i]) over [c * kScanChunk, ...)
+// in place; then the quantity's chunk totals (ct[stride * c]) by its last
+// block. Returns true in the block that finished the quantity last overall.
+template <typename T, bool MAX>
+__device__ bool scan_quantity(T* base, T* ct, uint32_t stride, uint32_t nw, uint32_t nchunk, uint32_t c, uint32_t q,
+                              AnaCtl* ctl, T* wt, uint32_t* flag) {
+  const uint32_t i = c * kScanChunk + threadIdx.x;
+  const bool in = i < nw;
+  T total;
+  const T x = block_xscan<T, MAX>(in ? base[(size_t)stride * i] : (T)0, wt, total);
+  if (in) base[(size_t)stride * i] = x;
+  // the chunk total reaches the device-coherent level before the ticket:
+  // an agent-scope store and a wait for its completion, not a fence (an
+  // agent-scope fence writes back the L2)
+  if (threadIdx.x == 0) {
+    __hip_atomic_store(ct + (size_t)stride * c, total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    *flag = __hip_atomic_fetch_add(&ctl->scan_tq[q], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == nchunk - 1;
   }
   __syncthreads();
-#pragma unroll
-  for (int q = 0; q < kWaveCnt; ++q) {
-    uint32_t before = __shfl_up(xc[q], 1, 64);
-    if (lane == 0) before = 0;
-    c[q] = before + wc[w][q];
+  if (!*flag) return false;
+  T carry = 0;
+  for (uint32_t b0 = 0; b0 < nchunk; b0 += kScanChunk) {
+    const uint32_t k = b0 + threadIdx.x;
+    const bool ok = k < nchunk;
+    const T y = ok ? __hip_atomic_load(ct + (size_t)stride * k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : (T)0;
+    T t;
+    const T e = block_xscan<T, MAX>(y, wt, t);
+    if (ok) ct[(size_t)stride * k] = MAX ? max(carry, e) : carry + e;
+    carry = MAX ? max(carry, t) : carry + t;
   }
-#pragma unroll
-  for (int q = 0; q < kEp; ++q) {
-    unsigned long long before = __shfl_up(xm[q], 1, 64);
-    if (lane == 0) before = 0;
-    m[q] = max(before, wm[w][q]);
+  if (threadIdx.x == 0) {
+    ctl->scan_tq[q] = 0;
+    __hip_atomic_store(&ctl->scan_tot[q], (uint64_t)carry, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    *flag = __hip_atomic_fetch_add(&ctl->scan_ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == kScanQ - 1;
   }
+  __syncthreads();
+  return *flag != 0;
 }
 
 __global__ __launch_bounds__(1024) void wave_scan_kernel(WaveScan S, uint32_t nchunk, AnaCtl* ctl) {
-  __shared__ uint32_t wc[kScanW + 1][kWaveCnt];
-  __shared__ unsigned long long wm[kScanW + 1][kEp];
-  __shared__ uint32_t carry_c[kWaveCnt];
-  __shared__ unsigned long long carry_m[kEp];
-  __shared__ uint32_t last;
-  uint32_t c[kWaveCnt];
-  unsigned long long m[kEp];
-  {
-    const uint32_t i = blockIdx.x * kScanChunk + threadIdx.x;
-    const bool in = i < S.nw;
-#pragma unroll
-    for (int q = 0; q < kWaveCnt; ++q) c[q] = in ? S.cnt[(size_t)kWaveCnt * i + q] : 0u;
-#pragma unroll
-    for (int q = 0; q < kEp; ++q) m[q] = in ? (unsigned long long)S.kmax[(size_t)kEp * i + q] : 0ull;
-    scan_all(c, m, wc, wm);
-    if (in) {
-#pragma unroll
-      for (int q = 0; q < kWaveCnt; ++q) S.cnt[(size_t)kWaveCnt * i + q] = c[q];
-#pragma unroll
-      for (int q = 0; q < kEp; ++q) S.kmax[(size_t)kEp * i + q] = m[q];
-    }
-    // The chunk totals reach the device-coherent level before its ticket:
-    // agent-scope stores and a wait for their completion, not a fence (an
-    // agent-scope fence writes back the L2).
-    if (threadIdx.x < kWaveCnt)
-      __hip_atomic_store(S.ccnt + (size_t)kWaveCnt * blockIdx.x + threadIdx.x, wc[kScanW][threadIdx.x],
-                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (threadIdx.x < kEp)
-      __hip_atomic_store(S.cmax + (size_t)kEp * blockIdx.x + threadIdx.x, (uint64_t)wm[kScanW][threadIdx.x],
-                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-  if (threadIdx.x < 64) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-  if (threadIdx.x == 0)
-    last = __hip_atomic_fetch_add(&ctl->scan_ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == nchunk - 1 ? 1u
-                                                                                                           : 0u;
-  __syncthreads();
-  if (!last) return;
-  if (threadIdx.x < kWaveCnt) carry_c[threadIdx.x] = 0;
-  if (threadIdx.x < kEp) carry_m[threadIdx.x] = 0;
-  __syncthreads();
-  for (uint32_t base = 0; base < nchunk; base += blockDim.x) {
-    const uint32_t i = base + threadIdx.x;
-    const bool in = i < nchunk;
-#pragma unroll
-    for (int q = 0; q < kWaveCnt; ++q)
-      c[q] = in ? __hip_atomic_load(S.ccnt + (size_t)kWaveCnt * i + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
-#pragma unroll
-    for (int q = 0; q < kEp; ++q)
-      m[q] = in ? (unsigned long long)__hip_atomic_load(S.cmax + (size_t)kEp * i + q, __ATOMIC_RELAXED,
-                                                        __HIP_MEMORY_SCOPE_AGENT) : 0ull;
-    scan_all(c, m, wc, wm);
-    if (in) {
-#pragma unroll
-      for (int q = 0; q < kWaveCnt; ++q) S.ccnt[(size_t)kWaveCnt * i + q] = carry_c[q] + c[q];
-#pragma unroll
-      for (int q = 0; q < kEp; ++q) S.cmax[(size_t)kEp * i + q] = max(carry_m[q], m[q]);
-    }
-    __syncthreads();
-    if (threadIdx.x < kWaveCnt) carry_c[threadIdx.x] += wc[kScanW][threadIdx.x];
-    if (threadIdx.x < kEp) carry_m[threadIdx.x] = max(carry_m[threadIdx.x], wm[kScanW][threadIdx.x]);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    ctl->scan_ticket = 0;
-    ctl->n_ad = carry_c[0];
-    ctl->n_k = carry_c[1];
-    ctl->n_ut = carry_c[2];
-    uint32_t b = 0;
-    for (int d = 0; d < kEp; ++d) {
-      ctl->kd_base[d] = b;
-      ctl->kd_total[d] = carry_c[3 + d];
-      b += carry_c[3 + d];
-    }
+  __shared__ unsigned long long wt[16];
+  __shared__ uint32_t flag;
+  const uint32_t q = blockIdx.x / nchunk, c = blockIdx.x % nchunk;
+  const bool last =
+      q < kWaveCnt
+          ? scan_quantity<uint32_t, false>(S.cnt + q, S.ccnt + q, kWaveCnt, S.nw, nchunk, c, q, ctl,
+                                           reinterpret_cast<uint32_t*>(wt), &flag)
+          : scan_quantity<unsigned long long, true>(reinterpret_cast<unsigned long long*>(S.kmax) + (q - kWaveCnt),
+                                                    reinterpret_cast<unsigned long long*>(S.cmax) + (q - kWaveCnt), kEp,
+                                                    S.nw, nchunk, c, q, ctl, wt, &flag);
+  if (!last || threadIdx.x != 0) return;
+  uint64_t tot[kWaveCnt];
+  for (int k = 0; k < kWaveCnt; ++k)
+    tot[k] = __hip_atomic_load(&ctl->scan_tot[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  ctl->scan_ticket = 0;
+  ctl->n_ad = (uint32_t)tot[0];
+  ctl->n_k = (uint32_t)tot[1];
+  ctl->n_ut = (uint32_t)tot[2];
+  uint32_t b = 0;
+  for (int d = 0; d < kEp; ++d) {
+    ctl->kd_base[d] = b;
+    ctl->kd_total[d] = (uint32_t)tot[3 + d];
+    b += (uint32_t)tot[3 + d];
   }
 }
 
@@ -3394,7 +3352,7 @@ static int enqueue_analysis(Workspace* ws, const odp_event* events, size_t n, ui
   WaveScan WS = v.wscan;
   WS.nw = nt * (kT / 64);
   const uint32_t nchunk = ceil_div32(WS.nw, kScanChunk);
-  hipLaunchKernelGGL(wave_scan_kernel, dim3(nchunk), dim3(1024), 0, side, WS, nchunk, ctl);
+  hipLaunchKernelGGL(wave_scan_kernel, dim3(nchunk * kScanQ), dim3(1024), 0, side, WS, nchunk, ctl);
   hipLaunchKernelGGL(subset_scatter_kernel, dim3(nt), dim3(kT), 0, side, events, v.cls, nn, WS, v.S, v.parts);
   // Unused transfers (their flags are merged after the join).
   UtArgs U;
