@@ -15,8 +15,9 @@
 //   subsets    ordered compaction of ALLOC/DELETE, KERNEL and copy-in (H2D or
 //              D2D into a device) records, each with its device's kernel
 //              count and latest kernel end so far
-//   sorts      records by digest (low bytes first, then short runs of equal
-//              low bytes sorted in place); ALLOC/DELETE by (device, device
+//   sorts      transfers by digest (the first pass drops every other record;
+//              low bytes first, then short runs of equal low bytes sorted in
+//              place); ALLOC/DELETE by (device, device
 //              address); when needed, KERNELs by (device, start) and by
 //              (device, end) and copy-ins by (endpoints, source address)
 //   DD/RT      forward and backward segmented scans over each digest group
@@ -79,6 +80,7 @@ struct WordMask {
 
 struct AnaCtl {
   uint32_t n;           // records
+  uint32_t n_tx;        // valid transfers (the digest sort keeps only these after its first pass)
   uint32_t n_ad;        // ALLOC/DELETE records
   uint32_t n_k;         // KERNEL records
   uint32_t n_pairs;     // paired allocations
@@ -135,7 +137,27 @@ struct SortJob {
   // 1: the classification writes the per-tile counts of the keys' least
   // significant byte, so a first pass on that byte needs no histogram launch
   uint32_t hist0_pre;
+  // The digest job's first pass keeps only the valid transfers (endpoint code
+  // other than kNotTransfer: in the value's top byte when *n_ptr < kPackLimit,
+  // else aux[value]); the passes after it sort *n_after0 elements. Null /
+  // 0 for the other jobs.
+  const uint32_t* n_after0;
+  const uint8_t* aux;
+  uint32_t drop0;
 };
+
+// Elements of job s that pass p reads.
+__device__ __forceinline__ uint32_t pass_len(const SortJob& s, uint32_t p) {
+  return (p > 0 && s.n_after0) ? *s.n_after0 : *s.n_ptr;
+}
+// Elements in the job's sorted order once its passes have run (all of them
+// when none ran).
+__device__ __forceinline__ uint32_t sorted_len(const SortJob& s) { return pass_len(s, s.npasses); }
+// Whether the first pass keeps the element of value val.
+__device__ __forceinline__ bool keep0(const SortJob& s, uint32_t val) {
+  const uint8_t a = *s.n_ptr < kPackLimit ? (uint8_t)(val >> 24) : s.aux[val];
+  return a != kNotTransfer;
+}
 constexpr uint32_t kNoWord = 0xFFFFFFFFu;
 
 struct JobSet {
@@ -255,7 +277,7 @@ __global__ void init_kernel(AnaCtl* ctl, odp_report* rep, uint32_t* totals, uint
     rep->status = 0;
     rep->first_bad_event = kNone;
     ctl->n = n;
-    ctl->n_ad = ctl->n_k = ctl->n_pairs = ctl->n_ut = 0;
+    ctl->n_ad = ctl->n_k = ctl->n_pairs = ctl->n_ut = ctl->n_tx = 0;
     ctl->first_bad = kNone;
     ctl->max_ep = 0;
     ctl->t_min = ~0ull;
@@ -285,9 +307,9 @@ __device__ __forceinline__ bool dev_ok(int d) { return d >= -1 && d <= ODP_MAX_D
 // One block per tile of kTile records; wavefront w takes the 1,024
 // consecutive records [tile*kTile + w*1024, ...) in 16 rounds of 64 and also
 // counts the ALLOC/DELETE, KERNEL and copy-in records it sees (for the
-// compaction). The block also counts its tile's digest sort keys by least
-// significant byte (hist0, row length ntc): the digest sort's first pass when
-// that byte varies.
+// compaction). The block also counts its tile's valid transfers by the least
+// significant byte of their digest (hist0, row length ntc): the digest sort's
+// first pass when that byte varies (that pass keeps only the transfers).
 __global__ __launch_bounds__(kT) void classify_kernel(const odp_event* __restrict__ ev, uint32_t n, uint8_t* __restrict__ flags,
                                                       uint8_t* __restrict__ cls, uint8_t* __restrict__ aux,
                                                       unsigned long long* __restrict__ keys, uint32_t* __restrict__ vals,
@@ -358,7 +380,7 @@ __global__ __launch_bounds__(kT) void classify_kernel(const odp_event* __restric
       cls[i] = c;
       aux[i] = a;
       keys[i] = key;
-      atomicAdd(&s_h0[key & 0xFF], 1u);
+      if (c == C_TRANSFER || c == C_COPYIN) atomicAdd(&s_h0[key & 0xFF], 1u);
       vals[i] = n < kPackLimit ? i | ((uint32_t)a << 24) : i;
       kor |= key;
       kand &= key;
@@ -770,7 +792,10 @@ __global__ __launch_bounds__(kT) void reduce_parts_kernel(Parts parts, uint32_t 
   }
   switch (slot) {
     case S_N_INVALID: rep->n_invalid = v; break;
-    case S_N_TRANSFERS: rep->n_transfers = v; break;
+    case S_N_TRANSFERS:
+      rep->n_transfers = v;
+      ctl->n_tx = (uint32_t)v;
+      break;
     case S_N_KERNELS: rep->n_kernels = v; break;
     case S_DIG_OR: ctl->m_digest.vor = v; break;
     case S_DIG_AND: ctl->m_digest.vand = v; break;
@@ -883,7 +908,7 @@ __global__ __launch_bounds__(kT) void sort_fix_kernel(SortJob* job, uint32_t p) 
   if (threadIdx.x == 0) s_np = __hip_atomic_load(&s.npasses, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __syncthreads();
   const uint32_t np = s_np;
-  const uint32_t n = *s.n_ptr;
+  const uint32_t n = pass_len(s, 1);  // the sorted elements (the fix runs after a pass)
   const uint32_t nft = (n + kFixTile - 1) / kFixTile;
   if (p >= 1 && np == p - 1 && p - 1 < s.np_full) {
     const unsigned long long* runs = s.keys[p & 1];
@@ -1005,7 +1030,7 @@ __device__ __forceinline__ bool job_tile(const JobSet& J, uint32_t p, const Sort
   const SortJob& c = J.jobs[j];
   s = &c;
   tile = blockIdx.x % J.stride;
-  n = *c.n_ptr;
+  n = pass_len(c, p);
   return p < c.npasses && (uint64_t)tile * kTile < n && tile < c.ntiles_max;
 }
 __device__ __forceinline__ bool next_tile(const JobSet& J, const SortJob* s, uint32_t& tile, uint32_t n) {
@@ -1033,10 +1058,12 @@ __global__ __launch_bounds__(kT) void sort_hist_kernel(JobSet J, uint32_t p) {
   const uint32_t b = tile * kTile;
   uint32_t d[kItems];
   const uint32_t shift = s->ps[p];
+  const bool drop = p == 0 && s->drop0;
 #pragma unroll
   for (int r = 0; r < kItems; ++r) {
     const uint32_t j = b + r * kT + threadIdx.x;
-    d[r] = j < n ? (uint32_t)(key_of(*s, p, src, j) >> shift) & 0xFF : 256u;
+    const bool in = j < n && (!drop || keep0(*s, s->vals[src][j]));
+    d[r] = in ? (uint32_t)(key_of(*s, p, src, j) >> shift) & 0xFF : 256u;
   }
 #pragma unroll
   for (int r = 0; r < kItems; ++r)
@@ -1056,7 +1083,7 @@ __global__ __launch_bounds__(kT) void sort_scan_kernel(JobSet J, uint32_t p) {
   if (j >= J.njobs) return;
   const SortJob& s = J.jobs[j];
   if (p >= s.npasses) return;
-  const uint32_t n = *s.n_ptr;
+  const uint32_t n = pass_len(s, p);
   const uint32_t nt = ceil_div32(n, kTile);
   __shared__ uint32_t wsum[kT / 64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -1103,7 +1130,9 @@ __global__ __launch_bounds__(kST) void sort_scatter_kernel(JobSet J, uint32_t p)
   __shared__ unsigned long long stage[kTile];
   __shared__ uint8_t sdig[kTile];
   __shared__ uint32_t ws[4], wt[4];
+  __shared__ uint32_t s_kept;       // elements of this tile the pass writes
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const bool drop = p == 0 && s->drop0;
   do {
   for (int x = 0; x < 256; x += 64) wcnt[w][x + lane] = 0;
   __syncthreads();
@@ -1129,10 +1158,16 @@ __global__ __launch_bounds__(kST) void sort_scatter_kernel(JobSet J, uint32_t p)
       if (j < n) ky[r] = word[vl[r]];
     }
   }
+  // bit r: this lane's element of round r is written by the pass
+  uint32_t inmask = 0;
 #pragma unroll
   for (int r = 0; r < kSRounds; ++r) {
     const uint32_t j = wb + r * 64 + lane;
-    const bool in = j < n;
+    inmask |= (uint32_t)(j < n && (!drop || keep0(*s, vl[r]))) << r;
+  }
+#pragma unroll
+  for (int r = 0; r < kSRounds; ++r) {
+    const bool in = (inmask >> r) & 1;
     const uint32_t d = in ? (uint32_t)(ky[r] >> shift) & 0xFF : 0u;
     uint64_t peers = __ballot(in);
 #pragma unroll
@@ -1176,6 +1211,7 @@ __global__ __launch_bounds__(kST) void sort_scatter_kernel(JobSet J, uint32_t p)
     if (lane == 63) wt[w] = y;
     lbase[d] = xsc - c;  // completed below with the sums of earlier wavefronts
     gbase[d] = y - tot + s->hist[(size_t)d * s->ntiles_max + tile];
+    if (d == 255) s_kept = c;
   }
   __syncthreads();
   if (threadIdx.x < 256) {
@@ -1187,14 +1223,14 @@ __global__ __launch_bounds__(kST) void sort_scatter_kernel(JobSet J, uint32_t p)
     }
     lbase[d] += pre;
     gbase[d] += gpre;
+    if (d == 255) s_kept += lbase[255];
   }
   __syncthreads();
-  const uint32_t cnt_tile = min(n - tb, (uint32_t)kTile);
+  const uint32_t cnt_tile = s_kept;
   // pass 1: values (and digits) into tile-local digit order
 #pragma unroll
   for (int r = 0; r < kSRounds; ++r) {
-    const uint32_t j = wb + r * 64 + lane;
-    if (j < n) {
+    if ((inmask >> r) & 1) {
       const uint32_t lp = lbase[dg[r]] + wcnt[w][dg[r]] + rk[r];
       reinterpret_cast<uint32_t*>(stage)[lp] = vl[r];
       sdig[lp] = (uint8_t)dg[r];
@@ -1207,10 +1243,8 @@ __global__ __launch_bounds__(kST) void sort_scatter_kernel(JobSet J, uint32_t p)
   }
   __syncthreads();
 #pragma unroll
-  for (int r = 0; r < kSRounds; ++r) {
-    const uint32_t j = wb + r * 64 + lane;
-    if (j < n) stage[lbase[dg[r]] + wcnt[w][dg[r]] + rk[r]] = ky[r];
-  }
+  for (int r = 0; r < kSRounds; ++r)
+    if ((inmask >> r) & 1) stage[lbase[dg[r]] + wcnt[w][dg[r]] + rk[r]] = ky[r];
   __syncthreads();
   for (uint32_t i = threadIdx.x; i < cnt_tile; i += kST) {
     const uint32_t d = sdig[i];
@@ -1533,7 +1567,8 @@ __device__ __forceinline__ BS<1> get_b<1>(const uint32_t* w) {
 
 struct DDArgs {
   const odp_event* ev;
-  uint32_t n;
+  uint32_t n;          // records of the log (values are packed when n < kPackLimit)
+  uint32_t small;      // 1: the digest job was sorted in one workgroup (every record kept)
   const uint8_t* aux;
   const SortJob* job;  // the digest job (keys/vals in buffer npasses & 1)
   const AnaCtl* ctl;
@@ -1621,12 +1656,16 @@ __device__ __forceinline__ void wave_bscan(uint32_t& f, BS<MODE>& v) {
 // Orders this wavefront's LDS writes before its later LDS reads by other lanes.
 __device__ __forceinline__ void wave_lds_fence() { __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront"); }
 
+// Elements of the digest job's sorted order the scans read.
+__device__ __forceinline__ uint32_t dd_len(const DDArgs& A) { return A.small ? A.n : sorted_len(*A.job); }
+
 // All 16 rounds of a wavefront at once: keys and values (coalesced), then
 // the endpoint codes gathered by value, all loads in flight together. Values
 // and codes go to the wavefront's LDS rows; bit r of heads / tails says
 // whether this lane's element of round r starts / ends its digest group.
+// n: the sorted elements; packed: codes in the values' top byte.
 __device__ __forceinline__ void load_wave(const unsigned long long* k, const uint32_t* v, const uint8_t* aux,
-                                          uint32_t n, uint32_t wb, uint32_t* s_val, uint8_t* s_code,
+                                          uint32_t n, bool packed, uint32_t wb, uint32_t* s_val, uint8_t* s_code,
                                           uint32_t& heads, uint32_t& tails) {
   const int lane = threadIdx.x & 63;
   unsigned long long key[kRounds];
@@ -1640,7 +1679,7 @@ __device__ __forceinline__ void load_wave(const unsigned long long* k, const uin
   const unsigned long long before = (lane == 0 && wb > 0 && wb < n) ? k[wb - 1] : 0ull;
   const unsigned long long after = (lane == 63 && wb + kWaveElems < n) ? k[wb + kWaveElems] : 0ull;
   uint8_t a[kRounds];
-  if (n < kPackLimit) {
+  if (packed) {
 #pragma unroll
     for (int r = 0; r < kRounds; ++r) {
       a[r] = wb + r * 64 + lane < n ? (uint8_t)(val[r] >> 24) : kNotTransfer;
@@ -1672,7 +1711,7 @@ __device__ __forceinline__ void load_wave(const unsigned long long* k, const uin
 // One round of 64 sorted elements: endpoint code (gathered by value) and
 // whether the element starts / ends its digest group.
 __device__ __forceinline__ void load_round(const unsigned long long* k, const uint32_t* v, const uint8_t* aux,
-                                           uint32_t n, uint32_t j, uint8_t& a, bool& head, bool& tail) {
+                                           uint32_t n, bool packed, uint32_t j, uint8_t& a, bool& head, bool& tail) {
   const int lane = threadIdx.x & 63;
   const bool in = j < n;
   const unsigned long long key = in ? k[j] : 0ull;
@@ -1682,7 +1721,7 @@ __device__ __forceinline__ void load_round(const unsigned long long* k, const ui
   if (lane == 63 && in && j + 1 < n) next = k[j + 1];
   head = in && (j == 0 || prev != key);
   tail = in && (j + 1 == n || next != key);
-  a = !in ? kNotTransfer : n < kPackLimit ? (uint8_t)(v[j] >> 24) : aux[v[j]];
+  a = !in ? kNotTransfer : packed ? (uint8_t)(v[j] >> 24) : aux[v[j]];
 }
 
 // Per-wavefront aggregates. The forward one folds the elements after the
@@ -1700,6 +1739,8 @@ __device__ void ddrt_agg_body(const DDArgs& A) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const uint32_t wid = blockIdx.x * (kT / 64) + w;
   const uint32_t wb = wid * kWaveElems;
+  const uint32_t ns = dd_len(A);
+  const bool packed = A.n < kPackLimit;
   uint32_t cf = 0, cb = 0;
   FS<MODE> fv = S::fid();
   BS<MODE> bv = S::bid();
@@ -1707,7 +1748,7 @@ __device__ void ddrt_agg_body(const DDArgs& A) {
   for (int r = kRounds - 1; r >= 0; --r) {
     uint8_t a;
     bool head, tail;
-    load_round(k, v, A.aux, A.n, wb + r * 64 + lane, a, head, tail);
+    load_round(k, v, A.aux, ns, packed, wb + r * 64 + lane, a, head, tail);
     uint32_t f = head;
     FS<MODE> x = S::flift(a);
     wave_fscan<MODE>(f, x);
@@ -1723,7 +1764,7 @@ __device__ void ddrt_agg_body(const DDArgs& A) {
   for (int r = 0; r < kRounds; ++r) {
     uint8_t a;
     bool head, tail;
-    load_round(k, v, A.aux, A.n, wb + r * 64 + lane, a, head, tail);
+    load_round(k, v, A.aux, ns, packed, wb + r * 64 + lane, a, head, tail);
     uint32_t g = tail;
     BS<MODE> y = S::blift(a);
     wave_bscan<MODE>(g, y);
@@ -1882,7 +1923,8 @@ __device__ void ddrt_final_body(const DDArgs& A, uint32_t (*s_val)[kWaveElems], 
   const uint32_t wb = wid * kWaveElems;
   // per round: value and endpoint code (LDS), start/end flags and forward results (bits)
   uint32_t heads, tails, fres = 0;
-  load_wave(k, v, A.aux, A.n, wb, s_val[w], s_code[w], heads, tails);
+  const uint32_t ns = dd_len(A);
+  load_wave(k, v, A.aux, ns, A.n < kPackLimit, wb, s_val[w], s_code[w], heads, tails);
   FS<MODE> carry = get_f<MODE>(A.carry[wid].fs);
 #pragma unroll 1
   for (int r = 0; r < kRounds; ++r) {
@@ -1919,7 +1961,7 @@ __device__ void ddrt_final_body(const DDArgs& A, uint32_t (*s_val)[kWaveElems], 
     const BS<MODE> yn = S::shfl_down(y, 1);
     BS<MODE> ex = lane == 63 ? bcarry : (gn ? yn : S::bop(yn, bcarry));
     if (tail) ex = S::bid();
-    if (j < A.n && a != kNotTransfer) {
+    if (j < ns && a != kNotTransfer) {
       const uint32_t sr = a >> 4, d = a & 15;
       uint8_t res = 0;
       if (fres & (1u << (2 * r))) res |= ODP_F_DD;
@@ -2586,7 +2628,8 @@ __global__ void finalize_kernel(AnaCtl* ctl, odp_report* rep) {
 struct Alg2Args {
   const SortJob* job;        // the digest job (keys/vals in buffer npasses & 1)
   const uint8_t* aux;
-  uint32_t n;
+  uint32_t n;                // records of the log
+  uint32_t small;            // 1: the digest job was sorted in one workgroup (every record kept)
   uint32_t* rx;              // [n] partner record, or kNone
   unsigned long long* npairs;
 };
@@ -2627,7 +2670,7 @@ __global__ __launch_bounds__(kT) void alg2_kernel(Alg2Args A) {
   const unsigned long long* k = s.keys[s.npasses & 1];
   const uint32_t* v = s.vals[s.npasses & 1];
   uint32_t* lists = s.vals[(s.npasses + 1) & 1];
-  const uint32_t n = A.n, lane = threadIdx.x & 63;
+  const uint32_t n = A.small ? A.n : sorted_len(s), lane = threadIdx.x & 63;
   const uint64_t lt = lanemask_lt();
   const uint32_t c0 = (blockIdx.x * kT + threadIdx.x) / 64 * 64;
   if (c0 >= n) return;
@@ -2890,6 +2933,9 @@ void build_jobs(const Views& v, SortJob* hj) {
   hj[kJobBig].word_bytes[0] = 8;
   hj[kJobBig].nwords = 1;
   hj[kJobBig].hist0_pre = 1;
+  hj[kJobBig].drop0 = 1;
+  hj[kJobBig].n_after0 = &ctl->n_tx;
+  hj[kJobBig].aux = v.aux;
   // ALLOC/DELETE by (device, device address); words least significant first
   hj[kJobAd].n_ptr = &ctl->n_ad;
   hj[kJobAd].vals[0] = v.S.ad_vals;
@@ -3470,6 +3516,7 @@ static int enqueue_analysis(Workspace* ws, const odp_event* events, size_t n, ui
   DDArgs D;
   D.ev = events;
   D.n = nn;
+  D.small = small;
   D.aux = v.aux;
   D.job = v.jobs + kJobBig;
   D.ctl = ctl;
@@ -3488,6 +3535,7 @@ static int enqueue_analysis(Workspace* ws, const odp_event* events, size_t n, ui
     G.job = v.jobs + kJobBig;
     G.aux = v.aux;
     G.n = nn;
+    G.small = small;
     G.rx = alg2_rx;
     G.npairs = alg2_np;
     hipLaunchKernelGGL(alg2_kernel, dim3(ceil_div32(n, kT)), dim3(kT), 0, stream, G);
