@@ -873,14 +873,16 @@ __global__ void sort_plan_kernel(JobSet J, uint32_t first_passes) {
   s.npasses = s.np_first;
 }
 
-// Local fix of the digest job, launched before each deferred pass p (p >=
-// np_first) and once after the last. After the passes 0..q-1 that ran, the
-// keys, sorted stably on those bytes, fall into runs of equal sorted bytes.
-// The duplicate and round-trip scans need each digest's elements together and
-// in input order only, so a run that holds one digest is done, and a run that
-// holds several (which may interleave) is done once sorted stably by the whole
-// key. Runs longer than kFixMax that hold several digests switch pass q on
-// instead; shorter ones are sorted in place.
+// Local fix of the digest job, launched before the first deferred pass
+// (p = np_first: the check) and once after the last (p = kFixFinal: the
+// sort). After the passes 0..p-1, the keys, sorted stably on those bytes, fall
+// into runs of equal sorted bytes. The duplicate and round-trip scans need
+// each digest's elements together and in input order only, so a run that
+// holds one digest is done, and a run that holds several (which may
+// interleave) is done once sorted stably by the whole key. A run longer than
+// kFixMax that holds several digests switches every remaining pass on (the
+// full stable sort then leaves nothing to fix); otherwise the short runs are
+// sorted in place after the (skipped) passes.
 //
 // Check (npasses == p): a "collision" is an element whose key differs from its
 // predecessor's in the same run. Each block stages a tile of kFixTile keys with
@@ -891,10 +893,11 @@ __global__ void sort_plan_kernel(JobSet J, uint32_t first_passes) {
 // keys[(p+1)&1][t * kFixTile/2 ...]; a tile holds at most kFixTile/2 first
 // collisions, since each has its run's previous element before it. No key
 // moves in the check, so every walk sees the same array.
-// Sort (npasses == p-1, so pass p-1 did not run): a block per tile of the
-// check before p-1, a thread per recorded run, each an insertion sort; the
-// runs are disjoint.
+// Sort (p = kFixFinal, npasses == np_first < np_full, so the check found no
+// long run and no deferred pass ran): a block per tile of the check, a thread
+// per recorded run, each an insertion sort; the runs are disjoint.
 constexpr uint32_t kFixMax = 128;
+constexpr uint32_t kFixFinal = 0xFFFFFFFFu;
 constexpr uint32_t kFixTile = 4 * kT;
 constexpr uint32_t kFixHalo = kFixMax + 1;
 constexpr uint32_t kWalkIdle = 0, kWalking = 1, kWalkEnd = 2, kWalkLong = 3;
@@ -910,11 +913,13 @@ __global__ __launch_bounds__(kT) void sort_fix_kernel(SortJob* job, uint32_t p) 
   const uint32_t np = s_np;
   const uint32_t n = pass_len(s, 1);  // the sorted elements (the fix runs after a pass)
   const uint32_t nft = (n + kFixTile - 1) / kFixTile;
-  if (p >= 1 && np == p - 1 && p - 1 < s.np_full) {
-    const unsigned long long* runs = s.keys[p & 1];
-    const uint32_t* cnt = s.vals[p & 1];
-    unsigned long long* k = s.keys[(p - 1) & 1];
-    uint32_t* v = s.vals[(p - 1) & 1];
+  if (p == kFixFinal) {
+    if (np != s.np_first || np >= s.np_full) return;
+    const uint32_t q = np;  // the pass the check ran before
+    const unsigned long long* runs = s.keys[(q + 1) & 1];
+    const uint32_t* cnt = s.vals[(q + 1) & 1];
+    unsigned long long* k = s.keys[q & 1];
+    uint32_t* v = s.vals[q & 1];
     for (uint32_t t = blockIdx.x; t < nft; t += gridDim.x) {
       const uint32_t c = cnt[t];
       for (uint32_t r = threadIdx.x; r < c; r += kT) {
@@ -1017,7 +1022,7 @@ __global__ __launch_bounds__(kT) void sort_fix_kernel(SortJob* job, uint32_t p) 
     }
     if (threadIdx.x == 0) cnt[t] = recorded;
   }
-  if (__syncthreads_or(long_mixed) && threadIdx.x == 0) s.npasses = p + 1;
+  if (__syncthreads_or(long_mixed) && threadIdx.x == 0) s.npasses = s.np_full;
 }
 
 // Locates this block's job and first tile; returns false when the block has
@@ -3506,12 +3511,12 @@ static int enqueue_analysis(Workspace* ws, const odp_event* events, size_t n, ui
     hipLaunchKernelGGL(sort_small_kernel, dim3(Jb.njobs), dim3(kQT), 0, stream, Jb);
   } else {
     for (uint32_t p = 0; p < 8; ++p) {
-      if (kfirst && p >= kfirst) hipLaunchKernelGGL(sort_fix_kernel, dim3(nft), dim3(kT), 0, stream, v.jobs + kJobBig, p);
+      if (kfirst && p == kfirst) hipLaunchKernelGGL(sort_fix_kernel, dim3(nft), dim3(kT), 0, stream, v.jobs + kJobBig, p);
       hipLaunchKernelGGL(sort_hist_kernel, dim3(Jh.stride), dim3(kT), 0, stream, Jh, p);
       hipLaunchKernelGGL(sort_scan_kernel, dim3(256), dim3(kT), 0, stream, Jb, p);
       hipLaunchKernelGGL(sort_scatter_kernel, dim3(nt), dim3(kST), 0, stream, Jb, p);
     }
-    if (kfirst) hipLaunchKernelGGL(sort_fix_kernel, dim3(nft), dim3(kT), 0, stream, v.jobs + kJobBig, 8u);
+    if (kfirst) hipLaunchKernelGGL(sort_fix_kernel, dim3(nft), dim3(kT), 0, stream, v.jobs + kJobBig, kFixFinal);
   }
   DDArgs D;
   D.ev = events;

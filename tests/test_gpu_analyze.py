@@ -209,7 +209,7 @@ def test_digests_sharing_low_bytes(odp, m, seed):
     """The digest sort first orders by the low bytes only (3 of them at 30,000
     records and at a million, 4 at ten million); runs of equal low bytes that hold several digests
     are then sorted in place by the whole digest when they are short, and
-    switch the next pass on when they are long. Planted digests that differ
+    switch every remaining pass on when one is long. Planted digests that differ
     from another only in byte 6 or 7, or only in byte 4, interleaved in time
     with it, land in short mixed runs (else their groups interleave and the
     flags go wrong); unrelated random digests take whatever the checks find.
@@ -241,8 +241,9 @@ def test_digests_sharing_low_bytes(odp, m, seed):
 def test_long_runs_of_shared_low_bytes(odp, m, byte):
     """Two groups of 400 records each whose digests differ only in one high
     byte, interleaved in time, form one run of equal low bytes longer than any
-    run sorted in place: the passes up to that byte must run, and the other
-    records (random digests, some in short mixed runs) still come out right."""
+    run sorted in place (in the low 3 or 4 bytes the first passes sort, or in
+    a higher byte): the remaining passes must run, and the other records
+    (random digests, some in short mixed runs) still come out right."""
     rng = np.random.default_rng(m + byte)
     ev = W.empty_events(m)
     ev["op"] = rng.choice([W.H2D, W.D2H, W.D2D], size=m)
