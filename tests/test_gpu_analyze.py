@@ -361,3 +361,37 @@ def test_allocation_groups_of_every_size(odp, pairs, keys, hot):
     ev["bytes"] = np.where(kern, 0, ev["bytes"])
     fg, rg = check(odp, ev)
     assert rg["ra_events"] > 0
+
+
+@pytest.mark.parametrize("m,tx_share", [(5_000, 0.5), (20_000, 0.02), (20_000, 0.0), (3_000, 1.0)])
+def test_digest_sort_keeps_only_transfers(odp, m, tx_share):
+    """The digest sort's first pass drops every record that is not a valid
+    transfer (KERNEL, ALLOC/DELETE, rejected records), which carry the
+    all-ones sort key. Transfers whose digest is itself all ones, or shares
+    its low bytes with it, must still be grouped with each other and nothing
+    else: logs from no transfers at all to transfers only, with rejected
+    records sprinkled in, must match the oracle."""
+    rng = np.random.default_rng(int(m * 10 + tx_share * 100))
+    ev = W.empty_events(m)
+    t = np.cumsum(rng.integers(0, 3, size=m)).astype(np.uint64)
+    ev["t_start"] = t
+    ev["t_end"] = t + 1
+    is_tx = rng.random(m) < tx_share
+    ev["op"] = np.where(is_tx, rng.choice([W.H2D, W.D2H, W.D2D], size=m),
+                        rng.choice([W.KERNEL, W.ALLOC, W.DELETE], size=m))
+    op = ev["op"]
+    src = rng.integers(0, 3, size=m)
+    dst = rng.integers(0, 3, size=m)
+    ev["src_dev"] = np.where(op == W.H2D, -1, src)
+    ev["dst_dev"] = np.where(op == W.D2H, -1, dst)
+    ones = np.uint64(0xFFFFFFFFFFFFFFFF)
+    pool = np.array([ones, ones ^ np.uint64(1 << 63), ones ^ np.uint64(1 << 40), 7, 8], dtype=np.uint64)
+    ev["digest"] = np.where(is_tx, rng.choice(pool, size=m), rng.integers(0, 1 << 62, size=m).astype(np.uint64))
+    var = rng.integers(0, 50, size=m).astype(np.uint64)
+    ev["src_addr"] = np.uint64(W.HOST_BASE) + var * np.uint64(4096)
+    ev["dst_addr"] = np.uint64(W.DEV_BASE) + var * np.uint64(4096)
+    ev["bytes"] = np.uint64(4096)
+    bad = rng.random(m) < 0.01
+    ev["t_end"][bad] = ev["t_start"][bad] - np.uint64(1) * (ev["t_start"][bad] > 0)
+    ev["dst_dev"][bad & (ev["t_start"] == 0)] = 42
+    check(odp, ev)
