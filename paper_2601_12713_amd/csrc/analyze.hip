@@ -2139,10 +2139,24 @@ __global__ __launch_bounds__(kT) void pair_scatter_kernel(PairArgs P) {
 // ---------------------------------------------------------------------------
 // Also writes the two sorted orders out as plain arrays of starts and ends,
 // so the binary searches of the unused-mapping rules read one array each.
-__global__ __launch_bounds__(kT) void kernel_ranges_kernel(const SortJob* ks, const SortJob* ke, const uint64_t* k_w_dev,
-                                                           const uint64_t* k_w_start, const uint64_t* k_w_end,
-                                                           const uint32_t* n_k, uint64_t* starts_sorted,
-                                                           uint64_t* ends_sorted, AnaCtl* ctl) {
+struct KernRangeArgs {
+  const SortJob *ks, *ke;
+  const uint64_t *k_w_dev, *k_w_start, *k_w_end;
+  const uint32_t* n_k;
+  uint64_t *starts_sorted, *ends_sorted;
+  AnaCtl* ctl;
+};
+// (grid-stride; run by side_misc_kernel)
+__device__ __forceinline__ void kernel_ranges_body(const KernRangeArgs& K) {
+  const SortJob* ks = K.ks;
+  const SortJob* ke = K.ke;
+  const uint64_t* k_w_dev = K.k_w_dev;
+  const uint64_t* k_w_start = K.k_w_start;
+  const uint64_t* k_w_end = K.k_w_end;
+  uint64_t* starts_sorted = K.starts_sorted;
+  uint64_t* ends_sorted = K.ends_sorted;
+  AnaCtl* ctl = K.ctl;
+  const uint32_t* n_k = K.n_k;
   if (!ctl->kern_sort) return;  // the chronological path reads the per-device lists instead
   const uint32_t n = *n_k;
   const uint32_t* v = ks->vals[ks->npasses & 1];
@@ -2198,7 +2212,8 @@ __device__ __forceinline__ bool same_pair_key(const uint64_t* haddr, const uint6
   return haddr[a] == haddr[b] && dev[a] == dev[b] && bytes[a] == bytes[b];
 }
 
-__global__ __launch_bounds__(kT) void pair_table_clear_kernel(PairTable T, const uint32_t* n_pairs) {
+// (grid-stride; run by side_misc_kernel)
+__device__ __forceinline__ void pair_table_clear_body(const PairTable& T, const uint32_t* n_pairs) {
   const uint32_t size = pair_table_mask(*n_pairs) + 1;
   for (uint32_t i = blockIdx.x * kT + threadIdx.x; i < size; i += gridDim.x * kT) {
     T.owner[i] = 0;
@@ -2476,7 +2491,8 @@ __global__ __launch_bounds__(kT) void ut_scan_kernel(UtArgs U) {
 // after it when that has the same key.
 // A wavefront takes 64 consecutive sorted elements, so each lane gets its
 // neighbour's key by a lane move and only the last lane loads one more.
-__global__ __launch_bounds__(kT) void ut_next_kernel(UtArgs U) {
+// (grid-stride by wavefronts; run by side_misc_kernel)
+__device__ __forceinline__ void ut_next_body(const UtArgs& U) {
   if (!U.ctl->ut_need_sort) return;
   const uint32_t n = *U.n_ut;
   const SortJob& s = *U.ut_job;
@@ -2496,6 +2512,16 @@ __global__ __launch_bounds__(kT) void ut_next_kernel(UtArgs U) {
     }
     if (in) U.next_q[q] = (j + 1 < n && an == a && cn == c) ? qn : kNone;
   }
+}
+
+// Three independent grid-stride jobs of the allocation path in one launch
+// (each a launch of its own before, mostly returning at once): the kernel
+// lists' ranges and sorted starts and ends, the next copy of each copy-in's
+// place (both only on their sorted paths), and the clearing of the RA table.
+__global__ __launch_bounds__(kT) void side_misc_kernel(KernRangeArgs K, UtArgs U, PairTable T, const uint32_t* n_pairs) {
+  kernel_ranges_body(K);
+  ut_next_body(U);
+  pair_table_clear_body(T, n_pairs);
 }
 
 // Over the copy-ins in log order: whether a kernel on the receiving device
@@ -3467,13 +3493,12 @@ static int enqueue_analysis(Workspace* ws, const odp_event* events, size_t n, ui
   hipLaunchKernelGGL(pair_count_kernel, dim3(nt), dim3(kT), 0, side, P);
   hipLaunchKernelGGL(scan_counts_kernel<2>, dim3(1), dim3(1024), 0, side, v.tile_cnt, nt, &ctl->n_pairs, nullptr);
   hipLaunchKernelGGL(pair_scatter_kernel, dim3(nt), dim3(kT), 0, side, P);
-  hipLaunchKernelGGL(kernel_ranges_kernel, dim3(grid_map), dim3(kT), 0, side, v.jobs + kJobKs, v.jobs + kJobKe,
-                     v.S.k_w_dev, v.S.k_w_start, v.S.k_w_end, &ctl->n_k, v.starts_sorted, v.ends_sorted, ctl);
-  hipLaunchKernelGGL(ut_next_kernel, dim3(grid_map), dim3(kT), 0, side, U);
+  const KernRangeArgs K{v.jobs + kJobKs, v.jobs + kJobKe, v.S.k_w_dev, v.S.k_w_start, v.S.k_w_end,
+                        &ctl->n_k, v.starts_sorted, v.ends_sorted, ctl};
+  hipLaunchKernelGGL(side_misc_kernel, dim3(grid_map), dim3(kT), 0, side, K, U, v.pt, &ctl->n_pairs);
   hipLaunchKernelGGL(ut_eval_kernel, dim3(grid_map), dim3(kT), 0, side, U);
 
-  // Pairs grouped by (host address, device, bytes) in a table.
-  hipLaunchKernelGGL(pair_table_clear_kernel, dim3(grid_map), dim3(kT), 0, side, v.pt, &ctl->n_pairs);
+  // Pairs grouped by (host address, device, bytes) in a table (cleared above).
   hipLaunchKernelGGL(pair_table_insert_kernel, dim3(grid_pair), dim3(kT), 0, side, v.pt, &ctl->n_pairs,
                      v.pr_w_haddr, v.pr_w_dev, v.pr_w_bytes);
 
